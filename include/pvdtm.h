@@ -1,0 +1,240 @@
+/*
+ * pvdtm.h -- C ABI of the MI355X (gfx950) matrix-free Chebyshev/stencil library.
+ *
+ * Operations follow Pieper, Hager, Fehske, "A domain-specific language and
+ * matrix-free stencil code for investigating electronic properties of Dirac
+ * and topological materials" (arXiv:1708.09689):
+ *   - lattice + stencil description: Sec. 3.2 (stencil blocks per neighbour
+ *     offset), Sec. 3.4 (cuboid geometry, per-dimension periodic BCs);
+ *   - model stencils: Sec. 2.1 (graphene), 2.2 (3D TI), 2.3 (Weyl);
+ *   - fused sweep y = alpha (H - beta) x + gamma y with partial dot products:
+ *     Sec. 3.2, generated-code listing (scale_h, shift_h, scale_z, dot_xx/xy/yy);
+ *   - KPM moments: Sec. 2.2 (DOS) and Sec. 4;
+ *   - Chebyshev time propagation: Sec. 4.1, Eq. (U_1);
+ *   - Chebyshev filter diagonalisation with Rayleigh-Ritz: Sec. 4.2.
+ *
+ * Conventions
+ * -----------
+ * Data layout.  A block of nb vectors is stored row-major [rows][nb], complex
+ * interleaved (re, im).  Row r = s*n_orb + o, site s = x + Lx*(y + Ly*z);
+ * element (x, y, z, o, c) is complex number ((s*n_orb + o)*nb + c).  x is the
+ * fastest lattice direction.
+ * Device pointers.  Every vector, potential, moment or gradient pointer is a
+ * device pointer (hipMalloc'd, or a torch CUDA tensor's data_ptr()); it is
+ * BORROWED: the caller keeps it alive until the work queued on `stream` has
+ * finished.  Complex128 blocks must be 16-byte aligned, complex64 8-byte.
+ * Host pointers.  Descriptors, coefficient arrays and scale/shift arrays are
+ * host memory, copied or consumed before the call returns.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * All launches are asynchronous on that stream unless a function says it
+ * synchronises.
+ * Errors.  Every argument is validated before the first launch; on error
+ * nothing is queued, the status is returned and pv_last_error() (thread
+ * local) holds a message.  No C++ exception crosses this interface.
+ * Workspace.  Functions that need scratch device memory take (work,
+ * work_bytes) from the caller; the matching *_workspace_size() call gives the
+ * minimum size.  Too small a workspace gives PV_ERR_WORKSPACE.
+ * Determinism.  Reductions use fixed-order two-pass sums (no floating-point
+ * atomics): repeated calls with the same inputs give bitwise equal results.
+ */
+#ifndef PVDTM_H
+#define PVDTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pv_status {
+    PV_OK = 0,
+    PV_ERR_INVALID_ARG = 1,
+    PV_ERR_UNSUPPORTED = 2,
+    PV_ERR_NOT_HERMITIAN = 3,
+    PV_ERR_WORKSPACE = 4,
+    PV_ERR_OOM = 5,
+    PV_ERR_HIP = 6,
+    PV_ERR_NONFINITE = 7,
+    PV_ERR_NO_DEVICE = 8,
+    PV_ERR_NOT_CONVERGED = 9
+} pv_status;
+
+/* Vector element type: complex128 or complex64 (FP32 vectors, FP64 dots). */
+typedef enum pv_dtype { PV_C128 = 0, PV_C64 = 1 } pv_dtype;
+/* Real type of the on-site field array. */
+typedef enum pv_rtype { PV_F64 = 0, PV_F32 = 1 } pv_rtype;
+/* How the real on-site field V enters H (Sec. 2): */
+typedef enum pv_pot_mode {
+    PV_POT_NONE = 0,     /* no field */
+    PV_POT_SITE = 1,     /* V[s] times the identity on the site's orbitals (V_n Gamma^0) */
+    PV_POT_ORBITAL = 2   /* V[s*n_orb + o] on the diagonal (v_{n,j} of the graphene cell) */
+} pv_pot_mode;
+
+#define PV_CHECK_HERMITIAN 1u
+
+/* Partial dot products requested from a sweep (Sec. 3.2 listing flags). */
+#define PV_DOT_XX 1u  /* <x, x>          */
+#define PV_DOT_XY 2u  /* <x, y_new>      */
+#define PV_DOT_YY 4u  /* <y_new, y_new>  */
+
+#define PV_MAX_TERMS 26
+#define PV_MAX_ORB 4
+#define PV_MAX_NB 64
+
+/*
+ * Lattice and stencil (Sec. 3.2, Sec. 3.4).  The operator is
+ *     (H x)[s] = sum_t B_t x[s + d_t] + (E0 + V_s) x[s]
+ * with d_t in {-1,0,1}^3 \ {0}; a neighbour that leaves [0, L) along an open
+ * dimension contributes nothing, along a periodic one it wraps.
+ *   dim       2 or 3 (dim 2 requires L[2] == 1 and d_t[2] == 0)
+ *   L         extents (x, y, z), each >= 1
+ *   n_orb     orbitals per site: 1, 2 or 4
+ *   periodic  per-dimension flag (nonzero = periodic)
+ *   n_terms   number of neighbour offsets, 0..PV_MAX_TERMS, pairwise distinct
+ *   offsets   [n_terms][3]
+ *   blocks    [n_terms][n_orb][n_orb] complex as (re, im) doubles; block[t][o][o']
+ *             multiplies x[s + d_t, o'] into row o
+ *   onsite    [n_orb][n_orb] complex (E0)
+ *   pot_mode  pv_pot_mode
+ *   flags     PV_CHECK_HERMITIAN: require B_{-d} = B_d^H and E0 = E0^H
+ *             (to 1e-14 relative); otherwise PV_ERR_NOT_HERMITIAN
+ */
+typedef struct pv_lattice_desc {
+    int dim;
+    int64_t L[3];
+    int n_orb;
+    int periodic[3];
+    int n_terms;
+    const int *offsets;
+    const double *blocks;
+    const double *onsite;
+    int pot_mode;
+    unsigned flags;
+} pv_lattice_desc;
+
+typedef struct pv_lattice pv_lattice;
+typedef struct pv_batch pv_batch;
+
+/* Thread-local message describing the last error of this thread. */
+const char *pv_last_error(void);
+const char *pv_status_string(pv_status s);
+int pv_version(void);
+
+/*
+ * Model stencils (host only, no device use).  Fill the descriptor arrays for
+ * a model of Sec. 2; the caller provides capacity offsets[PV_MAX_TERMS*3],
+ * blocks[PV_MAX_TERMS*PV_MAX_ORB*PV_MAX_ORB*2], onsite[PV_MAX_ORB*PV_MAX_ORB*2].
+ *   PV_MODEL_TI         Sec. 2.2 Eq. (TB_H_topi); params {t, m, Delta1, Delta2};
+ *                       Gamma^1 = tau_z sigma_0, Gamma^{j+1} = tau_x sigma_j,
+ *                       Gamma^5 = tau_y sigma_0, orbital o = 2 tau + sigma;
+ *                       hopping -(t/2)(G1 - i G_{j+1}) from n to n + e_j
+ *   PV_MODEL_GRAPHENE2  honeycomb, two-site cell on an (i, j) grid; params {t}:
+ *                       A(i,j) bonds to B(i,j), B(i-1,j), B(i,j-1) with -t
+ *   PV_MODEL_GRAPHENE4  Sec. 2.1 Eq. (graphene_model) four-site cell; params {t}
+ *   PV_MODEL_WEYL       Sec. 2.3 Eq. (TB_H_wsm); params {k0}
+ * On return *n_terms, *n_orb, *dim and *pot_mode describe the model.
+ */
+typedef enum pv_model {
+    PV_MODEL_TI = 0, PV_MODEL_GRAPHENE2 = 1, PV_MODEL_GRAPHENE4 = 2, PV_MODEL_WEYL = 3
+} pv_model;
+pv_status pv_model_stencil(int model, const double *params, int *dim, int *n_orb,
+                           int *n_terms, int *offsets, double *blocks, double *onsite,
+                           int *pot_mode);
+
+/* Create a lattice from a descriptor (host only; the library copies it and
+ * owns *out).  pv_lattice_destroy frees library state only. */
+pv_status pv_lattice_create(const pv_lattice_desc *desc, pv_lattice **out);
+void pv_lattice_destroy(pv_lattice *lat);
+
+/* Number of sites, rows (sites * n_orb) and the sweep kernel family chosen
+ * for this stencil (0 = generic dense blocks, >0 = a pattern-specialised
+ * kernel whose zero / real / imaginary block structure is compiled in). */
+pv_status pv_lattice_info(const pv_lattice *lat, int64_t *n_sites, int64_t *n_rows,
+                          int *kernel_family);
+
+/* Attach the on-site field: V_dev is a BORROWED device array of n_sites
+ * (PV_POT_SITE) or n_rows (PV_POT_ORBITAL) reals of type rtype; NULL means
+ * V = 0.  Replaces any previous field. */
+pv_status pv_lattice_set_potential(pv_lattice *lat, const void *V_dev, int rtype);
+
+/*
+ * One fused sweep (Sec. 3.2 listing), per column c of the nb-wide blocks:
+ *     y[:, c] = alpha[c] * (H x[:, c] - beta[c] x[:, c]) + gamma[c] * z[:, c]
+ * gamma[c] == 0 means z is not read (z may be NULL then for all columns).
+ * z may equal y (in-place recurrence); x must not overlap y or z.
+ * alpha, beta, gamma: host arrays [nb].  dot_flags selects partial dot
+ * products written to dots (device, [nb][4] doubles: <x,x>, Re<x,y>,
+ * Im<x,y>, <y,y>, accumulated in FP64); dots may be NULL when dot_flags==0.
+ * nb: power of two, 1..PV_MAX_NB.  Workspace: pv_spmmv_workspace_size().
+ */
+size_t pv_spmmv_workspace_size(const pv_lattice *lat, int dtype, int nb);
+pv_status pv_spmmv(pv_lattice *lat, int dtype, int nb, const void *x, const void *z, void *y,
+                   const double *alpha, const double *beta, const double *gamma,
+                   unsigned dot_flags, double *dots, void *work, size_t work_bytes,
+                   void *stream);
+
+/*
+ * KPM moments (Sec. 2.2 DOS, Sec. 4): for every column c of the start block r
+ *     mu[c][n] = Re <r_c, T_n(H~) r_c> / D,  H~ = (H - b)/a,  n = 0..M-1,
+ * with D = n_rows, formed from M/2 fused sweeps through
+ * mu_{2n} = 2<w_n,w_n>/D - mu_0 and mu_{2n+1} = 2 Re<w_n,w_{n+1}>/D - mu_1.
+ * M even, 2 <= M <= 65536; a > 0.  r is read only.  mu: device [nb][M] FP64.
+ */
+size_t pv_kpm_workspace_size(const pv_lattice *lat, int dtype, int nb, int M);
+pv_status pv_kpm_moments(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
+                         const void *r, double *mu, void *work, size_t work_bytes, void *stream);
+
+/* Jackson-damped DOS per row from moments (host arrays):
+ *   rho(E) = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(x)] / (pi a sqrt(1 - x^2)),
+ *   x = (E - b)/a; mu: [M] (e.g. the column mean), E, rho: [nE]. */
+pv_status pv_kpm_dos(int M, const double *mu, double a, double b, int nE, const double *E,
+                     double *rho);
+
+/*
+ * Chebyshev series applied to a block (Sec. 4.1 and 4.2):
+ *     Y = sum_{k=0}^{K} coef[k] T_k(H~) X,   coef: host complex [K+1] (re, im)
+ * using K fused sweeps whose epilogue accumulates coef[k] * w_k.  X and Y
+ * must not overlap.  K >= 0.
+ */
+size_t pv_cheb_series_workspace_size(const pv_lattice *lat, int dtype, int nb);
+pv_status pv_cheb_series(pv_lattice *lat, int dtype, int nb, double a, double b, int K,
+                         const double *coef, const void *X, void *Y, void *work,
+                         size_t work_bytes, void *stream);
+
+/*
+ * Chebyshev time propagation, Sec. 4.1 Eq. (U_1): nsteps steps of
+ *     psi <- exp(-i b dt) [c_0 + 2 sum_{k=1}^{M} c_k T_k(H~)] psi,
+ *     c_k = (-i)^k J_k(a dt)   (Bessel J_k by Miller's backward recurrence)
+ * in place on psi (device [rows][nb]).  M >= 1, nsteps >= 0.
+ */
+size_t pv_cheb_propagate_workspace_size(const pv_lattice *lat, int dtype, int nb);
+pv_status pv_cheb_propagate(pv_lattice *lat, int dtype, int nb, double a, double b, double dt,
+                            int M, int nsteps, void *psi, void *work, size_t work_bytes,
+                            void *stream);
+/* c_k = (-i)^k J_k(a dt), k = 0..M, complex (re, im) into host coef[M+1][2]. */
+pv_status pv_cheb_tp_coefficients(double a, double dt, int M, double *coef);
+
+/*
+ * Tall-skinny products with FP64 accumulation (Rayleigh-Ritz of Sec. 4.2):
+ *   pv_gram:         G[i][j] = sum_r conj(X[r][i]) Y[r][j]
+ *                    X [rows][nx], Y [rows][ny], G device complex128 [nx][ny]
+ *   pv_block_rotate: Y[r][j] = sum_i X[r][i] Q[i][j]
+ *                    X [rows][nx], Q device complex128 [nx][ny], Y [rows][ny]
+ *                    (Y must not overlap X)
+ * nx, ny in 1..PV_MAX_NB.
+ */
+size_t pv_gram_workspace_size(int64_t rows, int nx, int ny);
+pv_status pv_gram(int dtype, int64_t rows, int nx, int ny, const void *X, const void *Y,
+                  double *G, void *work, size_t work_bytes, void *stream);
+pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, const void *X,
+                          const double *Q, void *Y, void *stream);
+
+/* Scalar helper used to measure achievable bandwidth: dst = src (bytes, a
+ * multiple of 16), a plain streaming copy kernel. */
+pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PVDTM_H */

@@ -1,0 +1,336 @@
+"""Python binding of libpvdtm (MI355X matrix-free Chebyshev / stencil library).
+
+Argument marshalling only: every function here forwards to the C ABI declared
+in ``include/pvdtm.h`` under the same name.  Torch tensors provide device
+memory and the current HIP stream (``tensor.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``); no computation runs in Python or
+in torch.  If the HIP library is not built, every call raises.
+
+Vector blocks are torch complex tensors (complex128 or complex64) with
+``numel == n_rows * nb``, row-major [rows][nb] (any shape with that memory
+layout, e.g. [Lz, Ly, Lx, n_orb, nb]).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libpvdtm.so")
+
+PV_C128, PV_C64 = 0, 1
+PV_F64, PV_F32 = 0, 1
+PV_POT_NONE, PV_POT_SITE, PV_POT_ORBITAL = 0, 1, 2
+PV_CHECK_HERMITIAN = 1
+PV_DOT_XX, PV_DOT_XY, PV_DOT_YY = 1, 2, 4
+PV_MAX_TERMS, PV_MAX_ORB, PV_MAX_NB = 26, 4, 64
+PV_MODEL_TI, PV_MODEL_GRAPHENE2, PV_MODEL_GRAPHENE4, PV_MODEL_WEYL = 0, 1, 2, 3
+FAMILY_NAMES = {0: "generic", 1: "ti", 2: "graphene2", 3: "graphene4", 4: "weyl"}
+
+STATUS_NAMES = {0: "PV_OK", 1: "PV_ERR_INVALID_ARG", 2: "PV_ERR_UNSUPPORTED", 3: "PV_ERR_NOT_HERMITIAN",
+                4: "PV_ERR_WORKSPACE", 5: "PV_ERR_OOM", 6: "PV_ERR_HIP", 7: "PV_ERR_NONFINITE",
+                8: "PV_ERR_NO_DEVICE", 9: "PV_ERR_NOT_CONVERGED"}
+
+# exported symbols of include/pvdtm.h with (restype, argtypes)
+_vp, _sz, _i64, _d, _i, _u = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_uint
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class pv_lattice_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("L", ctypes.c_int64 * 3), ("n_orb", ctypes.c_int),
+                ("periodic", ctypes.c_int * 3), ("n_terms", ctypes.c_int), ("offsets", _ip),
+                ("blocks", _dp), ("onsite", _dp), ("pot_mode", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+SIGNATURES = {
+    "pv_last_error": (ctypes.c_char_p, []),
+    "pv_status_string": (ctypes.c_char_p, [_i]),
+    "pv_version": (_i, []),
+    "pv_model_stencil": (_i, [_i, _dp, _ip, _ip, _ip, _ip, _dp, _dp, _ip]),
+    "pv_lattice_create": (_i, [ctypes.POINTER(pv_lattice_desc), ctypes.POINTER(_vp)]),
+    "pv_lattice_destroy": (None, [_vp]),
+    "pv_lattice_info": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _ip]),
+    "pv_lattice_set_potential": (_i, [_vp, _vp, _i]),
+    "pv_spmmv_workspace_size": (_sz, [_vp, _i, _i]),
+    "pv_spmmv": (_i, [_vp, _i, _i, _vp, _vp, _vp, _dp, _dp, _dp, _u, _vp, _vp, _sz, _vp]),
+    "pv_kpm_workspace_size": (_sz, [_vp, _i, _i, _i]),
+    "pv_kpm_moments": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _sz, _vp]),
+    "pv_kpm_dos": (_i, [_i, _dp, _d, _d, _i, _dp, _dp]),
+    "pv_cheb_series_workspace_size": (_sz, [_vp, _i, _i]),
+    "pv_cheb_series": (_i, [_vp, _i, _i, _d, _d, _i, _dp, _vp, _vp, _vp, _sz, _vp]),
+    "pv_cheb_propagate_workspace_size": (_sz, [_vp, _i, _i]),
+    "pv_cheb_propagate": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _sz, _vp]),
+    "pv_cheb_tp_coefficients": (_i, [_d, _d, _i, _dp]),
+    "pv_gram_workspace_size": (_sz, [_i64, _i, _i]),
+    "pv_gram": (_i, [_i, _i64, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pv_block_rotate": (_i, [_i, _i64, _i, _i, _vp, _vp, _vp, _vp]),
+    "pv_stream_copy": (_i, [_vp, _vp, _sz, _vp]),
+}
+
+_lib = None
+
+
+class PvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libpvdtm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1708_09689_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise PvError(status, lib().pv_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+# ----------------------------------------------------------------- torch plumbing
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return PV_C128
+    if t.dtype == torch.complex64:
+        return PV_C64
+    raise TypeError(f"vector blocks must be complex128 or complex64, got {t.dtype}")
+
+
+def _vec(t, name, rows, nb, dtype=None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != rows * nb:
+        raise ValueError(f"{name} has {t.numel()} elements, expected rows*nb = {rows * nb}")
+    if dtype is not None and _dtype_code(t) != dtype:
+        raise TypeError(f"{name} dtype differs from the other blocks")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ----------------------------------------------------------------- model / lattice
+
+def pv_model_stencil(model: int, params=None) -> dict:
+    p = np.zeros(4) if params is None else np.asarray(params, dtype=np.float64).copy()
+    if params is None:
+        p = None
+    dim, n_orb, n_terms, pot = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    offs = np.zeros(PV_MAX_TERMS * 3, dtype=np.int32)
+    blocks = np.zeros(PV_MAX_TERMS * PV_MAX_ORB * PV_MAX_ORB * 2)
+    onsite = np.zeros(PV_MAX_ORB * PV_MAX_ORB * 2)
+    _check(lib().pv_model_stencil(model, None if p is None else _dptr(p), ctypes.byref(dim), ctypes.byref(n_orb),
+                                  ctypes.byref(n_terms), offs.ctypes.data_as(_ip), _dptr(blocks), _dptr(onsite),
+                                  ctypes.byref(pot)))
+    no, nt = n_orb.value, n_terms.value
+    b = blocks[: nt * no * no * 2].reshape(nt, no, no, 2)
+    e = onsite[: no * no * 2].reshape(no, no, 2)
+    return {"dim": dim.value, "n_orb": no, "offsets": offs[: 3 * nt].reshape(nt, 3).copy(),
+            "blocks": b[..., 0] + 1j * b[..., 1], "onsite": e[..., 0] + 1j * e[..., 1], "pot_mode": pot.value}
+
+
+class Lattice:
+    """Owns a pv_lattice handle (pv_lattice_create / pv_lattice_destroy)."""
+
+    def __init__(self, L, periodic, stencil: dict, check_hermitian: bool = True):
+        L = list(L) + [1] * (3 - len(L))
+        periodic = list(periodic) + [1] * (3 - len(periodic))
+        no = int(stencil["n_orb"])
+        offs = np.ascontiguousarray(np.asarray(stencil["offsets"], dtype=np.int32).reshape(-1))
+        B = np.asarray(stencil["blocks"], dtype=np.complex128).reshape(-1, no, no)
+        E = np.asarray(stencil["onsite"], dtype=np.complex128).reshape(no, no)
+        self._blocks = np.ascontiguousarray(np.stack([B.real, B.imag], axis=-1).reshape(-1))
+        self._onsite = np.ascontiguousarray(np.stack([E.real, E.imag], axis=-1).reshape(-1))
+        self._offs = offs
+        d = pv_lattice_desc()
+        d.dim = int(stencil["dim"])
+        d.L = (ctypes.c_int64 * 3)(*[int(v) for v in L])
+        d.n_orb = no
+        d.periodic = (ctypes.c_int * 3)(*[1 if p else 0 for p in periodic])
+        d.n_terms = B.shape[0]
+        d.offsets = offs.ctypes.data_as(_ip)
+        d.blocks = self._blocks.ctypes.data_as(_dp)
+        d.onsite = self._onsite.ctypes.data_as(_dp)
+        d.pot_mode = int(stencil.get("pot_mode", PV_POT_SITE))
+        d.flags = PV_CHECK_HERMITIAN if check_hermitian else 0
+        h = ctypes.c_void_p()
+        _check(lib().pv_lattice_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        ns, nr, fam = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        _check(lib().pv_lattice_info(h, ctypes.byref(ns), ctypes.byref(nr), ctypes.byref(fam)))
+        self.n_sites, self.n_rows, self.family = ns.value, nr.value, fam.value
+        self.n_orb = no
+        self.L = tuple(L)
+        self.periodic = tuple(periodic)
+        self.pot_mode = d.pot_mode
+        self._V = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pv_lattice_destroy(h)
+            self.handle = None
+
+    def set_potential(self, V):
+        """pv_lattice_set_potential: V is a device float64/float32 tensor (kept alive here) or None."""
+        torch = _torch()
+        if V is None:
+            _check(lib().pv_lattice_set_potential(self.handle, None, PV_F64))
+            self._V = None
+            return
+        if not V.is_cuda or not V.is_contiguous():
+            raise ValueError("V must be a contiguous device tensor")
+        n = self.n_sites if self.pot_mode == PV_POT_SITE else self.n_rows
+        if V.numel() != n:
+            raise ValueError(f"V has {V.numel()} entries, expected {n}")
+        rt = {torch.float64: PV_F64, torch.float32: PV_F32}.get(V.dtype)
+        if rt is None:
+            raise TypeError("V must be float64 or float32")
+        _check(lib().pv_lattice_set_potential(self.handle, ctypes.c_void_p(V.data_ptr()), rt))
+        self._V = V
+
+
+def pv_lattice_create(L, periodic, stencil, check_hermitian=True) -> Lattice:
+    return Lattice(L, periodic, stencil, check_hermitian)
+
+
+# ----------------------------------------------------------------- sweeps and algorithms
+
+def pv_spmmv(lat: Lattice, x, y, alpha, beta, gamma, z=None, dot_flags: int = 0, dots=None, nb=None):
+    """y = alpha (H x - beta x) + gamma z per column; optional FP64 dots [nb][4]."""
+    torch = _torch()
+    nb = nb if nb is not None else x.numel() // lat.n_rows
+    dt = _dtype_code(x)
+    a = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (nb,)).copy()
+    b = np.broadcast_to(np.asarray(beta, dtype=np.float64), (nb,)).copy()
+    g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (nb,)).copy()
+    if dot_flags and dots is None:
+        dots = torch.empty((nb, 4), dtype=torch.float64, device=x.device)
+    ws = _workspace(lib().pv_spmmv_workspace_size(lat.handle, dt, nb), x.device)
+    _check(lib().pv_spmmv(lat.handle, dt, nb, _vec(x, "x", lat.n_rows, nb), _vec(z, "z", lat.n_rows, nb, dt),
+                          _vec(y, "y", lat.n_rows, nb, dt), _dptr(a), _dptr(b), _dptr(g), dot_flags,
+                          None if dots is None else ctypes.c_void_p(dots.data_ptr()),
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return dots
+
+
+def pv_kpm_moments(lat: Lattice, r, M: int, a: float, b: float, mu=None, nb=None):
+    """mu[c][n] = Re <r_c, T_n(H~) r_c> / D (device FP64 [nb][M])."""
+    torch = _torch()
+    nb = nb if nb is not None else r.numel() // lat.n_rows
+    dt = _dtype_code(r)
+    if mu is None:
+        mu = torch.empty((nb, M), dtype=torch.float64, device=r.device)
+    ws = _workspace(lib().pv_kpm_workspace_size(lat.handle, dt, nb, M), r.device)
+    _check(lib().pv_kpm_moments(lat.handle, dt, nb, M, a, b, _vec(r, "r", lat.n_rows, nb),
+                                ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream()))
+    return mu
+
+
+def pv_kpm_dos(mu, E, a: float, b: float):
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64))
+    E = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
+    rho = np.zeros_like(E)
+    _check(lib().pv_kpm_dos(mu.size, _dptr(mu), a, b, E.size, _dptr(E), _dptr(rho)))
+    return rho
+
+
+def _coef_array(coef):
+    c = np.asarray(coef, dtype=np.complex128).reshape(-1)
+    return np.ascontiguousarray(np.stack([c.real, c.imag], axis=-1).reshape(-1))
+
+
+def pv_cheb_series(lat: Lattice, X, Y, a: float, b: float, coef, nb=None):
+    """Y = sum_k coef[k] T_k(H~) X."""
+    nb = nb if nb is not None else X.numel() // lat.n_rows
+    dt = _dtype_code(X)
+    c = _coef_array(coef)
+    ws = _workspace(lib().pv_cheb_series_workspace_size(lat.handle, dt, nb), X.device)
+    _check(lib().pv_cheb_series(lat.handle, dt, nb, a, b, c.size // 2 - 1, _dptr(c), _vec(X, "X", lat.n_rows, nb),
+                                _vec(Y, "Y", lat.n_rows, nb, dt), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream()))
+    return Y
+
+
+def pv_cheb_propagate(lat: Lattice, psi, a: float, b: float, dt: float, M: int, nsteps: int, nb=None):
+    """psi <- U(dt)^nsteps psi in place (Chebyshev propagator)."""
+    nb = nb if nb is not None else psi.numel() // lat.n_rows
+    dtc = _dtype_code(psi)
+    ws = _workspace(lib().pv_cheb_propagate_workspace_size(lat.handle, dtc, nb), psi.device)
+    _check(lib().pv_cheb_propagate(lat.handle, dtc, nb, a, b, dt, M, nsteps, _vec(psi, "psi", lat.n_rows, nb),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return psi
+
+
+def pv_cheb_tp_coefficients(a: float, dt: float, M: int) -> np.ndarray:
+    out = np.zeros(2 * (M + 1))
+    _check(lib().pv_cheb_tp_coefficients(a, dt, M, _dptr(out)))
+    return out[0::2] + 1j * out[1::2]
+
+
+def pv_gram(X, Y, G=None, rows=None):
+    """G = X^H Y (device complex128 [nx][ny]) for X [rows][nx], Y [rows][ny]."""
+    torch = _torch()
+    rows = rows if rows is not None else X.shape[0]
+    nx, ny = X.numel() // rows, Y.numel() // rows
+    dt = _dtype_code(X)
+    if G is None:
+        G = torch.empty((nx, ny), dtype=torch.complex128, device=X.device)
+    ws = _workspace(lib().pv_gram_workspace_size(rows, nx, ny), X.device)
+    _check(lib().pv_gram(dt, rows, nx, ny, _vec(X, "X", rows, nx), _vec(Y, "Y", rows, ny, dt),
+                         ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return G
+
+
+def pv_block_rotate(X, Q, Y, rows=None):
+    """Y = X Q, Q device complex128 [nx][ny]."""
+    rows = rows if rows is not None else X.shape[0]
+    nx, ny = X.numel() // rows, Y.numel() // rows
+    dt = _dtype_code(X)
+    _check(lib().pv_block_rotate(dt, rows, nx, ny, _vec(X, "X", rows, nx), ctypes.c_void_p(Q.data_ptr()),
+                                 _vec(Y, "Y", rows, ny, dt), _stream()))
+    return Y
+
+
+def pv_stream_copy(src, dst):
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("dst too small")
+    _check(lib().pv_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, _stream()))
+    return dst

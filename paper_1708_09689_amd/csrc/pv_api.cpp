@@ -1,0 +1,875 @@
+// C ABI of the library: argument validation, lattice descriptors, model
+// stencils, workspace layout and the host drivers of the Chebyshev
+// algorithms.  Every check runs before the first device call, so invalid
+// arguments never queue work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pv_kernels.hpp"
+#include "pvdtm.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+pv_status fail(pv_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+pv_status hip_fail(hipError_t e, const char* where) {
+    return fail(PV_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define PV_HIP(call)                                       \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int num_cus_of_current_device() {
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// lattice object
+// ---------------------------------------------------------------------------
+struct pv_lattice {
+    int dim = 3;
+    int64_t L[3] = {1, 1, 1};
+    int n_orb = 1;
+    int periodic[3] = {1, 1, 1};
+    int n_terms = 0;
+    std::vector<int> offsets;       // descriptor order
+    std::vector<double> blocks;     // descriptor order
+    std::vector<double> onsite;
+    int pot_mode = 0;
+    int family = pv::FAM_GENERIC;
+    std::vector<double> packed;     // coefficients in kernel order, on-site last
+    std::vector<int> packed_offs;   // generic family
+    int64_t n_sites = 0, n_rows = 0;
+    // device copies (uploaded on first use on a device)
+    std::mutex mu;
+    int dev = -1;
+    double* d_coef = nullptr;
+    int* d_offs = nullptr;
+    // borrowed field
+    const void* V = nullptr;
+    int vtype = 0;
+};
+
+namespace {
+
+template <class P>
+bool family_matches(const pv_lattice& l, std::vector<int>& order) {
+    if (l.n_orb != P::NO || l.n_terms != P::NT) return false;
+    if (P::DIM == 2 && l.L[2] != 1) return false;
+    const int NO = P::NO;
+    order.assign(P::NT, -1);
+    for (int t = 0; t < P::NT; ++t) {
+        for (int u = 0; u < l.n_terms; ++u)
+            if (l.offsets[3 * u] == P::off[t][0] && l.offsets[3 * u + 1] == P::off[t][1] &&
+                l.offsets[3 * u + 2] == P::off[t][2])
+                order[t] = u;
+        if (order[t] < 0) return false;
+    }
+    auto fits = [](unsigned char k, double re, double im) {
+        if (re != 0.0 && !(k == pv::CR || k == pv::CC)) return false;
+        if (im != 0.0 && !(k == pv::CI || k == pv::CC)) return false;
+        return true;
+    };
+    for (int t = 0; t <= P::NT; ++t) {
+        const double* B = (t < P::NT) ? &l.blocks[(size_t)order[t] * NO * NO * 2] : l.onsite.data();
+        for (int o = 0; o < NO; ++o)
+            for (int q = 0; q < NO; ++q) {
+                if (t == P::NT && o == q) continue;  // on-site diagonal is always general
+                if (!fits(P::code[t][o][q], B[(o * NO + q) * 2], B[(o * NO + q) * 2 + 1])) return false;
+            }
+    }
+    return true;
+}
+
+template <class P>
+bool try_family(pv_lattice& l) {
+    std::vector<int> order;
+    if (!family_matches<P>(l, order)) return false;
+    const int NO = P::NO;
+    l.family = P::FAMILY;
+    l.packed.assign((size_t)(P::NT + 1) * NO * NO * 2, 0.0);
+    for (int t = 0; t < P::NT; ++t)
+        std::memcpy(&l.packed[(size_t)t * NO * NO * 2], &l.blocks[(size_t)order[t] * NO * NO * 2],
+                    sizeof(double) * NO * NO * 2);
+    std::memcpy(&l.packed[(size_t)P::NT * NO * NO * 2], l.onsite.data(), sizeof(double) * NO * NO * 2);
+    l.packed_offs.clear();
+    return true;
+}
+
+void choose_family(pv_lattice& l) {
+    if (try_family<pv::PatTI>(l)) return;
+    if (try_family<pv::PatGraphene2>(l)) return;
+    if (try_family<pv::PatGraphene4>(l)) return;
+    if (try_family<pv::PatWeyl>(l)) return;
+    const int NO = l.n_orb;
+    l.family = pv::FAM_GENERIC;
+    l.packed.assign((size_t)(l.n_terms + 1) * NO * NO * 2, 0.0);
+    if (l.n_terms)
+        std::memcpy(l.packed.data(), l.blocks.data(), sizeof(double) * l.n_terms * NO * NO * 2);
+    std::memcpy(&l.packed[(size_t)l.n_terms * NO * NO * 2], l.onsite.data(), sizeof(double) * NO * NO * 2);
+    l.packed_offs = l.offsets;
+}
+
+pv_status ensure_device(pv_lattice* l) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(l->mu);
+    if (l->dev == dev && l->d_coef) return PV_OK;
+    if (l->d_coef) { (void)hipFree(l->d_coef); l->d_coef = nullptr; }
+    if (l->d_offs) { (void)hipFree(l->d_offs); l->d_offs = nullptr; }
+    const size_t cb = l->packed.size() * sizeof(double);
+    if (hipMalloc(&l->d_coef, cb) != hipSuccess) return fail(PV_ERR_OOM, "coefficient upload: out of memory");
+    PV_HIP(hipMemcpy(l->d_coef, l->packed.data(), cb, hipMemcpyHostToDevice));
+    if (!l->packed_offs.empty()) {
+        const size_t ob = l->packed_offs.size() * sizeof(int);
+        if (hipMalloc(&l->d_offs, ob) != hipSuccess) return fail(PV_ERR_OOM, "offset upload: out of memory");
+        PV_HIP(hipMemcpy(l->d_offs, l->packed_offs.data(), ob, hipMemcpyHostToDevice));
+    }
+    l->dev = dev;
+    return PV_OK;
+}
+
+size_t elem_bytes(int dtype) { return dtype == PV_C128 ? 16 : 8; }
+
+pv_status check_dtype(const pv_lattice* l, int dtype) {
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "dtype must be PV_C128 or PV_C64");
+    if (dtype == PV_C128 && l->V && l->vtype == PV_F32)
+        return fail(PV_ERR_UNSUPPORTED, "complex128 vectors need a float64 on-site field");
+    return PV_OK;
+}
+
+pv_status check_vec(const void* p, int dtype, const char* name) {
+    if (!p) return fail(PV_ERR_INVALID_ARG, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % elem_bytes(dtype))
+        return fail(PV_ERR_INVALID_ARG, "%s is not %zu-byte aligned", name, elem_bytes(dtype));
+    return PV_OK;
+}
+
+pv_status check_nb(int nb) {
+    if (!is_pow2(nb) || nb > PV_MAX_NB)
+        return fail(PV_ERR_UNSUPPORTED, "nb = %d: block width must be a power of two <= %d", nb, PV_MAX_NB);
+    return PV_OK;
+}
+
+pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
+    pv::SweepParams p{};
+    p.family = l->family;
+    p.dtype = dtype;
+    p.vtype = l->vtype;
+    p.n_orb = l->n_orb;
+    p.n_terms = l->n_terms;
+    p.pot_mode = l->V ? l->pot_mode : 0;
+    for (int d = 0; d < 3; ++d) {
+        p.L[d] = l->L[d];
+        p.periodic[d] = l->periodic[d];
+    }
+    p.nb = nb;
+    p.V = l->pot_mode ? l->V : nullptr;
+    p.coef = l->d_coef;
+    p.offs = l->d_offs;
+    return p;
+}
+
+int grid_for(const pv_lattice* l, int nb) {
+    pv::SweepParams p = base_params(l, 0, nb);
+    int ncu = num_cus_of_current_device();
+    if (ncu <= 0) ncu = 256;
+    return pv::sweep_grid(p, ncu);
+}
+
+size_t partial_bytes(const pv_lattice* l, int nb) { return align_up((size_t)grid_for(l, nb) * nb * 4 * sizeof(double)); }
+size_t vec_bytes(const pv_lattice* l, int dtype, int nb) {
+    return align_up((size_t)l->n_rows * nb * elem_bytes(dtype));
+}
+
+// Miller backward recurrence for J_0..J_kmax(z), normalised with
+// J_0 + 2 sum_{k>=1} J_{2k} = 1 (Abramowitz & Stegun 9.1.27, 9.1.46).
+void bessel_j(double z, int kmax, std::vector<double>& out) {
+    out.assign(kmax + 1, 0.0);
+    if (z == 0.0) { out[0] = 1.0; return; }
+    const bool neg = z < 0.0;
+    const double az = std::fabs(z);
+    int start = kmax + (int)az + 60;
+    start += start & 1;
+    std::vector<double> j(start + 2, 0.0);
+    j[start] = 1e-30;
+    for (int k = start; k > 0; --k) {
+        j[k - 1] = (2.0 * k / az) * j[k] - j[k + 1];
+        if (std::fabs(j[k - 1]) > 1e250)
+            for (int q = k - 1; q <= start; ++q) j[q] *= 1e-250;
+    }
+    double norm = j[0];
+    for (int k = 2; k <= start; k += 2) norm += 2.0 * j[k];
+    for (int k = 0; k <= kmax; ++k) out[k] = j[k] / norm * ((neg && (k & 1)) ? -1.0 : 1.0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// error helpers
+// ---------------------------------------------------------------------------
+extern "C" const char* pv_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* pv_status_string(pv_status s) {
+    switch (s) {
+        case PV_OK: return "ok";
+        case PV_ERR_INVALID_ARG: return "invalid argument";
+        case PV_ERR_UNSUPPORTED: return "unsupported";
+        case PV_ERR_NOT_HERMITIAN: return "stencil is not Hermitian";
+        case PV_ERR_WORKSPACE: return "workspace too small";
+        case PV_ERR_OOM: return "out of memory";
+        case PV_ERR_HIP: return "HIP runtime error";
+        case PV_ERR_NONFINITE: return "non-finite result";
+        case PV_ERR_NO_DEVICE: return "no device";
+        case PV_ERR_NOT_CONVERGED: return "not converged";
+    }
+    return "unknown status";
+}
+
+extern "C" int pv_version(void) { return 1; }
+
+// ---------------------------------------------------------------------------
+// model stencils (Sec. 2)
+// ---------------------------------------------------------------------------
+namespace {
+using cd = std::complex<double>;
+struct Mat4 {
+    cd a[4][4];
+};
+Mat4 kron2(const cd A[2][2], const cd B[2][2]) {
+    Mat4 m;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l) m.a[2 * i + k][2 * j + l] = A[i][j] * B[k][l];
+    return m;
+}
+void put_block(double* dst, int no, const cd* m) {
+    for (int i = 0; i < no * no; ++i) {
+        dst[2 * i] = m[i].real();
+        dst[2 * i + 1] = m[i].imag();
+    }
+}
+}  // namespace
+
+extern "C" pv_status pv_model_stencil(int model, const double* params, int* dim, int* n_orb, int* n_terms,
+                                      int* offsets, double* blocks, double* onsite, int* pot_mode) {
+    if (!dim || !n_orb || !n_terms || !offsets || !blocks || !onsite || !pot_mode)
+        return fail(PV_ERR_INVALID_ARG, "pv_model_stencil: NULL output");
+    const cd I(0.0, 1.0);
+    const cd s0[2][2] = {{1, 0}, {0, 1}};
+    const cd sx[2][2] = {{0, 1}, {1, 0}};
+    const cd sy[2][2] = {{0, -I}, {I, 0}};
+    const cd sz[2][2] = {{1, 0}, {0, -1}};
+    const int axis_off[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    std::memset(blocks, 0, sizeof(double) * PV_MAX_TERMS * PV_MAX_ORB * PV_MAX_ORB * 2);
+    std::memset(onsite, 0, sizeof(double) * PV_MAX_ORB * PV_MAX_ORB * 2);
+    switch (model) {
+        case PV_MODEL_TI: {
+            const double t = params ? params[0] : 1.0, m = params ? params[1] : 2.0;
+            const double d1 = params ? params[2] : 0.0, d2 = params ? params[3] : 0.0;
+            // Gamma^1 = tau_z s0, Gamma^{j+1} = tau_x sigma_j, Gamma^5 = tau_y s0
+            const Mat4 G1 = kron2(sz, s0), G5 = kron2(sy, s0);
+            const Mat4 Gj[3] = {kron2(sx, sx), kron2(sx, sy), kron2(sx, sz)};
+            *dim = 3;
+            *n_orb = 4;
+            *n_terms = 6;
+            *pot_mode = PV_POT_SITE;
+            for (int j = 0; j < 3; ++j) {
+                cd Am[16], AH[16];  // A = -(t/2)(G1 - i G_{j+1}) carries n -> n + e_j
+                for (int r = 0; r < 4; ++r)
+                    for (int c = 0; c < 4; ++c) Am[r * 4 + c] = -(t / 2.0) * (G1.a[r][c] - I * Gj[j].a[r][c]);
+                for (int r = 0; r < 4; ++r)
+                    for (int c = 0; c < 4; ++c) AH[r * 4 + c] = std::conj(Am[c * 4 + r]);
+                // (H x)[s] += A x[s - e_j] + A^H x[s + e_j]
+                for (int k = 0; k < 3; ++k) {
+                    offsets[(2 * j) * 3 + k] = axis_off[2 * j][k];
+                    offsets[(2 * j + 1) * 3 + k] = axis_off[2 * j + 1][k];
+                }
+                put_block(blocks + (2 * j) * 32, 4, Am);
+                put_block(blocks + (2 * j + 1) * 32, 4, AH);
+            }
+            cd E0[16];
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    cd g15 = 0.0;  // [G1, G5]/(2i)
+                    for (int k = 0; k < 4; ++k) g15 += G1.a[r][k] * G5.a[k][c] - G5.a[r][k] * G1.a[k][c];
+                    g15 /= (2.0 * I);
+                    E0[r * 4 + c] = m * G1.a[r][c] + d1 * G5.a[r][c] + d2 * g15;
+                }
+            put_block(onsite, 4, E0);
+            return PV_OK;
+        }
+        case PV_MODEL_GRAPHENE2: {
+            const double t = params ? params[0] : 1.0;
+            *dim = 2;
+            *n_orb = 2;
+            *n_terms = 4;
+            *pot_mode = PV_POT_SITE;
+            // A(s) couples to B(s), B(s - e_i), B(s - e_j) with -t
+            const int off[4][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
+            std::memcpy(offsets, off, sizeof(off));
+            for (int u = 0; u < 4; ++u) {
+                double* B = blocks + u * 8;
+                if ((u & 1) == 0) B[(0 * 2 + 1) * 2] = -t;  // row A, column B of s - e
+                else B[(1 * 2 + 0) * 2] = -t;               // row B, column A of s + e
+            }
+            onsite[(0 * 2 + 1) * 2] = -t;
+            onsite[(1 * 2 + 0) * 2] = -t;
+            return PV_OK;
+        }
+        case PV_MODEL_GRAPHENE4: {
+            const double t = params ? params[0] : 1.0;
+            *dim = 2;
+            *n_orb = 4;
+            *n_terms = 4;
+            *pot_mode = PV_POT_ORBITAL;
+            const int off[4][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
+            std::memcpy(offsets, off, sizeof(off));
+            // T_x carries n -> n + e_x: entries (1,0), (2,3); T_y: (0,3)
+            double* Bmx = blocks + 0 * 32;
+            double* Bpx = blocks + 1 * 32;
+            double* Bmy = blocks + 2 * 32;
+            double* Bpy = blocks + 3 * 32;
+            Bmx[(1 * 4 + 0) * 2] = -t;
+            Bmx[(2 * 4 + 3) * 2] = -t;
+            Bpx[(0 * 4 + 1) * 2] = -t;
+            Bpx[(3 * 4 + 2) * 2] = -t;
+            Bmy[(0 * 4 + 3) * 2] = -t;
+            Bpy[(3 * 4 + 0) * 2] = -t;
+            for (int a = 0; a < 3; ++a) {
+                onsite[(a * 4 + a + 1) * 2] = -t;
+                onsite[((a + 1) * 4 + a) * 2] = -t;
+            }
+            return PV_OK;
+        }
+        case PV_MODEL_WEYL: {
+            const double k0 = params ? params[0] : M_PI / 2.0;
+            *dim = 3;
+            *n_orb = 2;
+            *n_terms = 6;
+            *pot_mode = PV_POT_SITE;
+            cd A[3][4];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) {
+                    A[0][r * 2 + c] = sx[r][c] / 2.0;
+                    A[1][r * 2 + c] = (sx[r][c] + I * sy[r][c]) / 2.0;
+                    A[2][r * 2 + c] = (sx[r][c] + I * sz[r][c]) / 2.0;
+                }
+            for (int j = 0; j < 3; ++j) {
+                cd AH[4];
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 2; ++c) AH[r * 2 + c] = std::conj(A[j][c * 2 + r]);
+                for (int k = 0; k < 3; ++k) {
+                    offsets[(2 * j) * 3 + k] = axis_off[2 * j][k];
+                    offsets[(2 * j + 1) * 3 + k] = axis_off[2 * j + 1][k];
+                }
+                put_block(blocks + (2 * j) * 8, 2, A[j]);
+                put_block(blocks + (2 * j + 1) * 8, 2, AH);
+            }
+            cd E0[4];
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) E0[r * 2 + c] = -sx[r][c] * (2.0 + std::cos(k0));
+            put_block(onsite, 2, E0);
+            return PV_OK;
+        }
+        default:
+            return fail(PV_ERR_INVALID_ARG, "unknown model %d", model);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lattice
+// ---------------------------------------------------------------------------
+extern "C" pv_status pv_lattice_create(const pv_lattice_desc* d, pv_lattice** out) {
+    if (!d || !out) return fail(PV_ERR_INVALID_ARG, "pv_lattice_create: NULL argument");
+    *out = nullptr;
+    if (d->dim != 2 && d->dim != 3) return fail(PV_ERR_INVALID_ARG, "dim must be 2 or 3 (got %d)", d->dim);
+    for (int k = 0; k < 3; ++k)
+        if (d->L[k] < 1) return fail(PV_ERR_INVALID_ARG, "extent L[%d] = %lld must be >= 1", k, (long long)d->L[k]);
+    if (d->dim == 2 && d->L[2] != 1) return fail(PV_ERR_INVALID_ARG, "dim 2 requires L[2] == 1");
+    if (d->n_orb != 1 && d->n_orb != 2 && d->n_orb != 4)
+        return fail(PV_ERR_UNSUPPORTED, "n_orb = %d: supported are 1, 2, 4", d->n_orb);
+    if (d->n_terms < 0 || d->n_terms > PV_MAX_TERMS)
+        return fail(PV_ERR_INVALID_ARG, "n_terms = %d outside 0..%d", d->n_terms, PV_MAX_TERMS);
+    if (d->n_terms > 0 && (!d->offsets || !d->blocks))
+        return fail(PV_ERR_INVALID_ARG, "offsets/blocks NULL with n_terms > 0");
+    if (!d->onsite) return fail(PV_ERR_INVALID_ARG, "onsite block is NULL");
+    if (d->pot_mode < 0 || d->pot_mode > 2) return fail(PV_ERR_INVALID_ARG, "pot_mode %d invalid", d->pot_mode);
+    // overflow guard: elements of a PV_MAX_NB block must index in int64
+    const double sites = double(d->L[0]) * double(d->L[1]) * double(d->L[2]);
+    if (sites * d->n_orb * PV_MAX_NB * 16.0 > 9.0e18) return fail(PV_ERR_INVALID_ARG, "lattice too large");
+    const int no = d->n_orb;
+    for (int t = 0; t < d->n_terms; ++t) {
+        const int* o = d->offsets + 3 * t;
+        if (o[0] < -1 || o[0] > 1 || o[1] < -1 || o[1] > 1 || o[2] < -1 || o[2] > 1)
+            return fail(PV_ERR_UNSUPPORTED, "offset %d = (%d,%d,%d) outside {-1,0,1}^3", t, o[0], o[1], o[2]);
+        if (o[0] == 0 && o[1] == 0 && o[2] == 0)
+            return fail(PV_ERR_INVALID_ARG, "offset %d is zero (use the on-site block)", t);
+        if (d->dim == 2 && o[2] != 0) return fail(PV_ERR_INVALID_ARG, "offset %d has a z component on a 2D lattice", t);
+        for (int u = 0; u < t; ++u) {
+            const int* p = d->offsets + 3 * u;
+            if (p[0] == o[0] && p[1] == o[1] && p[2] == o[2])
+                return fail(PV_ERR_INVALID_ARG, "offsets %d and %d coincide", u, t);
+        }
+    }
+    const size_t bsz = (size_t)no * no * 2;
+    for (size_t i = 0; i < bsz * d->n_terms; ++i)
+        if (!std::isfinite(d->blocks[i])) return fail(PV_ERR_INVALID_ARG, "non-finite block coefficient");
+    for (size_t i = 0; i < bsz; ++i)
+        if (!std::isfinite(d->onsite[i])) return fail(PV_ERR_INVALID_ARG, "non-finite on-site coefficient");
+    if (d->flags & PV_CHECK_HERMITIAN) {
+        double scale = 0.0;
+        for (size_t i = 0; i < bsz * d->n_terms; ++i) scale = std::max(scale, std::fabs(d->blocks[i]));
+        for (size_t i = 0; i < bsz; ++i) scale = std::max(scale, std::fabs(d->onsite[i]));
+        const double tol = 1e-14 * std::max(scale, 1.0);
+        auto herm_pair = [&](const double* A, const double* B) {  // B == A^H ?
+            for (int r = 0; r < no; ++r)
+                for (int c = 0; c < no; ++c) {
+                    const double* a = A + (r * no + c) * 2;
+                    const double* b = B + (c * no + r) * 2;
+                    if (std::fabs(a[0] - b[0]) > tol || std::fabs(a[1] + b[1]) > tol) return false;
+                }
+            return true;
+        };
+        if (!herm_pair(d->onsite, d->onsite)) return fail(PV_ERR_NOT_HERMITIAN, "on-site block is not Hermitian");
+        for (int t = 0; t < d->n_terms; ++t) {
+            const int* o = d->offsets + 3 * t;
+            int partner = -1;
+            for (int u = 0; u < d->n_terms; ++u) {
+                const int* p = d->offsets + 3 * u;
+                if (p[0] == -o[0] && p[1] == -o[1] && p[2] == -o[2]) partner = u;
+            }
+            if (partner < 0) return fail(PV_ERR_NOT_HERMITIAN, "offset %d has no opposite offset", t);
+            if (!herm_pair(d->blocks + bsz * t, d->blocks + bsz * partner))
+                return fail(PV_ERR_NOT_HERMITIAN, "block of offset %d is not the adjoint of its opposite", t);
+        }
+    }
+    pv_lattice* l = new (std::nothrow) pv_lattice();
+    if (!l) return fail(PV_ERR_OOM, "host allocation failed");
+    l->dim = d->dim;
+    for (int k = 0; k < 3; ++k) {
+        l->L[k] = d->L[k];
+        l->periodic[k] = d->periodic[k] ? 1 : 0;
+    }
+    l->n_orb = no;
+    l->n_terms = d->n_terms;
+    l->offsets.assign(d->offsets, d->offsets + 3 * d->n_terms);
+    l->blocks.assign(d->blocks, d->blocks + bsz * d->n_terms);
+    l->onsite.assign(d->onsite, d->onsite + bsz);
+    l->pot_mode = d->pot_mode;
+    l->n_sites = d->L[0] * d->L[1] * d->L[2];
+    l->n_rows = l->n_sites * no;
+    choose_family(*l);
+    *out = l;
+    return PV_OK;
+}
+
+extern "C" void pv_lattice_destroy(pv_lattice* l) {
+    if (!l) return;
+    if (l->d_coef) (void)hipFree(l->d_coef);
+    if (l->d_offs) (void)hipFree(l->d_offs);
+    delete l;
+}
+
+extern "C" pv_status pv_lattice_info(const pv_lattice* l, int64_t* n_sites, int64_t* n_rows, int* family) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if (n_sites) *n_sites = l->n_sites;
+    if (n_rows) *n_rows = l->n_rows;
+    if (family) *family = l->family;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_lattice_set_potential(pv_lattice* l, const void* V, int rtype) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if (rtype != PV_F64 && rtype != PV_F32) return fail(PV_ERR_INVALID_ARG, "rtype must be PV_F64 or PV_F32");
+    if (V && l->pot_mode == PV_POT_NONE)
+        return fail(PV_ERR_INVALID_ARG, "lattice was created with PV_POT_NONE");
+    if (V && reinterpret_cast<uintptr_t>(V) % (rtype == PV_F64 ? 8 : 4))
+        return fail(PV_ERR_INVALID_ARG, "potential pointer misaligned");
+    l->V = V;
+    l->vtype = rtype;
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sweep
+// ---------------------------------------------------------------------------
+extern "C" size_t pv_spmmv_workspace_size(const pv_lattice* l, int dtype, int nb) {
+    (void)dtype;
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB) return 0;
+    return partial_bytes(l, nb) + align_up(sizeof(double) * 3 * nb);
+}
+
+extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y,
+                              const double* alpha, const double* beta, const double* gamma, unsigned dot_flags,
+                              double* dots, void* work, size_t work_bytes, void* stream) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if ((st = check_dtype(l, dtype)) != PV_OK) return st;
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if ((st = check_vec(x, dtype, "x")) != PV_OK) return st;
+    if ((st = check_vec(y, dtype, "y")) != PV_OK) return st;
+    if (!alpha || !beta || !gamma) return fail(PV_ERR_INVALID_ARG, "alpha/beta/gamma must be host arrays [nb]");
+    bool uniform = true, need_z = false;
+    for (int c = 0; c < nb; ++c) {
+        if (!std::isfinite(alpha[c]) || !std::isfinite(beta[c]) || !std::isfinite(gamma[c]))
+            return fail(PV_ERR_INVALID_ARG, "non-finite scale/shift in column %d", c);
+        if (alpha[c] != alpha[0] || beta[c] != beta[0] || gamma[c] != gamma[0]) uniform = false;
+        if (gamma[c] != 0.0) need_z = true;
+    }
+    if (need_z && (st = check_vec(z, dtype, "z")) != PV_OK) return st;
+    if (x == y || (need_z && x == z)) return fail(PV_ERR_INVALID_ARG, "x must not alias y or z");
+    if (dot_flags & ~7u) return fail(PV_ERR_INVALID_ARG, "unknown dot flags 0x%x", dot_flags);
+    if (dot_flags && !dots) return fail(PV_ERR_INVALID_ARG, "dots is NULL but dot products were requested");
+    const size_t need = pv_spmmv_workspace_size(l, dtype, nb);
+    if (work_bytes < need || (!work && need)) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pv::SweepParams p = base_params(l, dtype, nb);
+    p.grid = grid_for(l, nb);
+    p.x = x;
+    p.z = need_z ? z : nullptr;
+    p.y = y;
+    p.alpha = alpha[0];
+    p.beta = beta[0];
+    p.gamma = gamma[0];
+    p.ep = pv::EP_STORE_Y | (dot_flags ? pv::EP_DOTS : 0u);
+    char* w = static_cast<char*>(work);
+    p.partials = reinterpret_cast<double*>(w);
+    if (!uniform) {
+        double* colp = reinterpret_cast<double*>(w + partial_bytes(l, nb));
+        std::vector<double> h(3 * nb);
+        for (int c = 0; c < nb; ++c) {
+            h[3 * c] = alpha[c];
+            h[3 * c + 1] = beta[c];
+            h[3 * c + 2] = gamma[c];
+        }
+        PV_HIP(hipMemcpyAsync(colp, h.data(), sizeof(double) * 3 * nb, hipMemcpyHostToDevice, s));
+        p.colp = colp;
+    }
+    PV_HIP(pv::launch_sweep(p, s));
+    if (dot_flags) PV_HIP(pv::launch_reduce_dots(p.partials, p.grid, nb, 0, dots, 0, 0, 0.0, s));
+    if (!uniform) PV_HIP(hipStreamSynchronize(s));  // host staging buffer h goes out of scope
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// KPM
+// ---------------------------------------------------------------------------
+extern "C" size_t pv_kpm_workspace_size(const pv_lattice* l, int dtype, int nb, int M) {
+    (void)M;
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    return partial_bytes(l, nb) + 2 * vec_bytes(l, dtype, nb);
+}
+
+extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                                    double* mu, void* work, size_t work_bytes, void* stream) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if ((st = check_dtype(l, dtype)) != PV_OK) return st;
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if ((st = check_vec(r, dtype, "r")) != PV_OK) return st;
+    if (!mu) return fail(PV_ERR_INVALID_ARG, "mu is NULL");
+    if (M < 2 || (M & 1) || M > 65536) return fail(PV_ERR_INVALID_ARG, "M = %d must be even, 2..65536", M);
+    if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return fail(PV_ERR_INVALID_ARG, "need finite a > 0 and b");
+    const size_t need = pv_kpm_workspace_size(l, dtype, nb, M);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(work);
+    double* partials = reinterpret_cast<double*>(w);
+    void* A = w + partial_bytes(l, nb);
+    void* B = static_cast<char*>(A) + vec_bytes(l, dtype, nb);
+    pv::SweepParams p = base_params(l, dtype, nb);
+    p.grid = grid_for(l, nb);
+    p.partials = partials;
+    p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
+    const double invD = 1.0 / double(l->n_rows);
+    // w_1 = H~ w_0
+    p.x = r;
+    p.y = A;
+    p.z = nullptr;
+    p.alpha = 1.0 / a;
+    p.beta = b;
+    p.gamma = 0.0;
+    PV_HIP(pv::launch_sweep(p, s));
+    PV_HIP(pv::launch_reduce_dots(partials, p.grid, nb, 1, mu, M, 0, invD, s));
+    const void* prev = r;
+    void* cur = A;
+    p.alpha = 2.0 / a;
+    p.gamma = -1.0;
+    for (int n = 1; n < M / 2; ++n) {
+        void* next = (n == 1) ? B : const_cast<void*>(prev);
+        p.x = cur;
+        p.z = prev;
+        p.y = next;
+        PV_HIP(pv::launch_sweep(p, s));
+        PV_HIP(pv::launch_reduce_dots(partials, p.grid, nb, 2, mu, M, n, invD, s));
+        prev = cur;
+        cur = next;
+    }
+    return PV_OK;
+}
+
+extern "C" pv_status pv_kpm_dos(int M, const double* mu, double a, double b, int nE, const double* E, double* rho) {
+    if (M < 1 || !mu || nE < 0 || (nE && (!E || !rho)) || !(a > 0.0)) return fail(PV_ERR_INVALID_ARG, "pv_kpm_dos: bad arguments");
+    // Jackson damping g_n (Weisse et al. 2006)
+    const double q = M_PI / (M + 1);
+    std::vector<double> g(M);
+    for (int n = 0; n < M; ++n) g[n] = ((M - n + 1) * std::cos(q * n) + std::sin(q * n) / std::tan(q)) / (M + 1);
+    for (int e = 0; e < nE; ++e) {
+        const double x = (E[e] - b) / a;
+        if (!(x > -1.0 && x < 1.0)) { rho[e] = 0.0; continue; }
+        // T_n(x) by the three-term recurrence
+        double t0 = 1.0, t1 = x, acc = g[0] * mu[0];
+        if (M > 1) acc += 2.0 * g[1] * mu[1] * t1;
+        for (int n = 2; n < M; ++n) {
+            const double t2 = 2.0 * x * t1 - t0;
+            acc += 2.0 * g[n] * mu[n] * t2;
+            t0 = t1;
+            t1 = t2;
+        }
+        rho[e] = acc / (M_PI * a * std::sqrt(1.0 - x * x));
+    }
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev series / propagation
+// ---------------------------------------------------------------------------
+namespace {
+
+// acc/out: Y = sum_k coef_k T_k(H~) X.  The accumulator `acc` is written by
+// the first sweep and updated by the later ones; the last sweep writes
+// acc + coef_K w_K to `out` (which may be X itself when K >= 2, since X is no
+// longer read by then).  W1, W2: two work vectors.
+pv_status run_series(pv_lattice* l, int dtype, int nb, double a, double b, int K, const double* coef,
+                     const void* X, void* acc, void* out, void* W1, void* W2, hipStream_t s) {
+    const int64_t n_elem = l->n_rows * nb;
+    if (K == 0) {
+        PV_HIP(pv::launch_scale_block(dtype, n_elem, X, coef[0], coef[1], out, s));
+        return PV_OK;
+    }
+    pv::SweepParams p = base_params(l, dtype, nb);
+    p.grid = grid_for(l, nb);
+    // k = 1
+    p.x = X;
+    p.y = W1;
+    p.z = nullptr;
+    p.alpha = 1.0 / a;
+    p.beta = b;
+    p.gamma = 0.0;
+    p.eta0_re = coef[0];
+    p.eta0_im = coef[1];
+    p.eta_re = coef[2];
+    p.eta_im = coef[3];
+    p.acc_out = (K == 1) ? out : acc;
+    p.ep = pv::EP_ACC_INIT | (K >= 2 ? pv::EP_STORE_Y : 0u);
+    PV_HIP(pv::launch_sweep(p, s));
+    const void* prev = X;
+    void* cur = W1;
+    p.alpha = 2.0 / a;
+    p.gamma = -1.0;
+    for (int k = 2; k <= K; ++k) {
+        void* next = (k == 2) ? W2 : const_cast<void*>(prev);
+        p.x = cur;
+        p.z = prev;
+        p.y = next;
+        p.eta_re = coef[2 * k];
+        p.eta_im = coef[2 * k + 1];
+        p.acc_in = acc;
+        p.acc_out = (k == K) ? out : acc;
+        p.ep = pv::EP_ACC_ADD | (k < K ? pv::EP_STORE_Y : 0u);
+        PV_HIP(pv::launch_sweep(p, s));
+        prev = cur;
+        cur = next;
+    }
+    return PV_OK;
+}
+
+pv_status check_series_args(pv_lattice* l, int dtype, int nb, double a, double b) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if ((st = check_dtype(l, dtype)) != PV_OK) return st;
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return fail(PV_ERR_INVALID_ARG, "need finite a > 0 and b");
+    return PV_OK;
+}
+
+}  // namespace
+
+extern "C" size_t pv_cheb_series_workspace_size(const pv_lattice* l, int dtype, int nb) {
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    return 2 * vec_bytes(l, dtype, nb);
+}
+
+extern "C" pv_status pv_cheb_series(pv_lattice* l, int dtype, int nb, double a, double b, int K, const double* coef,
+                                    const void* X, void* Y, void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if ((st = check_series_args(l, dtype, nb, a, b)) != PV_OK) return st;
+    if ((st = check_vec(X, dtype, "X")) != PV_OK) return st;
+    if ((st = check_vec(Y, dtype, "Y")) != PV_OK) return st;
+    if (X == Y) return fail(PV_ERR_INVALID_ARG, "X and Y must differ");
+    if (K < 0 || !coef) return fail(PV_ERR_INVALID_ARG, "need K >= 0 and coef[K+1]");
+    for (int k = 0; k <= K; ++k)
+        if (!std::isfinite(coef[2 * k]) || !std::isfinite(coef[2 * k + 1]))
+            return fail(PV_ERR_INVALID_ARG, "non-finite series coefficient %d", k);
+    const size_t need = pv_cheb_series_workspace_size(l, dtype, nb);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    char* w = static_cast<char*>(work);
+    return run_series(l, dtype, nb, a, b, K, coef, X, Y, Y, w, w + vec_bytes(l, dtype, nb),
+                      static_cast<hipStream_t>(stream));
+}
+
+extern "C" pv_status pv_cheb_tp_coefficients(double a, double dt, int M, double* coef) {
+    if (M < 0 || !coef || !std::isfinite(a) || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "bad arguments");
+    std::vector<double> J;
+    bessel_j(a * dt, M, J);
+    for (int k = 0; k <= M; ++k) {
+        // (-i)^k J_k
+        const int r = k & 3;
+        const double re = (r == 0) ? J[k] : (r == 2 ? -J[k] : 0.0);
+        const double im = (r == 1) ? -J[k] : (r == 3 ? J[k] : 0.0);
+        coef[2 * k] = re;
+        coef[2 * k + 1] = im;
+    }
+    return PV_OK;
+}
+
+extern "C" size_t pv_cheb_propagate_workspace_size(const pv_lattice* l, int dtype, int nb) {
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    return 3 * vec_bytes(l, dtype, nb);
+}
+
+extern "C" pv_status pv_cheb_propagate(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M,
+                                       int nsteps, void* psi, void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if ((st = check_series_args(l, dtype, nb, a, b)) != PV_OK) return st;
+    if ((st = check_vec(psi, dtype, "psi")) != PV_OK) return st;
+    if (M < 1 || nsteps < 0 || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "need M >= 1, nsteps >= 0");
+    const size_t need = pv_cheb_propagate_workspace_size(l, dtype, nb);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    std::vector<double> coef(2 * (M + 1));
+    pv_cheb_tp_coefficients(a, dt, M, coef.data());
+    // eta_0 = e^{-i b dt} c_0, eta_k = 2 e^{-i b dt} c_k
+    const std::complex<double> ph = std::exp(std::complex<double>(0.0, -b * dt));
+    for (int k = 0; k <= M; ++k) {
+        std::complex<double> c(coef[2 * k], coef[2 * k + 1]);
+        c *= ph * (k ? 2.0 : 1.0);
+        coef[2 * k] = c.real();
+        coef[2 * k + 1] = c.imag();
+    }
+    char* w = static_cast<char*>(work);
+    const size_t vb = vec_bytes(l, dtype, nb);
+    void* W1 = w;
+    void* W2 = w + vb;
+    void* ACC = w + 2 * vb;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int step = 0; step < nsteps; ++step) {
+        if (M >= 2) {
+            if ((st = run_series(l, dtype, nb, a, b, M, coef.data(), psi, ACC, psi, W1, W2, s)) != PV_OK) return st;
+        } else {
+            if ((st = run_series(l, dtype, nb, a, b, M, coef.data(), psi, ACC, ACC, W1, W2, s)) != PV_OK) return st;
+            PV_HIP(pv::launch_copy(ACC, psi, (size_t)l->n_rows * nb * elem_bytes(dtype), s));
+        }
+    }
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gram / rotate / copy
+// ---------------------------------------------------------------------------
+extern "C" size_t pv_gram_workspace_size(int64_t rows, int nx, int ny) {
+    if (rows < 0 || nx < 1 || ny < 1 || nx > PV_MAX_NB || ny > PV_MAX_NB) return 0;
+    int ncu = num_cus_of_current_device();
+    if (ncu <= 0) ncu = 256;
+    return align_up((size_t)pv::gram_grid(rows, ncu) * nx * ny * 2 * sizeof(double));
+}
+
+extern "C" pv_status pv_gram(int dtype, int64_t rows, int nx, int ny, const void* X, const void* Y, double* G,
+                             void* work, size_t work_bytes, void* stream) {
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "bad dtype");
+    if (rows < 1 || nx < 1 || ny < 1 || nx > PV_MAX_NB || ny > PV_MAX_NB)
+        return fail(PV_ERR_INVALID_ARG, "need rows >= 1 and 1 <= nx, ny <= %d", PV_MAX_NB);
+    pv_status st;
+    if ((st = check_vec(X, dtype, "X")) != PV_OK) return st;
+    if ((st = check_vec(Y, dtype, "Y")) != PV_OK) return st;
+    if (!G) return fail(PV_ERR_INVALID_ARG, "G is NULL");
+    const size_t need = pv_gram_workspace_size(rows, nx, ny);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    int ncu = num_cus_of_current_device();
+    if (ncu <= 0) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    const int grid = pv::gram_grid(rows, ncu);
+    PV_HIP(pv::launch_gram(dtype, rows, nx, ny, X, Y, static_cast<double*>(work), grid, G,
+                           static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q, void* Y,
+                                     void* stream) {
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "bad dtype");
+    if (rows < 1 || nx < 1 || ny < 1 || nx > PV_MAX_NB || ny > PV_MAX_NB)
+        return fail(PV_ERR_INVALID_ARG, "need rows >= 1 and 1 <= nx, ny <= %d", PV_MAX_NB);
+    pv_status st;
+    if ((st = check_vec(X, dtype, "X")) != PV_OK) return st;
+    if ((st = check_vec(Y, dtype, "Y")) != PV_OK) return st;
+    if (!Q) return fail(PV_ERR_INVALID_ARG, "Q is NULL");
+    if (X == Y) return fail(PV_ERR_INVALID_ARG, "X and Y must differ");
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    PV_HIP(pv::launch_rotate(dtype, rows, nx, ny, X, Q, Y, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || bytes % 16 || (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+        return fail(PV_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and size");
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    PV_HIP(pv::launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}

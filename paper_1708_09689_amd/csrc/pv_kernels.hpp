@@ -1,0 +1,148 @@
+// Internal interface between the C ABI layer (pv_api.cpp) and the HIP kernels
+// (pv_kernels.hip).  Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pv {
+
+constexpr int PV_MAX_NB_K = 64;
+
+// Kernel families: a family fixes the stencil's offsets and the zero / real /
+// imaginary structure of every block at compile time; values stay runtime.
+enum Family : int {
+    FAM_GENERIC = 0,     // any offsets in {-1,0,1}^3, dense complex blocks
+    FAM_TI = 1,          // 3D TI (Sec. 2.2), n_orb = 4, offsets +-x, +-y, +-z
+    FAM_GRAPHENE2 = 2,   // two-site honeycomb, n_orb = 2, offsets +-x, +-y (2D)
+    FAM_GRAPHENE4 = 3,   // four-site graphene cell (Sec. 2.1), n_orb = 4 (2D)
+    FAM_WEYL = 4,        // Weyl semimetal (Sec. 2.3), n_orb = 2, 3D
+};
+
+// Block-entry codes.
+enum : unsigned char { CZ = 0, CR = 1, CI = 2, CC = 3 };
+
+// Epilogue flags of a sweep.
+enum : unsigned {
+    EP_STORE_Y = 1u,     // write y
+    EP_ACC_INIT = 2u,    // acc_out = eta0 * x + eta * y
+    EP_ACC_ADD = 4u,     // acc_out = acc_in + eta * y
+    EP_DOTS = 8u,        // per-block partial dots (xx, Re xy, Im xy, yy)
+};
+
+struct SweepParams {
+    int family;
+    int dtype;            // 0 = complex128, 1 = complex64
+    int vtype;            // 0 = float64 field, 1 = float32 field
+    int n_orb;
+    int n_terms;          // generic family only
+    int pot_mode;         // 0 none, 1 site, 2 orbital
+    int64_t L[3];
+    int periodic[3];
+    int nb;
+    const void* x;
+    const void* z;        // may alias y; NULL if gamma == 0 for all columns
+    void* y;
+    const void* acc_in;
+    void* acc_out;
+    const void* V;        // NULL = no field
+    const double* coef;   // device: [(n_terms + 1)][n_orb][n_orb][2], onsite last
+    const int* offs;      // device: [n_terms][3] (generic family only)
+    const double* colp;   // device: [nb][3] per-column alpha, beta, gamma or NULL
+    double alpha, beta, gamma;
+    double eta_re, eta_im, eta0_re, eta0_im;
+    unsigned ep;
+    double* partials;     // [grid][nb][4] when EP_DOTS
+    int grid;             // number of workgroups (multiple of 8)
+};
+
+// Number of workgroups the sweep uses for a lattice / nb (a multiple of 8,
+// enough to fill every CU, bounded by the number of tiles).
+int sweep_grid(const SweepParams& p, int num_cus);
+hipError_t launch_sweep(const SweepParams& p, hipStream_t s);
+
+// Fixed-order reduction of [grid][nb][4] partials.
+//   mode 0: dots[c][0..3] = sums
+//   mode 1: KPM first step: mu[c][0] = xx/D, mu[c][1] = Re xy / D
+//   mode 2: KPM step n >= 1: mu[c][2n] = 2 xx/D - mu[c][0], mu[c][2n+1] = 2 Re xy/D - mu[c][1]
+hipError_t launch_reduce_dots(const double* partials, int grid, int nb, int mode, double* out,
+                              int M, int step, double inv_D, hipStream_t s);
+
+hipError_t launch_scale_block(int dtype, int64_t n_elem, const void* x, double re, double im,
+                              void* y, hipStream_t s);
+
+hipError_t launch_gram(int dtype, int64_t rows, int nx, int ny, const void* X, const void* Y,
+                       double* partials, int grid, double* G, hipStream_t s);
+int gram_grid(int64_t rows, int num_cus);
+hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q,
+                         void* Y, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace pv
+
+namespace pv {
+
+// ---------------------------------------------------------------------------
+// Compiled stencil families.  Offsets use the descriptor convention
+// (H x)[s] += B_t x[s + d_t]; code[t][o][o'] says which entries of B_t may be
+// nonzero and whether they are real (CR), imaginary (CI) or complex (CC).
+// Row NT of `code` is the on-site block (its diagonal also carries V - beta).
+// ---------------------------------------------------------------------------
+
+// 3D TI (Sec. 2.2) with Gamma^1 = tau_z sigma_0, Gamma^{j+1} = tau_x sigma_j:
+// B_{-e_j} = -(t/2)(G1 - i G_{j+1}), B_{+e_j} = B_{-e_j}^H, E0 = m G1.
+struct PatTI {
+    static constexpr int FAMILY = FAM_TI, NO = 4, NT = 6, DIM = 3;
+    static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    static constexpr unsigned char code[NT + 1][NO][NO] = {
+        {{CR, CZ, CZ, CI}, {CZ, CR, CI, CZ}, {CZ, CI, CR, CZ}, {CI, CZ, CZ, CR}},
+        {{CR, CZ, CZ, CI}, {CZ, CR, CI, CZ}, {CZ, CI, CR, CZ}, {CI, CZ, CZ, CR}},
+        {{CR, CZ, CZ, CR}, {CZ, CR, CR, CZ}, {CZ, CR, CR, CZ}, {CR, CZ, CZ, CR}},
+        {{CR, CZ, CZ, CR}, {CZ, CR, CR, CZ}, {CZ, CR, CR, CZ}, {CR, CZ, CZ, CR}},
+        {{CR, CZ, CI, CZ}, {CZ, CR, CZ, CI}, {CI, CZ, CR, CZ}, {CZ, CI, CZ, CR}},
+        {{CR, CZ, CI, CZ}, {CZ, CR, CZ, CI}, {CI, CZ, CR, CZ}, {CZ, CI, CZ, CR}},
+        {{CR, CZ, CZ, CZ}, {CZ, CR, CZ, CZ}, {CZ, CZ, CR, CZ}, {CZ, CZ, CZ, CR}},
+    };
+};
+
+// Two-site honeycomb on an (i, j) grid: A(s) <- B(s), B(s - e_i), B(s - e_j).
+struct PatGraphene2 {
+    static constexpr int FAMILY = FAM_GRAPHENE2, NO = 2, NT = 4, DIM = 2;
+    static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
+    static constexpr unsigned char code[NT + 1][NO][NO] = {
+        {{CZ, CR}, {CZ, CZ}}, {{CZ, CZ}, {CR, CZ}},
+        {{CZ, CR}, {CZ, CZ}}, {{CZ, CZ}, {CR, CZ}},
+        {{CZ, CR}, {CR, CZ}},
+    };
+};
+
+// Four-site graphene cell (Sec. 2.1): B_{-x} = T_x, B_{+x} = T_x^T,
+// B_{-y} = T_y, B_{+y} = T_y^T, E0 = T_n (chain 0-1-2-3).
+struct PatGraphene4 {
+    static constexpr int FAMILY = FAM_GRAPHENE4, NO = 4, NT = 4, DIM = 2;
+    static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
+    static constexpr unsigned char code[NT + 1][NO][NO] = {
+        {{CZ, CZ, CZ, CZ}, {CR, CZ, CZ, CZ}, {CZ, CZ, CZ, CR}, {CZ, CZ, CZ, CZ}},
+        {{CZ, CR, CZ, CZ}, {CZ, CZ, CZ, CZ}, {CZ, CZ, CZ, CZ}, {CZ, CZ, CR, CZ}},
+        {{CZ, CZ, CZ, CR}, {CZ, CZ, CZ, CZ}, {CZ, CZ, CZ, CZ}, {CZ, CZ, CZ, CZ}},
+        {{CZ, CZ, CZ, CZ}, {CZ, CZ, CZ, CZ}, {CZ, CZ, CZ, CZ}, {CR, CZ, CZ, CZ}},
+        {{CZ, CR, CZ, CZ}, {CR, CZ, CR, CZ}, {CZ, CR, CZ, CR}, {CZ, CZ, CR, CZ}},
+    };
+};
+
+// Weyl semimetal (Sec. 2.3): B_{+-x} = sigma_x/2, B_{-y} = (sigma_x + i sigma_y)/2,
+// B_{-z} = (sigma_x + i sigma_z)/2 (and their adjoints), E0 = -sigma_x(2 + cos k0).
+struct PatWeyl {
+    static constexpr int FAMILY = FAM_WEYL, NO = 2, NT = 6, DIM = 3;
+    static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    static constexpr unsigned char code[NT + 1][NO][NO] = {
+        {{CZ, CR}, {CR, CZ}}, {{CZ, CR}, {CR, CZ}},
+        {{CZ, CR}, {CZ, CZ}}, {{CZ, CZ}, {CR, CZ}},
+        {{CI, CR}, {CR, CI}}, {{CI, CR}, {CR, CI}},
+        {{CZ, CR}, {CR, CZ}},
+    };
+};
+
+}  // namespace pv

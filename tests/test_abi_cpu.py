@@ -1,0 +1,155 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads and exports
+every declared symbol, model stencils equal the oracle's model terms,
+descriptor validation, stencil-family selection, and the host-only helpers."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1708_09689_amd as pv
+from oracle import chebtp, kpm, models
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pv.LIB_PATH):
+        pytest.skip("libpvdtm.so not built")
+    return pv.lib()
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "pvdtm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pv_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in pv.SIGNATURES, f"binding lacks {s}"
+
+
+def test_version_and_status_strings(lib):
+    assert lib.pv_version() >= 1
+    assert lib.pv_status_string(0) == b"ok"
+
+
+def oracle_descriptor(model):
+    """Descriptor-convention blocks from the oracle model: (H x)[s] += A x[s - e]
+    + A^H x[s + e] for every hop (e, A)."""
+    out = {}
+    for e, A in model.hops:
+        out[tuple(-np.asarray(e))] = A
+        out[tuple(np.asarray(e))] = A.conj().T
+    return out, model.onsite
+
+
+@pytest.mark.parametrize("code,model,params", [
+    (pv.PV_MODEL_TI, models.topological_insulator(t=1.0, m=2.0), [1.0, 2.0, 0.0, 0.0]),
+    (pv.PV_MODEL_TI, models.topological_insulator(t=0.7, m=1.3, delta1=0.2, delta2=-0.1), [0.7, 1.3, 0.2, -0.1]),
+    (pv.PV_MODEL_GRAPHENE2, models.graphene_two_site(t=1.0), [1.0]),
+    (pv.PV_MODEL_GRAPHENE4, models.graphene_four_site(t=1.0), [1.0]),
+    (pv.PV_MODEL_WEYL, models.weyl_semimetal(), [np.pi / 2]),
+])
+def test_model_stencils_equal_oracle_terms(lib, code, model, params):
+    st = pv.pv_model_stencil(code, params)
+    ref, E0 = oracle_descriptor(model)
+    assert st["n_orb"] == model.n_orb
+    assert len(st["offsets"]) == len(ref)
+    for off, B in zip(st["offsets"], st["blocks"]):
+        assert np.abs(B - ref[tuple(off)]).max() < 1e-15
+    assert np.abs(st["onsite"] - E0).max() < 1e-15
+
+
+@pytest.mark.parametrize("code,params,L,family", [
+    (pv.PV_MODEL_TI, [1.0, 2.0, 0, 0], (4, 4, 4), 1),
+    (pv.PV_MODEL_TI, [1.0, 2.0, 0.3, 0], (4, 4, 4), 0),   # Delta1 breaks the compiled on-site structure
+    (pv.PV_MODEL_GRAPHENE2, [1.0], (5, 4), 2),
+    (pv.PV_MODEL_GRAPHENE4, [1.0], (5, 4), 3),
+    (pv.PV_MODEL_WEYL, [np.pi / 2], (4, 3, 3), 4),
+])
+def test_family_selection(lib, code, params, L, family):
+    lat = pv.Lattice(L, (1, 1, 1), pv.pv_model_stencil(code, params))
+    assert lat.family == family
+    assert lat.n_sites == int(np.prod(L))
+
+
+def test_descriptor_validation(lib):
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0])
+    bad = dict(st)
+    bad["blocks"] = st["blocks"].copy()
+    bad["blocks"][0, 0, 3] += 0.1j
+    with pytest.raises(pv.PvError) as e:
+        pv.Lattice((4, 4, 4), (1, 1, 1), bad)
+    assert e.value.status == 3
+    pv.Lattice((4, 4, 4), (1, 1, 1), bad, check_hermitian=False)  # accepted without the check
+    # n_orb = 3 unsupported
+    s3 = {"dim": 3, "n_orb": 3, "offsets": np.zeros((0, 3)), "blocks": np.zeros((0, 3, 3)),
+          "onsite": np.eye(3), "pot_mode": 1}
+    with pytest.raises(pv.PvError) as e:
+        pv.Lattice((4, 4, 4), (1, 1, 1), s3)
+    assert e.value.status == 2
+    # offsets outside {-1,0,1}, zero offset, duplicates
+    for offs in ([[2, 0, 0]], [[0, 0, 0]]):
+        s = {"dim": 3, "n_orb": 1, "offsets": np.array(offs), "blocks": np.ones((1, 1, 1)),
+             "onsite": np.zeros((1, 1)), "pot_mode": 1}
+        with pytest.raises(pv.PvError):
+            pv.Lattice((4, 4, 4), (1, 1, 1), s, check_hermitian=False)
+    s = {"dim": 3, "n_orb": 1, "offsets": np.array([[1, 0, 0], [1, 0, 0]]), "blocks": np.ones((2, 1, 1)),
+         "onsite": np.zeros((1, 1)), "pot_mode": 1}
+    with pytest.raises(pv.PvError):
+        pv.Lattice((4, 4, 4), (1, 1, 1), s, check_hermitian=False)
+    # 2D lattice with L[2] != 1
+    g = pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0])
+    with pytest.raises(pv.PvError):
+        pv.Lattice((4, 4, 2), (1, 1, 1), g)
+
+
+def test_argument_errors_return_before_any_launch(lib):
+    lat = pv.Lattice((4, 4, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
+    one = np.ones(4)
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    # nb not a power of two
+    st = lib.pv_spmmv(lat.handle, 0, 3, fake, None, fake, pv._dptr(one), pv._dptr(one), pv._dptr(np.zeros(4)),
+                      0, None, fake, 1 << 20, None)
+    assert st == 2
+    # x aliases y
+    st = lib.pv_spmmv(lat.handle, 0, 1, fake, None, fake, pv._dptr(one), pv._dptr(one), pv._dptr(np.zeros(4)),
+                      0, None, fake, 1 << 20, None)
+    assert st == 1
+    # odd M
+    st = lib.pv_kpm_moments(lat.handle, 0, 1, 7, 7.0, 0.0, fake, fake, fake, 1 << 30, None)
+    assert st == 1
+    # workspace too small
+    st = lib.pv_kpm_moments(lat.handle, 0, 1, 8, 7.0, 0.0, fake, fake, fake, 16, None)
+    assert st == 4
+    # a <= 0
+    st = lib.pv_kpm_moments(lat.handle, 0, 1, 8, 0.0, 0.0, fake, fake, fake, 1 << 30, None)
+    assert st == 1
+    assert b"a > 0" in lib.pv_last_error()
+    # misaligned complex128 pointer
+    st = lib.pv_kpm_moments(lat.handle, 0, 1, 8, 7.0, 0.0, ctypes.c_void_p((1 << 20) + 8), fake, fake, 1 << 30, None)
+    assert st == 1
+
+
+def test_tp_coefficients_match_oracle(lib):
+    for adt in (0.0, 3.3, 30.6, -12.0):
+        c = pv.pv_cheb_tp_coefficients(1.0, adt, 80)
+        ref = chebtp.tp_coefficients(1.0, adt, 80)
+        assert np.abs(c - ref).max() < 1e-15
+
+
+def test_kpm_dos_matches_oracle(lib):
+    g = np.random.default_rng(3)
+    mu = np.concatenate([[1.0], 0.3 * g.standard_normal(63) / np.arange(1, 64)])
+    E = np.linspace(-6.9, 6.9, 101)
+    rho = pv.pv_kpm_dos(mu, E, 7.0, 0.0)
+    ref = kpm.dos(mu, E, 7.0, 0.0)
+    assert np.abs(rho - ref).max() < 1e-13

@@ -1,0 +1,164 @@
+"""GPU parity of the fused stencil sweep (pv_spmmv) against the oracle.
+
+Tolerances: complex128 -- 1e-13 relative to max|y| (different summation
+order, FMA contraction on both sides); delta vectors -- bit-exact (one
+nonzero product per entry); complex64 vectors -- 2e-6 relative (FP32 stencil
+arithmetic, unit round-off 6e-8 times at most ~20 accumulated terms of
+comparable size)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1708_09689_amd as pv  # noqa: E402
+from oracle import spmmv  # noqa: E402
+import workloads as W  # noqa: E402
+
+from gpu_common import Case, dev, host, rel_err  # noqa: E402
+
+
+@pytest.mark.parametrize("name,L,periodic", [
+    ("ti", (5, 4, 3), (1, 1, 1)),
+    ("ti", (7, 3, 4), (0, 1, 0)),
+    ("ti_delta", (4, 3, 3), (1, 0, 1)),
+    ("graphene2", (9, 5), (0, 1)),
+    ("graphene4", (6, 5), (1, 0)),
+    ("weyl", (5, 4, 3), (1, 1, 0)),
+])
+def test_delta_vectors_bit_exact(name, L, periodic):
+    c = Case(name, L, periodic, Wd=1.0)
+    cols = [0, 1, c.D // 3, c.D // 2 + 1, c.D - 1, 7, 11, c.D - 5]
+    X = W.basis_block(c.D, cols)
+    y = torch.empty((c.D, len(cols)), dtype=torch.complex128, device="cuda")
+    pv.pv_spmmv(c.lat, dev(X), y, 1.0, 0.0, 0.0)
+    ref = spmmv.spmmv(c.H, X, 1.0, 0.0, 0.0)
+    assert np.array_equal(host(y), ref)
+
+
+@pytest.mark.parametrize("name,L,periodic", [
+    ("ti", (37, 5, 4), (1, 1, 1)),      # ragged x-rows for every tile width
+    ("ti", (16, 9, 7), (0, 0, 1)),
+    ("ti", (1, 2, 3), (1, 1, 1)),       # extents 1 and 2 along periodic axes
+    ("ti_delta", (12, 6, 5), (1, 1, 0)),
+    ("graphene2", (70, 9), (0, 1)),
+    ("graphene4", (21, 10), (1, 1)),
+    ("weyl", (19, 6, 5), (1, 1, 0)),
+])
+@pytest.mark.parametrize("nb", [1, 4, 32])
+def test_sweep_matches_oracle_c128(name, L, periodic, nb):
+    c = Case(name, L, periodic, Wd=2.0, seed=nb)
+    x = c.block(nb, seed=1)
+    z = c.block(nb, seed=2)
+    g = W.generator(5, 7, nb)
+    alpha, beta, gamma = 0.5 + g.random(nb), g.standard_normal(nb), g.standard_normal(nb)
+    y = dev(z.copy())
+    dots = pv.pv_spmmv(c.lat, dev(x), y, alpha, beta, gamma, z=y, dot_flags=7)
+    ref = spmmv.spmmv(c.H, x, alpha, beta, gamma, z)
+    out = host(y)
+    assert rel_err(out, ref) < 1e-13
+    xx, xy, yy = spmmv.block_dots(x, ref)
+    d = host(dots)
+    assert np.abs(d[:, 0] - xx).max() < 1e-12 * xx.max()
+    assert np.abs(d[:, 1] + 1j * d[:, 2] - xy).max() < 1e-12 * np.sqrt(xx.max() * yy.max())
+    assert np.abs(d[:, 3] - yy).max() < 1e-12 * yy.max()
+
+
+@pytest.mark.parametrize("nb", [1, 2, 8, 16, 64])
+def test_sweep_all_block_widths(nb):
+    c = Case("ti", (11, 6, 5), (1, 1, 1), Wd=1.0)
+    x = c.block(nb)
+    y = torch.empty((c.D, nb), dtype=torch.complex128, device="cuda")
+    pv.pv_spmmv(c.lat, dev(x), y, 0.25, 0.1, 0.0)
+    assert rel_err(host(y), spmmv.spmmv(c.H, x, 0.25, 0.1, 0.0)) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["ti", "graphene2", "weyl"])
+@pytest.mark.parametrize("vdtype", [np.float64, np.float32])
+def test_sweep_c64_error_bound(name, vdtype):
+    L = {"ti": (13, 6, 5), "graphene2": (40, 12), "weyl": (9, 6, 5)}[name]
+    c = Case(name, L, (1, 1, 1), Wd=2.0, vdtype=vdtype)
+    nb = 4
+    x = c.block(nb, dtype=np.complex64)
+    z = c.block(nb, seed=2, dtype=np.complex64)
+    y = dev(z.copy())
+    dots = pv.pv_spmmv(c.lat, dev(x), y, 2.0 / 7.0, 0.0, -1.0, z=y, dot_flags=7)
+    Vq = c.V.astype(vdtype).astype(np.float64)
+    import oracle.hamiltonian as oh
+    Hq = oh.assemble(c.model, c.olat, Vq)
+    ref = spmmv.spmmv(Hq, x.astype(np.complex128), 2.0 / 7.0, 0.0, -1.0, z.astype(np.complex128))
+    assert rel_err(host(y).astype(np.complex128), ref) < 2e-6
+    # dots accumulate in FP64 from the FP32 values
+    xx, _, _ = spmmv.block_dots(x.astype(np.complex128), x.astype(np.complex128))
+    assert np.abs(host(dots)[:, 0] - xx).max() < 1e-12 * xx.max()
+
+
+def test_per_column_and_gamma_zero_semantics():
+    c = Case("ti", (9, 4, 4), (1, 1, 1))
+    nb = 4
+    x = c.block(nb)
+    z = np.full((c.D, nb), np.nan + 0j)
+    y = dev(z)
+    alpha = np.array([1.0, 0.5, 2.0, 1.0])
+    beta = np.array([0.0, 1.0, -2.0, 0.5])
+    pv.pv_spmmv(c.lat, dev(x), y, alpha, beta, np.zeros(nb))   # gamma = 0: y is write-only
+    out = host(y)
+    assert np.isfinite(out).all()
+    assert rel_err(out, spmmv.spmmv(c.H, x, alpha, beta, 0.0)) < 1e-13
+
+
+def test_sweep_is_deterministic():
+    c = Case("ti", (33, 17, 9), (1, 1, 1))
+    x = dev(c.block(4))
+    y1 = torch.empty_like(x)
+    y2 = torch.empty_like(x)
+    d1 = pv.pv_spmmv(c.lat, x, y1, 1.0, 0.0, 0.0, dot_flags=7)
+    d2 = pv.pv_spmmv(c.lat, x, y2, 1.0, 0.0, 0.0, dot_flags=7)
+    assert torch.equal(y1, y2) and torch.equal(d1, d2)
+
+
+def test_generic_family_random_hermitian_stencil():
+    """A stencil with diagonal offsets and dense random blocks (no compiled
+    family): generic kernel against the explicit matrix of the same stencil."""
+    import scipy.sparse as sp
+    g = np.random.default_rng(11)
+    offs = [(1, 0, 0), (0, 1, 0), (1, 1, 0), (1, -1, 1), (0, 0, 1)]
+    no = 2
+    blocks, offsets = [], []
+    for o in offs:
+        B = g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))
+    E0 = E0 + E0.conj().T
+    st = {"dim": 3, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_ORBITAL}
+    L, per = (6, 5, 4), (1, 0, 1)
+    lat = pv.Lattice(L, per, st)
+    assert lat.family == 0
+    from oracle import lattice as olat_mod
+    ol = olat_mod.Lattice(L, per, no)
+    V = W.uniform_potential(ol.n_rows, 1.0, W.generator(3, 1))
+    lat.set_potential(dev(V))
+    # explicit matrix straight from the stencil definition (H x)[s] += B_t x[s + d_t]
+    rows, cols, vals = [], [], []
+    s = np.arange(ol.n_sites)
+    for o, B in zip(offsets, blocks):
+        nbr, ok = ol.shift(s, o)
+        for a in range(no):
+            for b in range(no):
+                rows.append(s[ok] * no + a)
+                cols.append(nbr[ok] * no + b)
+                vals.append(np.full(ok.sum(), B[a, b]))
+    for a in range(no):
+        for b in range(no):
+            rows.append(s * no + a)
+            cols.append(s * no + b)
+            vals.append(np.full(s.size, E0[a, b] + (V[s * no + a] if a == b else 0)))
+    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(ol.n_rows, ol.n_rows)).tocsr()
+    x = W.gaussian_block(ol.n_rows, 8, W.generator(3, 2))
+    y = torch.empty((ol.n_rows, 8), dtype=torch.complex128, device="cuda")
+    pv.pv_spmmv(lat, dev(x), y, 1.0, 0.3, 0.0)
+    assert rel_err(host(y), spmmv.spmmv(H, x, 1.0, 0.3, 0.0)) < 1e-13
