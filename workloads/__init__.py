@@ -156,3 +156,16 @@ def sample_sites(n_sites: int, count: int, gen: np.random.Generator) -> np.ndarr
     """Distinct sorted site indices, for sampled checks and finite differences."""
     count = min(int(count), int(n_sites))
     return np.sort(gen.choice(int(n_sites), size=count, replace=False)).astype(np.int64)
+
+
+def random_phase_device(n_rows: int, nb: int, seed: int, device, dtype="complex128"):
+    """Random-phase block generated on the device with torch's seeded
+    generator (for large performance runs where host generation and upload
+    would dominate; same distribution as random_phase_block, different
+    stream).  Returns a contiguous torch tensor [n_rows, nb]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(MASTER_SEED + seed))
+    real = torch.float64 if dtype == "complex128" else torch.float32
+    phi = torch.rand((int(n_rows), int(nb)), generator=g, device=device, dtype=real) * (2.0 * math.pi)
+    return torch.polar(torch.ones_like(phi), phi).contiguous()
