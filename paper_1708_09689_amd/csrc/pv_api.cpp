@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -85,6 +86,7 @@ struct pv_lattice {
     int dev = -1;
     double* d_coef = nullptr;
     int* d_offs = nullptr;
+    void* d_zero = nullptr;                            // one x-row of zeros (widest block)
     // borrowed field
     const void* V = nullptr;
     int vtype = 0;
@@ -158,6 +160,7 @@ pv_status ensure_device(pv_lattice* l) {
     if (l->dev == dev && l->d_coef) return PV_OK;
     if (l->d_coef) { (void)hipFree(l->d_coef); l->d_coef = nullptr; }
     if (l->d_offs) { (void)hipFree(l->d_offs); l->d_offs = nullptr; }
+    if (l->d_zero) { (void)hipFree(l->d_zero); l->d_zero = nullptr; }
     const size_t cb = l->packed.size() * sizeof(double);
     if (hipMalloc(&l->d_coef, cb) != hipSuccess) return fail(PV_ERR_OOM, "coefficient upload: out of memory");
     PV_HIP(hipMemcpy(l->d_coef, l->packed.data(), cb, hipMemcpyHostToDevice));
@@ -166,8 +169,30 @@ pv_status ensure_device(pv_lattice* l) {
         if (hipMalloc(&l->d_offs, ob) != hipSuccess) return fail(PV_ERR_OOM, "offset upload: out of memory");
         PV_HIP(hipMemcpy(l->d_offs, l->packed_offs.data(), ob, hipMemcpyHostToDevice));
     }
+    {
+        const size_t zb = (size_t)l->L[0] * l->n_orb * PV_MAX_NB * 16;
+        if (hipMalloc(&l->d_zero, zb) != hipSuccess) return fail(PV_ERR_OOM, "zero row: out of memory");
+        PV_HIP(hipMemset(l->d_zero, 0, zb));
+    }
     l->dev = dev;
     return PV_OK;
+}
+
+// Rows per y-slab: an XCD's slab plane (Lx * BY sites of the nb-wide block)
+// is kept near PV_SLAB_BYTES (default 2 MiB) so the +-z neighbour rows of a
+// plane are still in that XCD's 4 MiB L2 when the next plane is swept.
+int slab_rows(const pv_lattice* l, int dtype, int nb) {
+    static long long target = -1;
+    if (target < 0) {
+        const char* e = getenv("PV_SLAB_BYTES");
+        target = e ? atoll(e) : (2ll << 20);
+    }
+    const long long site = (long long)l->n_orb * nb * (dtype == PV_C128 ? 16 : 8);
+    const long long ny_max = (l->L[1] + 7) / 8;
+    long long by = target / (l->L[0] * site);
+    if (by < 1) by = 1;
+    if (by > ny_max) by = ny_max;
+    return int(by);
 }
 
 size_t elem_bytes(int dtype) { return dtype == PV_C128 ? 16 : 8; }
@@ -211,12 +236,12 @@ pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     return p;
 }
 
-int grid_for(const pv_lattice* l, int nb) {
-    pv::SweepParams p = base_params(l, 0, nb);
-    int ncu = num_cus_of_current_device();
-    if (ncu <= 0) ncu = 256;
-    return pv::sweep_grid(p, ncu);
+int num_cus() {
+    const int n = num_cus_of_current_device();
+    return n > 0 ? n : 256;
 }
+
+int64_t grid_for(const pv_lattice* l, int nb) { return pv::sweep_grid_max(l->L, l->n_orb, nb); }
 
 size_t partial_bytes(const pv_lattice* l, int nb) { return align_up((size_t)grid_for(l, nb) * nb * 4 * sizeof(double)); }
 size_t vec_bytes(const pv_lattice* l, int dtype, int nb) {
@@ -242,6 +267,15 @@ void bessel_j(double z, int kmax, std::vector<double>& out) {
     double norm = j[0];
     for (int k = 2; k <= start; k += 2) norm += 2.0 * j[k];
     for (int k = 0; k <= kmax; ++k) out[k] = j[k] / norm * ((neg && (k & 1)) ? -1.0 : 1.0);
+}
+
+
+// Slab height and zero row of a sweep (the device state of the lattice must
+// be current).
+pv_status fill_traversal(pv_lattice* l, int dtype, int nb, pv::SweepParams& p) {
+    p.slab_rows = slab_rows(l, dtype, nb);
+    p.zero_row = l->d_zero;
+    return PV_OK;
 }
 
 }  // namespace
@@ -440,6 +474,7 @@ extern "C" pv_status pv_lattice_create(const pv_lattice_desc* d, pv_lattice** ou
     // overflow guard: elements of a PV_MAX_NB block must index in int64
     const double sites = double(d->L[0]) * double(d->L[1]) * double(d->L[2]);
     if (sites * d->n_orb * PV_MAX_NB * 16.0 > 9.0e18) return fail(PV_ERR_INVALID_ARG, "lattice too large");
+    if (sites >= 2147483648.0) return fail(PV_ERR_UNSUPPORTED, "more than 2^31 - 1 sites");
     const int no = d->n_orb;
     for (int t = 0; t < d->n_terms; ++t) {
         const int* o = d->offsets + 3 * t;
@@ -510,6 +545,7 @@ extern "C" void pv_lattice_destroy(pv_lattice* l) {
     if (!l) return;
     if (l->d_coef) (void)hipFree(l->d_coef);
     if (l->d_offs) (void)hipFree(l->d_offs);
+    if (l->d_zero) (void)hipFree(l->d_zero);
     delete l;
 }
 
@@ -568,7 +604,7 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
     if ((st = ensure_device(l)) != PV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     pv::SweepParams p = base_params(l, dtype, nb);
-    p.grid = grid_for(l, nb);
+    if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
     p.x = x;
     p.z = need_z ? z : nullptr;
     p.y = y;
@@ -589,7 +625,7 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
         PV_HIP(hipMemcpyAsync(colp, h.data(), sizeof(double) * 3 * nb, hipMemcpyHostToDevice, s));
         p.colp = colp;
     }
-    PV_HIP(pv::launch_sweep(p, s));
+    PV_HIP(pv::launch_sweep(p, num_cus(), s));
     if (dot_flags) PV_HIP(pv::launch_reduce_dots(p.partials, p.grid, nb, 0, dots, 0, 0, 0.0, s));
     if (!uniform) PV_HIP(hipStreamSynchronize(s));  // host staging buffer h goes out of scope
     return PV_OK;
@@ -623,7 +659,7 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     void* A = w + partial_bytes(l, nb);
     void* B = static_cast<char*>(A) + vec_bytes(l, dtype, nb);
     pv::SweepParams p = base_params(l, dtype, nb);
-    p.grid = grid_for(l, nb);
+    if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
     p.partials = partials;
     p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
     const double invD = 1.0 / double(l->n_rows);
@@ -634,7 +670,7 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     p.alpha = 1.0 / a;
     p.beta = b;
     p.gamma = 0.0;
-    PV_HIP(pv::launch_sweep(p, s));
+    PV_HIP(pv::launch_sweep(p, num_cus(), s));
     PV_HIP(pv::launch_reduce_dots(partials, p.grid, nb, 1, mu, M, 0, invD, s));
     const void* prev = r;
     void* cur = A;
@@ -645,7 +681,7 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
         p.x = cur;
         p.z = prev;
         p.y = next;
-        PV_HIP(pv::launch_sweep(p, s));
+        PV_HIP(pv::launch_sweep(p, num_cus(), s));
         PV_HIP(pv::launch_reduce_dots(partials, p.grid, nb, 2, mu, M, n, invD, s));
         prev = cur;
         cur = next;
@@ -693,7 +729,8 @@ pv_status run_series(pv_lattice* l, int dtype, int nb, double a, double b, int K
         return PV_OK;
     }
     pv::SweepParams p = base_params(l, dtype, nb);
-    p.grid = grid_for(l, nb);
+    pv_status st;
+    if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
     // k = 1
     p.x = X;
     p.y = W1;
@@ -707,7 +744,7 @@ pv_status run_series(pv_lattice* l, int dtype, int nb, double a, double b, int K
     p.eta_im = coef[3];
     p.acc_out = (K == 1) ? out : acc;
     p.ep = pv::EP_ACC_INIT | (K >= 2 ? pv::EP_STORE_Y : 0u);
-    PV_HIP(pv::launch_sweep(p, s));
+    PV_HIP(pv::launch_sweep(p, num_cus(), s));
     const void* prev = X;
     void* cur = W1;
     p.alpha = 2.0 / a;
@@ -722,7 +759,7 @@ pv_status run_series(pv_lattice* l, int dtype, int nb, double a, double b, int K
         p.acc_in = acc;
         p.acc_out = (k == K) ? out : acc;
         p.ep = pv::EP_ACC_ADD | (k < K ? pv::EP_STORE_Y : 0u);
-        PV_HIP(pv::launch_sweep(p, s));
+        PV_HIP(pv::launch_sweep(p, num_cus(), s));
         prev = cur;
         cur = next;
     }

@@ -10,17 +10,25 @@
 //     acc = eta0 x + eta y   or   acc += eta y     (Chebyshev series, Sec. 4)
 //     partial sums of <x,x>, <x,y>, <y,y>           (fused dots, Sec. 3.2/3.5)
 //
-// Work decomposition: one lane owns one (site, column) pair and computes all
-// n_orb rows of that site; a workgroup of 256 lanes covers 256/nb consecutive
-// sites of one x-row (a "tile").  Lanes with consecutive column index touch
-// consecutive addresses, so wide blocks are coalesced along the column; for
-// nb = 1 a wave touches 64 consecutive sites.  The grid is persistent (a
-// bounded number of workgroups strides over tiles) and XCD-aware: workgroup b
-// runs on XCD b % 8, so each XCD is handed one contiguous eighth of the tiles
-// and the +-y / +-z neighbours a workgroup reads were loaded by workgroups of
+// Work decomposition: one lane owns one element (site s, orbital row o,
+// column c) of the output block.  A workgroup of 256 lanes covers 256
+// consecutive elements, so every load of a neighbour's entries is a fully
+// coalesced wave-wide access of 64 consecutive complex numbers (shifted by
+// the neighbour's site offset; entries of other orbitals of the same site
+// are a fixed lane-dependent offset within the same cache lines).  Because
+// n_orb * nb divides 256, a lane keeps the same (o, c) for the whole launch:
+// its row's stencil coefficients live in registers.  Block structure is
+// compiled in per family: for every neighbour block and entry kind (real,
+// imaginary, complex) the kernel carries "slots" -- the k-th nonzero of that
+// kind in the lane's row -- so the TI stencil costs 12 two-FMA complex
+// updates per row.  The grid is persistent, sized from the occupancy of the
+// instantiation, and XCD-aware: workgroup b runs on XCD b % 8, each XCD takes
+// one contiguous eighth of the tiles, and its resident workgroups sweep that
+// range together, so the +-y / +-z neighbour rows they read were fetched by
 // the same XCD shortly before (same L2).
 #include "pv_kernels.hpp"
 
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
 
@@ -42,6 +50,32 @@ __device__ __forceinline__ void sfor(F&& f) {
 
 constexpr int kBlock = 256;
 
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+
+// Round-up division by a runtime constant (Granlund & Montgomery): exact for
+// every 32-bit numerator.
+struct FastDiv {
+    uint32_t d, m, l;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f{d, 0u, 0u};
+    if (d > 1) {
+        uint32_t l = 0;
+        while ((1ull << l) < d) ++l;
+        f.l = l;
+        f.m = uint32_t((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    }
+    return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    if (f.d == 1) return n;
+    const uint32_t t = __umulhi(n, f.m);
+    return (t + ((n - t) >> 1)) >> (f.l - 1);
+}
+
 template <typename T, typename VT>
 struct KArgs {
     const cplx<T>* x;
@@ -49,50 +83,28 @@ struct KArgs {
     cplx<T>* y;
     const cplx<T>* acc_in;
     cplx<T>* acc_out;
+    const cplx<T>* zsrc;    // z, or x when no column reads z (a valid dummy)
+    const cplx<T>* asrc;    // acc_in, or x when not accumulating
     const VT* V;
     const double* coef;
     const int* offs;
     const double* colp;
     double* partials;
-    int64_t Lx, Ly, Lz;
-    int64_t ntx, ntiles;
+    int64_t n_elem, ntiles;
+    int tpb;
+    // traversal: XCD part k (rows y in [Ly k/8, Ly (k+1)/8), all z) is swept
+    // in slabs of BY rows, each slab plane by plane, each plane row by row
+    const cplx<T>* zero_row;   // rowel zeros: neighbour rows dropped by open BCs read here
+    int rowel, ntx, BY;
+    FastDiv fd_ntx, fd_slab, fd_pf;
+    int Lx, Ly, Lz;
     int px, py, pz;
-    int nb, lognb, tile_sites;
+    int nb, lognb, logsite;
     int n_terms, pot_mode;
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;
 };
-
-// Site index of s + d (d a lattice offset in {-1,0,1}^3), wrapping along
-// periodic dimensions; returns false when an open boundary drops it.
-template <typename A>
-__device__ __forceinline__ bool neighbour(const A& a, int64_t s, int64_t x, int64_t y, int64_t z,
-                                          int dx, int dy, int dz, int64_t& out) {
-    bool ok = true;
-    int64_t o = s;
-    if (dx != 0) {
-        const int64_t xn = x + dx;
-        if (xn < 0) { ok = ok && a.px; o += a.Lx - 1; }
-        else if (xn >= a.Lx) { ok = ok && a.px; o -= a.Lx - 1; }
-        else o += dx;
-    }
-    if (dy != 0) {
-        const int64_t yn = y + dy;
-        if (yn < 0) { ok = ok && a.py; o += (a.Ly - 1) * a.Lx; }
-        else if (yn >= a.Ly) { ok = ok && a.py; o -= (a.Ly - 1) * a.Lx; }
-        else o += dy * a.Lx;
-    }
-    if (dz != 0) {
-        const int64_t zn = z + dz;
-        const int64_t pl = a.Lx * a.Ly;
-        if (zn < 0) { ok = ok && a.pz; o += (a.Lz - 1) * pl; }
-        else if (zn >= a.Lz) { ok = ok && a.pz; o -= (a.Lz - 1) * pl; }
-        else o += dz * pl;
-    }
-    out = o;
-    return ok;
-}
 
 template <typename T>
 __device__ __forceinline__ void mac(T& ar, T& ai, unsigned char k, T cr, T ci, cplx<T> v) {
@@ -101,112 +113,180 @@ __device__ __forceinline__ void mac(T& ar, T& ai, unsigned char k, T cr, T ci, c
     else if (k == CC) { ar += cr * v.re - ci * v.im; ai += cr * v.im + ci * v.re; }
 }
 
-// Column of block t used by at least one row?
+// Slots of a compiled family: for block t (t == NT: off-diagonal part of the
+// on-site block) and entry kind, slot k holds the k-th nonzero of that kind
+// in each row o (q[o] = its column, -1 if the row has fewer).
 template <class P>
-constexpr bool col_used(int t, int q) {
-    for (int o = 0; o < P::NO; ++o)
-        if (P::code[t][o][q] != CZ) return true;
-    return false;
-}
+struct Slots {
+    static constexpr int MAX = 96;
+    int n = 0;
+    int t[MAX] = {};
+    unsigned char kind[MAX] = {};
+    signed char q[MAX][4] = {};
+    constexpr Slots() {
+        constexpr int NO = P::NO;
+        for (int tt = 0; tt <= P::NT; ++tt)
+            for (int kd = 1; kd <= 3; ++kd) {
+                int K = 0;
+                for (int o = 0; o < NO; ++o) {
+                    int cnt = 0;
+                    for (int qq = 0; qq < NO; ++qq)
+                        if (!(tt == P::NT && qq == o) && P::code[tt][o][qq] == kd) ++cnt;
+                    if (cnt > K) K = cnt;
+                }
+                for (int k = 0; k < K; ++k) {
+                    t[n] = tt;
+                    kind[n] = (unsigned char)kd;
+                    for (int o = 0; o < 4; ++o) q[n][o] = -1;
+                    for (int o = 0; o < NO; ++o) {
+                        int cnt = 0;
+                        for (int qq = 0; qq < NO; ++qq)
+                            if (!(tt == P::NT && qq == o) && P::code[tt][o][qq] == kd) {
+                                if (cnt == k) q[n][o] = (signed char)qq;
+                                ++cnt;
+                            }
+                    }
+                    ++n;
+                }
+            }
+    }
+};
 
 // Generic family descriptor: NO orbitals, runtime offsets, dense blocks.
 template <int NO_>
 struct PatGeneric {
     static constexpr int FAMILY = FAM_GENERIC, NO = NO_, NT = 0, DIM = 3;
+    static constexpr int off[1][3] = {{0, 0, 0}};
+    static constexpr unsigned char code[1][NO_][NO_] = {};   // no compiled slots
 };
 
-// H-part of one (site, column): h[o] = sum_t B_t x[s+d_t] + (E0 + V - beta) x[s].
-template <class P, typename T, typename VT>
-__device__ __forceinline__ void apply_site(const KArgs<T, VT>& a, int64_t s, int64_t x, int64_t y,
-                                           int64_t z, int c, const cplx<T> (&xc)[P::NO], T beta,
-                                           T (&hr)[P::NO], T (&hi)[P::NO]) {
-    constexpr int NO = P::NO;
-    const int nb = a.nb;
-    for (int o = 0; o < NO; ++o) { hr[o] = T(0); hi[o] = T(0); }
-    if constexpr (P::FAMILY == FAM_GENERIC) {
-        for (int t = 0; t < a.n_terms; ++t) {
-            int64_t ns;
-            const bool ok = neighbour(a, s, x, y, z, a.offs[3 * t], a.offs[3 * t + 1], a.offs[3 * t + 2], ns);
-            cplx<T> v[NO];
-            for (int q = 0; q < NO; ++q) {
-                v[q] = ok ? a.x[(ns * NO + q) * nb + c] : cplx<T>{T(0), T(0)};
-            }
-            const double* cb = a.coef + (size_t)t * NO * NO * 2;
-            for (int o = 0; o < NO; ++o)
-                for (int q = 0; q < NO; ++q)
-                    mac<T>(hr[o], hi[o], CC, T(cb[(o * NO + q) * 2]), T(cb[(o * NO + q) * 2 + 1]), v[q]);
-        }
-        const double* cb = a.coef + (size_t)a.n_terms * NO * NO * 2;
-        for (int o = 0; o < NO; ++o)
-            for (int q = 0; q < NO; ++q)
-                mac<T>(hr[o], hi[o], CC, T(cb[(o * NO + q) * 2]), T(cb[(o * NO + q) * 2 + 1]), xc[q]);
-    } else {
-        sfor<P::NT>([&](auto tt) {
-            constexpr int t = decltype(tt)::value;
-            int64_t ns;
-            const bool ok = neighbour(a, s, x, y, z, P::off[t][0], P::off[t][1], P::off[t][2], ns);
-            sfor<NO>([&](auto qq) {
-                constexpr int q = decltype(qq)::value;
-                if constexpr (col_used<P>(t, q)) {
-                    const cplx<T> v = ok ? a.x[(ns * NO + q) * nb + c] : cplx<T>{T(0), T(0)};
-                    sfor<NO>([&](auto oo) {
-                        constexpr int o = decltype(oo)::value;
-                        constexpr unsigned char k = P::code[t][o][q];
-                        if constexpr (k != CZ) {
-                            const double* e = a.coef + ((t * NO + o) * NO + q) * 2;
-                            mac<T>(hr[o], hi[o], k, T(e[0]), T(e[1]), v);
-                        }
-                    });
-                }
-            });
-        });
-        constexpr int t = P::NT;
-        sfor<NO>([&](auto oo) {
-            constexpr int o = decltype(oo)::value;
-            sfor<NO>([&](auto qq) {
-                constexpr int q = decltype(qq)::value;
-                constexpr unsigned char k = P::code[t][o][q];
-                if constexpr (o != q && k != CZ) {
-                    const double* e = a.coef + ((t * NO + o) * NO + q) * 2;
-                    mac<T>(hr[o], hi[o], k, T(e[0]), T(e[1]), xc[q]);
-                }
-            });
-        });
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_nt(const cplx<T>* p) {
+    const vec2<T> v = __builtin_nontemporal_load(reinterpret_cast<const vec2<T>*>(p));
+    return cplx<T>{v.x, v.y};
+}
+
+template <typename T>
+__device__ __forceinline__ void st_nt(cplx<T>* p, T re, T im) {
+    vec2<T> v;
+    v.x = re;
+    v.y = im;
+    __builtin_nontemporal_store(v, reinterpret_cast<vec2<T>*>(p));
+}
+
+// Loads at a 32-bit byte offset from a (workgroup-uniform) row pointer.
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_row(const cplx<T>* row, uint32_t boff) {
+    return *reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(row) + boff);
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_row_nt(const cplx<T>* row, uint32_t boff) {
+    return ld_nt(reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(row) + boff));
+}
+
+// Epilogue shared by every family: y = alpha h + gamma z, store / accumulate,
+// FP64 partial dots of (x, y).  zv and av were loaded at the top of the
+// element (unconditionally, from a valid address) so that every load of an
+// element is in flight at the same time; gamma == 0 selects zero instead of
+// gamma * z, so z is never used for such columns.
+template <typename T, typename VT>
+__device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, cplx<T> xc, cplx<T> zv, cplx<T> av,
+                                         T hr, T hi, T alT, T gaT, T er, T ei, T e0r, T e0i, double& dxx,
+                                         double& dxr, double& dxi, double& dyy) {
+    T yr = alT * hr, yi = alT * hi;
+    yr += (gaT != T(0)) ? gaT * zv.re : T(0);
+    yi += (gaT != T(0)) ? gaT * zv.im : T(0);
+    const unsigned ep = a.ep;
+    if (ep & EP_STORE_Y) st_nt(a.y + e, yr, yi);
+    if (ep & EP_ACC_INIT) {
+        st_nt(a.acc_out + e, e0r * xc.re - e0i * xc.im + er * yr - ei * yi,
+              e0r * xc.im + e0i * xc.re + er * yi + ei * yr);
+    } else if (ep & EP_ACC_ADD) {
+        st_nt(a.acc_out + e, av.re + er * yr - ei * yi, av.im + er * yi + ei * yr);
     }
-    // diagonal: on-site diagonal (specialised families), field, shift
-    for (int o = 0; o < NO; ++o) {
-        T d = -beta;
-        T di = T(0);
-        if constexpr (P::FAMILY != FAM_GENERIC) {
-            const double* e = a.coef + ((P::NT * NO + o) * NO + o) * 2;
-            d += T(e[0]);
-            di = T(e[1]);
-        }
-        if (a.V != nullptr) {
-            if (a.pot_mode == 1) d += T(a.V[s]);
-            else if (a.pot_mode == 2) d += T(a.V[s * NO + o]);
-        }
-        hr[o] += d * xc[o].re - di * xc[o].im;
-        hi[o] += d * xc[o].im + di * xc[o].re;
+    if (ep & EP_DOTS) {
+        const double xr = double(xc.re), xi = double(xc.im);
+        const double dyr = double(yr), dyi = double(yi);
+        dxx += xr * xr + xi * xi;
+        dxr += xr * dyr + xi * dyi;
+        dxi += xr * dyi - xi * dyr;
+        dyy += dyr * dyr + dyi * dyi;
     }
 }
 
+template <typename T>
+__device__ __forceinline__ cplx<T> zero_unless(bool ok, cplx<T> v) {
+    return cplx<T>{ok ? v.re : T(0), ok ? v.im : T(0)};
+}
+
+#ifndef PV_SWEEP_WAVES_PER_EU
+#define PV_SWEEP_WAVES_PER_EU 1
+#endif
+
+// Row (y + dy, z + dz) of row (y, z), wrapped along periodic dimensions;
+// false when an open boundary drops it.  Uniform over a tile.
+template <typename A>
+__device__ __forceinline__ bool neighbour_row(const A& a, int y, int z, int dy, int dz, int& row) {
+    int yn = y + dy, zn = z + dz;
+    bool ok = true;
+    if (dy) {
+        const bool lo = yn < 0, hi = yn >= a.Ly;
+        ok = ok && (a.py || !(lo || hi));
+        yn += lo ? a.Ly : (hi ? -a.Ly : 0);
+    }
+    if (dz) {
+        const bool lo = zn < 0, hi = zn >= a.Lz;
+        ok = ok && (a.pz || !(lo || hi));
+        zn += lo ? a.Lz : (hi ? -a.Lz : 0);
+    }
+    row = zn * a.Ly + yn;
+    return ok;
+}
+
+__device__ __forceinline__ FastDiv make_fastdiv_dev(uint32_t d) {
+    FastDiv f{d, 0u, 0u};
+    if (d > 1) {
+        const uint32_t l = 32u - __clz(d - 1u);
+        f.l = l;
+        f.m = uint32_t((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    }
+    return f;
+}
+
+// Element offset of the x-neighbour (x + dx) inside its row, relative to the
+// lane's own element xe; false when an open boundary drops it.
+template <typename A>
+__device__ __forceinline__ bool x_shift(const A& a, int x, int dx, int& dxe) {
+    const int site = 1 << a.logsite;
+    if (dx == 0) { dxe = 0; return true; }
+    const int xn = x + dx;
+    if (xn < 0) { dxe = (a.Lx - 1) * site; return a.px; }
+    if (xn >= a.Lx) { dxe = -(a.Lx - 1) * site; return a.px; }
+    dxe = dx * site;
+    return true;
+}
+
 template <class P, typename T, typename VT>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(KArgs<T, VT> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_SWEEP_WAVES_PER_EU)))
+void sweep_kernel(KArgs<T, VT> a) {
     constexpr int NO = P::NO;
     const int tid = threadIdx.x;
     const int nb = a.nb;
     const int c = tid & (nb - 1);
-    const int sl = tid >> a.lognb;
+    const int o = (tid >> a.lognb) & (NO - 1);
 
-    // XCD-aware tile schedule: workgroup b runs on XCD b % 8.
+    // Workgroup b runs on XCD b % 8 (the hardware deals workgroups out
+    // round-robin); XCD k owns the rows y in [Ly k/8, Ly (k+1)/8) for every z
+    // and its workgroups sweep them slab by slab, so the +-y and +-z
+    // neighbour rows a tile reads were fetched into the same L2 shortly
+    // before.
     const int b = blockIdx.x;
-    const int xcd = b & 7;
-    const int local = b >> 3;
-    const int gx = gridDim.x >> 3;
-    const int64_t per = (a.ntiles + 7) >> 3;
-    const int64_t t0 = per * xcd;
-    const int64_t t1 = min(t0 + per, a.ntiles);
+    const int k = b & 7;
+    const int ny = int((int64_t)a.Ly * (k + 1) / 8) - int((int64_t)a.Ly * k / 8);
+    const int64_t ntl = (int64_t)a.ntx * ny * a.Lz;
+    const int64_t t0 = (int64_t)(b >> 3) * a.tpb;
+    const int64_t t1 = min(t0 + a.tpb, ntl);
 
     double al = a.alpha, be = a.beta, ga = a.gamma;
     if (a.colp != nullptr) {
@@ -216,54 +296,127 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(KArgs<T, VT> a) {
     }
     const T alT = T(al), beT = T(be), gaT = T(ga);
     const T er = T(a.eta_re), ei = T(a.eta_im), e0r = T(a.eta0_re), e0i = T(a.eta0_im);
-    const unsigned ep = a.ep;
+
+    // diagonal of the on-site block for this lane's row
+    const int nt_onsite = (P::FAMILY != FAM_GENERIC) ? P::NT : a.n_terms;
+    const T dgr = T(a.coef[(((size_t)nt_onsite * NO + o) * NO + o) * 2]);
+    const T dgi = T(a.coef[(((size_t)nt_onsite * NO + o) * NO + o) * 2 + 1]);
 
     double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
 
-    for (int64_t t = t0 + local; t < t1; t += gx) {
-        const int64_t xt = t % a.ntx;
-        const int64_t row = t / a.ntx;
-        const int64_t yy = row % a.Ly;
-        const int64_t zz = row / a.Ly;
-        const int64_t xx = xt * a.tile_sites + sl;
-        if (xx >= a.Lx) continue;  // ragged end of an x-row
-        const int64_t s = xx + a.Lx * (yy + a.Ly * zz);
-        const int64_t base = s * NO * nb + c;
-
-        cplx<T> xc[NO];
-        for (int o = 0; o < NO; ++o) xc[o] = a.x[base + o * nb];
-        T hr[NO], hi[NO];
-        apply_site<P, T, VT>(a, s, xx, yy, zz, c, xc, beT, hr, hi);
-
-        for (int o = 0; o < NO; ++o) {
-            const int64_t idx = base + o * nb;
-            T yr = alT * hr[o], yi = alT * hi[o];
-            if (gaT != T(0)) {
-                const cplx<T> zv = a.z[idx];
-                yr += gaT * zv.re;
-                yi += gaT * zv.im;
-            }
-            if (ep & EP_STORE_Y) a.y[idx] = cplx<T>{yr, yi};
-            if (ep & EP_ACC_INIT) {
-                a.acc_out[idx] = cplx<T>{e0r * xc[o].re - e0i * xc[o].im + er * yr - ei * yi,
-                                         e0r * xc[o].im + e0i * xc[o].re + er * yi + ei * yr};
-            } else if (ep & EP_ACC_ADD) {
-                const cplx<T> av = a.acc_in[idx];
-                a.acc_out[idx] = cplx<T>{av.re + er * yr - ei * yi, av.im + er * yi + ei * yr};
-            }
-            if (ep & EP_DOTS) {
-                const double xr = double(xc[o].re), xi = double(xc[o].im);
-                const double dyr = double(yr), dyi = double(yi);
-                dxx += xr * xr + xi * xi;
-                dxr += xr * dyr + xi * dyi;
-                dxi += xr * dyi - xi * dyr;
-                dyy += dyr * dyr + dyi * dyi;
-            }
+    // per-lane slot data of compiled families
+    static constexpr Slots<P> S{};
+    constexpr int NS = (P::FAMILY != FAM_GENERIC) ? S.n : 0;
+    T cre[NS > 0 ? NS : 1], cim[NS > 0 ? NS : 1];
+    int dq[NS > 0 ? NS : 1];
+    sfor<NS>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        int q = S.q[j][0];
+        if constexpr (NO > 1) { if (o == 1) q = S.q[j][1]; }
+        if constexpr (NO > 2) { if (o == 2) q = S.q[j][2]; if (o == 3) q = S.q[j][3]; }
+        if (q >= 0) {
+            const double* e = a.coef + ((S.t[j] * NO + o) * NO + q) * 2;
+            cre[j] = T(e[0]);
+            cim[j] = T(e[1]);
+            dq[j] = (q - o) * nb;
+        } else {
+            cre[j] = T(0);
+            cim[j] = T(0);
+            dq[j] = 0;
         }
+    });
+
+    constexpr uint32_t ES = sizeof(cplx<T>);
+    const int y0 = int((int64_t)a.Ly * k / 8);
+    for (int64_t t = t0; t < t1; ++t) {
+        // tile -> (row, x-tile): uniform over the workgroup.  Part k is swept
+        // in slabs of BY rows; a slab plane by plane (z), a plane row by row.
+        const uint32_t tt32 = uint32_t(t);
+        const uint32_t slab_tiles = uint32_t(a.ntx) * uint32_t(a.BY) * uint32_t(a.Lz);
+        const uint32_t yb = fdiv(tt32, a.fd_slab);
+        const uint32_t rr = tt32 - yb * slab_tiles;
+        const int by = min(a.BY, ny - int(yb) * a.BY);
+        const uint32_t ptiles = uint32_t(a.ntx) * uint32_t(by);
+        const uint32_t zz = (by == a.BY) ? fdiv(rr, a.fd_pf) : fdiv(rr, make_fastdiv_dev(ptiles));
+        const uint32_t r2 = rr - zz * ptiles;
+        const uint32_t yy = fdiv(r2, a.fd_ntx);
+        const int xt = int(r2 - yy * uint32_t(a.ntx));
+        const int y = y0 + int(yb) * a.BY + int(yy);
+        const int z = int(zz);
+        const int row = z * a.Ly + y;
+        const int xe = xt * kBlock + tid;           // element inside the row
+        if (xe >= a.rowel) continue;                // ragged end of the row
+        const int x = xe >> a.logsite;
+        const int64_t rb = (int64_t)row * a.rowel;
+        const uint32_t off0 = uint32_t(xe) * ES;    // byte offset inside a row
+        const cplx<T>* xrow = a.x + rb;
+        const cplx<T> xc = ld_row(xrow, off0);
+        const cplx<T> zv = ld_row_nt(a.zsrc + rb, off0);
+        cplx<T> av{T(0), T(0)};
+        if (a.ep & EP_ACC_ADD) av = ld_row_nt(a.acc_in + rb, off0);
+        T vs = T(0);
+        if (a.V != nullptr) {
+            const VT* vrow = a.V + (int64_t)row * a.Lx * (a.pot_mode == 1 ? 1 : NO);
+            vs = T(a.pot_mode == 1 ? vrow[x] : vrow[x * NO + o]);
+        }
+        T hr, hi;
+        const T d = dgr - beT + vs;
+        hr = d * xc.re - dgi * xc.im;
+        hi = d * xc.im + dgi * xc.re;
+        if constexpr (P::FAMILY != FAM_GENERIC) {
+            cplx<T> nv[NS > 0 ? NS : 1];
+            bool okt[P::NT > 0 ? P::NT : 1];
+            sfor<P::NT>([&](auto tt) {
+                constexpr int tb = decltype(tt)::value;
+                constexpr int dy = P::off[tb][1], dz = P::off[tb][2];
+                const cplx<T>* prow = xrow;
+                if constexpr (dy != 0 || dz != 0) {
+                    int nrow;
+                    const bool rok = neighbour_row(a, y, z, dy, dz, nrow);
+                    prow = rok ? a.x + (int64_t)nrow * a.rowel : a.zero_row;
+                }
+                int dxe;
+                okt[tb] = x_shift(a, x, P::off[tb][0], dxe);
+                sfor<NS>([&](auto jj) {
+                    constexpr int j = decltype(jj)::value;
+                    if constexpr (S.t[j] == tb) nv[j] = ld_row(prow, uint32_t(xe + dxe + dq[j]) * ES);
+                });
+            });
+            sfor<NS>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                if constexpr (S.t[j] == P::NT) nv[j] = ld_row(xrow, uint32_t(xe + dq[j]) * ES);
+            });
+            sfor<NS>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                if constexpr (S.t[j] < P::NT && P::off[S.t[j] < P::NT ? S.t[j] : 0][0] != 0) {
+                    // x neighbour: lane-dependent open boundary
+                    if (!a.px) nv[j] = zero_unless(okt[S.t[j]], nv[j]);
+                }
+                mac<T>(hr, hi, S.kind[j], cre[j], cim[j], nv[j]);
+            });
+        } else {
+            const int own = xe - o * nb;            // orbital-0 element of this site and column
+            for (int tb = 0; tb < a.n_terms; ++tb) {
+                const int dy = a.offs[3 * tb + 1], dz = a.offs[3 * tb + 2];
+                int nrow;
+                const bool rok = neighbour_row(a, y, z, dy, dz, nrow);
+                const cplx<T>* prow = rok ? a.x + (int64_t)nrow * a.rowel : a.zero_row;
+                int dxe;
+                const bool ok = x_shift(a, x, a.offs[3 * tb], dxe);
+                const double* cb = a.coef + ((size_t)tb * NO + o) * NO * 2;
+                for (int q = 0; q < NO; ++q)
+                    mac<T>(hr, hi, CC, T(cb[2 * q]), T(cb[2 * q + 1]),
+                           zero_unless(ok, ld_row(prow, uint32_t(own + dxe + q * nb) * ES)));
+            }
+            const double* cb = a.coef + ((size_t)a.n_terms * NO + o) * NO * 2;
+            for (int q = 0; q < NO; ++q)
+                if (q != o) mac<T>(hr, hi, CC, T(cb[2 * q]), T(cb[2 * q + 1]), ld_row(xrow, uint32_t(own + q * nb) * ES));
+        }
+        epilogue(a, rb + xe, xc, zv, av, hr, hi, alT, gaT, er, ei, e0r, e0i, dxx, dxr, dxi, dyy);
     }
 
-    if (ep & EP_DOTS) {
-        // lanes with the same column: lane = site * nb + c inside the wave
+    if (a.ep & EP_DOTS) {
+        // lanes with the same column: lane = (site * NO + o) * nb + c inside the wave
         for (int m = nb; m < 64; m <<= 1) {
             dxx += __shfl_xor(dxx, m);
             dxr += __shfl_xor(dxr, m);
@@ -288,22 +441,52 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(KArgs<T, VT> a) {
     }
 }
 
+// Tiles per workgroup: enough workgroups to keep every CU busy for several
+// rounds (>= 64 per CU), at most 16 tiles each (bounds the partial-dot
+// buffer).  PV_TILES_PER_BLOCK overrides it for tuning runs.
+int tiles_per_block(int64_t ntiles) {
+    static int forced = -2;
+    if (forced == -2) {
+        const char* e = getenv("PV_TILES_PER_BLOCK");
+        forced = e ? atoi(e) : -1;
+    }
+    if (forced > 0) return forced;
+    int64_t tpb = ntiles / (256 * 64);
+    if (tpb < 1) tpb = 1;
+    if (tpb > 16) tpb = 16;
+    return int(tpb);
+}
+
 template <class P, typename T, typename VT>
-hipError_t launch_typed(const SweepParams& p, hipStream_t s) {
+int occupancy_blocks() {
+    static int cached = -1;
+    if (cached < 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<P, T, VT>, kBlock, 0) != hipSuccess || n < 1)
+            n = 1;
+        cached = n;
+    }
+    return cached;
+}
+
+template <class P, typename T, typename VT>
+hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
     KArgs<T, VT> a;
     a.x = static_cast<const cplx<T>*>(p.x);
     a.z = static_cast<const cplx<T>*>(p.z);
     a.y = static_cast<cplx<T>*>(p.y);
     a.acc_in = static_cast<const cplx<T>*>(p.acc_in);
     a.acc_out = static_cast<cplx<T>*>(p.acc_out);
+    a.zsrc = a.z ? a.z : a.x;
+    a.asrc = ((p.ep & EP_ACC_ADD) && a.acc_in) ? a.acc_in : a.x;
     a.V = static_cast<const VT*>(p.V);
     a.coef = p.coef;
     a.offs = p.offs;
     a.colp = p.colp;
     a.partials = p.partials;
-    a.Lx = p.L[0];
-    a.Ly = p.L[1];
-    a.Lz = p.L[2];
+    a.Lx = int(p.L[0]);
+    a.Ly = int(p.L[1]);
+    a.Lz = int(p.L[2]);
     a.px = p.periodic[0] != 0;
     a.py = p.periodic[1] != 0;
     a.pz = p.periodic[2] != 0;
@@ -311,9 +494,18 @@ hipError_t launch_typed(const SweepParams& p, hipStream_t s) {
     int lg = 0;
     while ((1 << lg) < p.nb) ++lg;
     a.lognb = lg;
-    a.tile_sites = kBlock / p.nb;
-    a.ntx = (p.L[0] + a.tile_sites - 1) / a.tile_sites;
-    a.ntiles = a.ntx * p.L[1] * p.L[2];
+    int lo = 0;
+    while ((1 << lo) < P::NO) ++lo;
+    a.logsite = lg + lo;
+    a.n_elem = p.L[0] * p.L[1] * p.L[2] * P::NO * p.nb;
+    a.rowel = int(p.L[0] * P::NO * p.nb);
+    a.ntx = (a.rowel + kBlock - 1) / kBlock;
+    a.fd_ntx = make_fastdiv(uint32_t(a.ntx));
+    a.BY = p.slab_rows;
+    a.fd_slab = make_fastdiv(uint32_t(a.ntx) * uint32_t(a.BY) * uint32_t(p.L[2]));
+    a.fd_pf = make_fastdiv(uint32_t(a.ntx) * uint32_t(a.BY));
+    a.zero_row = static_cast<const cplx<T>*>(p.zero_row);
+    a.ntiles = int64_t(a.ntx) * ((p.L[1] + 7) / 8) * p.L[2];   // tiles of the largest XCD part
     a.n_terms = p.n_terms;
     a.pot_mode = p.pot_mode;
     a.alpha = p.alpha;
@@ -324,18 +516,21 @@ hipError_t launch_typed(const SweepParams& p, hipStream_t s) {
     a.eta0_re = p.eta0_re;
     a.eta0_im = p.eta0_im;
     a.ep = p.ep;
+    (void)num_cus;
+    a.tpb = tiles_per_block(a.ntiles * 8);
+    p.grid = int(8 * ((a.ntiles + a.tpb - 1) / a.tpb));
     hipLaunchKernelGGL((sweep_kernel<P, T, VT>), dim3(p.grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 template <class P>
-hipError_t launch_family(const SweepParams& p, hipStream_t s) {
+hipError_t launch_family(SweepParams& p, int num_cus, hipStream_t s) {
     if (p.dtype == 0) {
         if (p.vtype != 0) return hipErrorInvalidValue;
-        return launch_typed<P, double, double>(p, s);
+        return launch_typed<P, double, double>(p, num_cus, s);
     }
-    if (p.vtype == 0) return launch_typed<P, float, double>(p, s);
-    return launch_typed<P, float, float>(p, s);
+    if (p.vtype == 0) return launch_typed<P, float, double>(p, num_cus, s);
+    return launch_typed<P, float, float>(p, num_cus, s);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -487,38 +682,47 @@ __global__ __launch_bounds__(kBlock) void rotate_kernel(const cplx<T>* __restric
     }
 }
 
-__global__ __launch_bounds__(kBlock) void copy_kernel(const uint4* __restrict__ src,
-                                                      uint4* __restrict__ dst, int64_t n) {
-    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
-        dst[k] = src[k];
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+
+// Streaming copy: each lane moves 4 x 16 B per iteration with all loads
+// issued before the stores; nontemporal on both sides.
+__global__ __launch_bounds__(kBlock) void copy_kernel(const u32x4* __restrict__ src,
+                                                      u32x4* __restrict__ dst, int64_t n) {
+    const int64_t chunk = 4 * (int64_t)kBlock;
+    for (int64_t base = blockIdx.x * chunk; base < n; base += (int64_t)gridDim.x * chunk) {
+        u32x4 r[4];
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            if (i < n) r[k] = __builtin_nontemporal_load(src + i);
+        }
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            if (i < n) __builtin_nontemporal_store(r[k], dst + i);
+        }
+    }
 }
 
 }  // namespace
 
-int sweep_grid(const SweepParams& p, int num_cus) {
-    const int tile_sites = kBlock / p.nb;
-    const int64_t ntx = (p.L[0] + tile_sites - 1) / tile_sites;
-    const int64_t ntiles = ntx * p.L[1] * p.L[2];
-    int64_t g = ntiles;
-    const int64_t cap = (int64_t)num_cus * 8;
-    if (g > cap) g = cap;
-    g = (g + 7) / 8 * 8;
-    if (g < 8) g = 8;
-    return int(g);
+int64_t sweep_grid_max(const int64_t L[3], int n_orb, int nb) {
+    const int64_t rowel = L[0] * n_orb * nb;
+    const int64_t ntiles = (rowel + kBlock - 1) / kBlock * ((L[1] + 7) / 8) * L[2];
+    const int tpb = tiles_per_block(ntiles * 8);
+    return 8 * ((ntiles + tpb - 1) / tpb);
 }
 
-hipError_t launch_sweep(const SweepParams& p, hipStream_t s) {
+hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s) {
     switch (p.family) {
-        case FAM_TI: return launch_family<PatTI>(p, s);
-        case FAM_GRAPHENE2: return launch_family<PatGraphene2>(p, s);
-        case FAM_GRAPHENE4: return launch_family<PatGraphene4>(p, s);
-        case FAM_WEYL: return launch_family<PatWeyl>(p, s);
+        case FAM_TI: return launch_family<PatTI>(p, num_cus, s);
+        case FAM_GRAPHENE2: return launch_family<PatGraphene2>(p, num_cus, s);
+        case FAM_GRAPHENE4: return launch_family<PatGraphene4>(p, num_cus, s);
+        case FAM_WEYL: return launch_family<PatWeyl>(p, num_cus, s);
         default: break;
     }
     switch (p.n_orb) {
-        case 1: return launch_family<PatGeneric<1>>(p, s);
-        case 2: return launch_family<PatGeneric<2>>(p, s);
-        case 4: return launch_family<PatGeneric<4>>(p, s);
+        case 1: return launch_family<PatGeneric<1>>(p, num_cus, s);
+        case 2: return launch_family<PatGeneric<2>>(p, num_cus, s);
+        case 4: return launch_family<PatGeneric<4>>(p, num_cus, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -588,8 +792,11 @@ hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X,
 
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const int64_t n = int64_t(bytes / 16);
-    hipLaunchKernelGGL(copy_kernel, dim3(elementwise_grid(n)), dim3(kBlock), 0, s,
-                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+    int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(copy_kernel, dim3(int(g)), dim3(kBlock), 0, s, static_cast<const u32x4*>(src),
+                       static_cast<u32x4*>(dst), n);
     return hipGetLastError();
 }
 

@@ -51,17 +51,20 @@ struct SweepParams {
     const double* coef;   // device: [(n_terms + 1)][n_orb][n_orb][2], onsite last
     const int* offs;      // device: [n_terms][3] (generic family only)
     const double* colp;   // device: [nb][3] per-column alpha, beta, gamma or NULL
+    const void* zero_row;   // device zeros, >= L[0]*n_orb*nb elements
+    int slab_rows;          // rows per y-slab of the sweep order
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;
     double* partials;     // [grid][nb][4] when EP_DOTS
-    int grid;             // number of workgroups (multiple of 8)
+    int grid;             // set by launch_sweep: number of workgroups
 };
 
-// Number of workgroups the sweep uses for a lattice / nb (a multiple of 8,
-// enough to fill every CU, bounded by the number of tiles).
-int sweep_grid(const SweepParams& p, int num_cus);
-hipError_t launch_sweep(const SweepParams& p, hipStream_t s);
+// Number of workgroups a sweep of an nb-wide block over the lattice uses
+// (partial-dot buffers are sized with it); launch_sweep stores the same
+// number in p.grid.
+int64_t sweep_grid_max(const int64_t L[3], int n_orb, int nb);
+hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s);
 
 // Fixed-order reduction of [grid][nb][4] partials.
 //   mode 0: dots[c][0..3] = sums
