@@ -219,16 +219,47 @@ pv_status pv_cheb_tp_coefficients(double a, double dt, int M, double *coef);
  * Tall-skinny products with FP64 accumulation (Rayleigh-Ritz of Sec. 4.2):
  *   pv_gram:         G[i][j] = sum_r conj(X[r][i]) Y[r][j]
  *                    X [rows][nx], Y [rows][ny], G device complex128 [nx][ny]
- *   pv_block_rotate: Y[r][j] = sum_i X[r][i] Q[i][j]
+ *   pv_block_rotate: Y[r][j] = (accumulate ? Y[r][j] : 0) + sum_i X[r][i] Q[i][j]
  *                    X [rows][nx], Q device complex128 [nx][ny], Y [rows][ny]
- *                    (Y must not overlap X)
+ *                    (Y must not overlap X); sums in FP64
  * nx, ny in 1..PV_MAX_NB.
  */
 size_t pv_gram_workspace_size(int64_t rows, int nx, int ny);
 pv_status pv_gram(int dtype, int64_t rows, int nx, int ny, const void *X, const void *Y,
                   double *G, void *work, size_t work_bytes, void *stream);
 pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, const void *X,
-                          const double *Q, void *Y, void *stream);
+                          const double *Q, int accumulate, void *Y, void *stream);
+
+/*
+ * Chebyshev filter diagonalisation, Sec. 4.2: interior eigenpairs of H in the
+ * window [lam_l, lam_r] (energy units, inside [b - a, b + a]).  Each
+ * iteration filters the search space X (ns = bw * nblk columns, stored as
+ * nblk device blocks [rows][bw] back to back, i.e. [nblk][rows][bw]) with
+ *     p(H~) = sum_{k=0}^{degree} g_k c_k T_k(H~),
+ *     c_0 = (acos x_l - acos x_r)/pi, c_k = 2 (sin(k acos x_l) - sin(k acos x_r))/(k pi),
+ *     g_k Jackson damping, x = (lam - b)/a,
+ * orthonormalises it with Cholesky QR applied twice (FP64 Gram and host
+ * factorisation), and performs Rayleigh-Ritz: H_S = Q^H H Q (FP64), host
+ * Jacobi eigensolver, X <- Q U with Ritz pairs ordered by |theta - centre|,
+ * residuals ||H x_i - theta_i x_i|| from a shifted sweep with fused <y,y>.
+ * Stops when the n_target Ritz pairs closest to the window centre lie in the
+ * window with residual <= tol, or after max_iter iterations
+ * (PV_ERR_NOT_CONVERGED; outputs still filled).  Synchronises the stream.
+ * In/out: X (start block -> Ritz vectors); out: theta[ns], res[ns] (host),
+ * *n_conv (converged among the n_target), *iters.
+ */
+size_t pv_chebfd_workspace_size(const pv_lattice *lat, int dtype, int bw, int nblk);
+pv_status pv_chebfd(pv_lattice *lat, int dtype, int bw, int nblk, double a, double b,
+                    double lam_l, double lam_r, int degree, int n_target, double tol,
+                    int max_iter, void *X, double *theta, double *res, int *n_conv, int *iters,
+                    void *work, size_t work_bytes, void *stream);
+/* g_k c_k, k = 0..K, of the ChebFD window filter (host). */
+pv_status pv_chebfd_filter_coefficients(double lam_l, double lam_r, double a, double b, int K,
+                                        double *coef);
+/* Host Hermitian eigensolver used by Rayleigh-Ritz (cyclic Jacobi, FP64):
+ * A complex row-major [n][n] (re, im), w ascending [n], V [n][n] complex with
+ * the eigenvectors as columns. */
+pv_status pv_host_heev(int n, const double *A, double *w, double *V);
 
 /* Scalar helper used to measure achievable bandwidth: dst = src (bytes, a
  * multiple of 16), a plain streaming copy kernel. */

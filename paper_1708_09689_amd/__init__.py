@@ -67,8 +67,12 @@ SIGNATURES = {
     "pv_cheb_tp_coefficients": (_i, [_d, _d, _i, _dp]),
     "pv_gram_workspace_size": (_sz, [_i64, _i, _i]),
     "pv_gram": (_i, [_i, _i64, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
-    "pv_block_rotate": (_i, [_i, _i64, _i, _i, _vp, _vp, _vp, _vp]),
+    "pv_block_rotate": (_i, [_i, _i64, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "pv_stream_copy": (_i, [_vp, _vp, _sz, _vp]),
+    "pv_chebfd_workspace_size": (_sz, [_vp, _i, _i, _i]),
+    "pv_chebfd": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _i, _vp, _dp, _dp, _ip, _ip, _vp, _sz, _vp]),
+    "pv_chebfd_filter_coefficients": (_i, [_d, _d, _d, _d, _i, _dp]),
+    "pv_host_heev": (_i, [_i, _dp, _dp, _dp]),
 }
 
 _lib = None
@@ -318,13 +322,13 @@ def pv_gram(X, Y, G=None, rows=None):
     return G
 
 
-def pv_block_rotate(X, Q, Y, rows=None):
-    """Y = X Q, Q device complex128 [nx][ny]."""
+def pv_block_rotate(X, Q, Y, rows=None, accumulate=False):
+    """Y = X Q (+ Y when accumulate), Q device complex128 [nx][ny]."""
     rows = rows if rows is not None else X.shape[0]
     nx, ny = X.numel() // rows, Y.numel() // rows
     dt = _dtype_code(X)
     _check(lib().pv_block_rotate(dt, rows, nx, ny, _vec(X, "X", rows, nx), ctypes.c_void_p(Q.data_ptr()),
-                                 _vec(Y, "Y", rows, ny, dt), _stream()))
+                                 1 if accumulate else 0, _vec(Y, "Y", rows, ny, dt), _stream()))
     return Y
 
 
@@ -334,3 +338,37 @@ def pv_stream_copy(src, dst):
         raise ValueError("dst too small")
     _check(lib().pv_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, _stream()))
     return dst
+
+
+def pv_chebfd_filter_coefficients(lam_l, lam_r, a, b, K):
+    out = np.zeros(K + 1)
+    _check(lib().pv_chebfd_filter_coefficients(lam_l, lam_r, a, b, K, _dptr(out)))
+    return out
+
+
+def pv_host_heev(A):
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    n = A.shape[0]
+    a = np.ascontiguousarray(np.stack([A.real, A.imag], axis=-1).reshape(-1))
+    w = np.zeros(n)
+    V = np.zeros(2 * n * n)
+    _check(lib().pv_host_heev(n, _dptr(a), _dptr(w), _dptr(V)))
+    return w, (V[0::2] + 1j * V[1::2]).reshape(n, n)
+
+
+def pv_chebfd(lat: Lattice, X, bw: int, a: float, b: float, lam_l: float, lam_r: float, degree: int,
+              n_target: int, tol: float, max_iter: int = 20, raise_on_fail: bool = True):
+    """Chebyshev filter diagonalisation.  X: device block [nblk, rows, bw]
+    (start vectors in, Ritz vectors out).  Returns (theta, res, n_conv, iters)."""
+    nblk = X.numel() // (lat.n_rows * bw)
+    dt = _dtype_code(X)
+    ns = bw * nblk
+    theta, res = np.zeros(ns), np.zeros(ns)
+    nc, it = ctypes.c_int(), ctypes.c_int()
+    ws = _workspace(lib().pv_chebfd_workspace_size(lat.handle, dt, bw, nblk), X.device)
+    st = lib().pv_chebfd(lat.handle, dt, bw, nblk, a, b, lam_l, lam_r, degree, n_target, tol, max_iter,
+                         _vec(X, "X", lat.n_rows, ns), _dptr(theta), _dptr(res), ctypes.byref(nc),
+                         ctypes.byref(it), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream())
+    if st != 0 and (raise_on_fail or st != 9):
+        _check(st)
+    return theta, res, nc.value, it.value

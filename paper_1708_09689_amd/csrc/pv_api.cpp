@@ -886,8 +886,8 @@ extern "C" pv_status pv_gram(int dtype, int64_t rows, int nx, int ny, const void
     return PV_OK;
 }
 
-extern "C" pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q, void* Y,
-                                     void* stream) {
+extern "C" pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q,
+                                     int accumulate, void* Y, void* stream) {
     if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "bad dtype");
     if (rows < 1 || nx < 1 || ny < 1 || nx > PV_MAX_NB || ny > PV_MAX_NB)
         return fail(PV_ERR_INVALID_ARG, "need rows >= 1 and 1 <= nx, ny <= %d", PV_MAX_NB);
@@ -898,7 +898,7 @@ extern "C" pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, co
     if (X == Y) return fail(PV_ERR_INVALID_ARG, "X and Y must differ");
     int dev;
     if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
-    PV_HIP(pv::launch_rotate(dtype, rows, nx, ny, X, Q, Y, static_cast<hipStream_t>(stream)));
+    PV_HIP(pv::launch_rotate(dtype, rows, nx, ny, X, Q, accumulate ? 1 : 0, Y, static_cast<hipStream_t>(stream)));
     return PV_OK;
 }
 
@@ -908,5 +908,235 @@ extern "C" pv_status pv_stream_copy(const void* src, void* dst, size_t bytes, vo
     int dev;
     if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
     PV_HIP(pv::launch_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev filter diagonalisation (Sec. 4.2)
+// ---------------------------------------------------------------------------
+#include "pv_dense.hpp"
+
+extern "C" pv_status pv_host_heev(int n, const double* A, double* w, double* V) {
+    if (n < 1 || !A || !w || !V) return fail(PV_ERR_INVALID_ARG, "pv_host_heev: bad arguments");
+    std::vector<pvd::cd> M((size_t)n * n), U;
+    for (size_t i = 0; i < M.size(); ++i) M[i] = pvd::cd(A[2 * i], A[2 * i + 1]);
+    std::vector<double> ev;
+    pvd::heev_jacobi(n, M, ev, U);
+    for (int i = 0; i < n; ++i) w[i] = ev[i];
+    for (size_t i = 0; i < U.size(); ++i) {
+        V[2 * i] = U[i].real();
+        V[2 * i + 1] = U[i].imag();
+    }
+    return PV_OK;
+}
+
+extern "C" pv_status pv_chebfd_filter_coefficients(double lam_l, double lam_r, double a, double b, int K,
+                                                   double* coef) {
+    if (K < 0 || !coef || !(a > 0.0)) return fail(PV_ERR_INVALID_ARG, "bad filter arguments");
+    const double xl = (lam_l - b) / a, xr = (lam_r - b) / a;
+    if (!(xl >= -1.0 && xl < xr && xr <= 1.0)) return fail(PV_ERR_INVALID_ARG, "window must lie inside the scaled spectrum");
+    const double al = std::acos(xl), ar = std::acos(xr);
+    // Jackson damping with N = K + 1 terms (Weisse et al. 2006), Chebyshev
+    // series of the window indicator
+    const int N = K + 1;
+    const double q = M_PI / (N + 1);
+    for (int k = 0; k <= K; ++k) {
+        const double g = ((N - k + 1) * std::cos(q * k) + std::sin(q * k) / std::tan(q)) / (N + 1);
+        const double c = (k == 0) ? (al - ar) / M_PI : 2.0 * (std::sin(k * al) - std::sin(k * ar)) / (k * M_PI);
+        coef[k] = g * c;
+    }
+    return PV_OK;
+}
+
+namespace {
+
+struct FdLayout {
+    size_t vb;      // bytes of one [rows][bw] block
+    size_t Y, W, S1, S2, gp, sp, G, D;
+    size_t total;
+};
+
+FdLayout fd_layout(const pv_lattice* l, int dtype, int bw, int nblk) {
+    FdLayout L{};
+    L.vb = vec_bytes(l, dtype, bw);
+    size_t off = 0;
+    L.Y = off; off += L.vb * nblk;
+    L.W = off; off += L.vb * nblk;
+    L.S1 = off; off += L.vb;
+    L.S2 = off; off += L.vb;
+    L.gp = off; off += pv_gram_workspace_size(l->n_rows, bw, bw);
+    L.sp = off; off += pv_spmmv_workspace_size(l, dtype, bw);
+    const size_t ns = (size_t)bw * nblk;
+    L.G = off; off += align_up(ns * ns * 2 * sizeof(double));
+    L.D = off; off += align_up((size_t)bw * 4 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" size_t pv_chebfd_workspace_size(const pv_lattice* l, int dtype, int bw, int nblk) {
+    if (!l || !is_pow2(bw) || bw > PV_MAX_NB || nblk < 1 || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    return fd_layout(l, dtype, bw, nblk).total;
+}
+
+extern "C" pv_status pv_chebfd(pv_lattice* l, int dtype, int bw, int nblk, double a, double b, double lam_l,
+                               double lam_r, int degree, int n_target, double tol, int max_iter, void* X,
+                               double* theta, double* res, int* n_conv, int* iters, void* work, size_t work_bytes,
+                               void* stream) {
+    pv_status st;
+    if ((st = check_series_args(l, dtype, bw, a, b)) != PV_OK) return st;
+    if ((st = check_vec(X, dtype, "X")) != PV_OK) return st;
+    const int ns = bw * nblk;
+    if (nblk < 1 || ns > 1024) return fail(PV_ERR_INVALID_ARG, "need 1 <= bw*nblk <= 1024");
+    if (degree < 1 || n_target < 1 || n_target > ns || !(tol > 0.0) || max_iter < 1)
+        return fail(PV_ERR_INVALID_ARG, "need degree >= 1, 1 <= n_target <= bw*nblk, tol > 0, max_iter >= 1");
+    if (!theta || !res || !n_conv || !iters) return fail(PV_ERR_INVALID_ARG, "NULL output");
+    std::vector<double> fc(degree + 1);
+    if ((st = pv_chebfd_filter_coefficients(lam_l, lam_r, a, b, degree, fc.data())) != PV_OK) return st;
+    const FdLayout Lw = fd_layout(l, dtype, bw, nblk);
+    if (!work || work_bytes < Lw.total) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, Lw.total);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(work);
+    char* Xc = static_cast<char*>(X);
+    auto blk = [&](char* base, int i) { return static_cast<void*>(base + Lw.vb * i); };
+    char* Yb = w + Lw.Y;
+    char* Wb = w + Lw.W;
+    double* Gd = reinterpret_cast<double*>(w + Lw.G);
+    double* Dd = reinterpret_cast<double*>(w + Lw.D);
+    const int64_t rows = l->n_rows;
+    std::vector<double> coef(2 * (degree + 1), 0.0);
+    for (int k = 0; k <= degree; ++k) coef[2 * k] = fc[k];
+    const double centre = 0.5 * (lam_l + lam_r);
+    std::vector<double> Gh((size_t)ns * ns * 2);
+
+    // G = A^H B over all block pairs (A, B given as nblk blocks) -> host G[ns][ns]
+    auto block_gram = [&](char* A, char* B, bool hermitian) -> pv_status {
+        for (int i = 0; i < nblk; ++i)
+            for (int j = hermitian ? i : 0; j < nblk; ++j) {
+                pv_status e = pv_gram(dtype, rows, bw, bw, blk(A, i), blk(B, j), Gd, w + Lw.gp, Lw.sp - Lw.gp, stream);
+                if (e != PV_OK) return e;
+                std::vector<double> g((size_t)bw * bw * 2);
+                PV_HIP(hipMemcpyAsync(g.data(), Gd, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+                PV_HIP(hipStreamSynchronize(s));
+                for (int r = 0; r < bw; ++r)
+                    for (int c = 0; c < bw; ++c) {
+                        const size_t dst = ((size_t)(i * bw + r) * ns + (j * bw + c)) * 2;
+                        Gh[dst] = g[(r * bw + c) * 2];
+                        Gh[dst + 1] = g[(r * bw + c) * 2 + 1];
+                        if (hermitian && i != j) {
+                            const size_t t = ((size_t)(j * bw + c) * ns + (i * bw + r)) * 2;
+                            Gh[t] = g[(r * bw + c) * 2];
+                            Gh[t + 1] = -g[(r * bw + c) * 2 + 1];
+                        }
+                    }
+            }
+        return PV_OK;
+    };
+    // OUT_j = sum_i IN_i M_ij for an ns x ns host matrix M
+    auto block_rotate = [&](char* IN, const std::vector<pvd::cd>& M, char* OUT) -> pv_status {
+        std::vector<double> q((size_t)bw * bw * 2);
+        for (int j = 0; j < nblk; ++j)
+            for (int i = 0; i < nblk; ++i) {
+                for (int r = 0; r < bw; ++r)
+                    for (int c = 0; c < bw; ++c) {
+                        const pvd::cd v = M[(size_t)(i * bw + r) * ns + (j * bw + c)];
+                        q[(r * bw + c) * 2] = v.real();
+                        q[(r * bw + c) * 2 + 1] = v.imag();
+                    }
+                PV_HIP(hipMemcpyAsync(Gd, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice, s));
+                pv_status e = pv_block_rotate(dtype, rows, bw, bw, blk(IN, i), Gd, i > 0, blk(OUT, j), stream);
+                if (e != PV_OK) return e;
+                PV_HIP(hipStreamSynchronize(s));  // q is reused for the next block
+            }
+        return PV_OK;
+    };
+    auto host_matrix = [&]() {
+        std::vector<pvd::cd> M((size_t)ns * ns);
+        for (size_t i = 0; i < M.size(); ++i) M[i] = pvd::cd(Gh[2 * i], Gh[2 * i + 1]);
+        return M;
+    };
+
+    std::vector<double> th(ns), rr(ns);
+    std::vector<int> order(ns);
+    int it = 0;
+    bool converged = false;
+    for (it = 1; it <= max_iter; ++it) {
+        // 1. filter every block: Y_b = p(H~) X_b
+        for (int bb = 0; bb < nblk; ++bb)
+            if ((st = run_series(l, dtype, bw, a, b, degree, coef.data(), blk(Xc, bb), blk(Yb, bb), blk(Yb, bb),
+                                 w + Lw.S1, w + Lw.S2, s)) != PV_OK)
+                return st;
+        // 2. orthonormalise: Cholesky QR, twice (Y <-> W)
+        char* cur = Yb;
+        char* oth = Wb;
+        for (int pass = 0; pass < 2; ++pass) {
+            if ((st = block_gram(cur, cur, true)) != PV_OK) return st;
+            std::vector<pvd::cd> R = host_matrix(), Minv;
+            if (!pvd::cholesky_upper(ns, R))
+                return fail(PV_ERR_NOT_CONVERGED, "filtered block lost rank (Cholesky failed) in iteration %d", it);
+            pvd::invert_upper(ns, R, Minv);
+            if ((st = block_rotate(cur, Minv, oth)) != PV_OK) return st;
+            std::swap(cur, oth);
+        }
+        // cur = Q (orthonormal), oth = scratch
+        // 3. Rayleigh-Ritz: H Q into oth, H_S = Q^H H Q
+        {
+            const std::vector<double> one(bw, 1.0), zero(bw, 0.0);
+            for (int bb = 0; bb < nblk; ++bb)
+                if ((st = pv_spmmv(l, dtype, bw, blk(cur, bb), nullptr, blk(oth, bb), one.data(), zero.data(),
+                                   zero.data(), 0, nullptr, w + Lw.sp, pv_spmmv_workspace_size(l, dtype, bw),
+                                   stream)) != PV_OK)
+                    return st;
+        }
+        if ((st = block_gram(cur, oth, false)) != PV_OK) return st;
+        std::vector<pvd::cd> Hs = host_matrix(), U;
+        for (int i = 0; i < ns; ++i)
+            for (int j = i + 1; j < ns; ++j) {
+                const pvd::cd m = 0.5 * (Hs[(size_t)i * ns + j] + std::conj(Hs[(size_t)j * ns + i]));
+                Hs[(size_t)i * ns + j] = m;
+                Hs[(size_t)j * ns + i] = std::conj(m);
+            }
+        std::vector<double> ev;
+        pvd::heev_jacobi(ns, Hs, ev, U);
+        // order Ritz pairs by distance from the window centre
+        for (int i = 0; i < ns; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int i, int j) { return std::fabs(ev[i] - centre) < std::fabs(ev[j] - centre); });
+        std::vector<pvd::cd> Uo((size_t)ns * ns);
+        for (int r = 0; r < ns; ++r)
+            for (int c = 0; c < ns; ++c) Uo[(size_t)r * ns + c] = U[(size_t)r * ns + order[c]];
+        for (int c = 0; c < ns; ++c) th[c] = ev[order[c]];
+        // 4. Ritz vectors into X
+        if ((st = block_rotate(cur, Uo, Xc)) != PV_OK) return st;
+        // 5. residuals ||H q - theta q|| with per-column shifts and the fused <y,y>
+        for (int bb = 0; bb < nblk; ++bb) {
+            const std::vector<double> one(bw, 1.0), zero(bw, 0.0);
+            std::vector<double> sh(th.begin() + bb * bw, th.begin() + (bb + 1) * bw);
+            if ((st = pv_spmmv(l, dtype, bw, blk(Xc, bb), nullptr, blk(oth, bb), one.data(), sh.data(), zero.data(),
+                               PV_DOT_YY, Dd, w + Lw.sp, pv_spmmv_workspace_size(l, dtype, bw), stream)) != PV_OK)
+                return st;
+            std::vector<double> d((size_t)bw * 4);
+            PV_HIP(hipMemcpyAsync(d.data(), Dd, d.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            PV_HIP(hipStreamSynchronize(s));
+            for (int c = 0; c < bw; ++c) rr[bb * bw + c] = std::sqrt(std::max(d[c * 4 + 3], 0.0));
+        }
+        converged = true;
+        for (int i = 0; i < n_target; ++i)
+            if (!(th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol)) converged = false;
+        if (converged) break;
+    }
+    if (it > max_iter) it = max_iter;
+    int nc = 0;
+    for (int i = 0; i < n_target; ++i)
+        if (th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol) ++nc;
+    for (int i = 0; i < ns; ++i) {
+        theta[i] = th[i];
+        res[i] = rr[i];
+    }
+    *n_conv = nc;
+    *iters = it;
+    if (!converged) return fail(PV_ERR_NOT_CONVERGED, "%d of %d target pairs converged after %d iterations", nc, n_target, it);
     return PV_OK;
 }

@@ -666,12 +666,18 @@ __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double* __re
 template <typename T>
 __global__ __launch_bounds__(kBlock) void rotate_kernel(const cplx<T>* __restrict__ X,
                                                         const double* __restrict__ Q, int64_t rows,
-                                                        int nx, int ny, cplx<T>* __restrict__ Y) {
+                                                        int nx, int ny, int accumulate,
+                                                        cplx<T>* __restrict__ Y) {
     const int64_t n = rows * ny;
     for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
         const int64_t r = e / ny;
         const int j = int(e - r * ny);
         double sr = 0.0, si = 0.0;
+        if (accumulate) {
+            const cplx<T> y0 = Y[e];
+            sr = double(y0.re);
+            si = double(y0.im);
+        }
         for (int i = 0; i < nx; ++i) {
             const cplx<T> u = X[r * nx + i];
             const double qr = Q[(i * ny + j) * 2], qi = Q[(i * ny + j) * 2 + 1];
@@ -778,15 +784,17 @@ hipError_t launch_gram(int dtype, int64_t rows, int nx, int ny, const void* X, c
     return hipGetLastError();
 }
 
-hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q, void* Y,
-                         hipStream_t s) {
+hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q, int accumulate,
+                         void* Y, hipStream_t s) {
     const int g = elementwise_grid(rows * ny);
     if (dtype == 0)
         hipLaunchKernelGGL(rotate_kernel<double>, dim3(g), dim3(kBlock), 0, s,
-                           static_cast<const cplx<double>*>(X), Q, rows, nx, ny, static_cast<cplx<double>*>(Y));
+                           static_cast<const cplx<double>*>(X), Q, rows, nx, ny, accumulate,
+                           static_cast<cplx<double>*>(Y));
     else
         hipLaunchKernelGGL(rotate_kernel<float>, dim3(g), dim3(kBlock), 0, s,
-                           static_cast<const cplx<float>*>(X), Q, rows, nx, ny, static_cast<cplx<float>*>(Y));
+                           static_cast<const cplx<float>*>(X), Q, rows, nx, ny, accumulate,
+                           static_cast<cplx<float>*>(Y));
     return hipGetLastError();
 }
 

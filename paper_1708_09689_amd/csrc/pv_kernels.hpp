@@ -80,7 +80,7 @@ hipError_t launch_gram(int dtype, int64_t rows, int nx, int ny, const void* X, c
                        double* partials, int grid, double* G, hipStream_t s);
 int gram_grid(int64_t rows, int num_cus);
 hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q,
-                         void* Y, hipStream_t s);
+                         int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace pv

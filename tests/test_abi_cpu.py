@@ -153,3 +153,33 @@ def test_kpm_dos_matches_oracle(lib):
     rho = pv.pv_kpm_dos(mu, E, 7.0, 0.0)
     ref = kpm.dos(mu, E, 7.0, 0.0)
     assert np.abs(rho - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 48])
+def test_host_jacobi_eigensolver(lib, n):
+    g = np.random.default_rng(n)
+    A = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    A = A + A.conj().T
+    w, V = pv.pv_host_heev(A)
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(w - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.abs(V.conj().T @ V - np.eye(n)).max() < 1e-12
+    assert np.abs(A @ V - V * w[None, :]).max() < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+def test_host_jacobi_degenerate_pairs(lib):
+    """Kramers-like doubly degenerate spectrum: eigenvalues exact, vectors orthonormal."""
+    g = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(g.standard_normal((12, 12)) + 1j * g.standard_normal((12, 12)))
+    d = np.repeat(np.linspace(-2, 2, 6), 2)
+    A = Q @ np.diag(d) @ Q.conj().T
+    w, V = pv.pv_host_heev(A)
+    assert np.abs(w - np.sort(d)).max() < 1e-12
+    assert np.abs(V.conj().T @ V - np.eye(12)).max() < 1e-12
+
+
+def test_chebfd_filter_coefficients_match_oracle(lib):
+    from oracle import chebfd
+    for (l, r, a, b, K) in [(-0.8, 0.8, 7.0, 0.0, 300), (-1.0, 0.5, 6.0, 0.2, 50), (0.1, 0.3, 3.1, 0.0, 1)]:
+        c = pv.pv_chebfd_filter_coefficients(l, r, a, b, K)
+        assert np.abs(c - chebfd.filter_coefficients(l, r, a, b, K)).max() < 1e-15
