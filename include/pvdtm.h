@@ -261,6 +261,28 @@ pv_status pv_chebfd_filter_coefficients(double lam_l, double lam_r, double a, do
  * the eigenvectors as columns. */
 pv_status pv_host_heev(int n, const double *A, double *w, double *V);
 
+/*
+ * Batched KPM over independent lattices (disorder realisations, possibly of
+ * different sizes) of one stencil family: every Chebyshev step of all
+ * instances is ONE kernel launch (each workgroup serves one instance, argument
+ * records in a device table) followed by one per-instance fixed-order
+ * reduction; the M/2 steps are captured into a HIP graph on the first call and
+ * replayed on later calls with identical arguments (pointers, a, b, fields,
+ * workspace).  Per instance i: mu[i][c][n] = Re <r_i,c, T_n(H~_i) r_i,c> / D_i,
+ * H~_i = (H_i - b[i]) / a[i].  r: host array of n device pointers; mu: device
+ * [n][nb][M].  The library owns the lattice list (borrowed lattices must
+ * outlive the batch) and the graph; the workspace holds the argument tables,
+ * so it must stay allocated while the graph may be replayed.
+ */
+pv_status pv_batch_create(int n, pv_lattice *const *lats, pv_batch **out);
+void pv_batch_destroy(pv_batch *batch);
+size_t pv_batch_kpm_workspace_size(const pv_batch *batch, int dtype, int nb, int M);
+pv_status pv_batch_kpm_moments(pv_batch *batch, int dtype, int nb, int M, const double *a,
+                               const double *b, const void *const *r, double *mu, void *work,
+                               size_t work_bytes, void *stream);
+/* Number of graph captures and replays performed so far (diagnostics). */
+pv_status pv_batch_stats(const pv_batch *batch, int *captures, int *replays);
+
 /* Scalar helper used to measure achievable bandwidth: dst = src (bytes, a
  * multiple of 16), a plain streaming copy kernel. */
 pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);

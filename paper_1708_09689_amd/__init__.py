@@ -73,6 +73,11 @@ SIGNATURES = {
     "pv_chebfd": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _i, _vp, _dp, _dp, _ip, _ip, _vp, _sz, _vp]),
     "pv_chebfd_filter_coefficients": (_i, [_d, _d, _d, _d, _i, _dp]),
     "pv_host_heev": (_i, [_i, _dp, _dp, _dp]),
+    "pv_batch_create": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "pv_batch_destroy": (None, [_vp]),
+    "pv_batch_kpm_workspace_size": (_sz, [_vp, _i, _i, _i]),
+    "pv_batch_kpm_moments": (_i, [_vp, _i, _i, _i, _dp, _dp, ctypes.POINTER(_vp), _vp, _vp, _sz, _vp]),
+    "pv_batch_stats": (_i, [_vp, _ip, _ip]),
 }
 
 _lib = None
@@ -372,3 +377,49 @@ def pv_chebfd(lat: Lattice, X, bw: int, a: float, b: float, lam_l: float, lam_r:
     if st != 0 and (raise_on_fail or st != 9):
         _check(st)
     return theta, res, nc.value, it.value
+
+
+class Batch:
+    """pv_batch_create / pv_batch_destroy over a list of Lattice objects (kept alive here)."""
+
+    def __init__(self, lattices):
+        self.lattices = list(lattices)
+        arr = (_vp * len(self.lattices))(*[l.handle.value for l in self.lattices])
+        h = ctypes.c_void_p()
+        _check(lib().pv_batch_create(len(self.lattices), arr, ctypes.byref(h)))
+        self.handle = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.pv_batch_destroy(h)
+            self.handle = None
+
+    def stats(self):
+        c, r = ctypes.c_int(), ctypes.c_int()
+        _check(lib().pv_batch_stats(self.handle, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
+
+
+def pv_batch_kpm_moments(batch: Batch, rs, M: int, a, b, mu=None, nb=None):
+    """Moments of every instance: rs list of device blocks; returns mu [n][nb][M].
+    The workspace is cached on the Batch object (the captured graph refers to it)."""
+    torch = _torch()
+    n = len(batch.lattices)
+    nb = nb if nb is not None else rs[0].numel() // batch.lattices[0].n_rows
+    dt = _dtype_code(rs[0])
+    for l, r in zip(batch.lattices, rs):
+        _vec(r, "r", l.n_rows, nb, dt)
+    if mu is None:
+        mu = torch.empty((n, nb, M), dtype=torch.float64, device=rs[0].device)
+    need = lib().pv_batch_kpm_workspace_size(batch.handle, dt, nb, M)
+    if batch._ws is None or batch._ws.numel() < need:
+        batch._ws = _workspace(need, rs[0].device)
+    av = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (n,)))
+    bv = np.ascontiguousarray(np.broadcast_to(np.asarray(b, dtype=np.float64), (n,)))
+    ptrs = (_vp * n)(*[r.data_ptr() for r in rs])
+    _check(lib().pv_batch_kpm_moments(batch.handle, dt, nb, M, _dptr(av), _dptr(bv), ptrs,
+                                      ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(batch._ws.data_ptr()),
+                                      batch._ws.numel(), _stream()))
+    return mu

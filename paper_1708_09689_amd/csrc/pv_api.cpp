@@ -1140,3 +1140,220 @@ extern "C" pv_status pv_chebfd(pv_lattice* l, int dtype, int bw, int nblk, doubl
     if (!converged) return fail(PV_ERR_NOT_CONVERGED, "%d of %d target pairs converged after %d iterations", nc, n_target, it);
     return PV_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Batched KPM over independent lattices, captured into a HIP graph
+// ---------------------------------------------------------------------------
+struct pv_batch {
+    std::vector<pv_lattice*> lats;
+    int family = 0, n_orb = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint64_t> key;
+    int captures = 0, replays = 0;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t tables, block_inst, inst_block0, invD, partials, vecs, total;
+    std::vector<size_t> vec_off;  // per instance: A at vec_off[i], B at vec_off[i] + vb_i
+    std::vector<int64_t> ntiles;
+    std::vector<int> tpb, nblocks;
+    int total_blocks;
+};
+
+pv_status batch_layout(const pv_batch* B, int dtype, int nb, BatchLayout& L) {
+    const int n = int(B->lats.size());
+    L.ntiles.resize(n);
+    L.tpb.resize(n);
+    L.nblocks.resize(n);
+    L.total_blocks = 0;
+    std::vector<char> rec(pv::batch_record_bytes());
+    for (int i = 0; i < n; ++i) {
+        pv::SweepParams p = base_params(B->lats[i], dtype, nb);
+        p.vtype = (dtype == PV_C128) ? 0 : B->lats[i]->vtype;
+        if (pv::batch_fill_record(p, rec.data(), &L.ntiles[i], &L.tpb[i]) != hipSuccess)
+            return fail(PV_ERR_UNSUPPORTED, "instance %d: unsupported field / vector type combination", i);
+        L.nblocks[i] = int((L.ntiles[i] + L.tpb[i] - 1) / L.tpb[i]);
+        L.total_blocks += L.nblocks[i];
+    }
+    size_t off = 0;
+    L.tables = off; off += align_up(4 * (size_t)n * pv::batch_record_bytes());
+    L.block_inst = off; off += align_up(sizeof(int) * L.total_blocks);
+    L.inst_block0 = off; off += align_up(sizeof(int) * (n + 1));
+    L.invD = off; off += align_up(sizeof(double) * n);
+    L.partials = off; off += align_up((size_t)L.total_blocks * nb * 4 * sizeof(double));
+    L.vecs = off;
+    L.vec_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        L.vec_off[i] = off;
+        off += 2 * vec_bytes(B->lats[i], dtype, nb);
+    }
+    L.total = off;
+    return PV_OK;
+}
+
+void release_graph(pv_batch* B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->key.clear();
+}
+
+}  // namespace
+
+extern "C" pv_status pv_batch_create(int n, pv_lattice* const* lats, pv_batch** out) {
+    if (!out || n < 1 || !lats) return fail(PV_ERR_INVALID_ARG, "pv_batch_create: need n >= 1 lattices");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (!lats[i]) return fail(PV_ERR_INVALID_ARG, "lattice %d is NULL", i);
+    for (int i = 1; i < n; ++i)
+        if (lats[i]->family != lats[0]->family || lats[i]->n_orb != lats[0]->n_orb)
+            return fail(PV_ERR_UNSUPPORTED, "lattice %d has another stencil family than lattice 0", i);
+    pv_batch* B = new (std::nothrow) pv_batch();
+    if (!B) return fail(PV_ERR_OOM, "host allocation failed");
+    B->lats.assign(lats, lats + n);
+    B->family = lats[0]->family;
+    B->n_orb = lats[0]->n_orb;
+    *out = B;
+    return PV_OK;
+}
+
+extern "C" void pv_batch_destroy(pv_batch* B) {
+    if (!B) return;
+    release_graph(B);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
+    delete B;
+}
+
+extern "C" pv_status pv_batch_stats(const pv_batch* B, int* captures, int* replays) {
+    if (!B) return fail(PV_ERR_INVALID_ARG, "batch is NULL");
+    if (captures) *captures = B->captures;
+    if (replays) *replays = B->replays;
+    return PV_OK;
+}
+
+extern "C" size_t pv_batch_kpm_workspace_size(const pv_batch* B, int dtype, int nb, int M) {
+    (void)M;
+    if (!B || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    BatchLayout L;
+    if (batch_layout(B, dtype, nb, L) != PV_OK) return 0;
+    return L.total;
+}
+
+extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M, const double* a, const double* b,
+                                          const void* const* r, double* mu, void* work, size_t work_bytes,
+                                          void* stream) {
+    if (!B) return fail(PV_ERR_INVALID_ARG, "batch is NULL");
+    pv_status st;
+    const int n = int(B->lats.size());
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if (M < 2 || (M & 1) || M > 65536) return fail(PV_ERR_INVALID_ARG, "M = %d must be even, 2..65536", M);
+    if (!a || !b || !r || !mu) return fail(PV_ERR_INVALID_ARG, "a, b, r and mu are required");
+    for (int i = 0; i < n; ++i) {
+        if ((st = check_dtype(B->lats[i], dtype)) != PV_OK) return st;
+        if ((st = check_vec(r[i], dtype, "r[i]")) != PV_OK) return st;
+        if (!(a[i] > 0.0) || !std::isfinite(a[i]) || !std::isfinite(b[i]))
+            return fail(PV_ERR_INVALID_ARG, "instance %d: need finite a > 0 and b", i);
+    }
+    BatchLayout L;
+    if ((st = batch_layout(B, dtype, nb, L)) != PV_OK) return st;
+    if (!work || work_bytes < L.total) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, L.total);
+    for (int i = 0; i < n; ++i)
+        if ((st = ensure_device(B->lats[i])) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // fingerprint of everything the captured graph bakes in
+    std::vector<uint64_t> key = {(uint64_t)dtype, (uint64_t)nb, (uint64_t)M, (uint64_t)(uintptr_t)work,
+                                 (uint64_t)work_bytes, (uint64_t)(uintptr_t)mu};
+    for (int i = 0; i < n; ++i) {
+        uint64_t ab[2];
+        std::memcpy(&ab[0], &a[i], 8);
+        std::memcpy(&ab[1], &b[i], 8);
+        key.insert(key.end(), {(uint64_t)(uintptr_t)r[i], ab[0], ab[1], (uint64_t)(uintptr_t)B->lats[i]->V,
+                               (uint64_t)B->lats[i]->vtype, (uint64_t)(uintptr_t)B->lats[i]->d_coef});
+    }
+    if (B->exec && key == B->key) {
+        PV_HIP(hipGraphLaunch(B->exec, s));
+        ++B->replays;
+        return PV_OK;
+    }
+    release_graph(B);
+    // a replay of the previous graph may still read the tables in `work`
+    PV_HIP(hipStreamSynchronize(s));
+
+    char* w = static_cast<char*>(work);
+    const size_t rb = pv::batch_record_bytes();
+    std::vector<char> tables(4 * (size_t)n * rb);
+    std::vector<int> block_inst(L.total_blocks), inst_block0(n + 1);
+    std::vector<double> invD(n);
+    int b0 = 0;
+    for (int i = 0; i < n; ++i) {
+        pv_lattice* l = B->lats[i];
+        inst_block0[i] = b0;
+        for (int k = 0; k < L.nblocks[i]; ++k) block_inst[b0 + k] = i;
+        b0 += L.nblocks[i];
+        invD[i] = 1.0 / double(l->n_rows);
+        void* A = w + L.vec_off[i];
+        void* Bv = w + L.vec_off[i] + vec_bytes(l, dtype, nb);
+        for (int v = 0; v < 4; ++v) {
+            pv::SweepParams p = base_params(l, dtype, nb);
+            if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
+            p.partials = reinterpret_cast<double*>(w + L.partials);
+            p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
+            p.beta = b[i];
+            if (v == 0) {          // w_1 = H~ w_0
+                p.x = r[i]; p.y = A; p.z = nullptr; p.alpha = 1.0 / a[i]; p.gamma = 0.0;
+            } else if (v == 1) {   // w_2 = 2 H~ w_1 - w_0
+                p.x = A; p.z = r[i]; p.y = Bv; p.alpha = 2.0 / a[i]; p.gamma = -1.0;
+            } else if (v == 2) {   // even step n >= 2: x = B, in place over A
+                p.x = Bv; p.z = A; p.y = A; p.alpha = 2.0 / a[i]; p.gamma = -1.0;
+            } else {               // odd step n >= 3: x = A, in place over B
+                p.x = A; p.z = Bv; p.y = Bv; p.alpha = 2.0 / a[i]; p.gamma = -1.0;
+            }
+            int64_t nt;
+            int tpb;
+            if (pv::batch_fill_record(p, tables.data() + ((size_t)v * n + i) * rb, &nt, &tpb) != hipSuccess)
+                return fail(PV_ERR_UNSUPPORTED, "instance %d: unsupported type combination", i);
+        }
+    }
+    inst_block0[n] = b0;
+    PV_HIP(hipMemcpy(w + L.tables, tables.data(), tables.size(), hipMemcpyHostToDevice));
+    PV_HIP(hipMemcpy(w + L.block_inst, block_inst.data(), sizeof(int) * block_inst.size(), hipMemcpyHostToDevice));
+    PV_HIP(hipMemcpy(w + L.inst_block0, inst_block0.data(), sizeof(int) * inst_block0.size(), hipMemcpyHostToDevice));
+    PV_HIP(hipMemcpy(w + L.invD, invD.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+
+    if (!B->cap) PV_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    const int* d_bi = reinterpret_cast<const int*>(w + L.block_inst);
+    const int* d_i0 = reinterpret_cast<const int*>(w + L.inst_block0);
+    const double* d_invD = reinterpret_cast<const double*>(w + L.invD);
+    const double* d_part = reinterpret_cast<const double*>(w + L.partials);
+    const int vtype = (dtype == PV_C128) ? 0 : B->lats[0]->vtype;
+    for (int i = 1; i < n; ++i)
+        if (dtype != PV_C128 && B->lats[i]->vtype != vtype && (B->lats[i]->V || B->lats[0]->V))
+            return fail(PV_ERR_UNSUPPORTED, "all instances of a batch need the same field type");
+    PV_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (int step = 0; step < M / 2 && e == hipSuccess; ++step) {
+        const int v = step == 0 ? 0 : (step == 1 ? 1 : (step % 2 == 0 ? 2 : 3));
+        e = pv::launch_batch_sweep(B->family, B->n_orb, dtype, vtype, w + L.tables + (size_t)v * n * rb, d_bi, d_i0,
+                                   L.total_blocks, B->cap);
+        if (e == hipSuccess)
+            e = pv::launch_batch_reduce(d_part, d_i0, n, nb, step == 0 ? 1 : 2, mu, M, step, d_invD, B->cap);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e != hipSuccess ? e : e2, "batched KPM graph capture");
+    }
+    B->graph = g;
+    PV_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    B->key = key;
+    ++B->captures;
+    PV_HIP(hipGraphLaunch(B->exec, s));
+    return PV_OK;
+}

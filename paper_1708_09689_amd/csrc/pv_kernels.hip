@@ -29,6 +29,7 @@
 #include "pv_kernels.hpp"
 
 #include <cstdlib>
+#include <cstring>
 #include <type_traits>
 #include <utility>
 
@@ -267,26 +268,17 @@ __device__ __forceinline__ bool x_shift(const A& a, int x, int dx, int& dxe) {
     return true;
 }
 
+// The work of one workgroup: tiles [t0, t1) of the part of the lattice made of
+// rows y in [y0, y0 + ny) (all z), swept slab by slab; partial dots go to
+// partials[b_out].
 template <class P, typename T, typename VT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_SWEEP_WAVES_PER_EU)))
-void sweep_kernel(KArgs<T, VT> a) {
+__device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, int y0, int ny, int64_t t0,
+                                            int64_t t1) {
     constexpr int NO = P::NO;
     const int tid = threadIdx.x;
     const int nb = a.nb;
     const int c = tid & (nb - 1);
     const int o = (tid >> a.lognb) & (NO - 1);
-
-    // Workgroup b runs on XCD b % 8 (the hardware deals workgroups out
-    // round-robin); XCD k owns the rows y in [Ly k/8, Ly (k+1)/8) for every z
-    // and its workgroups sweep them slab by slab, so the +-y and +-z
-    // neighbour rows a tile reads were fetched into the same L2 shortly
-    // before.
-    const int b = blockIdx.x;
-    const int k = b & 7;
-    const int ny = int((int64_t)a.Ly * (k + 1) / 8) - int((int64_t)a.Ly * k / 8);
-    const int64_t ntl = (int64_t)a.ntx * ny * a.Lz;
-    const int64_t t0 = (int64_t)(b >> 3) * a.tpb;
-    const int64_t t1 = min(t0 + a.tpb, ntl);
 
     double al = a.alpha, be = a.beta, ga = a.gamma;
     if (a.colp != nullptr) {
@@ -327,7 +319,6 @@ void sweep_kernel(KArgs<T, VT> a) {
     });
 
     constexpr uint32_t ES = sizeof(cplx<T>);
-    const int y0 = int((int64_t)a.Ly * k / 8);
     for (int64_t t = t0; t < t1; ++t) {
         // tile -> (row, x-tile): uniform over the workgroup.  Part k is swept
         // in slabs of BY rows; a slab plane by plane (z), a plane row by row.
@@ -436,9 +427,45 @@ void sweep_kernel(KArgs<T, VT> a) {
             const int cc = tid >> 2, k = tid & 3;
             double sum = 0.0;
             for (int w = 0; w < kBlock / 64; ++w) sum += red[w][cc][k];
-            a.partials[((size_t)b * nb + cc) * 4 + k] = sum;
+            a.partials[((size_t)b_out * nb + cc) * 4 + k] = sum;
         }
     }
+}
+
+// One sweep over a whole lattice.  Workgroup b runs on XCD b % 8 (the
+// hardware deals workgroups out round-robin); XCD k owns the rows y in
+// [Ly k/8, Ly (k+1)/8) for every z and its workgroups sweep them slab by slab,
+// so the +-y and +-z neighbour rows a tile reads were fetched into the same L2
+// shortly before.
+template <class P, typename T, typename VT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_SWEEP_WAVES_PER_EU)))
+void sweep_kernel(KArgs<T, VT> a) {
+    const int b = blockIdx.x;
+    const int k = b & 7;
+    const int y0 = int((int64_t)a.Ly * k / 8);
+    const int ny = int((int64_t)a.Ly * (k + 1) / 8) - y0;
+    const int64_t ntl = (int64_t)a.ntx * ny * a.Lz;
+    const int64_t t0 = (int64_t)(b >> 3) * a.tpb;
+    const int64_t t1 = min(t0 + a.tpb, ntl);
+    sweep_block<P, T, VT>(a, b, y0, ny, t0, t1);
+}
+
+// One sweep over a batch of independent lattices of the same family in a
+// single launch: workgroup b serves instance block_inst[b], whose argument
+// record (geometry, buffers, scale and shift) is table[instance]; each
+// instance's workgroups are consecutive and cover its tiles in order.
+template <class P, typename T, typename VT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_SWEEP_WAVES_PER_EU)))
+void batch_sweep_kernel(const KArgs<T, VT>* __restrict__ table, const int* __restrict__ block_inst,
+                        const int* __restrict__ inst_block0) {
+    const int b = blockIdx.x;
+    const int i = __builtin_amdgcn_readfirstlane(block_inst[b]);
+    const int lb = b - __builtin_amdgcn_readfirstlane(inst_block0[i]);
+    const KArgs<T, VT> a = table[i];
+    const int64_t ntl = (int64_t)a.ntx * a.Ly * a.Lz;
+    const int64_t t0 = (int64_t)lb * a.tpb;
+    const int64_t t1 = min(t0 + a.tpb, ntl);
+    sweep_block<P, T, VT>(a, b, 0, a.Ly, t0, t1);
 }
 
 // Tiles per workgroup: enough workgroups to keep every CU busy for several
@@ -469,9 +496,10 @@ int occupancy_blocks() {
     return cached;
 }
 
+// Kernel arguments from the launch description.  whole_part: one part
+// covering the lattice (used by batched launches) instead of 8 XCD parts.
 template <class P, typename T, typename VT>
-hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
-    KArgs<T, VT> a;
+void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
     a.x = static_cast<const cplx<T>*>(p.x);
     a.z = static_cast<const cplx<T>*>(p.z);
     a.y = static_cast<cplx<T>*>(p.y);
@@ -516,8 +544,21 @@ hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
     a.eta0_re = p.eta0_re;
     a.eta0_im = p.eta0_im;
     a.ep = p.ep;
+    a.tpb = p.tpb > 0 ? p.tpb : tiles_per_block(a.ntiles * 8);
+    if (whole_part) {
+        a.BY = int(p.L[1]);
+        a.fd_slab = make_fastdiv(uint32_t(a.ntx) * uint32_t(p.L[1]) * uint32_t(p.L[2]));
+        a.fd_pf = make_fastdiv(uint32_t(a.ntx) * uint32_t(p.L[1]));
+        a.ntiles = int64_t(a.ntx) * p.L[1] * p.L[2];
+        a.tpb = p.tpb > 0 ? p.tpb : 4;
+    }
+}
+
+template <class P, typename T, typename VT>
+hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
     (void)num_cus;
-    a.tpb = tiles_per_block(a.ntiles * 8);
+    KArgs<T, VT> a;
+    make_kargs<P, T, VT>(p, false, a);
     p.grid = int(8 * ((a.ntiles + a.tpb - 1) / a.tpb));
     hipLaunchKernelGGL((sweep_kernel<P, T, VT>), dim3(p.grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
@@ -573,6 +614,47 @@ __global__ __launch_bounds__(kBlock) void reduce_dots_kernel(const double* __res
             double* mu = out + (size_t)c * M;
             mu[2 * step] = 2.0 * xx * inv_D - mu[0];
             mu[2 * step + 1] = 2.0 * xr * inv_D - mu[1];
+        }
+    }
+}
+
+// Per-instance fixed-order reduction of a batched sweep: workgroup
+// (instance i, column c) sums the partials of the instance's workgroups
+// [inst_block0[i], inst_block0[i+1]) and updates mu[i][c][.] (modes 1, 2 of
+// reduce_dots_kernel).
+__global__ __launch_bounds__(kBlock) void batch_reduce_kernel(const double* __restrict__ partials,
+                                                              const int* __restrict__ inst_block0, int nb,
+                                                              int mode, double* mu, int M, int step,
+                                                              const double* __restrict__ invD) {
+    const int i = blockIdx.x / nb, c = blockIdx.x % nb;
+    const int b0 = inst_block0[i], b1 = inst_block0[i + 1];
+    const int tid = threadIdx.x;
+    double s0 = 0, s1 = 0;
+    for (int b = b0 + tid; b < b1; b += kBlock) {
+        const double* q = partials + ((size_t)b * nb + c) * 4;
+        s0 += q[0];
+        s1 += q[1];
+    }
+    __shared__ double sh[2][kBlock];
+    sh[0][tid] = s0;
+    sh[1][tid] = s1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            sh[0][tid] += sh[0][tid + w];
+            sh[1][tid] += sh[1][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double* m = mu + ((size_t)i * nb + c) * M;
+        const double xx = sh[0][0], xr = sh[1][0], d = invD[i];
+        if (mode == 1) {
+            m[0] = xx * d;
+            m[1] = xr * d;
+        } else {
+            m[2 * step] = 2.0 * xx * d - m[0];
+            m[2 * step + 1] = 2.0 * xr * d - m[1];
         }
     }
 }
@@ -805,6 +887,73 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
     if (g < 1) g = 1;
     hipLaunchKernelGGL(copy_kernel, dim3(int(g)), dim3(kBlock), 0, s, static_cast<const u32x4*>(src),
                        static_cast<u32x4*>(dst), n);
+    return hipGetLastError();
+}
+
+template <class X>
+struct Tag {
+    using type = X;
+};
+
+// Calls f(Tag<P>, Tag<T>, Tag<VT>) for the compiled instantiation of a launch.
+template <class F>
+hipError_t dispatch(int family, int n_orb, int dtype, int vtype, F&& f) {
+    auto types = [&](auto tp) -> hipError_t {
+        if (dtype == 0) {
+            if (vtype != 0) return hipErrorInvalidValue;
+            return f(tp, Tag<double>{}, Tag<double>{});
+        }
+        if (vtype == 0) return f(tp, Tag<float>{}, Tag<double>{});
+        return f(tp, Tag<float>{}, Tag<float>{});
+    };
+    switch (family) {
+        case FAM_TI: return types(Tag<PatTI>{});
+        case FAM_GRAPHENE2: return types(Tag<PatGraphene2>{});
+        case FAM_GRAPHENE4: return types(Tag<PatGraphene4>{});
+        case FAM_WEYL: return types(Tag<PatWeyl>{});
+        default: break;
+    }
+    switch (n_orb) {
+        case 1: return types(Tag<PatGeneric<1>>{});
+        case 2: return types(Tag<PatGeneric<2>>{});
+        case 4: return types(Tag<PatGeneric<4>>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t batch_record_bytes() { return sizeof(KArgs<double, double>); }
+
+hipError_t batch_fill_record(const SweepParams& p, void* dst, int64_t* ntiles, int* tpb) {
+    return dispatch(p.family, p.n_orb, p.dtype, p.vtype, [&](auto tp, auto tt, auto tv) -> hipError_t {
+        using P = typename decltype(tp)::type;
+        using T = typename decltype(tt)::type;
+        using VT = typename decltype(tv)::type;
+        static_assert(sizeof(KArgs<T, VT>) == sizeof(KArgs<double, double>), "record sizes differ");
+        KArgs<T, VT> a;
+        make_kargs<P, T, VT>(p, true, a);
+        std::memcpy(dst, &a, sizeof(a));
+        *ntiles = a.ntiles;
+        *tpb = a.tpb;
+        return hipSuccess;
+    });
+}
+
+hipError_t launch_batch_sweep(int family, int n_orb, int dtype, int vtype, const void* table, const int* block_inst,
+                              const int* inst_block0, int grid, hipStream_t s) {
+    return dispatch(family, n_orb, dtype, vtype, [&](auto tp, auto tt, auto tv) -> hipError_t {
+        using P = typename decltype(tp)::type;
+        using T = typename decltype(tt)::type;
+        using VT = typename decltype(tv)::type;
+        hipLaunchKernelGGL((batch_sweep_kernel<P, T, VT>), dim3(grid), dim3(kBlock), 0, s,
+                           static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_reduce(const double* partials, const int* inst_block0, int n_inst, int nb, int mode,
+                               double* mu, int M, int step, const double* invD, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(n_inst * nb), dim3(kBlock), 0, s, partials, inst_block0, nb, mode,
+                       mu, M, step, invD);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct SweepParams {
     const double* colp;   // device: [nb][3] per-column alpha, beta, gamma or NULL
     const void* zero_row;   // device zeros, >= L[0]*n_orb*nb elements
     int slab_rows;          // rows per y-slab of the sweep order
+    int tpb;                // tiles per workgroup (0 = heuristic)
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;
@@ -82,6 +83,18 @@ int gram_grid(int64_t rows, int num_cus);
 hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q,
                          int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+// Batched sweeps: one argument record per instance (built on the host with
+// batch_fill_record from that instance's launch description, whole lattice
+// as one part), a table of records in device memory, and per-workgroup
+// instance maps.  *ntiles / *tpb receive the instance's tile count and tiles
+// per workgroup.
+size_t batch_record_bytes();
+hipError_t batch_fill_record(const SweepParams& p, void* dst, int64_t* ntiles, int* tpb);
+hipError_t launch_batch_sweep(int family, int n_orb, int dtype, int vtype, const void* table, const int* block_inst,
+                              const int* inst_block0, int grid, hipStream_t s);
+hipError_t launch_batch_reduce(const double* partials, const int* inst_block0, int n_inst, int nb, int mode,
+                               double* mu, int M, int step, const double* invD, hipStream_t s);
 
 }  // namespace pv
 
