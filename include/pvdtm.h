@@ -262,6 +262,37 @@ pv_status pv_chebfd_filter_coefficients(double lam_l, double lam_r, double a, do
 pv_status pv_host_heev(int n, const double *A, double *w, double *V);
 
 /*
+ * Gradients with respect to the on-site field V (discrete adjoints of the
+ * recurrences above; a and b are fixed numbers, not differentiated).
+ *
+ * pv_kpm_moments_vjp: for L = sum_{c,n} gbar[c][n] mu[c][n] (mu as computed
+ * by pv_kpm_moments), gradV = dL/dV.  With N = M/2 and w_k = T_k(H~) r, the
+ * adjoint vectors follow lambda_k = G_k + 2 H~ lambda_{k+1} - lambda_{k+2}
+ * (k = N..1), G_k = dL/dw_k from the product doubling, and
+ *   dL/dV_m = (1/a) Re [<lambda_1, P_m w_0> + 2 sum_{k=1}^{N-1} <lambda_{k+1}, P_m w_k>]
+ * (P_m: rows of site m, or row m for PV_POT_ORBITAL).  The forward vectors are
+ * checkpointed in pairs every ckpt_every steps and recomputed per segment.
+ * gbar: device [nb][M]; gradV: device [n_sites] (site field) or [n_rows]
+ * (orbital field), overwritten.  Needs n_orb*nb <= 64 for a site field.
+ * Synchronises the stream once (gbar is read on the host).
+ *
+ * pv_cheb_propagate_vjp: for psi_T = U(dt)^nsteps psi0 (pv_cheb_propagate)
+ * and a cotangent psibar (dL = Re <psibar, d psi_T>), returns gradV = dL/dV
+ * and, if psi0bar != NULL, the cotangent of psi0.  Every step is reversed
+ * with the Clenshaw-type adjoint of the series sum_k eta_k T_k(H~).
+ */
+size_t pv_kpm_vjp_workspace_size(const pv_lattice *lat, int dtype, int nb, int M, int ckpt_every);
+pv_status pv_kpm_moments_vjp(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
+                             const void *r, const double *gbar, double *gradV, int ckpt_every,
+                             void *work, size_t work_bytes, void *stream);
+size_t pv_cheb_propagate_vjp_workspace_size(const pv_lattice *lat, int dtype, int nb, int M,
+                                            int nsteps);
+pv_status pv_cheb_propagate_vjp(pv_lattice *lat, int dtype, int nb, double a, double b, double dt,
+                                int M, int nsteps, const void *psi0, const void *psibar,
+                                void *psi0bar, double *gradV, void *work, size_t work_bytes,
+                                void *stream);
+
+/*
  * Batched KPM over independent lattices (disorder realisations, possibly of
  * different sizes) of one stencil family: every Chebyshev step of all
  * instances is ONE kernel launch (each workgroup serves one instance, argument

@@ -78,6 +78,10 @@ SIGNATURES = {
     "pv_batch_kpm_workspace_size": (_sz, [_vp, _i, _i, _i]),
     "pv_batch_kpm_moments": (_i, [_vp, _i, _i, _i, _dp, _dp, ctypes.POINTER(_vp), _vp, _vp, _sz, _vp]),
     "pv_batch_stats": (_i, [_vp, _ip, _ip]),
+    "pv_kpm_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
+    "pv_kpm_moments_vjp": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
+    "pv_cheb_propagate_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
+    "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
 }
 
 _lib = None
@@ -423,3 +427,92 @@ def pv_batch_kpm_moments(batch: Batch, rs, M: int, a, b, mu=None, nb=None):
                                       ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(batch._ws.data_ptr()),
                                       batch._ws.numel(), _stream()))
     return mu
+
+
+def _grad_len(lat: Lattice) -> int:
+    return lat.n_rows if lat.pot_mode == PV_POT_ORBITAL else lat.n_sites
+
+
+def pv_kpm_moments_vjp(lat: Lattice, r, M: int, a: float, b: float, gbar, ckpt_every: int = 16, gradV=None, nb=None):
+    """dL/dV for L = sum gbar * mu (gbar device [nb][M] float64)."""
+    torch = _torch()
+    nb = nb if nb is not None else r.numel() // lat.n_rows
+    dt = _dtype_code(r)
+    if gradV is None:
+        gradV = torch.empty(_grad_len(lat), dtype=torch.float64, device=r.device)
+    gbar = gbar.contiguous()
+    ws = _workspace(lib().pv_kpm_vjp_workspace_size(lat.handle, dt, nb, M, ckpt_every), r.device)
+    _check(lib().pv_kpm_moments_vjp(lat.handle, dt, nb, M, a, b, _vec(r, "r", lat.n_rows, nb),
+                                    ctypes.c_void_p(gbar.data_ptr()), ctypes.c_void_p(gradV.data_ptr()), ckpt_every,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return gradV
+
+
+def pv_cheb_propagate_vjp(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, want_psi0bar=True, nb=None):
+    """(dL/dV, cotangent of psi0) for psi_T = U^nsteps psi0 and cotangent psibar of psi_T."""
+    torch = _torch()
+    nb = nb if nb is not None else psi0.numel() // lat.n_rows
+    dtc = _dtype_code(psi0)
+    gradV = torch.empty(_grad_len(lat), dtype=torch.float64, device=psi0.device)
+    psi0bar = torch.empty_like(psi0) if want_psi0bar else None
+    psibar = psibar.contiguous()
+    ws = _workspace(lib().pv_cheb_propagate_vjp_workspace_size(lat.handle, dtc, nb, M, nsteps), psi0.device)
+    _check(lib().pv_cheb_propagate_vjp(lat.handle, dtc, nb, a, b, dt, M, nsteps, _vec(psi0, "psi0", lat.n_rows, nb),
+                                       _vec(psibar, "psibar", lat.n_rows, nb, dtc),
+                                       None if psi0bar is None else ctypes.c_void_p(psi0bar.data_ptr()),
+                                       ctypes.c_void_p(gradV.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                       ws.numel(), _stream()))
+    return gradV, psi0bar
+
+
+def _autograd():
+    torch = _torch()
+
+    class KPMMoments(torch.autograd.Function):
+        """mu = KPM moments of the lattice with on-site field V (differentiable in V)."""
+
+        @staticmethod
+        def forward(ctx, V, lat, r, M, a, b, ckpt_every):
+            lat.set_potential(V.detach())
+            mu = pv_kpm_moments(lat, r, M, a, b)
+            ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, ctx.ck = lat, r, M, a, b, ckpt_every
+            ctx.V = V.detach()
+            return mu
+
+        @staticmethod
+        def backward(ctx, gbar):
+            ctx.lat.set_potential(ctx.V)
+            g = pv_kpm_moments_vjp(ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, gbar.to(torch.float64), ctx.ck)
+            return g.to(ctx.V.dtype), None, None, None, None, None, None
+
+    class Propagate(torch.autograd.Function):
+        """psi_T = U(dt)^nsteps psi0 for the lattice with field V (differentiable in V and psi0)."""
+
+        @staticmethod
+        def forward(ctx, V, psi0, lat, a, b, dt, M, nsteps):
+            lat.set_potential(V.detach())
+            psi = psi0.detach().clone()
+            pv_cheb_propagate(lat, psi, a, b, dt, M, nsteps)
+            ctx.lat, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n = lat, a, b, dt, M, nsteps
+            ctx.V = V.detach()
+            ctx.psi0 = psi0.detach()
+            return psi
+
+        @staticmethod
+        def backward(ctx, psibar):
+            ctx.lat.set_potential(ctx.V)
+            g, p0 = pv_cheb_propagate_vjp(ctx.lat, ctx.psi0, psibar, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n)
+            return g.to(ctx.V.dtype), p0, None, None, None, None, None, None
+
+    return KPMMoments, Propagate
+
+
+def kpm_moments(V, lat: Lattice, r, M: int, a: float, b: float, ckpt_every: int = 16):
+    """Differentiable KPM moments mu(V) (torch.autograd.Function around
+    pv_kpm_moments / pv_kpm_moments_vjp)."""
+    return _autograd()[0].apply(V, lat, r, M, a, b, ckpt_every)
+
+
+def cheb_propagate(V, psi0, lat: Lattice, a: float, b: float, dt: float, M: int, nsteps: int):
+    """Differentiable Chebyshev propagation psi_T(V, psi0)."""
+    return _autograd()[1].apply(V, psi0, lat, a, b, dt, M, nsteps)

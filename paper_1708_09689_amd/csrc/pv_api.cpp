@@ -1357,3 +1357,252 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     PV_HIP(hipGraphLaunch(B->exec, s));
     return PV_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Adjoints with respect to the on-site field (gradients of KPM moments and
+// of Chebyshev propagation)
+// ---------------------------------------------------------------------------
+namespace {
+
+pv_status check_grad_args(pv_lattice* l, int dtype, int nb, double a, double b, const double* gradV) {
+    pv_status st;
+    if ((st = check_series_args(l, dtype, nb, a, b)) != PV_OK) return st;
+    if (l->pot_mode == PV_POT_NONE) return fail(PV_ERR_INVALID_ARG, "lattice has no on-site field to differentiate");
+    if (l->pot_mode == PV_POT_SITE && l->n_orb * nb > 64)
+        return fail(PV_ERR_UNSUPPORTED, "gradient of a site field needs n_orb * nb <= 64");
+    if (!gradV) return fail(PV_ERR_INVALID_ARG, "gradV is NULL");
+    return PV_OK;
+}
+
+size_t grad_len(const pv_lattice* l) { return size_t(l->pot_mode == PV_POT_ORBITAL ? l->n_rows : l->n_sites); }
+
+// One sweep y = alpha (H - beta) x + gamma z with the adjoint epilogue.
+pv_status adjoint_sweep(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y, double alpha,
+                        double beta, double gamma, const void* w0, const void* w1, const void* w2,
+                        const double* gcoef, double* grad, double gx, double gy, unsigned ep, hipStream_t s) {
+    pv::SweepParams p = base_params(l, dtype, nb);
+    pv_status st;
+    if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
+    p.x = x;
+    p.z = z;
+    p.y = y;
+    p.alpha = alpha;
+    p.beta = beta;
+    p.gamma = gamma;
+    p.gw[0] = w0;
+    p.gw[1] = w1;
+    p.gw[2] = w2;
+    p.gcoef = gcoef;
+    p.grad = grad;
+    p.gx = gx;
+    p.gy = gy;
+    p.grad_mode = l->pot_mode;
+    p.ep = ep;
+    PV_HIP(pv::launch_sweep(p, num_cus(), s));
+    return PV_OK;
+}
+
+}  // namespace
+
+extern "C" size_t pv_kpm_vjp_workspace_size(const pv_lattice* l, int dtype, int nb, int M, int ckpt) {
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || M < 2 || (M & 1) || ckpt < 1 ||
+        (dtype != PV_C128 && dtype != PV_C64))
+        return 0;
+    const int N = M / 2, J = (N - 1) / ckpt + 1;
+    const size_t vb = vec_bytes(l, dtype, nb);
+    return vb * (2 * (size_t)J + ckpt + 2 + 2) + align_up((size_t)(N + 1) * 3 * nb * 2 * sizeof(double));
+}
+
+extern "C" pv_status pv_kpm_moments_vjp(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                                        const double* gbar, double* gradV, int ckpt, void* work, size_t work_bytes,
+                                        void* stream) {
+    pv_status st;
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if ((st = check_grad_args(l, dtype, nb, a, b, gradV)) != PV_OK) return st;
+    if ((st = check_vec(r, dtype, "r")) != PV_OK) return st;
+    if (M < 2 || (M & 1) || M > 65536) return fail(PV_ERR_INVALID_ARG, "M = %d must be even, 2..65536", M);
+    if (!gbar) return fail(PV_ERR_INVALID_ARG, "gbar is NULL");
+    if (ckpt < 1) return fail(PV_ERR_INVALID_ARG, "checkpoint interval must be >= 1");
+    const size_t need = pv_kpm_vjp_workspace_size(l, dtype, nb, M, ckpt);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int N = M / 2, C = ckpt, J = (N - 1) / C + 1;
+    const size_t vb = vec_bytes(l, dtype, nb);
+    const double invD = 1.0 / double(l->n_rows);
+    char* w = static_cast<char*>(work);
+    auto ck = [&](int j, int which) { return static_cast<void*>(w + vb * (2 * (size_t)j + which)); };
+    char* S = w + vb * 2 * (size_t)J;                  // C segment vectors
+    void* L0 = S + vb * C;
+    void* L1 = S + vb * (C + 1);
+    void* F0 = S + vb * (C + 2);                       // forward ring
+    void* F1 = S + vb * (C + 3);
+    double* table = reinterpret_cast<double*>(S + vb * (C + 4));
+
+    // cotangent of the moments -> coefficients of the adjoint source terms
+    std::vector<double> g((size_t)nb * M);
+    PV_HIP(hipMemcpyAsync(g.data(), gbar, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    PV_HIP(hipStreamSynchronize(s));
+    std::vector<double> tab((size_t)(N + 1) * 3 * nb * 2, 0.0);
+    for (int c = 0; c < nb; ++c) {
+        const double* gc = &g[(size_t)c * M];
+        double ghat1 = gc[1];
+        for (int n = 1; n <= N - 1; ++n) ghat1 -= gc[2 * n + 1];
+        for (int k = 1; k <= N; ++k) {
+            double* row = &tab[(size_t)k * 3 * nb * 2];
+            row[(0 * nb + c) * 2] = (k == 1 ? ghat1 : 2.0 * gc[2 * k - 1]) * invD;
+            row[(1 * nb + c) * 2] = (k < N ? 4.0 * gc[2 * k] : 0.0) * invD;
+            row[(2 * nb + c) * 2] = (k < N ? 2.0 * gc[2 * k + 1] : 0.0) * invD;
+        }
+    }
+    PV_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PV_HIP(pv::launch_zero(gradV, grad_len(l) * sizeof(double), s));
+    PV_HIP(pv::launch_zero(L0, vb, s));
+    PV_HIP(pv::launch_zero(L1, vb, s));
+    const size_t vbytes = (size_t)l->n_rows * nb * elem_bytes(dtype);
+
+    // forward recurrence, keeping (w_{jC}, w_{jC+1}) for j = 0..J-1
+    const unsigned store = pv::EP_STORE_Y;
+    if ((st = adjoint_sweep(l, dtype, nb, r, nullptr, F0, 1.0 / a, b, 0.0, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, 0, 0, store, s)) != PV_OK)
+        return st;
+    PV_HIP(pv::launch_copy(r, ck(0, 0), vbytes, s));
+    PV_HIP(pv::launch_copy(F0, ck(0, 1), vbytes, s));
+    {
+        const void* prev = r;
+        void* cur = F0;
+        for (int k = 1; k <= (J - 1) * C; ++k) {
+            void* next = (k == 1) ? F1 : const_cast<void*>(prev);
+            if ((st = adjoint_sweep(l, dtype, nb, cur, prev, next, 2.0 / a, b, -1.0, nullptr, nullptr, nullptr,
+                                    nullptr, nullptr, 0, 0, store, s)) != PV_OK)
+                return st;
+            prev = cur;
+            cur = next;
+            if (k % C == 0) {
+                PV_HIP(pv::launch_copy(prev, ck(k / C, 0), vbytes, s));
+                PV_HIP(pv::launch_copy(cur, ck(k / C, 1), vbytes, s));
+            }
+        }
+    }
+
+    // reverse sweep over segments: recompute w_{jC}..w_{min((j+1)C+1, N)}, then
+    // lambda_k = G_k + 2 H~ lambda_{k+1} - lambda_{k+2} for k = min((j+1)C, N)..jC+1
+    void* lx = L0;   // lambda_{k+1}
+    void* lz = L1;   // lambda_{k+2}, overwritten by lambda_k
+    for (int j = J - 1; j >= 0; --j) {
+        const int k_hi = std::min((j + 1) * C, N);
+        auto wv = [&](int i) -> void* {
+            if (i == j * C) return ck(j, 0);
+            if (i == j * C + 1) return ck(j, 1);
+            return S + vb * (size_t)(i - j * C - 2);
+        };
+        for (int i = j * C + 2; i <= std::min(k_hi + 1, N); ++i)
+            if ((st = adjoint_sweep(l, dtype, nb, wv(i - 1), wv(i - 2), wv(i), 2.0 / a, b, -1.0, nullptr, nullptr,
+                                    nullptr, nullptr, nullptr, 0, 0, store, s)) != PV_OK)
+                return st;
+        for (int k = k_hi; k >= j * C + 1; --k) {
+            if ((st = adjoint_sweep(l, dtype, nb, lx, lz, lz, 2.0 / a, b, -1.0, wv(k - 1), wv(k),
+                                    k < N ? wv(k + 1) : nullptr, table + (size_t)k * 3 * nb * 2, gradV, 2.0 / a,
+                                    k == 1 ? 1.0 / a : 0.0, store | pv::EP_GTERMS | pv::EP_GRAD, s)) != PV_OK)
+                return st;
+            std::swap(lx, lz);
+        }
+    }
+    return PV_OK;
+}
+
+extern "C" size_t pv_cheb_propagate_vjp_workspace_size(const pv_lattice* l, int dtype, int nb, int M, int nsteps) {
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || M < 1 || nsteps < 1 || (dtype != PV_C128 && dtype != PV_C64))
+        return 0;
+    const size_t vb = vec_bytes(l, dtype, nb);
+    return vb * ((size_t)nsteps + M + 4) + align_up((size_t)(M + 1) * 3 * nb * 2 * sizeof(double));
+}
+
+extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M,
+                                           int nsteps, const void* psi0, const void* psibar, void* psi0bar,
+                                           double* gradV, void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if ((st = check_grad_args(l, dtype, nb, a, b, gradV)) != PV_OK) return st;
+    if ((st = check_vec(psi0, dtype, "psi0")) != PV_OK) return st;
+    if ((st = check_vec(psibar, dtype, "psibar")) != PV_OK) return st;
+    if (psi0bar && (st = check_vec(psi0bar, dtype, "psi0bar")) != PV_OK) return st;
+    if (M < 1 || nsteps < 1 || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "need M >= 1, nsteps >= 1");
+    const size_t need = pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t vb = vec_bytes(l, dtype, nb);
+    const size_t vbytes = (size_t)l->n_rows * nb * elem_bytes(dtype);
+    char* w = static_cast<char*>(work);
+    auto state = [&](int i) -> void* { return w + vb * (size_t)i; };          // psi_1 .. psi_{nsteps-1} (slot 0 unused)
+    auto wk = [&](int k) -> void* { return w + vb * ((size_t)nsteps + k - 1); };  // w_1 .. w_M
+    void* L0 = w + vb * ((size_t)nsteps + M);
+    void* L1 = w + vb * ((size_t)nsteps + M + 1);
+    void* Y0 = w + vb * ((size_t)nsteps + M + 2);
+    void* Y1 = w + vb * ((size_t)nsteps + M + 3);
+    double* table = reinterpret_cast<double*>(w + vb * ((size_t)nsteps + M + 4));
+
+    // series coefficients of one step: eta_0 = e^{-ibdt} c_0, eta_k = 2 e^{-ibdt} c_k
+    std::vector<double> coef(2 * (M + 1));
+    pv_cheb_tp_coefficients(a, dt, M, coef.data());
+    const std::complex<double> ph = std::exp(std::complex<double>(0.0, -b * dt));
+    for (int k = 0; k <= M; ++k) {
+        std::complex<double> c(coef[2 * k], coef[2 * k + 1]);
+        c *= ph * (k ? 2.0 : 1.0);
+        coef[2 * k] = c.real();
+        coef[2 * k + 1] = c.imag();
+    }
+    // adjoint source of lambda_k: conj(eta_k) * Ybar in the third slot
+    std::vector<double> tab((size_t)(M + 1) * 3 * nb * 2, 0.0);
+    for (int k = 0; k <= M; ++k)
+        for (int c = 0; c < nb; ++c) {
+            double* row = &tab[(size_t)k * 3 * nb * 2];
+            row[(2 * nb + c) * 2] = coef[2 * k];
+            row[(2 * nb + c) * 2 + 1] = -coef[2 * k + 1];
+        }
+    PV_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PV_HIP(pv::launch_zero(gradV, grad_len(l) * sizeof(double), s));
+
+    // forward: psi_{i+1} = U psi_i, keep psi_1 .. psi_{nsteps-1}
+    auto psi = [&](int i) -> const void* { return i == 0 ? psi0 : state(i); };
+    for (int i = 0; i + 1 < nsteps; ++i)
+        if ((st = run_series(l, dtype, nb, a, b, M, coef.data(), psi(i), state(i + 1), state(i + 1), wk(1),
+                             M >= 2 ? wk(2) : L0, s)) != PV_OK)
+            return st;
+
+    PV_HIP(pv::launch_copy(psibar, Y0, vbytes, s));
+    void* ybar = Y0;
+    void* ynew = Y1;
+    const unsigned store = pv::EP_STORE_Y;
+    for (int i = nsteps - 1; i >= 0; --i) {
+        const void* X = psi(i);
+        // recompute w_1 .. w_M of this step
+        auto wv = [&](int k) -> const void* { return k == 0 ? X : wk(k); };
+        if ((st = adjoint_sweep(l, dtype, nb, X, nullptr, wk(1), 1.0 / a, b, 0.0, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, 0, 0, store, s)) != PV_OK)
+            return st;
+        for (int k = 2; k <= M; ++k)
+            if ((st = adjoint_sweep(l, dtype, nb, wv(k - 1), wv(k - 2), wk(k), 2.0 / a, b, -1.0, nullptr, nullptr,
+                                    nullptr, nullptr, nullptr, 0, 0, store, s)) != PV_OK)
+                return st;
+        PV_HIP(pv::launch_zero(L0, vb, s));
+        PV_HIP(pv::launch_zero(L1, vb, s));
+        void* lx = L0;
+        void* lz = L1;
+        for (int k = M; k >= 1; --k) {
+            if ((st = adjoint_sweep(l, dtype, nb, lx, lz, lz, 2.0 / a, b, -1.0, wv(k - 1), wv(k), ybar,
+                                    table + (size_t)k * 3 * nb * 2, gradV, 2.0 / a, k == 1 ? 1.0 / a : 0.0,
+                                    store | pv::EP_GTERMS | pv::EP_GRAD, s)) != PV_OK)
+                return st;
+            std::swap(lx, lz);
+        }
+        // lambda_0 = conj(eta_0) Ybar + H~ lambda_1 - lambda_2  ->  cotangent of psi_i
+        if ((st = adjoint_sweep(l, dtype, nb, lx, lz, ynew, 1.0 / a, b, -1.0, nullptr, nullptr, ybar, table, nullptr,
+                                0, 0, store | pv::EP_GTERMS, s)) != PV_OK)
+            return st;
+        std::swap(ybar, ynew);
+    }
+    if (psi0bar) PV_HIP(pv::launch_copy(ybar, psi0bar, vbytes, s));
+    return PV_OK;
+}

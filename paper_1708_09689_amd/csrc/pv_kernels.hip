@@ -87,6 +87,13 @@ struct KArgs {
     const cplx<T>* zsrc;    // z, or x when no column reads z (a valid dummy)
     const cplx<T>* asrc;    // acc_in, or x when not accumulating
     const VT* V;
+    const cplx<T>* gw0;     // adjoint terms: w_{k-1}, w_k, w_{k+1} (or NULL)
+    const cplx<T>* gw1;
+    const cplx<T>* gw2;
+    const double* gcoef;    // [3][nb] complex coefficients of the gw terms
+    double* grad;           // on-site field gradient
+    double gx, gy;
+    int ggroup;             // lanes per gradient entry: n_orb*nb (site field) or nb (orbital field)
     const double* coef;
     const int* offs;
     const double* colp;
@@ -186,19 +193,40 @@ __device__ __forceinline__ cplx<T> ld_row_nt(const cplx<T>* row, uint32_t boff) 
     return ld_nt(reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(row) + boff));
 }
 
-// Epilogue shared by every family: y = alpha h + gamma z, store / accumulate,
-// FP64 partial dots of (x, y).  zv and av were loaded at the top of the
-// element (unconditionally, from a valid address) so that every load of an
-// element is in flight at the same time; gamma == 0 selects zero instead of
+// Epilogue shared by every family: y = alpha h + gamma z (+ sum_j g_j w_j),
+// store / accumulate, FP64 partial dots of (x, y), and the on-site field
+// gradient.  zv and av were loaded at the top of the element
+// (unconditionally, from a valid address) so that every load of an element
+// is in flight at the same time; gamma == 0 selects zero instead of
 // gamma * z, so z is never used for such columns.
+//
+// Adjoint options (Clenshaw-type recurrences for gradients):
+//   EP_GTERMS  y += sum_{j=0..2} gcoef[j][c] * gw_j[e]   (complex coefficients;
+//              gw_j == NULL skips the term)
+//   EP_GRAD    grad[site or row] += gx Re(conj(x) gw_1) + gy Re(conj(y) gw_0),
+//              summed over the site's (or row's) lanes with a fixed xor tree
+//              and written by one lane, read-modify-write (no atomics)
 template <typename T, typename VT>
-__device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, cplx<T> xc, cplx<T> zv, cplx<T> av,
-                                         T hr, T hi, T alT, T gaT, T er, T ei, T e0r, T e0i, double& dxx,
-                                         double& dxr, double& dxi, double& dyy) {
+__device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, int64_t gidx, int glane, cplx<T> xc,
+                                         cplx<T> zv, cplx<T> av, T hr, T hi, T alT, T gaT, T er, T ei, T e0r,
+                                         T e0i, int c, double& dxx, double& dxr, double& dxi, double& dyy) {
     T yr = alT * hr, yi = alT * hi;
     yr += (gaT != T(0)) ? gaT * zv.re : T(0);
     yi += (gaT != T(0)) ? gaT * zv.im : T(0);
     const unsigned ep = a.ep;
+    cplx<T> gv[3] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
+    if (ep & (EP_GTERMS | EP_GRAD)) {
+        const cplx<T>* gws[3] = {a.gw0, a.gw1, a.gw2};
+        for (int j = 0; j < 3; ++j)
+            if (gws[j] != nullptr) gv[j] = ld_nt(gws[j] + e);
+    }
+    if (ep & EP_GTERMS) {
+        for (int j = 0; j < 3; ++j) {
+            const T cr = T(a.gcoef[(j * a.nb + c) * 2]), ci = T(a.gcoef[(j * a.nb + c) * 2 + 1]);
+            yr += cr * gv[j].re - ci * gv[j].im;
+            yi += cr * gv[j].im + ci * gv[j].re;
+        }
+    }
     if (ep & EP_STORE_Y) st_nt(a.y + e, yr, yi);
     if (ep & EP_ACC_INIT) {
         st_nt(a.acc_out + e, e0r * xc.re - e0i * xc.im + er * yr - ei * yi,
@@ -213,6 +241,12 @@ __device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, cplx<
         dxr += xr * dyr + xi * dyi;
         dxi += xr * dyi - xi * dyr;
         dyy += dyr * dyr + dyi * dyi;
+    }
+    if (ep & EP_GRAD) {
+        double g = a.gx * (double(xc.re) * double(gv[1].re) + double(xc.im) * double(gv[1].im)) +
+                   a.gy * (double(yr) * double(gv[0].re) + double(yi) * double(gv[0].im));
+        for (int m = 1; m < a.ggroup; m <<= 1) g += __shfl_xor(g, m);
+        if (glane == 0) a.grad[gidx] += g;
     }
 }
 
@@ -403,7 +437,10 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
             for (int q = 0; q < NO; ++q)
                 if (q != o) mac<T>(hr, hi, CC, T(cb[2 * q]), T(cb[2 * q + 1]), ld_row(xrow, uint32_t(own + q * nb) * ES));
         }
-        epilogue(a, rb + xe, xc, zv, av, hr, hi, alT, gaT, er, ei, e0r, e0i, dxx, dxr, dxi, dyy);
+        const int64_t site = (int64_t)row * a.Lx + x;
+        const int64_t gidx = a.ggroup == nb ? site * NO + o : site;
+        epilogue(a, rb + xe, gidx, tid & (a.ggroup - 1), xc, zv, av, hr, hi, alT, gaT, er, ei, e0r, e0i, c, dxx, dxr,
+                 dxi, dyy);
     }
 
     if (a.ep & EP_DOTS) {
@@ -508,6 +545,14 @@ void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
     a.zsrc = a.z ? a.z : a.x;
     a.asrc = ((p.ep & EP_ACC_ADD) && a.acc_in) ? a.acc_in : a.x;
     a.V = static_cast<const VT*>(p.V);
+    a.gw0 = static_cast<const cplx<T>*>(p.gw[0]);
+    a.gw1 = static_cast<const cplx<T>*>(p.gw[1]);
+    a.gw2 = static_cast<const cplx<T>*>(p.gw[2]);
+    a.gcoef = p.gcoef;
+    a.grad = p.grad;
+    a.gx = p.gx;
+    a.gy = p.gy;
+    a.ggroup = (p.grad_mode == 2) ? p.nb : P::NO * p.nb;
     a.coef = p.coef;
     a.offs = p.offs;
     a.colp = p.colp;
@@ -772,6 +817,12 @@ __global__ __launch_bounds__(kBlock) void rotate_kernel(const cplx<T>* __restric
 
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
+// dst[0..n) = 0 for 32-bit words (gradients, zero vectors of the adjoint).
+__global__ __launch_bounds__(kBlock) void zero_kernel(uint32_t* __restrict__ dst, int64_t n) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+        dst[k] = 0u;
+}
+
 // Streaming copy: each lane moves 4 x 16 B per iteration with all loads
 // issued before the stores; nontemporal on both sides.
 __global__ __launch_bounds__(kBlock) void copy_kernel(const u32x4* __restrict__ src,
@@ -922,6 +973,12 @@ hipError_t dispatch(int family, int n_orb, int dtype, int vtype, F&& f) {
 }
 
 size_t batch_record_bytes() { return sizeof(KArgs<double, double>); }
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s) {
+    const int64_t n = int64_t(bytes / 4);
+    hipLaunchKernelGGL(zero_kernel, dim3(elementwise_grid(n)), dim3(kBlock), 0, s, static_cast<uint32_t*>(dst), n);
+    return hipGetLastError();
+}
 
 hipError_t batch_fill_record(const SweepParams& p, void* dst, int64_t* ntiles, int* tpb) {
     return dispatch(p.family, p.n_orb, p.dtype, p.vtype, [&](auto tp, auto tt, auto tv) -> hipError_t {

@@ -30,6 +30,8 @@ enum : unsigned {
     EP_ACC_INIT = 2u,    // acc_out = eta0 * x + eta * y
     EP_ACC_ADD = 4u,     // acc_out = acc_in + eta * y
     EP_DOTS = 8u,        // per-block partial dots (xx, Re xy, Im xy, yy)
+    EP_GTERMS = 16u,     // y += sum_j gcoef[j][c] gw_j (adjoint source terms)
+    EP_GRAD = 32u,       // grad += gx Re(conj(x) gw_1) + gy Re(conj(y) gw_0) per site/row
 };
 
 struct SweepParams {
@@ -48,6 +50,11 @@ struct SweepParams {
     const void* acc_in;
     void* acc_out;
     const void* V;        // NULL = no field
+    const void* gw[3];    // adjoint terms (EP_GTERMS / EP_GRAD)
+    const double* gcoef;  // device [3][nb] complex
+    double* grad;         // device gradient, n_sites (grad_mode 1) or n_rows (grad_mode 2)
+    double gx, gy;
+    int grad_mode;
     const double* coef;   // device: [(n_terms + 1)][n_orb][n_orb][2], onsite last
     const int* offs;      // device: [n_terms][3] (generic family only)
     const double* colp;   // device: [nb][3] per-column alpha, beta, gamma or NULL
@@ -90,6 +97,8 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // instance maps.  *ntiles / *tpb receive the instance's tile count and tiles
 // per workgroup.
 size_t batch_record_bytes();
+// dst = 0 (bytes a multiple of 4)
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t batch_fill_record(const SweepParams& p, void* dst, int64_t* ntiles, int* tpb);
 hipError_t launch_batch_sweep(int family, int n_orb, int dtype, int vtype, const void* table, const int* block_inst,
                               const int* inst_block0, int grid, hipStream_t s);

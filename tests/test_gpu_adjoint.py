@@ -1,0 +1,119 @@
+"""GPU parity of the adjoint (on-site field gradients) against the oracle's
+discrete adjoints and against central finite differences of the GPU forward.
+
+Tolerances (complex128): gradient vs oracle adjoint 1e-10 relative to
+max|grad|; vs central differences (h = 1e-6) 1e-6 relative.  complex64
+vectors: 1e-3 relative (FP32 recurrences on both forward and adjoint)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1708_09689_amd as pv  # noqa: E402
+from oracle import adjoint, chebtp  # noqa: E402
+import oracle.hamiltonian as oh  # noqa: E402
+import workloads as W  # noqa: E402
+
+from gpu_common import Case, dev, host  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("L,nb,M,ck", [((4, 3, 5), 1, 32, 4), ((5, 5, 4), 4, 64, 16), ((3, 3, 3), 2, 2, 1),
+                                       ((6, 4, 3), 16, 40, 3), ((4, 4, 4), 8, 34, 100)])
+def test_kpm_vjp_matches_oracle(L, nb, M, ck):
+    c = Case("ti", L, (1, 1, 1), Wd=1.0, seed=11)
+    r = c.block(nb, kind="phase")
+    gbar = W.generator(4, W.STREAM_COTANGENT, nb).standard_normal((nb, M))
+    g = host(pv.pv_kpm_moments_vjp(c.lat, dev(r), M, 7.0, 0.1, dev(gbar), ckpt_every=ck))
+    ref = adjoint.kpm_vjp(c.H, 4, "site", r, M, 7.0, 0.1, gbar)
+    assert rel(g, ref) < 1e-10
+
+
+def test_kpm_vjp_orbital_field_graphene4():
+    c = Case("graphene4", (5, 4), (1, 0), Wd=0.5, seed=12)
+    r = c.block(4, kind="phase")
+    gbar = W.generator(5, W.STREAM_COTANGENT).standard_normal((4, 24))
+    g = host(pv.pv_kpm_moments_vjp(c.lat, dev(r), 24, 3.5, 0.0, dev(gbar), ckpt_every=5))
+    ref = adjoint.kpm_vjp(c.H, 4, "orbital", r, 24, 3.5, 0.0, gbar)
+    assert rel(g, ref) < 1e-10
+
+
+def test_kpm_vjp_against_gpu_finite_differences():
+    c = Case("ti", (4, 4, 3), (1, 1, 1), Wd=1.0, seed=13)
+    r = dev(c.block(2, kind="phase"))
+    M = 32
+    gbar = W.generator(6, W.STREAM_COTANGENT).standard_normal((2, M))
+    g = host(pv.pv_kpm_moments_vjp(c.lat, r, M, 7.0, 0.0, dev(gbar)))
+    sites = W.sample_sites(c.olat.n_sites, 6, W.generator(6, W.STREAM_FD_SITES))
+    h = 1e-6
+    for m in sites:
+        vals = []
+        for sgn in (+1, -1):
+            V = c.V.copy()
+            V[m] += sgn * h
+            c.lat.set_potential(dev(V))
+            vals.append(float((host(pv.pv_kpm_moments(c.lat, r, M, 7.0, 0.0)) * gbar).sum()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[m]) < 1e-6 * np.abs(g).max()
+    c.lat.set_potential(c.Vd)
+
+
+def test_kpm_vjp_c64_stated_error():
+    c = Case("ti", (6, 5, 4), (1, 1, 1), Wd=1.0, seed=14, vdtype=np.float32)
+    r = c.block(8, kind="phase", dtype=np.complex64)
+    gbar = W.generator(7, W.STREAM_COTANGENT).standard_normal((8, 48))
+    g = host(pv.pv_kpm_moments_vjp(c.lat, dev(r), 48, 7.0, 0.0, dev(gbar)))
+    Hq = oh.assemble(c.model, c.olat, c.V.astype(np.float32).astype(np.float64))
+    ref = adjoint.kpm_vjp(Hq, 4, "site", r.astype(np.complex128), 48, 7.0, 0.0, gbar)
+    assert rel(g, ref) < 1e-3
+
+
+@pytest.mark.parametrize("M,nsteps,nb", [(1, 2, 1), (3, 1, 2), (64, 3, 1), (40, 2, 4)])
+def test_propagate_vjp_matches_oracle(M, nsteps, nb):
+    c = Case("graphene2", (24, 10), (0, 1), Wd=0.3, seed=15)
+    psi0 = c.block(nb, seed=3)
+    psibar = c.block(nb, seed=4)
+    a, b, dt = 3.3, 0.05, 2.0 if M < 64 else 8.0
+    g, p0 = pv.pv_cheb_propagate_vjp(c.lat, dev(psi0), dev(psibar), a, b, dt, M, nsteps)
+    p0_ref, g_ref = adjoint.propagate_vjp(c.H, 2, "site", psi0, a, b, dt, M, nsteps, psibar)
+    assert rel(host(g), g_ref) < 1e-10
+    assert rel(host(p0), p0_ref) < 1e-10
+
+
+def test_autograd_transmission_gradient():
+    """torch.autograd through the wave-packet propagation: T = sum over the
+    right part of the ribbon of |psi_T|^2, gradient w.r.t. V vs oracle."""
+    Li, Lj = 48, 12
+    c = Case("graphene2", (Li, Lj), (0, 1), with_field=False)
+    Vn = W.dot_array_potential(Li, Lj, n_dots=(1, 1), radius=4, V0=0.1, pitch=16, first_centre=(24, 6))
+    psi0 = W.gaussian_wave_packet(Li, Lj, i0=10, width=4, energy=0.2).reshape(-1, 1)
+    a, b, dt, M, S = 3.06, 0.05, 4.0, 32, 3
+    V = dev(Vn).requires_grad_(True)
+    psiT = pv.cheb_propagate(V, dev(psi0), c.lat, a, b, dt, M, S)
+    region = torch.zeros(c.D, 1, dtype=torch.bool, device="cuda")
+    region.view(Lj, Li, 2)[:, Li // 2:, :] = True
+    T = (psiT.abs() ** 2)[region].sum()
+    T.backward()
+    H = oh.assemble(c.model, c.olat, Vn)
+    psiT_ref = chebtp.propagate(H, psi0, a, b, dt, M, S)
+    mask = region.cpu().numpy()
+    psibar = 2.0 * np.where(mask, psiT_ref, 0)
+    _, g_ref = adjoint.propagate_vjp(H, 2, "site", psi0, a, b, dt, M, S, psibar)
+    assert rel(V.grad.cpu().numpy(), g_ref) < 1e-9
+
+
+def test_autograd_kpm_dos_gradient():
+    c = Case("ti", (4, 4, 4), (1, 1, 1), Wd=1.0, seed=16)
+    r = dev(c.block(2, kind="phase"))
+    V = c.Vd.clone().requires_grad_(True)
+    mu = pv.kpm_moments(V, c.lat, r, 16, 7.0, 0.0)
+    w = torch.linspace(-1.0, 1.0, 16, dtype=torch.float64, device="cuda")
+    (mu * w).sum().backward()
+    gbar = np.tile(np.linspace(-1.0, 1.0, 16), (2, 1))
+    ref = adjoint.kpm_vjp(c.H, 4, "site", host(r), 16, 7.0, 0.0, gbar)
+    assert rel(V.grad.cpu().numpy(), ref) < 1e-10
