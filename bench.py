@@ -123,6 +123,165 @@ def cpu_baseline(nb: int, budget_s: float = 12.0) -> dict:
                       f"{sweeps} Chebyshev sweeps + dots in {el:.1f} s, scipy CSR + numpy, 1 thread"}
 
 
+def _timed(torch, fn, reps=1):
+    """Average ms of fn() over reps calls, timed with events on the current stream."""
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_kpm16(pv, torch, W, dev):
+    """TI 16^3 periodic, W = 1, one random-phase column, M = 128 (a = 7):
+    eager launches vs the same run replayed as a captured HIP graph."""
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lat = pv.Lattice((16, 16, 16), (1, 1, 1), st)
+    lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(0, W.STREAM_POTENTIAL))).to(dev))
+    r = torch.from_numpy(W.random_phase_block(lat.n_rows, 1, W.generator(0, W.STREAM_VECTORS))).to(dev)
+    mu = torch.empty((1, 128), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        pv.pv_kpm_moments(lat, r, 128, 7.0, 0.0, mu=mu)
+    ms_eager = _timed(torch, lambda: pv.pv_kpm_moments(lat, r, 128, 7.0, 0.0, mu=mu), 20)
+    batch = pv.Batch([lat])
+    for _ in range(3):
+        pv.pv_batch_kpm_moments(batch, [r], 128, [7.0], [0.0])
+    ms_graph = _timed(torch, lambda: pv.pv_batch_kpm_moments(batch, [r], 128, [7.0], [0.0]), 20)
+    lups = lat.n_rows * 64
+    return {"workload": "TI 16x16x16 periodic, W=1, nb=1, M=128 (64 sweeps), complex128",
+            "us_per_kpm_eager": round(ms_eager * 1e3, 1), "us_per_kpm_graph": round(ms_graph * 1e3, 1),
+            "GLUP/s_eager": round(lups / (ms_eager * 1e-3) / 1e9, 3),
+            "GLUP/s_graph": round(lups / (ms_graph * 1e-3) / 1e9, 3), "captures_replays": batch.stats(),
+            "note": "cache-resident (0.6 MB): launch-latency bound, no HBM roofline claim"}
+
+
+def bench_chebtp_graphene(pv, torch, W, dev, steps=5):
+    """Graphene two-site cells 1024 x 1024 (open x, periodic y), 8x8 dot array
+    (radius 20, V0 = 0.1), Gaussian packet (width 50, E = 0.2), a = 3.06,
+    b = 0.05, dt = 10, M = 64 sweeps per time step."""
+    Li = Lj = 1024
+    st = pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0])
+    lat = pv.Lattice((Li, Lj), (0, 1), st)
+    lat.set_potential(torch.from_numpy(W.dot_array_potential(Li, Lj)).to(dev))
+    psi = torch.from_numpy(W.gaussian_wave_packet(Li, Lj, i0=200, width=50, energy=0.2).reshape(-1, 1)).to(dev)
+    pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, 1)
+    ms = _timed(torch, lambda: pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, steps)) / steps
+    norm = float(torch.linalg.vector_norm(psi).item())
+    lups = lat.n_rows * 64
+    by = lat.n_rows * (4 * 16) + lat.n_sites * 8   # x, z, acc in/out (+y) per sweep, field
+    return {"workload": "graphene 1024x1024 cells x 2 sites, open x / periodic y, dot array, packet; "
+                        f"{steps} time steps of dt=10, M=64, complex128",
+            "ms_per_time_step": round(ms, 4), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
+            "norm_after": round(norm, 12), "approx_GB/s": round(by * 64 / (ms * 1e-3) / 1e9, 1),
+            "note": "working set ~170 MB: largely resident in the 256 MB Infinity Cache"}
+
+
+def bench_filter(pv, torch, lat, dev, nb=32, K=8):
+    """Chebyshev filter / propagation sweeps (accumulate epilogue) on the
+    256x256x64 TI at nb = 32: Y = sum_k c_k T_k(H~) X."""
+    import workloads as W
+    X = W.random_phase_device(lat.n_rows, nb, 77, dev)
+    Y = torch.empty_like(X)
+    coef = np.linspace(1.0, 0.1, K + 1)
+    pv.pv_cheb_series(lat, X, Y, A_SCALE, B_SHIFT, coef)
+    ms = _timed(torch, lambda: pv.pv_cheb_series(lat, X, Y, A_SCALE, B_SHIFT, coef), 2) / K
+    by = lat.n_rows * nb * 16 * 5 + lat.n_sites * 8
+    return {"workload": f"TI 256x256x64, nb={nb}, complex128, series of degree {K} (filter step)",
+            "ms_per_sweep": round(ms, 4), "GLUP/s": round(lat.n_rows * nb / (ms * 1e-3) / 1e9, 3),
+            "GB/s": round(by / (ms * 1e-3) / 1e9, 1), "bytes_per_LUP": 80}
+
+
+def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16, loop_M=64):
+    """96 TI disorder realisations, L ~ U{24..96}, W ~ U[0.5, 3], 16 random-phase
+    columns, M = 1024: one graph-captured batched launch per step with
+    complex64 vectors and FP64 moments, vs a per-instance complex128 loop
+    (timed over loop_M moments)."""
+    inst = W.batch_instances(n, W.generator(3, W.STREAM_SIZES))
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lats, Vs, rs = [], [], []
+    for i, (L, Wd) in enumerate(inst):
+        lat = pv.Lattice((L, L, L), (1, 1, 1), st)
+        V = torch.from_numpy(W.uniform_potential(lat.n_sites, Wd, W.generator(3, W.STREAM_POTENTIAL, i))).to(dev)
+        lats.append(lat)
+        Vs.append(V)
+    sites = sum(l.n_sites for l in lats)
+    for lat, V in zip(lats, Vs):
+        lat.set_potential(V.float())
+    rs = [W.random_phase_device(l.n_rows, nb, 300 + i, dev, "complex64") for i, l in enumerate(lats)]
+    batch = pv.Batch(lats)
+    a = [7.0 + 0.5 * Wd for (_, Wd) in inst]
+    t0 = time.perf_counter()
+    mu = pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0)       # capture + first run
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    ms = _timed(torch, lambda: pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0), 1)
+    ok = bool(torch.isfinite(mu).all().item()) and float((mu[:, :, 0] - 1).abs().max().item()) < 1e-5
+    lups = sum(l.n_rows for l in lats) * nb * (M // 2)
+    b64 = sum(3 * l.n_rows * nb * 8 + l.n_sites * 4 for l in lats) * (M // 2)
+    del rs
+    torch.cuda.empty_cache()
+    # per-instance complex128 loop (each instance its own launches)
+    for lat, V in zip(lats, Vs):
+        lat.set_potential(V)
+    r128 = [W.random_phase_device(l.n_rows, nb, 300 + i, dev) for i, l in enumerate(lats)]
+    ms_loop = _timed(torch, lambda: [pv.pv_kpm_moments(l, r, loop_M, a_i, 0.0) for l, r, a_i in zip(lats, r128, a)], 1)
+    lups_loop = sum(l.n_rows for l in lats) * nb * (loop_M // 2)
+    return {"workload": f"{n} TI realisations L~U{{24..96}} ({sites} sites), W~U[0.5,3], nb={nb}, M={M}",
+            "batched_c64": {"ms_per_run": round(ms, 2), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
+                            "GB/s": round(b64 / (ms * 1e-3) / 1e9, 1), "first_call_s_incl_capture": round(first, 2),
+                            "mu0_check": ok, "launches_per_run": 2 * (M // 2), "graph_replays": batch.stats()[1]},
+            "loop_c128": {"M": loop_M, "ms_per_run": round(ms_loop, 2),
+                          "GLUP/s": round(lups_loop / (ms_loop * 1e-3) / 1e9, 3)}}
+
+
+def bench_adjoint(pv, torch, W, dev, ckpt=16):
+    """TI 64^3 periodic, W = 1, nb = 8, M = 256: KPM forward vs the gradient
+    (checkpointed forward + segment recompute + adjoint sweeps); graphene
+    512 x 512 transmission gradient (50 steps, dt = 10, M = 64)."""
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lat = pv.Lattice((64, 64, 64), (1, 1, 1), st)
+    lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(4, W.STREAM_POTENTIAL))).to(dev))
+    r = W.random_phase_device(lat.n_rows, 8, 400, dev)
+    M = 256
+    gbar = torch.from_numpy(W.generator(4, W.STREAM_COTANGENT).standard_normal((8, M))).to(dev)
+    pv.pv_kpm_moments(lat, r, M, 7.0, 0.0)
+    ms_f = _timed(torch, lambda: pv.pv_kpm_moments(lat, r, M, 7.0, 0.0), 2)
+    pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, ckpt)
+    ms_b = _timed(torch, lambda: pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, ckpt), 2)
+    lups = lat.n_rows * 8 * (M // 2)
+    out = {"ti": {"workload": "TI 64^3, W=1, nb=8, M=256, checkpoint every 16, complex128",
+                  "fwd_ms": round(ms_f, 3), "fwd_GLUP/s": round(lups / (ms_f * 1e-3) / 1e9, 3),
+                  "grad_ms": round(ms_b, 3), "grad_over_fwd": round(ms_b / ms_f, 2),
+                  "fwd+adj_GLUP/s": round(lups / ((ms_f + ms_b) * 1e-3) / 1e9, 3),
+                  "note": "GLUP/s counted on the forward's LUPs; the gradient pass runs forward + recompute + adjoint"}}
+    Li = Lj = 512
+    g2 = pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0])
+    lg = pv.Lattice((Li, Lj), (0, 1), g2)
+    Vg = torch.from_numpy(W.dot_array_potential(Li, Lj, radius=10, pitch=32, first_centre=(224, 144))).to(dev)
+    psi0 = torch.from_numpy(W.gaussian_wave_packet(Li, Lj, i0=100, width=25, energy=0.2).reshape(-1, 1)).to(dev)
+    region = torch.zeros(lg.n_rows, 1, dtype=torch.bool, device=dev)
+    region.view(Lj, Li, 2)[:, 464:, :] = True
+
+    def grad_T():
+        V = Vg.clone().requires_grad_(True)
+        psiT = pv.cheb_propagate(V, psi0, lg, 3.06, 0.05, 10.0, 64, 50)
+        T = (psiT.abs() ** 2)[region].sum()
+        T.backward()
+        return T
+    grad_T()
+    ms_g = _timed(torch, grad_T, 1)
+    psi = psi0.clone()
+    ms_gf = _timed(torch, lambda: pv.pv_cheb_propagate(lg, psi, 3.06, 0.05, 10.0, 64, 50), 1)
+    out["graphene"] = {"workload": "graphene 512x512x2, 50 steps dt=10 M=64, dT/dV by autograd",
+                       "fwd_ms": round(ms_gf, 2), "fwd+adj_ms": round(ms_g, 2),
+                       "fwd_GLUP/s": round(lg.n_rows * 64 * 50 / (ms_gf * 1e-3) / 1e9, 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +292,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the per-workload measurements")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -186,6 +346,20 @@ def main():
                 del s2
                 torch.cuda.empty_cache()
 
+    configs = {}
+    if not args.no_configs:
+        set_field("c128")
+        for name, fn in (("kpm_ti16", lambda: bench_kpm16(pv, torch, W, dev)),
+                         ("filter_sweeps_ti256", lambda: bench_filter(pv, torch, lat, dev)),
+                         ("chebtp_graphene1024", lambda: bench_chebtp_graphene(pv, torch, W, dev)),
+                         ("batched_kpm_96", lambda: bench_batch(pv, torch, W, dev)),
+                         ("adjoint", lambda: bench_adjoint(pv, torch, W, dev))):
+            t0 = time.perf_counter()
+            configs[name] = fn()
+            torch.cuda.empty_cache()
+            print(f"# {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        set_field(args.dtype)
+
     cpu = None if args.no_cpu else cpu_baseline(args.nb)
 
     out = {
@@ -212,6 +386,7 @@ def main():
         "copy_probe_GBs": None if copy_gbs is None else round(copy_gbs, 1),
         "frac_of_copy_probe": None if copy_gbs is None else round(achieved / copy_gbs, 4),
         "variants": variants,
+        "workloads": configs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

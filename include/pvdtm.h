@@ -298,8 +298,9 @@ pv_status pv_cheb_propagate_vjp(pv_lattice *lat, int dtype, int nb, double a, do
  * instances is ONE kernel launch (each workgroup serves one instance, argument
  * records in a device table) followed by one per-instance fixed-order
  * reduction; the M/2 steps are captured into a HIP graph on the first call and
- * replayed on later calls with identical arguments (pointers, a, b, fields,
- * workspace).  Per instance i: mu[i][c][n] = Re <r_i,c, T_n(H~_i) r_i,c> / D_i,
+ * replayed on later calls with identical arguments (r pointers, a, b, fields,
+ * workspace); the graph writes the moments into the workspace and each call
+ * then copies them to mu, so mu may differ between calls.  Per instance i: mu[i][c][n] = Re <r_i,c, T_n(H~_i) r_i,c> / D_i,
  * H~_i = (H_i - b[i]) / a[i].  r: host array of n device pointers; mu: device
  * [n][nb][M].  The library owns the lattice list (borrowed lattices must
  * outlive the batch) and the graph; the workspace holds the argument tables,

@@ -1157,14 +1157,14 @@ struct pv_batch {
 namespace {
 
 struct BatchLayout {
-    size_t tables, block_inst, inst_block0, invD, partials, vecs, total;
+    size_t tables, block_inst, inst_block0, invD, partials, moments, vecs, total;
     std::vector<size_t> vec_off;  // per instance: A at vec_off[i], B at vec_off[i] + vb_i
     std::vector<int64_t> ntiles;
     std::vector<int> tpb, nblocks;
     int total_blocks;
 };
 
-pv_status batch_layout(const pv_batch* B, int dtype, int nb, BatchLayout& L) {
+pv_status batch_layout(const pv_batch* B, int dtype, int nb, int M, BatchLayout& L) {
     const int n = int(B->lats.size());
     L.ntiles.resize(n);
     L.tpb.resize(n);
@@ -1185,6 +1185,7 @@ pv_status batch_layout(const pv_batch* B, int dtype, int nb, BatchLayout& L) {
     L.inst_block0 = off; off += align_up(sizeof(int) * (n + 1));
     L.invD = off; off += align_up(sizeof(double) * n);
     L.partials = off; off += align_up((size_t)L.total_blocks * nb * 4 * sizeof(double));
+    L.moments = off; off += align_up((size_t)n * nb * M * sizeof(double));
     L.vecs = off;
     L.vec_off.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -1237,10 +1238,9 @@ extern "C" pv_status pv_batch_stats(const pv_batch* B, int* captures, int* repla
 }
 
 extern "C" size_t pv_batch_kpm_workspace_size(const pv_batch* B, int dtype, int nb, int M) {
-    (void)M;
-    if (!B || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    if (!B || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64) || M < 2 || M > 65536) return 0;
     BatchLayout L;
-    if (batch_layout(B, dtype, nb, L) != PV_OK) return 0;
+    if (batch_layout(B, dtype, nb, M, L) != PV_OK) return 0;
     return L.total;
 }
 
@@ -1260,15 +1260,18 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
             return fail(PV_ERR_INVALID_ARG, "instance %d: need finite a > 0 and b", i);
     }
     BatchLayout L;
-    if ((st = batch_layout(B, dtype, nb, L)) != PV_OK) return st;
+    if ((st = batch_layout(B, dtype, nb, M, L)) != PV_OK) return st;
     if (!work || work_bytes < L.total) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, L.total);
     for (int i = 0; i < n; ++i)
         if ((st = ensure_device(B->lats[i])) != PV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    // fingerprint of everything the captured graph bakes in
+    // fingerprint of everything the captured graph bakes in; the graph writes
+    // the moments into the workspace, so the caller's mu may move between calls
     std::vector<uint64_t> key = {(uint64_t)dtype, (uint64_t)nb, (uint64_t)M, (uint64_t)(uintptr_t)work,
-                                 (uint64_t)work_bytes, (uint64_t)(uintptr_t)mu};
+                                 (uint64_t)work_bytes};
+    char* const mu_ws = static_cast<char*>(work) + L.moments;
+    const size_t mu_bytes = (size_t)n * nb * M * sizeof(double);
     for (int i = 0; i < n; ++i) {
         uint64_t ab[2];
         std::memcpy(&ab[0], &a[i], 8);
@@ -1278,6 +1281,7 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     }
     if (B->exec && key == B->key) {
         PV_HIP(hipGraphLaunch(B->exec, s));
+        PV_HIP(hipMemcpyAsync(mu, mu_ws, mu_bytes, hipMemcpyDeviceToDevice, s));
         ++B->replays;
         return PV_OK;
     }
@@ -1342,7 +1346,8 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
         e = pv::launch_batch_sweep(B->family, B->n_orb, dtype, vtype, w + L.tables + (size_t)v * n * rb, d_bi, d_i0,
                                    L.total_blocks, B->cap);
         if (e == hipSuccess)
-            e = pv::launch_batch_reduce(d_part, d_i0, n, nb, step == 0 ? 1 : 2, mu, M, step, d_invD, B->cap);
+            e = pv::launch_batch_reduce(d_part, d_i0, n, nb, step == 0 ? 1 : 2, reinterpret_cast<double*>(mu_ws), M,
+                                        step, d_invD, B->cap);
     }
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
@@ -1355,6 +1360,7 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     B->key = key;
     ++B->captures;
     PV_HIP(hipGraphLaunch(B->exec, s));
+    PV_HIP(hipMemcpyAsync(mu, mu_ws, mu_bytes, hipMemcpyDeviceToDevice, s));
     return PV_OK;
 }
 

@@ -39,11 +39,18 @@ def test_batched_kpm_c128_matches_each_instance_and_replays():
     mu2 = host(pv.pv_batch_kpm_moments(batch, rd, 64, a, b))
     assert np.array_equal(mu1, mu2)
     assert batch.stats() == (1, 1)
+    # the output buffer may move between calls without a new capture
+    keep = [torch.empty(n, device="cuda") for n in (1000, 3000)]
+    out = torch.full((len(cases), 4, 64), np.nan, dtype=torch.float64, device="cuda")
+    pv.pv_batch_kpm_moments(batch, rd, 64, a, b, mu=out)
+    assert np.array_equal(mu1, host(out))
+    assert batch.stats() == (1, 2)
+    del keep
     # a different start block pointer forces a new capture
     rd[2] = dev(rs[2] * 1.0)
     mu3 = host(pv.pv_batch_kpm_moments(batch, rd, 64, a, b))
     assert np.array_equal(mu1, mu3)
-    assert batch.stats() == (2, 1)
+    assert batch.stats() == (2, 2)
 
 
 def test_batched_kpm_c64_stated_error():
