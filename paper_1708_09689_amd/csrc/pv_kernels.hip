@@ -28,6 +28,7 @@
 // the same XCD shortly before (same L2).
 #include "pv_kernels.hpp"
 
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -53,6 +54,7 @@ constexpr int kBlock = 256;
 
 template <typename T>
 using vec2 = T __attribute__((ext_vector_type(2)));
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
 // Round-up division by a runtime constant (Granlund & Montgomery): exact for
 // every 32-bit numerator.
@@ -112,6 +114,11 @@ struct KArgs {
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;
+    // staged traversal (staged_kernel): column tiles of one row walked along
+    // the outer dimension w; m is the middle dimension (y in 3D, none in 2D)
+    int st_site, st_seg, st_nxs;   // elements per site, ring row length, column tiles per row
+    int st_Lm, st_Lw, st_pm, st_pw;
+    int st_C, st_Bm, st_parts;     // planes per walk, strip height, 8 XCD parts or 1
 };
 
 template <typename T>
@@ -207,13 +214,13 @@ __device__ __forceinline__ cplx<T> ld_row_nt(const cplx<T>* row, uint32_t boff) 
 //              summed over the site's (or row's) lanes with a fixed xor tree
 //              and written by one lane, read-modify-write (no atomics)
 template <typename T, typename VT>
-__device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, int64_t gidx, int glane, cplx<T> xc,
-                                         cplx<T> zv, cplx<T> av, T hr, T hi, T alT, T gaT, T er, T ei, T e0r,
-                                         T e0i, int c, double& dxx, double& dxr, double& dxi, double& dyy) {
+__device__ __forceinline__ void epilogue_ep(const KArgs<T, VT>& a, const unsigned ep, int64_t e, int64_t gidx,
+                                            int glane, cplx<T> xc, cplx<T> zv, cplx<T> av, T hr, T hi, T alT, T gaT,
+                                            T er, T ei, T e0r, T e0i, int c, double& dxx, double& dxr, double& dxi,
+                                            double& dyy) {
     T yr = alT * hr, yi = alT * hi;
     yr += (gaT != T(0)) ? gaT * zv.re : T(0);
     yi += (gaT != T(0)) ? gaT * zv.im : T(0);
-    const unsigned ep = a.ep;
     cplx<T> gv[3] = {{T(0), T(0)}, {T(0), T(0)}, {T(0), T(0)}};
     if (ep & (EP_GTERMS | EP_GRAD)) {
         const cplx<T>* gws[3] = {a.gw0, a.gw1, a.gw2};
@@ -248,6 +255,13 @@ __device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, int64
         for (int m = 1; m < a.ggroup; m <<= 1) g += __shfl_xor(g, m);
         if (glane == 0) a.grad[gidx] += g;
     }
+}
+
+template <typename T, typename VT>
+__device__ __forceinline__ void epilogue(const KArgs<T, VT>& a, int64_t e, int64_t gidx, int glane, cplx<T> xc,
+                                         cplx<T> zv, cplx<T> av, T hr, T hi, T alT, T gaT, T er, T ei, T e0r,
+                                         T e0i, int c, double& dxx, double& dxr, double& dxi, double& dyy) {
+    epilogue_ep(a, a.ep, e, gidx, glane, xc, zv, av, hr, hi, alT, gaT, er, ei, e0r, e0i, c, dxx, dxr, dxi, dyy);
 }
 
 template <typename T>
@@ -302,6 +316,32 @@ __device__ __forceinline__ bool x_shift(const A& a, int x, int dx, int& dxe) {
     return true;
 }
 
+// Per-lane data of a compiled family: for every slot the complex coefficient
+// of the lane's row and the element offset of the partner orbital inside the
+// site (zero coefficient where the row has fewer entries of that kind).
+template <class P, typename T, int NS, int NA>
+__device__ __forceinline__ void slot_coefficients(const double* coef, int o, int nb, T (&cre)[NA], T (&cim)[NA],
+                                                  int (&dq)[NA]) {
+    constexpr int NO = P::NO;
+    static constexpr Slots<P> S{};
+    sfor<NS>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        int q = S.q[j][0];
+        if constexpr (NO > 1) { if (o == 1) q = S.q[j][1]; }
+        if constexpr (NO > 2) { if (o == 2) q = S.q[j][2]; if (o == 3) q = S.q[j][3]; }
+        if (q >= 0) {
+            const double* e = coef + ((S.t[j] * NO + o) * NO + q) * 2;
+            cre[j] = T(e[0]);
+            cim[j] = T(e[1]);
+            dq[j] = (q - o) * nb;
+        } else {
+            cre[j] = T(0);
+            cim[j] = T(0);
+            dq[j] = 0;
+        }
+    });
+}
+
 // The work of one workgroup: tiles [t0, t1) of the part of the lattice made of
 // rows y in [y0, y0 + ny) (all z), swept slab by slab; partial dots go to
 // partials[b_out].
@@ -335,22 +375,7 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
     constexpr int NS = (P::FAMILY != FAM_GENERIC) ? S.n : 0;
     T cre[NS > 0 ? NS : 1], cim[NS > 0 ? NS : 1];
     int dq[NS > 0 ? NS : 1];
-    sfor<NS>([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        int q = S.q[j][0];
-        if constexpr (NO > 1) { if (o == 1) q = S.q[j][1]; }
-        if constexpr (NO > 2) { if (o == 2) q = S.q[j][2]; if (o == 3) q = S.q[j][3]; }
-        if (q >= 0) {
-            const double* e = a.coef + ((S.t[j] * NO + o) * NO + q) * 2;
-            cre[j] = T(e[0]);
-            cim[j] = T(e[1]);
-            dq[j] = (q - o) * nb;
-        } else {
-            cre[j] = T(0);
-            cim[j] = T(0);
-            dq[j] = 0;
-        }
-    });
+    slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
 
     constexpr uint32_t ES = sizeof(cplx<T>);
     for (int64_t t = t0; t < t1; ++t) {
@@ -505,6 +530,368 @@ void batch_sweep_kernel(const KArgs<T, VT>* __restrict__ table, const int* __res
     sweep_block<P, T, VT>(a, b, 0, a.Ly, t0, t1);
 }
 
+// ---------------------------------------------------------------------------
+// Staged sweep.  A workgroup owns a column tile of TW consecutive elements of
+// the rows (m, w) -- w the outer lattice index (z in 3D, y in 2D), m the
+// middle one (y in 3D, none in 2D) -- and walks w.  The rows (m, w-1),
+// (m, w), (m, w+1), each with one site of x halo on both sides, live in a
+// three-slot LDS ring, so a walk fetches every element of its rows once; the
+// rows (m -+ 1, w) of 3D lattices are staged per step, and the field values
+// of the tile's rows too.  The next step's rows, field values, z and acc_in
+// are loaded into registers while the current step computes from LDS, and
+// written to LDS behind a barrier.  Every load is a 16-byte chunk per lane.
+//
+// Walks are items of an XCD part (8 parts: split along m when the lattice has
+// at least 8 middle rows, along w otherwise).  Items are numbered walk chunk
+// first, then strips of st_Bm middle rows, then x tile, then m; the G
+// workgroups of a part take items j, j + G, ... so the workgroups resident on
+// one XCD walk a compact block of neighbouring columns side by side and read
+// each other's rows (m -+ 1, w) and x halos from the same L2.
+// ---------------------------------------------------------------------------
+template <typename T, int E>
+struct Staged {
+    static constexpr int ES = int(sizeof(cplx<T>));
+    static constexpr int CE = 16 / ES;                       // elements per 16-byte chunk
+    static constexpr int TW = kBlock * E;                    // elements per column tile
+    static constexpr int TCH = TW / (CE * kBlock);           // chunks per lane of a row without halo
+    static constexpr int RCH = (TW + 2 * 256 + CE * kBlock - 1) / (CE * kBlock);  // with halo (site <= 256)
+    static_assert(TW % (CE * kBlock) == 0, "a tile must be whole chunks per lane");
+};
+
+// Barrier for LDS hand-offs only: waits for this wave's LDS operations, not
+// for its global loads and stores, so prefetches and y stores stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // gfx9 encoding: lgkmcnt(0), vmcnt and expcnt unlimited
+    __builtin_amdgcn_s_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ u32x4 ld_chunk(const void* base, uint32_t boff) {
+    return *reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(base) + boff);
+}
+
+template <class P, typename T, typename VT, int E>
+struct StagedCtx {
+    using S = Staged<T, E>;
+    static constexpr int NTR = P::DIM == 3 ? 2 : 0;
+    const KArgs<T, VT>& a;
+    cplx<T>* ring;
+    cplx<T>* tra;
+    T* vl;
+    int tid, nch, m;
+    // per walk: byte offsets inside a row of this lane's ring chunks (x
+    // wrapped; open boundaries are applied when computing), side chunks,
+    // field entries and own elements (clamped into the row)
+    uint32_t roff[S::RCH];
+    uint32_t soff[S::TCH];
+    uint32_t voff[E];
+    uint32_t eoff[E];
+
+    __device__ __forceinline__ int64_t row_of(int mm, int ww) const {
+        return P::DIM == 3 ? (int64_t)ww * a.Ly + mm : (int64_t)ww;
+    }
+    // Row (mm, ww) after wrapping periodic dimensions; -1 when an open
+    // boundary drops it.
+    __device__ __forceinline__ int64_t row_idx(int mm, int ww) const {
+        bool ok = true;
+        if (ww < 0 || ww >= a.st_Lw) {
+            ok = a.st_pw;
+            ww += ww < 0 ? a.st_Lw : -a.st_Lw;
+            if (ww >= a.st_Lw) ww %= a.st_Lw;   // w + 2 on a lattice of one plane
+        }
+        if (mm < 0 || mm >= a.st_Lm) {
+            ok = ok && a.st_pm;
+            mm += mm < 0 ? a.st_Lm : -a.st_Lm;
+        }
+        return ok ? row_of(mm, ww) : -1;
+    }
+    __device__ __forceinline__ const cplx<T>* row_ptr(int mm, int ww) const {
+        const int64_t r = row_idx(mm, ww);
+        return r >= 0 ? a.x + r * a.rowel : a.zero_row;
+    }
+    __device__ __forceinline__ void setup(int xe0) {
+        const int rowel = a.rowel;
+#pragma unroll
+        for (int k = 0; k < S::RCH; ++k) {
+            int g = xe0 - a.st_site + (tid + k * kBlock) * S::CE;
+            if (g < 0) g += rowel;
+            if (g >= rowel) g %= rowel;
+            roff[k] = uint32_t(g) * S::ES;
+        }
+#pragma unroll
+        for (int k = 0; k < S::TCH; ++k) {
+            const int g = xe0 + (tid + k * kBlock) * S::CE;
+            soff[k] = uint32_t(g < rowel ? g : rowel - S::CE) * S::ES;
+        }
+        const int rowlen = a.Lx * P::NO;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            int r = (xe0 >> a.lognb) + tid + k * kBlock;   // orbital row inside the lattice row
+            if (r >= rowlen) r = rowlen - 1;
+            voff[k] = uint32_t(a.pot_mode == 1 ? r / P::NO : r);
+            const int xe = xe0 + tid + k * kBlock;
+            eoff[k] = uint32_t(xe < rowel ? xe : rowel - 1) * S::ES;
+        }
+    }
+    __device__ __forceinline__ void load_ring(int ww, u32x4 (&r)[S::RCH]) const {
+        const cplx<T>* rp = row_ptr(m, ww);
+#pragma unroll
+        for (int k = 0; k < S::RCH; ++k)
+            if (k * kBlock < nch) r[k] = ld_chunk<T>(rp, roff[k]);
+    }
+    __device__ __forceinline__ void store_ring(int slot, const u32x4 (&r)[S::RCH]) const {
+        u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
+#pragma unroll
+        for (int k = 0; k < S::RCH; ++k)
+            if (k * kBlock < nch && tid + k * kBlock < nch) d[tid + k * kBlock] = r[k];
+    }
+    __device__ __forceinline__ void load_side(int ww, u32x4 (&r)[NTR > 0 ? NTR : 1][S::TCH]) const {
+        if constexpr (NTR > 0) {
+#pragma unroll
+            for (int h = 0; h < NTR; ++h) {
+                const cplx<T>* rp = row_ptr(m + (h == 0 ? -1 : 1), ww);
+#pragma unroll
+                for (int k = 0; k < S::TCH; ++k) r[h][k] = ld_chunk<T>(rp, soff[k]);
+            }
+        }
+    }
+    __device__ __forceinline__ void store_side(const u32x4 (&r)[NTR > 0 ? NTR : 1][S::TCH]) const {
+        if constexpr (NTR > 0) {
+#pragma unroll
+            for (int h = 0; h < NTR; ++h) {
+                u32x4* d = reinterpret_cast<u32x4*>(tra + h * S::TW);
+#pragma unroll
+                for (int k = 0; k < S::TCH; ++k) d[tid + k * kBlock] = r[h][k];
+            }
+        }
+    }
+    // Field of the tile's orbital rows (TW / nb of them) in row ww.
+    __device__ __forceinline__ void load_field(int ww, T (&v)[E]) const {
+        if (a.V == nullptr) return;
+        const int64_t r = row_of(m, ww);
+        const VT* vb = a.V + r * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if (k * kBlock < (S::TW >> a.lognb)) v[k] = T(vb[voff[k]]);
+    }
+    __device__ __forceinline__ void store_field(const T (&v)[E]) const {
+        if (a.V == nullptr) return;
+        const int nrow = S::TW >> a.lognb;
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if (tid + k * kBlock < nrow) vl[tid + k * kBlock] = v[k];
+    }
+    // The lane's z and acc_in elements of row ww.
+    __device__ __forceinline__ void load_lane(int ww, unsigned ep, cplx<T> (&zv)[E], cplx<T> (&av)[E]) const {
+        const int64_t rb = row_of(m, ww) * a.rowel;
+        const cplx<T>* zr = a.zsrc + rb;
+        const cplx<T>* ar = a.asrc + rb;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            zv[k] = ld_row_nt(zr, eoff[k]);
+            if (ep & EP_ACC_ADD) av[k] = ld_row_nt(ar, eoff[k]);
+        }
+    }
+};
+
+template <class P, typename T, typename VT, int E, unsigned EPM>
+__device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, int part, int jb, int G) {
+    using S = Staged<T, E>;
+    using Ctx = StagedCtx<P, T, VT, E>;
+    constexpr int NO = P::NO;
+    constexpr int NTR = Ctx::NTR;
+    static_assert(P::FAMILY != FAM_GENERIC, "staged sweeps need a compiled family");
+    extern __shared__ __align__(16) unsigned char smem[];
+    const unsigned ep = EPM ? EPM : a.ep;
+    const int tid = threadIdx.x;
+    const int nb = a.nb;
+    const int c = tid & (nb - 1);
+    const int o = (tid >> a.lognb) & (NO - 1);
+    const int site = a.st_site;
+
+    double al = a.alpha, be = a.beta, ga = a.gamma;
+    if (a.colp != nullptr) {
+        al = a.colp[3 * c];
+        be = a.colp[3 * c + 1];
+        ga = a.colp[3 * c + 2];
+    }
+    const T alT = T(al), beT = T(be), gaT = T(ga);
+    const T er = T(a.eta_re), ei = T(a.eta_im), e0r = T(a.eta0_re), e0i = T(a.eta0_im);
+    const T dgr = T(a.coef[(((size_t)P::NT * NO + o) * NO + o) * 2]);
+    const T dgi = T(a.coef[(((size_t)P::NT * NO + o) * NO + o) * 2 + 1]);
+    static constexpr Slots<P> SL{};
+    constexpr int NS = SL.n;
+    T cre[NS], cim[NS];
+    int dq[NS];
+    slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
+    double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
+
+    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, tid, a.st_seg / S::CE, 0};
+    cx.tra = cx.ring + 3 * a.st_seg;
+    cx.vl = reinterpret_cast<T*>(cx.tra + NTR * S::TW);
+
+    // this part's ranges of m and w
+    int m0 = 0, m1 = a.st_Lm, wA = 0, wB = a.st_Lw;
+    if (a.st_parts == 8) {
+        if (a.st_Lm >= 8) {
+            m0 = a.st_Lm * part / 8;
+            m1 = a.st_Lm * (part + 1) / 8;
+        } else {
+            wA = a.st_Lw * part / 8;
+            wB = a.st_Lw * (part + 1) / 8;
+        }
+    }
+    const int nm = m1 - m0, nW = wB - wA;
+    const int nwc = nW > 0 ? (nW + a.st_C - 1) / a.st_C : 0;
+    const int bms = min(a.st_Bm, nm);
+    const int per_wc = nm * a.st_nxs;
+    const int items = nwc * per_wc;
+
+    for (int j = jb; j < items; j += G) {
+        const int wc = j / per_wc;
+        const int rem = j - wc * per_wc;
+        const int ms = (rem / (bms * a.st_nxs)) * bms;
+        const int bm = min(bms, nm - ms);
+        const int r2 = rem - ms * a.st_nxs;
+        const int xs = r2 / bm;
+        cx.m = m0 + ms + (r2 - xs * bm);
+        const int xe0 = xs * S::TW;
+        cx.setup(xe0);
+        const int wa = wA + wc * a.st_C;
+        const int wb = min(wa + a.st_C, wB);
+
+        // prologue: ring rows wa - 1, wa, wa + 1 in slots 0, 1, 2
+        u32x4 rr[3][S::RCH];
+        u32x4 tr[NTR > 0 ? NTR : 1][S::TCH];
+        T vv[E];
+        cplx<T> zv[E], av[E];
+        cx.load_ring(wa - 1, rr[0]);
+        cx.load_ring(wa, rr[1]);
+        cx.load_ring(wa + 1, rr[2]);
+        cx.load_side(wa, tr);
+        cx.load_field(wa, vv);
+        cx.load_lane(wa, ep, zv, av);
+        cx.store_ring(0, rr[0]);
+        cx.store_ring(1, rr[1]);
+        cx.store_ring(2, rr[2]);
+        cx.store_side(tr);
+        cx.store_field(vv);
+        lds_barrier();
+
+        for (int w = wa; w < wb; ++w) {
+            const int s = w - wa;
+            // prefetch of the next step (unconditional so that the compiler's
+            // wait counts stay exact; after the last step of a walk it reads a
+            // valid row again and nobody uses it)
+            const int wn = w + 1 < wb ? w + 1 : w;
+            cplx<T> zn[E], an[E];
+            cx.load_ring(wn + 1, rr[0]);
+            cx.load_side(wn, tr);
+            cx.load_field(wn, vv);
+            cx.load_lane(wn, ep, zn, an);
+
+            const cplx<T>* rm = cx.ring + (s % 3) * a.st_seg + site;
+            const cplx<T>* r0 = cx.ring + ((s + 1) % 3) * a.st_seg + site;
+            const cplx<T>* rp = cx.ring + ((s + 2) % 3) * a.st_seg + site;
+            const int64_t rowi = cx.row_of(cx.m, w);
+            const int64_t rb = rowi * a.rowel;
+            T yr[E], yi[E];
+            cplx<T> xs_[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int l = tid + k * kBlock;
+                const int xe = xe0 + l;
+                const int x = xe >> a.logsite;
+                const bool xlo = a.px || x > 0, xhi = a.px || x < a.Lx - 1;
+                const cplx<T> xc = r0[l];
+                const T vs = a.V != nullptr ? cx.vl[l >> a.lognb] : T(0);
+                const T d = dgr - beT + vs;
+                T hr = d * xc.re - dgi * xc.im;
+                T hi = d * xc.im + dgi * xc.re;
+                sfor<NS>([&](auto jj) {
+                    constexpr int jx = decltype(jj)::value;
+                    constexpr int t = SL.t[jx];
+                    cplx<T> v;
+                    if constexpr (t == P::NT) {
+                        v = r0[l + dq[jx]];
+                    } else {
+                        constexpr int tt = t < P::NT ? t : 0;
+                        constexpr int dx = P::off[tt][0];
+                        constexpr int dm = P::DIM == 3 ? P::off[tt][1] : 0;
+                        constexpr int dw = P::DIM == 3 ? P::off[tt][2] : P::off[tt][1];
+                        if constexpr (dm == 0) {
+                            const cplx<T>* rw = dw < 0 ? rm : (dw > 0 ? rp : r0);
+                            v = rw[l + dx * site + dq[jx]];
+                            if constexpr (dx < 0) v = zero_unless(xlo, v);
+                            if constexpr (dx > 0) v = zero_unless(xhi, v);
+                        } else {
+                            static_assert(dx == 0 && dw == 0, "side rows carry no x or w offset");
+                            v = cx.tra[(dm < 0 ? 0 : S::TW) + l + dq[jx]];
+                        }
+                    }
+                    mac<T>(hr, hi, SL.kind[jx], cre[jx], cim[jx], v);
+                });
+                xs_[k] = xc;
+                yr[k] = hr;
+                yi[k] = hi;
+            }
+            // hand the prefetched rows over, then finish the elements (the
+            // stores go out after the LDS writes, so waiting for the
+            // prefetch never waits for them)
+            lds_barrier();
+            cx.store_ring(s % 3, rr[0]);
+            cx.store_side(tr);
+            cx.store_field(vv);
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int xe = xe0 + tid + k * kBlock;
+                if (xe < a.rowel) {
+                    const int64_t st = rowi * a.Lx + (xe >> a.logsite);
+                    const int64_t gidx = a.ggroup == nb ? st * NO + o : st;
+                    epilogue_ep(a, ep, rb + xe, gidx, tid & (a.ggroup - 1), xs_[k], zv[k], av[k], yr[k], yi[k], alT,
+                                gaT, er, ei, e0r, e0i, c, dxx, dxr, dxi, dyy);
+                }
+                zv[k] = zn[k];
+                av[k] = an[k];
+            }
+            lds_barrier();
+        }
+    }
+
+    if (ep & EP_DOTS) {
+        for (int mm = nb; mm < 64; mm <<= 1) {
+            dxx += __shfl_xor(dxx, mm);
+            dxr += __shfl_xor(dxr, mm);
+            dxi += __shfl_xor(dxi, mm);
+            dyy += __shfl_xor(dyy, mm);
+        }
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(smem);   // the ring is free after the last barrier
+        const int wave = tid >> 6, lane = tid & 63;
+        if (lane < nb) {
+            red[(wave * PV_MAX_NB_K + lane) * 4 + 0] = dxx;
+            red[(wave * PV_MAX_NB_K + lane) * 4 + 1] = dxr;
+            red[(wave * PV_MAX_NB_K + lane) * 4 + 2] = dxi;
+            red[(wave * PV_MAX_NB_K + lane) * 4 + 3] = dyy;
+        }
+        __syncthreads();
+        if (tid < nb * 4) {
+            const int cc = tid >> 2, q = tid & 3;
+            double sum = 0.0;
+            for (int wv = 0; wv < kBlock / 64; ++wv) sum += red[(wv * PV_MAX_NB_K + cc) * 4 + q];
+            a.partials[((size_t)b_out * nb + cc) * 4 + q] = sum;
+        }
+    }
+}
+
+template <class P, typename T, typename VT, int E, unsigned EPM>
+__global__ __launch_bounds__(kBlock) void staged_kernel(KArgs<T, VT> a) {
+    if (a.st_parts == 8)
+        staged_block<P, T, VT, E, EPM>(a, blockIdx.x, blockIdx.x & 7, blockIdx.x >> 3, gridDim.x >> 3);
+    else
+        staged_block<P, T, VT, E, EPM>(a, blockIdx.x, 0, blockIdx.x, gridDim.x);
+}
+
 // Tiles per workgroup: enough workgroups to keep every CU busy for several
 // rounds (>= 64 per CU), at most 16 tiles each (bounds the partial-dot
 // buffer).  PV_TILES_PER_BLOCK overrides it for tuning runs.
@@ -599,8 +986,118 @@ void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
     }
 }
 
+int env_int(const char* name, int dflt) {
+    const char* e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+// LDS of a staged workgroup: three ring rows with halo, the side rows of 3D
+// lattices, and the field of the tile's orbital rows.
+template <class P, typename T, int E>
+size_t staged_lds_bytes(int nb) {
+    using S = Staged<T, E>;
+    const int seg = S::TW + 2 * P::NO * nb;
+    const int ntr = P::DIM == 3 ? 2 : 0;
+    return size_t(3 * seg + ntr * S::TW) * S::ES + size_t(S::TW / nb) * sizeof(T);
+}
+
+template <class P, typename T, typename VT, int E, unsigned EPM>
+hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
+    using S = Staged<T, E>;
+    KArgs<T, VT> a;
+    make_kargs<P, T, VT>(p, false, a);
+    a.st_site = P::NO * p.nb;
+    a.st_seg = S::TW + 2 * a.st_site;
+    a.st_nxs = (a.rowel + S::TW - 1) / S::TW;
+    if (P::DIM == 3) {
+        a.st_Lm = a.Ly; a.st_Lw = a.Lz; a.st_pm = a.py; a.st_pw = a.pz;
+    } else {
+        a.st_Lm = 1; a.st_Lw = a.Ly; a.st_pm = 0; a.st_pw = a.py;
+    }
+    const size_t lds = staged_lds_bytes<P, T, E>(p.nb);
+    const void* kern = reinterpret_cast<const void*>(&staged_kernel<P, T, VT, E, EPM>);
+    // workgroups resident per CU at this LDS size (cached per size)
+    static size_t occ_lds[8] = {};
+    static int occ_n[8] = {};
+    int occ = 0;
+    for (int i = 0; i < 8; ++i)
+        if (occ_lds[i] == lds) occ = occ_n[i];
+    if (occ == 0) {
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+            if (e != hipSuccess) return e;
+        }
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, staged_kernel<P, T, VT, E, EPM>, kBlock, lds) !=
+                hipSuccess || occ < 1)
+            occ = 1;
+        for (int i = 0; i < 8; ++i)
+            if (occ_lds[i] == 0) {
+                occ_lds[i] = lds;
+                occ_n[i] = occ;
+                break;
+            }
+    }
+    int G8 = p.st_G8 > 0 ? p.st_G8 : (num_cus >= 8 ? num_cus / 8 : 1) * occ;
+    if (G8 > 256) G8 = 256;
+    // the largest part: a split along m when there are 8 middle rows, else along w
+    const bool split_m = a.st_Lm >= 8;
+    const int nm = split_m ? (a.st_Lm + 7) / 8 : a.st_Lm;
+    const int nW = split_m ? a.st_Lw : (a.st_Lw + 7) / 8;
+    const int cols = nm * a.st_nxs;
+    if (nW < 1) {
+        a.st_C = 1;
+    } else if (p.st_C > 0) {
+        a.st_C = p.st_C < nW ? p.st_C : nW;
+    } else {
+        int nwc = (G8 + cols - 1) / cols;
+        if (nwc > nW) nwc = nW;
+        a.st_C = (nW + nwc - 1) / nwc;
+    }
+    const int items = nW < 1 ? 1 : ((nW + a.st_C - 1) / a.st_C) * cols;
+    if (G8 > items) G8 = items;
+    int bx = int(std::lround(std::sqrt(double(G8) * a.st_site / S::TW)));
+    if (bx > a.st_nxs) bx = a.st_nxs;
+    if (bx < 1) bx = 1;
+    a.st_Bm = p.st_Bm > 0 ? p.st_Bm : (G8 / bx > 1 ? G8 / bx : 1);
+    a.st_parts = 8;
+    p.grid = 8 * G8;
+    hipLaunchKernelGGL((staged_kernel<P, T, VT, E, EPM>), dim3(p.grid), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+// Epilogue specialisations of the staged kernel: the Chebyshev step with
+// fused dots (KPM), the series step (propagation, filters), and every other
+// combination with the flags read at run time.
+template <class P, typename T, typename VT, int E>
+hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
+    constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD;
+    if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
+    if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
+    return launch_staged<P, T, VT, E, 0u>(p, num_cus, s);
+}
+
+// Sweep kernel of a launch: the staged kernel for compiled families when the
+// block is 16-byte aligned (its chunk loads), else the direct kernel.
+// p.kernel (or PV_SWEEP) 1 forces direct, 2 staged; p.st_E (or PV_STAGED_E)
+// selects the elements per lane.
 template <class P, typename T, typename VT>
 hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
+    if constexpr (P::FAMILY != FAM_GENERIC) {
+        static const int env_kernel = env_int("PV_SWEEP", 0);
+        static const int env_e = env_int("PV_STAGED_E", 0);
+        const int kind = p.kernel > 0 ? p.kernel : env_kernel;
+        const bool aligned = ((reinterpret_cast<uintptr_t>(p.x) | reinterpret_cast<uintptr_t>(p.zero_row)) & 15) == 0;
+        if (kind != 1 && aligned) {
+            // elements per lane: two for complex64 (16-byte chunks), and for
+            // complex128 from nb = 8 on (longer tiles: fewer halo chunks per
+            // element, more bytes in flight per workgroup)
+            const int e = p.st_E > 0 ? p.st_E : (env_e > 0 ? env_e : (sizeof(T) == 8 && p.nb < 8 ? 1 : 2));
+            if constexpr (sizeof(T) == 8)
+                return e == 2 ? launch_staged_ep<P, T, VT, 2>(p, num_cus, s) : launch_staged_ep<P, T, VT, 1>(p, num_cus, s);
+            else
+                return e == 4 ? launch_staged_ep<P, T, VT, 4>(p, num_cus, s) : launch_staged_ep<P, T, VT, 2>(p, num_cus, s);
+        }
+    }
     (void)num_cus;
     KArgs<T, VT> a;
     make_kargs<P, T, VT>(p, false, a);
@@ -815,8 +1312,6 @@ __global__ __launch_bounds__(kBlock) void rotate_kernel(const cplx<T>* __restric
     }
 }
 
-using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
-
 // dst[0..n) = 0 for 32-bit words (gradients, zero vectors of the adjoint).
 __global__ __launch_bounds__(kBlock) void zero_kernel(uint32_t* __restrict__ dst, int64_t n) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
@@ -847,7 +1342,8 @@ int64_t sweep_grid_max(const int64_t L[3], int n_orb, int nb) {
     const int64_t rowel = L[0] * n_orb * nb;
     const int64_t ntiles = (rowel + kBlock - 1) / kBlock * ((L[1] + 7) / 8) * L[2];
     const int tpb = tiles_per_block(ntiles * 8);
-    return 8 * ((ntiles + tpb - 1) / tpb);
+    const int64_t direct = 8 * ((ntiles + tpb - 1) / tpb);
+    return direct > 8 * 256 ? direct : 8 * 256;   // staged: at most 256 workgroups per XCD part
 }
 
 hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s) {

@@ -59,8 +59,11 @@ struct SweepParams {
     const int* offs;      // device: [n_terms][3] (generic family only)
     const double* colp;   // device: [nb][3] per-column alpha, beta, gamma or NULL
     const void* zero_row;   // device zeros, >= L[0]*n_orb*nb elements
-    int slab_rows;          // rows per y-slab of the sweep order
-    int tpb;                // tiles per workgroup (0 = heuristic)
+    int slab_rows;          // rows per y-slab of the sweep order (direct kernel)
+    int tpb;                // tiles per workgroup (direct kernel; 0 = heuristic)
+    int kernel;             // 0 = choose, 1 = direct, 2 = staged
+    int st_E, st_C, st_Bm, st_G8;   // staged kernel: elements per lane, planes per walk,
+                                    // strip height, workgroups per XCD (0 = heuristic)
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;
