@@ -319,6 +319,55 @@ pv_status pv_batch_stats(const pv_batch *batch, int *captures, int *replays);
  * multiple of 16), a plain streaming copy kernel. */
 pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/*
+ * Launch shape of the stencil sweep for one (dtype, nb) of a lattice -- the
+ * GPU counterpart of the cache-blocking choices of Sec. 3.1 (layer
+ * conditions, blocking factor).  Zero fields take the library's defaults.
+ *   kernel           0 choose, 1 direct (every neighbour load goes through the
+ *                    caches; any stencil), 2 staged (LDS ring of rows along
+ *                    the outer lattice axis; compiled stencil families with
+ *                    16-byte aligned blocks, otherwise direct is used)
+ *   elems_per_lane   staged: 1 or 2 (complex128), 2 or 4 (complex64)
+ *   walk_planes      staged: outer-axis planes per walk of a workgroup
+ *   strip_rows       staged: middle-axis rows per strip of the work order
+ *   groups_per_xcd   staged: workgroups per XCD, 1..256
+ *   tiles_per_group  direct: row tiles per workgroup, up to 64 (values below
+ *                    the default are raised to it)
+ *   slab_rows        direct: y rows per slab of the sweep order
+ * The shape changes speed only: every shape computes the same result up to
+ * the summation order of the fused dot products.
+ */
+typedef struct pv_tuning {
+    int kernel;
+    int elems_per_lane;
+    int walk_planes;
+    int strip_rows;
+    int groups_per_xcd;
+    int tiles_per_group;
+    int slab_rows;
+} pv_tuning;
+
+/* Set (t != NULL) or reset to defaults (t == NULL) the shape used for
+ * (dtype, nb); PV_ERR_INVALID_ARG for values outside the ranges above. */
+pv_status pv_lattice_set_tuning(pv_lattice *lat, int dtype, int nb, const pv_tuning *t);
+pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tuning *t);
+
+/*
+ * Autotuner: times candidate shapes of one Chebyshev step (sweep with fused
+ * dots and its reduction) on the stream's device and applies the fastest to
+ * the lattice for (dtype, nb).  cache_path names a JSON-lines file (NULL:
+ * the PV_TUNE_CACHE environment variable, else no cache); an entry whose key
+ * (stencil family, orbitals, extents, boundary conditions, nb, dtype, field
+ * type, device architecture and CU count) matches is applied without timing,
+ * and a new result is appended.  work: pv_autotune_workspace_size() bytes,
+ * overwritten.  Synchronises the stream.  out and ms (either may be NULL)
+ * receive the chosen shape and its time per step in milliseconds (0 when
+ * the shape came from the cache).
+ */
+size_t pv_autotune_workspace_size(const pv_lattice *lat, int dtype, int nb);
+pv_status pv_autotune(pv_lattice *lat, int dtype, int nb, const char *cache_path, void *work,
+                      size_t work_bytes, void *stream, pv_tuning *out, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

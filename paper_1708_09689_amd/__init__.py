@@ -46,6 +46,13 @@ class pv_lattice_desc(ctypes.Structure):
                 ("blocks", _dp), ("onsite", _dp), ("pot_mode", ctypes.c_int), ("flags", ctypes.c_uint)]
 
 
+class pv_tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("kernel", "elems_per_lane", "walk_planes", "strip_rows",
+                                            "groups_per_xcd", "tiles_per_group", "slab_rows")]
+
+
+TUNING_FIELDS = [f[0] for f in pv_tuning._fields_]
+
 SIGNATURES = {
     "pv_last_error": (ctypes.c_char_p, []),
     "pv_status_string": (ctypes.c_char_p, [_i]),
@@ -82,6 +89,10 @@ SIGNATURES = {
     "pv_kpm_moments_vjp": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_cheb_propagate_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pv_lattice_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
+    "pv_lattice_get_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
+    "pv_autotune_workspace_size": (_sz, [_vp, _i, _i]),
+    "pv_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p, _vp, _sz, _vp, ctypes.POINTER(pv_tuning), _dp]),
 }
 
 _lib = None
@@ -347,6 +358,36 @@ def pv_stream_copy(src, dst):
         raise ValueError("dst too small")
     _check(lib().pv_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, _stream()))
     return dst
+
+
+def pv_lattice_set_tuning(lat, dtype: int, nb: int, tuning=None):
+    """Launch shape for (dtype, nb): dict with keys of TUNING_FIELDS (missing = 0), None = defaults."""
+    if tuning is None:
+        _check(lib().pv_lattice_set_tuning(lat.handle, dtype, nb, None))
+        return
+    bad = set(tuning) - set(TUNING_FIELDS)
+    if bad:
+        raise ValueError(f"unknown tuning fields {sorted(bad)}")
+    t = pv_tuning(**{k: int(v) for k, v in tuning.items()})
+    _check(lib().pv_lattice_set_tuning(lat.handle, dtype, nb, ctypes.byref(t)))
+
+
+def pv_lattice_get_tuning(lat, dtype: int, nb: int) -> dict:
+    t = pv_tuning()
+    _check(lib().pv_lattice_get_tuning(lat.handle, dtype, nb, ctypes.byref(t)))
+    return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+
+def pv_autotune(lat, nb: int, dtype: int = PV_C128, cache_path=None, device="cuda"):
+    """Time candidate launch shapes of one Chebyshev step and apply the fastest;
+    returns (shape dict, ms per step; 0.0 when taken from the cache)."""
+    ws = _workspace(lib().pv_autotune_workspace_size(lat.handle, dtype, nb), device)
+    t = pv_tuning()
+    ms = ctypes.c_double()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().pv_autotune(lat.handle, dtype, nb, path, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(),
+                             ctypes.byref(t), ctypes.byref(ms)))
+    return {k: getattr(t, k) for k in TUNING_FIELDS}, ms.value
 
 
 def pv_chebfd_filter_coefficients(lam_l, lam_r, a, b, K):

@@ -90,6 +90,8 @@ struct pv_lattice {
     // borrowed field
     const void* V = nullptr;
     int vtype = 0;
+    // launch shapes per (dtype, log2 nb)
+    pv_tuning tune[2][7] = {};
 };
 
 namespace {
@@ -272,8 +274,22 @@ void bessel_j(double z, int kmax, std::vector<double>& out) {
 
 // Slab height and zero row of a sweep (the device state of the lattice must
 // be current).
+int log2_nb(int nb) {
+    int k = 0;
+    while ((1 << k) < nb) ++k;
+    return k;
+}
+
 pv_status fill_traversal(pv_lattice* l, int dtype, int nb, pv::SweepParams& p) {
-    p.slab_rows = slab_rows(l, dtype, nb);
+    const pv_tuning& t = l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    const int ny_max = int((l->L[1] + 7) / 8);
+    p.slab_rows = t.slab_rows > 0 ? std::min(t.slab_rows, ny_max) : slab_rows(l, dtype, nb);
+    p.tpb = t.tiles_per_group;
+    p.kernel = t.kernel;
+    p.st_E = t.elems_per_lane;
+    p.st_C = t.walk_planes;
+    p.st_Bm = t.strip_rows;
+    p.st_G8 = t.groups_per_xcd;
     p.zero_row = l->d_zero;
     return PV_OK;
 }
@@ -912,6 +928,231 @@ extern "C" pv_status pv_stream_copy(const void* src, void* dst, size_t bytes, vo
 }
 
 // ---------------------------------------------------------------------------
+// Launch shapes and the autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+pv_status check_tuning(int dtype, const pv_tuning& t) {
+    if (t.kernel < 0 || t.kernel > 2) return fail(PV_ERR_INVALID_ARG, "tuning.kernel = %d (0, 1 or 2)", t.kernel);
+    const int e = t.elems_per_lane;
+    if (e != 0 && (dtype == PV_C128 ? (e != 1 && e != 2) : (e != 2 && e != 4)))
+        return fail(PV_ERR_INVALID_ARG, "tuning.elems_per_lane = %d not available for this dtype", e);
+    if (t.walk_planes < 0 || t.strip_rows < 0 || t.slab_rows < 0)
+        return fail(PV_ERR_INVALID_ARG, "tuning: negative walk_planes, strip_rows or slab_rows");
+    if (t.groups_per_xcd < 0 || t.groups_per_xcd > 256)
+        return fail(PV_ERR_INVALID_ARG, "tuning.groups_per_xcd = %d (0..256)", t.groups_per_xcd);
+    if (t.tiles_per_group < 0 || t.tiles_per_group > 64)
+        return fail(PV_ERR_INVALID_ARG, "tuning.tiles_per_group = %d (0..64)", t.tiles_per_group);
+    return PV_OK;
+}
+
+std::string tune_key(const pv_lattice* l, int dtype, int nb) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "family=%d orb=%d L=%lldx%lldx%lld bc=%d%d%d nb=%d dtype=%d vtype=%d dev=%s cus=%d",
+                  l->family, l->n_orb, (long long)l->L[0], (long long)l->L[1], (long long)l->L[2], l->periodic[0],
+                  l->periodic[1], l->periodic[2], nb, dtype, l->V ? l->vtype : -1, arch.c_str(), cus);
+    return buf;
+}
+
+const char* const kTuneFields[7] = {"kernel",          "elems_per_lane",  "walk_planes", "strip_rows",
+                                    "groups_per_xcd", "tiles_per_group", "slab_rows"};
+
+int* tune_field(pv_tuning& t, int i) {
+    int* f[7] = {&t.kernel, &t.elems_per_lane, &t.walk_planes, &t.strip_rows,
+                 &t.groups_per_xcd, &t.tiles_per_group, &t.slab_rows};
+    return f[i];
+}
+
+// Cache lines: {"key": "...", "kernel": k, ..., "ms": t}.  Returns true and
+// fills t for the last line whose key matches.
+bool cache_lookup(const char* path, const std::string& key, pv_tuning& t) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[4096];
+    const std::string want = "\"key\": \"" + key + "\"";
+    while (std::fgets(line, sizeof line, f)) {
+        if (!std::strstr(line, want.c_str())) continue;
+        pv_tuning r{};
+        bool ok = true;
+        for (int i = 0; i < 7 && ok; ++i) {
+            const std::string name = std::string("\"") + kTuneFields[i] + "\": ";
+            const char* q = std::strstr(line, name.c_str());
+            if (!q) { ok = false; break; }
+            *tune_field(r, i) = int(std::strtol(q + name.size(), nullptr, 10));
+        }
+        if (ok) {
+            t = r;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_append(const char* path, const std::string& key, const pv_tuning& t, double ms) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\"", key.c_str());
+    pv_tuning c = t;
+    for (int i = 0; i < 7; ++i) std::fprintf(f, ", \"%s\": %d", kTuneFields[i], *tune_field(c, i));
+    std::fprintf(f, ", \"ms\": %.6f}\n", ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" pv_status pv_lattice_set_tuning(pv_lattice* l, int dtype, int nb, const pv_tuning* t) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    pv_tuning z{};
+    if (t && (st = check_tuning(dtype, *t)) != PV_OK) return st;
+    l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)] = t ? *t : z;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_lattice_get_tuning(const pv_lattice* l, int dtype, int nb, pv_tuning* t) {
+    if (!l || !t) return fail(PV_ERR_INVALID_ARG, "lattice or output is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    *t = l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    return PV_OK;
+}
+
+extern "C" size_t pv_autotune_workspace_size(const pv_lattice* l, int dtype, int nb) {
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    return 2 * vec_bytes(l, dtype, nb) + partial_bytes(l, nb) + align_up(sizeof(double) * 4 * nb);
+}
+
+extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* cache_path, void* work,
+                                 size_t work_bytes, void* stream, pv_tuning* out, double* ms_out) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if ((st = check_dtype(l, dtype)) != PV_OK) return st;
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    const size_t need = pv_autotune_workspace_size(l, dtype, nb);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!cache_path) cache_path = std::getenv("PV_TUNE_CACHE");
+    const std::string key = tune_key(l, dtype, nb);
+    pv_tuning best{};
+    if (cache_path && cache_lookup(cache_path, key, best) && check_tuning(dtype, best) == PV_OK) {
+        l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)] = best;
+        if (out) *out = best;
+        if (ms_out) *ms_out = 0.0;
+        return PV_OK;
+    }
+
+    // buffers: x = 0, y = 0; the step y = 2 H~ x - y with fused dots
+    char* w = static_cast<char*>(work);
+    const size_t vb = vec_bytes(l, dtype, nb);
+    void* x = w;
+    void* y = w + vb;
+    double* part = reinterpret_cast<double*>(w + 2 * vb);
+    double* dots = reinterpret_cast<double*>(w + 2 * vb + partial_bytes(l, nb));
+    PV_HIP(pv::launch_zero(w, 2 * vb, s));
+    hipEvent_t e0, e1;
+    PV_HIP(hipEventCreate(&e0));
+    PV_HIP(hipEventCreate(&e1));
+    pv_tuning& slot = l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    const pv_tuning saved = slot;
+    auto run = [&](int reps) -> hipError_t {
+        for (int r = 0; r < reps; ++r) {
+            pv::SweepParams p = base_params(l, dtype, nb);
+            fill_traversal(l, dtype, nb, p);
+            p.x = x; p.z = y; p.y = y;
+            p.alpha = 2.0 / 8.0; p.beta = 0.0; p.gamma = -1.0;
+            p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
+            p.partials = part;
+            hipError_t e = pv::launch_sweep(p, num_cus(), s);
+            if (e == hipSuccess) e = pv::launch_reduce_dots(part, p.grid, nb, 0, dots, 0, 0, 0.0, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    // time of one step under shape t (milliseconds); warm-up first, then
+    // enough repetitions for about 20 ms
+    auto measure = [&](const pv_tuning& t, double& ms) -> hipError_t {
+        slot = t;
+        hipError_t e = run(1);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+        if ((e = run(1)) != hipSuccess) return e;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        float t1 = 0.f;
+        if ((e = hipEventElapsedTime(&t1, e0, e1)) != hipSuccess) return e;
+        int reps = t1 > 0.f ? int(20.0 / t1) : 20;
+        reps = reps < 2 ? 2 : (reps > 50 ? 50 : reps);
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+        if ((e = run(reps)) != hipSuccess) return e;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+        float tt = 0.f;
+        if ((e = hipEventElapsedTime(&tt, e0, e1)) != hipSuccess) return e;
+        ms = double(tt) / reps;
+        return hipSuccess;
+    };
+    double best_ms = 1e300;
+    hipError_t herr = hipSuccess;
+    auto consider = [&](const pv_tuning& t) {
+        if (herr != hipSuccess) return;
+        double ms = 0;
+        herr = measure(t, ms);
+        if (herr == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    };
+    // 1. kernel and elements per lane at default shapes
+    pv_tuning t{};
+    t.kernel = 1;
+    consider(t);
+    const bool compiled = l->family != pv::FAM_GENERIC;
+    if (compiled) {
+        const int es[2] = {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4};
+        for (int e : es) {
+            t = pv_tuning{};
+            t.kernel = 2;
+            t.elems_per_lane = e;
+            consider(t);
+        }
+    }
+    if (best.kernel == 2) {
+        // 2. strip height, 3. planes per walk, 4. workgroups per XCD
+        for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
+        const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
+        for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
+        for (int v : {32, 64, 96, 128}) { t = best; t.groups_per_xcd = v; consider(t); }
+    } else {
+        for (int v : {32, 64}) { t = best; t.tiles_per_group = v; consider(t); }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (herr != hipSuccess) {
+        slot = saved;
+        return hip_fail(herr, "autotune");
+    }
+    slot = best;
+    if (cache_path) cache_append(cache_path, key, best, best_ms);
+    if (out) *out = best;
+    if (ms_out) *ms_out = best_ms;
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Chebyshev filter diagonalisation (Sec. 4.2)
 // ---------------------------------------------------------------------------
 #include "pv_dense.hpp"
@@ -1159,32 +1400,69 @@ namespace {
 struct BatchLayout {
     size_t tables, block_inst, inst_block0, invD, partials, moments, vecs, total;
     std::vector<size_t> vec_off;  // per instance: A at vec_off[i], B at vec_off[i] + vb_i
-    std::vector<int64_t> ntiles;
-    std::vector<int> tpb, nblocks;
+    std::vector<int> nblocks;
     int total_blocks;
+    int staged;
 };
 
-pv_status batch_layout(const pv_batch* B, int dtype, int nb, int M, BatchLayout& L) {
+// Launch description of instance i of a batch (the batch takes the kernel
+// choice and elements per lane of lattice 0's tuning for every instance).
+pv::SweepParams batch_params(const pv_batch* B, int i, int dtype, int nb) {
+    pv::SweepParams p = base_params(B->lats[i], dtype, nb);
+    p.vtype = (dtype == PV_C128) ? 0 : B->lats[i]->vtype;
+    const pv_tuning& t = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    p.kernel = t.kernel;
+    p.st_E = t.elems_per_lane;
+    return p;
+}
+
+// The staged kernel serves a batch unless lattice 0's tuning asks for the
+// direct one; by default only batches of instances averaging at least 2^20
+// elements per block (smaller ones are launch-latency bound).
+bool batch_may_stage(const pv_batch* B, int dtype, int nb) {
+    static const char* env = std::getenv("PV_SWEEP");
+    if (B->family == pv::FAM_GENERIC || (env && std::atoi(env) == 1)) return false;
+    const int kind = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)].kernel;
+    if (kind != 0 || (env && std::atoi(env) == 2)) return kind != 1;
+    int64_t elems = 0;
+    for (const pv_lattice* l : B->lats) elems += l->n_rows * nb;
+    return elems / int64_t(B->lats.size()) >= (int64_t(1) << 20);
+}
+
+pv_status batch_counts(const pv_batch* B, int dtype, int nb, int staged, std::vector<int>& nblocks, int& total) {
     const int n = int(B->lats.size());
-    L.ntiles.resize(n);
-    L.tpb.resize(n);
-    L.nblocks.resize(n);
-    L.total_blocks = 0;
+    nblocks.assign(n, 0);
+    total = 0;
     std::vector<char> rec(pv::batch_record_bytes());
     for (int i = 0; i < n; ++i) {
-        pv::SweepParams p = base_params(B->lats[i], dtype, nb);
-        p.vtype = (dtype == PV_C128) ? 0 : B->lats[i]->vtype;
-        if (pv::batch_fill_record(p, rec.data(), &L.ntiles[i], &L.tpb[i]) != hipSuccess)
+        const pv::SweepParams p = batch_params(B, i, dtype, nb);
+        if (pv::batch_fill_record(p, staged, rec.data(), &nblocks[i]) != hipSuccess)
             return fail(PV_ERR_UNSUPPORTED, "instance %d: unsupported field / vector type combination", i);
-        L.nblocks[i] = int((L.ntiles[i] + L.tpb[i] - 1) / L.tpb[i]);
-        L.total_blocks += L.nblocks[i];
+        total += nblocks[i];
     }
+    return PV_OK;
+}
+
+// Workspace layout for the direct or the staged kernel; the regions are
+// sized for the larger of the two, so the layout does not depend on which.
+pv_status batch_layout(const pv_batch* B, int dtype, int nb, int M, int staged, BatchLayout& L) {
+    const int n = int(B->lats.size());
+    pv_status st;
+    std::vector<int> nd, ns;
+    int td = 0, ts = 0;
+    if ((st = batch_counts(B, dtype, nb, 0, nd, td)) != PV_OK) return st;
+    const bool may = batch_may_stage(B, dtype, nb);
+    if (may && (st = batch_counts(B, dtype, nb, 1, ns, ts)) != PV_OK) return st;
+    L.staged = staged && may;
+    L.nblocks = L.staged ? ns : nd;
+    L.total_blocks = L.staged ? ts : td;
+    const int cap = std::max(td, ts);
     size_t off = 0;
     L.tables = off; off += align_up(4 * (size_t)n * pv::batch_record_bytes());
-    L.block_inst = off; off += align_up(sizeof(int) * L.total_blocks);
+    L.block_inst = off; off += align_up(sizeof(int) * cap);
     L.inst_block0 = off; off += align_up(sizeof(int) * (n + 1));
     L.invD = off; off += align_up(sizeof(double) * n);
-    L.partials = off; off += align_up((size_t)L.total_blocks * nb * 4 * sizeof(double));
+    L.partials = off; off += align_up((size_t)cap * nb * 4 * sizeof(double));
     L.moments = off; off += align_up((size_t)n * nb * M * sizeof(double));
     L.vecs = off;
     L.vec_off.resize(n);
@@ -1240,7 +1518,7 @@ extern "C" pv_status pv_batch_stats(const pv_batch* B, int* captures, int* repla
 extern "C" size_t pv_batch_kpm_workspace_size(const pv_batch* B, int dtype, int nb, int M) {
     if (!B || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64) || M < 2 || M > 65536) return 0;
     BatchLayout L;
-    if (batch_layout(B, dtype, nb, M, L) != PV_OK) return 0;
+    if (batch_layout(B, dtype, nb, M, 0, L) != PV_OK) return 0;
     return L.total;
 }
 
@@ -1259,8 +1537,12 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
         if (!(a[i] > 0.0) || !std::isfinite(a[i]) || !std::isfinite(b[i]))
             return fail(PV_ERR_INVALID_ARG, "instance %d: need finite a > 0 and b", i);
     }
+    // the staged kernel reads the start blocks in 16-byte chunks
+    int aligned = 1;
+    for (int i = 0; i < n; ++i)
+        if (reinterpret_cast<uintptr_t>(r[i]) % 16) aligned = 0;
     BatchLayout L;
-    if ((st = batch_layout(B, dtype, nb, M, L)) != PV_OK) return st;
+    if ((st = batch_layout(B, dtype, nb, M, aligned, L)) != PV_OK) return st;
     if (!work || work_bytes < L.total) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, L.total);
     for (int i = 0; i < n; ++i)
         if ((st = ensure_device(B->lats[i])) != PV_OK) return st;
@@ -1268,8 +1550,10 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
 
     // fingerprint of everything the captured graph bakes in; the graph writes
     // the moments into the workspace, so the caller's mu may move between calls
+    const pv_tuning& t0 = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
     std::vector<uint64_t> key = {(uint64_t)dtype, (uint64_t)nb, (uint64_t)M, (uint64_t)(uintptr_t)work,
-                                 (uint64_t)work_bytes};
+                                 (uint64_t)work_bytes, (uint64_t)L.staged, (uint64_t)t0.kernel,
+                                 (uint64_t)t0.elems_per_lane};
     char* const mu_ws = static_cast<char*>(work) + L.moments;
     const size_t mu_bytes = (size_t)n * nb * M * sizeof(double);
     for (int i = 0; i < n; ++i) {
@@ -1304,8 +1588,9 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
         void* A = w + L.vec_off[i];
         void* Bv = w + L.vec_off[i] + vec_bytes(l, dtype, nb);
         for (int v = 0; v < 4; ++v) {
-            pv::SweepParams p = base_params(l, dtype, nb);
-            if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
+            pv::SweepParams p = batch_params(B, i, dtype, nb);
+            p.zero_row = l->d_zero;
+            p.slab_rows = slab_rows(l, dtype, nb);
             p.partials = reinterpret_cast<double*>(w + L.partials);
             p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
             p.beta = b[i];
@@ -1318,9 +1603,9 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
             } else {               // odd step n >= 3: x = A, in place over B
                 p.x = A; p.z = Bv; p.y = Bv; p.alpha = 2.0 / a[i]; p.gamma = -1.0;
             }
-            int64_t nt;
-            int tpb;
-            if (pv::batch_fill_record(p, tables.data() + ((size_t)v * n + i) * rb, &nt, &tpb) != hipSuccess)
+            int nblk = 0;
+            if (pv::batch_fill_record(p, L.staged, tables.data() + ((size_t)v * n + i) * rb, &nblk) != hipSuccess ||
+                nblk != L.nblocks[i])
                 return fail(PV_ERR_UNSUPPORTED, "instance %d: unsupported type combination", i);
         }
     }
@@ -1339,12 +1624,15 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     for (int i = 1; i < n; ++i)
         if (dtype != PV_C128 && B->lats[i]->vtype != vtype && (B->lats[i]->V || B->lats[0]->V))
             return fail(PV_ERR_UNSUPPORTED, "all instances of a batch need the same field type");
+    pv::SweepParams p0 = batch_params(B, 0, dtype, nb);
+    p0.vtype = vtype;
+    p0.ep = pv::EP_STORE_Y | pv::EP_DOTS;
     PV_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     for (int step = 0; step < M / 2 && e == hipSuccess; ++step) {
         const int v = step == 0 ? 0 : (step == 1 ? 1 : (step % 2 == 0 ? 2 : 3));
-        e = pv::launch_batch_sweep(B->family, B->n_orb, dtype, vtype, w + L.tables + (size_t)v * n * rb, d_bi, d_i0,
-                                   L.total_blocks, B->cap);
+        e = pv::launch_batch_sweep(p0, L.staged, w + L.tables + (size_t)v * n * rb, d_bi, d_i0, L.total_blocks,
+                                   B->cap);
         if (e == hipSuccess)
             e = pv::launch_batch_reduce(d_part, d_i0, n, nb, step == 0 ? 1 : 2, reinterpret_cast<double*>(mu_ws), M,
                                         step, d_invD, B->cap);

@@ -884,6 +884,22 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     }
 }
 
+// Staged sweep over a batch of lattices in one launch: instance i owns the
+// workgroups [inst_block0[i], inst_block0[i+1]), a multiple of 8 starting at
+// a multiple of 8, split into its 8 XCD parts like a single-lattice launch.
+template <class P, typename T, typename VT, int E, unsigned EPM>
+__global__ __launch_bounds__(kBlock) void batch_staged_kernel(const KArgs<T, VT>* __restrict__ table,
+                                                              const int* __restrict__ block_inst,
+                                                              const int* __restrict__ inst_block0) {
+    const int b = blockIdx.x;
+    const int i = __builtin_amdgcn_readfirstlane(block_inst[b]);
+    const int b0 = __builtin_amdgcn_readfirstlane(inst_block0[i]);
+    const int b1 = __builtin_amdgcn_readfirstlane(inst_block0[i + 1]);
+    const KArgs<T, VT> a = table[i];
+    const int lb = b - b0;
+    staged_block<P, T, VT, E, EPM>(a, b, lb & 7, lb >> 3, (b1 - b0) >> 3);
+}
+
 template <class P, typename T, typename VT, int E, unsigned EPM>
 __global__ __launch_bounds__(kBlock) void staged_kernel(KArgs<T, VT> a) {
     if (a.st_parts == 8)
@@ -976,7 +992,12 @@ void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
     a.eta0_re = p.eta0_re;
     a.eta0_im = p.eta0_im;
     a.ep = p.ep;
-    a.tpb = p.tpb > 0 ? p.tpb : tiles_per_block(a.ntiles * 8);
+    {
+        // a requested count below the default would need more partial-dot
+        // rows than a workspace holds: raise it to the default
+        const int dflt = tiles_per_block(a.ntiles * 8);
+        a.tpb = p.tpb > dflt ? p.tpb : dflt;
+    }
     if (whole_part) {
         a.BY = int(p.L[1]);
         a.fd_slab = make_fastdiv(uint32_t(a.ntx) * uint32_t(p.L[1]) * uint32_t(p.L[2]));
@@ -1001,11 +1022,13 @@ size_t staged_lds_bytes(int nb) {
     return size_t(3 * seg + ntr * S::TW) * S::ES + size_t(S::TW / nb) * sizeof(T);
 }
 
-template <class P, typename T, typename VT, int E, unsigned EPM>
-hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
+// Geometry of a staged sweep for a target of G8 workgroups per XCD part:
+// walk length, strip height, parts.  Returns the workgroups per part actually
+// useful (at most the items of the largest part).  full_walk: one walk per
+// column (no splitting of the outer axis).
+template <class P, typename T, typename VT, int E>
+int staged_setup(const SweepParams& p, int G8, bool full_walk, KArgs<T, VT>& a) {
     using S = Staged<T, E>;
-    KArgs<T, VT> a;
-    make_kargs<P, T, VT>(p, false, a);
     a.st_site = P::NO * p.nb;
     a.st_seg = S::TW + 2 * a.st_site;
     a.st_nxs = (a.rowel + S::TW - 1) / S::TW;
@@ -1014,6 +1037,36 @@ hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
     } else {
         a.st_Lm = 1; a.st_Lw = a.Ly; a.st_pm = 0; a.st_pw = a.py;
     }
+    // the largest part: a split along m when there are 8 middle rows, else along w
+    const bool split_m = a.st_Lm >= 8;
+    const int nm = split_m ? (a.st_Lm + 7) / 8 : a.st_Lm;
+    const int nW = split_m ? a.st_Lw : (a.st_Lw + 7) / 8;
+    const int cols = nm * a.st_nxs;
+    if (nW < 1) {
+        a.st_C = 1;
+    } else if (p.st_C > 0) {
+        a.st_C = p.st_C < nW ? p.st_C : nW;
+    } else if (full_walk) {
+        a.st_C = nW;
+    } else {
+        int nwc = (G8 + cols - 1) / cols;
+        if (nwc > nW) nwc = nW;
+        a.st_C = (nW + nwc - 1) / nwc;
+    }
+    const int items = nW < 1 ? 1 : ((nW + a.st_C - 1) / a.st_C) * cols;
+    if (G8 > items) G8 = items;
+    int bx = int(std::lround(std::sqrt(double(G8) * a.st_site / S::TW)));
+    if (bx > a.st_nxs) bx = a.st_nxs;
+    if (bx < 1) bx = 1;
+    a.st_Bm = p.st_Bm > 0 ? p.st_Bm : (G8 / bx > 1 ? G8 / bx : 1);
+    a.st_parts = 8;
+    return G8;
+}
+
+template <class P, typename T, typename VT, int E, unsigned EPM>
+hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
+    KArgs<T, VT> a;
+    make_kargs<P, T, VT>(p, false, a);
     const size_t lds = staged_lds_bytes<P, T, E>(p.nb);
     const void* kern = reinterpret_cast<const void*>(&staged_kernel<P, T, VT, E, EPM>);
     // workgroups resident per CU at this LDS size (cached per size)
@@ -1039,27 +1092,7 @@ hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
     }
     int G8 = p.st_G8 > 0 ? p.st_G8 : (num_cus >= 8 ? num_cus / 8 : 1) * occ;
     if (G8 > 256) G8 = 256;
-    // the largest part: a split along m when there are 8 middle rows, else along w
-    const bool split_m = a.st_Lm >= 8;
-    const int nm = split_m ? (a.st_Lm + 7) / 8 : a.st_Lm;
-    const int nW = split_m ? a.st_Lw : (a.st_Lw + 7) / 8;
-    const int cols = nm * a.st_nxs;
-    if (nW < 1) {
-        a.st_C = 1;
-    } else if (p.st_C > 0) {
-        a.st_C = p.st_C < nW ? p.st_C : nW;
-    } else {
-        int nwc = (G8 + cols - 1) / cols;
-        if (nwc > nW) nwc = nW;
-        a.st_C = (nW + nwc - 1) / nwc;
-    }
-    const int items = nW < 1 ? 1 : ((nW + a.st_C - 1) / a.st_C) * cols;
-    if (G8 > items) G8 = items;
-    int bx = int(std::lround(std::sqrt(double(G8) * a.st_site / S::TW)));
-    if (bx > a.st_nxs) bx = a.st_nxs;
-    if (bx < 1) bx = 1;
-    a.st_Bm = p.st_Bm > 0 ? p.st_Bm : (G8 / bx > 1 ? G8 / bx : 1);
-    a.st_parts = 8;
+    G8 = staged_setup<P, T, VT, E>(p, G8, false, a);
     p.grid = 8 * G8;
     hipLaunchKernelGGL((staged_kernel<P, T, VT, E, EPM>), dim3(p.grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
@@ -1076,6 +1109,27 @@ hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
     return launch_staged<P, T, VT, E, 0u>(p, num_cus, s);
 }
 
+// Epilogues the staged kernel takes by default: plain sweeps, the Chebyshev
+// step with dots and the series steps.  The adjoint epilogues (extra vector
+// terms and the field gradient) default to the direct kernel, which issues
+// their loads together with the neighbour loads.
+// Small blocks (below 2^20 elements, cache resident) are launch-latency
+// bound, where the direct kernel's single pass beats the staged walks.
+bool staged_default(const SweepParams& p) {
+    const int64_t elems = p.L[0] * p.L[1] * p.L[2] * p.n_orb * p.nb;
+    return (p.ep & (EP_GTERMS | EP_GRAD)) == 0 && elems >= (int64_t(1) << 20);
+}
+
+// Elements per lane of a staged launch: two for complex64 (16-byte chunks),
+// and for complex128 from nb = 8 on (longer tiles: fewer halo chunks per
+// element, more bytes in flight per workgroup).
+int staged_elems(const SweepParams& p) {
+    static const int env_e = env_int("PV_STAGED_E", 0);
+    if (p.st_E > 0) return p.st_E;
+    if (env_e > 0) return env_e;
+    return p.dtype == 0 && p.nb < 8 ? 1 : 2;
+}
+
 // Sweep kernel of a launch: the staged kernel for compiled families when the
 // block is 16-byte aligned (its chunk loads), else the direct kernel.
 // p.kernel (or PV_SWEEP) 1 forces direct, 2 staged; p.st_E (or PV_STAGED_E)
@@ -1084,14 +1138,10 @@ template <class P, typename T, typename VT>
 hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
     if constexpr (P::FAMILY != FAM_GENERIC) {
         static const int env_kernel = env_int("PV_SWEEP", 0);
-        static const int env_e = env_int("PV_STAGED_E", 0);
         const int kind = p.kernel > 0 ? p.kernel : env_kernel;
         const bool aligned = ((reinterpret_cast<uintptr_t>(p.x) | reinterpret_cast<uintptr_t>(p.zero_row)) & 15) == 0;
-        if (kind != 1 && aligned) {
-            // elements per lane: two for complex64 (16-byte chunks), and for
-            // complex128 from nb = 8 on (longer tiles: fewer halo chunks per
-            // element, more bytes in flight per workgroup)
-            const int e = p.st_E > 0 ? p.st_E : (env_e > 0 ? env_e : (sizeof(T) == 8 && p.nb < 8 ? 1 : 2));
+        if (aligned && (kind == 2 || (kind == 0 && staged_default(p)))) {
+            const int e = staged_elems(p);
             if constexpr (sizeof(T) == 8)
                 return e == 2 ? launch_staged_ep<P, T, VT, 2>(p, num_cus, s) : launch_staged_ep<P, T, VT, 1>(p, num_cus, s);
             else
@@ -1476,27 +1526,66 @@ hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t batch_fill_record(const SweepParams& p, void* dst, int64_t* ntiles, int* tpb) {
+hipError_t batch_fill_record(const SweepParams& p, int staged, void* dst, int* nblocks) {
     return dispatch(p.family, p.n_orb, p.dtype, p.vtype, [&](auto tp, auto tt, auto tv) -> hipError_t {
         using P = typename decltype(tp)::type;
         using T = typename decltype(tt)::type;
         using VT = typename decltype(tv)::type;
         static_assert(sizeof(KArgs<T, VT>) == sizeof(KArgs<double, double>), "record sizes differ");
         KArgs<T, VT> a;
+        if constexpr (P::FAMILY != FAM_GENERIC) {
+            if (staged) {
+                make_kargs<P, T, VT>(p, false, a);
+                const int e = staged_elems(p);
+                int G8;
+                if constexpr (sizeof(T) == 8)
+                    G8 = e == 2 ? staged_setup<P, T, VT, 2>(p, 1 << 30, true, a)
+                                : staged_setup<P, T, VT, 1>(p, 1 << 30, true, a);
+                else
+                    G8 = e == 4 ? staged_setup<P, T, VT, 4>(p, 1 << 30, true, a)
+                                : staged_setup<P, T, VT, 2>(p, 1 << 30, true, a);
+                std::memcpy(dst, &a, sizeof(a));
+                *nblocks = 8 * G8;
+                return hipSuccess;
+            }
+        }
         make_kargs<P, T, VT>(p, true, a);
         std::memcpy(dst, &a, sizeof(a));
-        *ntiles = a.ntiles;
-        *tpb = a.tpb;
+        *nblocks = int((a.ntiles + a.tpb - 1) / a.tpb);
         return hipSuccess;
     });
 }
 
-hipError_t launch_batch_sweep(int family, int n_orb, int dtype, int vtype, const void* table, const int* block_inst,
+hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* table, const int* block_inst,
                               const int* inst_block0, int grid, hipStream_t s) {
-    return dispatch(family, n_orb, dtype, vtype, [&](auto tp, auto tt, auto tv) -> hipError_t {
+    return dispatch(p.family, p.n_orb, p.dtype, p.vtype, [&](auto tp, auto tt, auto tv) -> hipError_t {
         using P = typename decltype(tp)::type;
         using T = typename decltype(tt)::type;
         using VT = typename decltype(tv)::type;
+        if constexpr (P::FAMILY != FAM_GENERIC) {
+            if (staged) {
+                constexpr unsigned KPM = EP_STORE_Y | EP_DOTS;
+                auto go = [&](auto ke) -> hipError_t {
+                    constexpr int E = decltype(ke)::value;
+                    const size_t lds = staged_lds_bytes<P, T, E>(p.nb);
+                    if (lds > 65536) {
+                        hipError_t e = hipFuncSetAttribute(
+                            reinterpret_cast<const void*>(&batch_staged_kernel<P, T, VT, E, KPM>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+                        if (e != hipSuccess) return e;
+                    }
+                    hipLaunchKernelGGL((batch_staged_kernel<P, T, VT, E, KPM>), dim3(grid), dim3(kBlock), lds, s,
+                                       static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0);
+                    return hipGetLastError();
+                };
+                if (p.ep != KPM) return hipErrorInvalidValue;
+                const int e = staged_elems(p);
+                if constexpr (sizeof(T) == 8)
+                    return e == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 1>{});
+                else
+                    return e == 4 ? go(std::integral_constant<int, 4>{}) : go(std::integral_constant<int, 2>{});
+            }
+        }
         hipLaunchKernelGGL((batch_sweep_kernel<P, T, VT>), dim3(grid), dim3(kBlock), 0, s,
                            static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0);
         return hipGetLastError();

@@ -95,15 +95,18 @@ hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X,
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 // Batched sweeps: one argument record per instance (built on the host with
-// batch_fill_record from that instance's launch description, whole lattice
-// as one part), a table of records in device memory, and per-workgroup
-// instance maps.  *ntiles / *tpb receive the instance's tile count and tiles
-// per workgroup.
+// batch_fill_record from that instance's launch description), a table of
+// records in device memory, and per-workgroup instance maps.  staged: every
+// instance takes the staged kernel (compiled family, 16-byte aligned blocks;
+// then *nblocks is a multiple of 8 and instances must start at multiples of
+// 8), else the direct kernel over the whole lattice.  *nblocks receives the
+// instance's workgroup count.  launch_batch_sweep takes the launch
+// description of any instance (family, types, nb, tuning, epilogue).
 size_t batch_record_bytes();
 // dst = 0 (bytes a multiple of 4)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
-hipError_t batch_fill_record(const SweepParams& p, void* dst, int64_t* ntiles, int* tpb);
-hipError_t launch_batch_sweep(int family, int n_orb, int dtype, int vtype, const void* table, const int* block_inst,
+hipError_t batch_fill_record(const SweepParams& p, int staged, void* dst, int* nblocks);
+hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* table, const int* block_inst,
                               const int* inst_block0, int grid, hipStream_t s);
 hipError_t launch_batch_reduce(const double* partials, const int* inst_block0, int n_inst, int nb, int mode,
                                double* mu, int M, int step, const double* invD, hipStream_t s);

@@ -72,3 +72,22 @@ def test_batched_equals_single_lattice_path():
     for i, c in enumerate(cases):
         single = host(pv.pv_kpm_moments(c.lat, rd[i], 32, a[i], b[i]))
         assert np.abs(mu[i] - single).max() < 1e-14
+
+
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_batched_direct_and_staged_kernels_agree(dtype):
+    """Lattice 0's tuning selects the kernel of the whole batch; both give the
+    same moments up to the summation order of the dots."""
+    vd = np.float64 if dtype == np.complex128 else np.float32
+    cases, rs, a, b = instances(dtype, vd, nb=8)
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    batch = pv.Batch([c.lat for c in cases])
+    rd = [dev(r) for r in rs]
+    pv.pv_lattice_set_tuning(cases[0].lat, code, 8, {"kernel": 2})
+    mu_s = host(pv.pv_batch_kpm_moments(batch, rd, 48, a, b)).copy()
+    pv.pv_lattice_set_tuning(cases[0].lat, code, 8, {"kernel": 1})
+    mu_d = host(pv.pv_batch_kpm_moments(batch, rd, 48, a, b)).copy()
+    pv.pv_lattice_set_tuning(cases[0].lat, code, 8, None)
+    assert batch.stats()[0] == 2          # the kernel change forced a new capture
+    tol = 1e-13 if dtype == np.complex128 else 1e-6
+    assert np.abs(mu_s - mu_d).max() < tol
