@@ -32,6 +32,13 @@ WORKLOAD_INDEX = 2            # seeds of the 256x256x64 TI workload
 A_SCALE, B_SHIFT = 7.0, 0.0
 
 
+# HBM-side bytes per Chebyshev-step launch of the staged sweep kernel as built
+# now, from FETCH_SIZE / WRITE_SIZE counters scaled by the copy-kernel factors
+# (profiles/staged_kernel_ti256x256x64_*_counters.txt); (dtype, nb) pairs
+# without a counter run report null.
+COUNTED_TRAFFIC = {("c128", 32): 30_707_000_000, ("c64", 16): 9_312_000_000}
+
+
 def bytes_per_step(n_rows: int, n_sites: int, nb: int, dtype: str) -> int:
     """Algorithmic HBM bytes of one Chebyshev sweep: read x (w_k), read z
     (w_{k-1}), write y (w_{k+1}), read the on-site field once per site."""
@@ -380,8 +387,9 @@ def main():
                    "lattice": list(L_BENCH), "n_orb": 4, "nb": args.nb, "rows": lat.n_rows,
                    "a": A_SCALE, "b": B_SHIFT, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "sweep_kernel<PatTI> + reduce_dots_kernel (per step)",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": COUNTED_TRAFFIC.get((args.dtype, args.nb)),
+                     "kernel": "staged_kernel<PatTI> (Chebyshev step, fused dots) + reduce_dots_kernel",
                      "bytes_per_launch": nbytes},
         "copy_probe_GBs": None if copy_gbs is None else round(copy_gbs, 1),
         "frac_of_copy_probe": None if copy_gbs is None else round(achieved / copy_gbs, 4),
