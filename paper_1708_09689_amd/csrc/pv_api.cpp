@@ -1422,6 +1422,7 @@ pv::SweepParams batch_params(const pv_batch* B, int i, int dtype, int nb) {
 bool batch_may_stage(const pv_batch* B, int dtype, int nb) {
     static const char* env = std::getenv("PV_SWEEP");
     if (B->family == pv::FAM_GENERIC || (env && std::atoi(env) == 1)) return false;
+    if (B->n_orb * nb > pv::STAGED_MAX_SITE) return false;
     const int kind = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)].kernel;
     if (kind != 0 || (env && std::atoi(env) == 2)) return kind != 1;
     int64_t elems = 0;

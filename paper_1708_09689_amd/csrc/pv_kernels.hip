@@ -272,6 +272,10 @@ __device__ __forceinline__ cplx<T> zero_unless(bool ok, cplx<T> v) {
 #ifndef PV_SWEEP_WAVES_PER_EU
 #define PV_SWEEP_WAVES_PER_EU 1
 #endif
+#ifndef PV_STAGED_WAVES_PER_EU
+#define PV_STAGED_WAVES_PER_EU 2
+#endif
+
 
 // Row (y + dy, z + dz) of row (y, z), wrapped along periodic dimensions;
 // false when an open boundary drops it.  Uniform over a tile.
@@ -536,10 +540,12 @@ void batch_sweep_kernel(const KArgs<T, VT>* __restrict__ table, const int* __res
 // middle one (y in 3D, none in 2D) -- and walks w.  The rows (m, w-1),
 // (m, w), (m, w+1), each with one site of x halo on both sides, live in a
 // three-slot LDS ring, so a walk fetches every element of its rows once; the
-// rows (m -+ 1, w) of 3D lattices are staged per step, and the field values
-// of the tile's rows too.  The next step's rows, field values, z and acc_in
-// are loaded into registers while the current step computes from LDS, and
-// written to LDS behind a barrier.  Every load is a 16-byte chunk per lane.
+// rows (m -+ 1, w) of 3D lattices, the tile's z (and acc_in) elements and its
+// field values are staged per step.  Every global load is a 16-byte chunk
+// per lane.  Loads run two steps ahead: step s issues the rows of step s + 2
+// into one of two register sets while it computes from LDS, then hands the
+// other set (issued one step earlier) to LDS behind a barrier that waits for
+// LDS operations only, so loads and y stores stay in flight across steps.
 //
 // Walks are items of an XCD part (8 parts: split along m when the lattice has
 // at least 8 middle rows, along w otherwise).  Items are numbered walk chunk
@@ -554,7 +560,7 @@ struct Staged {
     static constexpr int CE = 16 / ES;                       // elements per 16-byte chunk
     static constexpr int TW = kBlock * E;                    // elements per column tile
     static constexpr int TCH = TW / (CE * kBlock);           // chunks per lane of a row without halo
-    static constexpr int RCH = (TW + 2 * 256 + CE * kBlock - 1) / (CE * kBlock);  // with halo (site <= 256)
+    static constexpr int RCH = (TW + 2 * STAGED_MAX_SITE + CE * kBlock - 1) / (CE * kBlock);  // with halo
     static_assert(TW % (CE * kBlock) == 0, "a tile must be whole chunks per lane");
 };
 
@@ -570,22 +576,42 @@ __device__ __forceinline__ u32x4 ld_chunk(const void* base, uint32_t boff) {
     return *reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(base) + boff);
 }
 
-template <class P, typename T, typename VT, int E>
-struct StagedCtx {
+template <typename T>
+__device__ __forceinline__ u32x4 ld_chunk_nt(const void* base, uint32_t boff) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(base) + boff));
+}
+
+// One step's worth of rows in flight: ring row with halo, side rows, z and
+// acc_in chunks, field values.
+template <class P, typename T, int E>
+struct StagedSet {
     using S = Staged<T, E>;
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
+    u32x4 ring[S::RCH];
+    u32x4 side[NTR > 0 ? NTR : 1][S::TCH];
+    u32x4 z[S::TCH];
+    u32x4 acc[S::TCH];
+    T v[E];
+};
+
+template <class P, typename T, typename VT, int E, bool ACC>
+struct StagedCtx {
+    using S = Staged<T, E>;
+    using Set = StagedSet<P, T, E>;
+    static constexpr int NTR = Set::NTR;
     const KArgs<T, VT>& a;
-    cplx<T>* ring;
-    cplx<T>* tra;
-    T* vl;
-    int tid, nch, m;
+    cplx<T>* ring;   // [3][seg]
+    cplx<T>* tra;    // [NTR][TW]
+    cplx<T>* zl;     // [TW]
+    cplx<T>* al;     // [TW] (ACC only)
+    T* vl;           // [TW / nb]
+    int tid, nch, m, wb;
     // per walk: byte offsets inside a row of this lane's ring chunks (x
-    // wrapped; open boundaries are applied when computing), side chunks,
-    // field entries and own elements (clamped into the row)
+    // wrapped; open boundaries are applied when computing), row chunks and
+    // field entries (clamped into the row)
     uint32_t roff[S::RCH];
     uint32_t soff[S::TCH];
     uint32_t voff[E];
-    uint32_t eoff[E];
 
     __device__ __forceinline__ int64_t row_of(int mm, int ww) const {
         return P::DIM == 3 ? (int64_t)ww * a.Ly + mm : (int64_t)ww;
@@ -597,7 +623,7 @@ struct StagedCtx {
         if (ww < 0 || ww >= a.st_Lw) {
             ok = a.st_pw;
             ww += ww < 0 ? a.st_Lw : -a.st_Lw;
-            if (ww >= a.st_Lw) ww %= a.st_Lw;   // w + 2 on a lattice of one plane
+            if (ww >= a.st_Lw) ww %= a.st_Lw;   // w + 3 on a lattice of few planes
         }
         if (mm < 0 || mm >= a.st_Lm) {
             ok = ok && a.st_pm;
@@ -629,75 +655,97 @@ struct StagedCtx {
             int r = (xe0 >> a.lognb) + tid + k * kBlock;   // orbital row inside the lattice row
             if (r >= rowlen) r = rowlen - 1;
             voff[k] = uint32_t(a.pot_mode == 1 ? r / P::NO : r);
-            const int xe = xe0 + tid + k * kBlock;
-            eoff[k] = uint32_t(xe < rowel ? xe : rowel - 1) * S::ES;
         }
     }
-    __device__ __forceinline__ void load_ring(int ww, u32x4 (&r)[S::RCH]) const {
+    // Issue the loads of ring row (m, w_ring) and of the per-step rows of
+    // outer index w_row (clamped to the walk) into the set.
+    __device__ __forceinline__ void issue(Set& st, int w_ring, int w_row) const {
+        const cplx<T>* rp = row_ptr(m, w_ring);
+#pragma unroll
+        for (int k = 0; k < S::RCH; ++k)
+            if (k * kBlock < nch) st.ring[k] = ld_chunk<T>(rp, roff[k]);
+        const int wr = w_row < wb ? w_row : wb - 1;
+        if constexpr (NTR > 0) {
+#pragma unroll
+            for (int h = 0; h < NTR; ++h) {
+                const cplx<T>* sp = row_ptr(m + (h == 0 ? -1 : 1), wr);
+#pragma unroll
+                for (int k = 0; k < S::TCH; ++k) st.side[h][k] = ld_chunk<T>(sp, soff[k]);
+            }
+        }
+        const int64_t rw = row_of(m, wr);
+        const cplx<T>* zr = a.zsrc + rw * a.rowel;
+#pragma unroll
+        for (int k = 0; k < S::TCH; ++k) st.z[k] = ld_chunk_nt<T>(zr, soff[k]);
+        if constexpr (ACC) {
+            const cplx<T>* ar = a.asrc + rw * a.rowel;
+#pragma unroll
+            for (int k = 0; k < S::TCH; ++k) st.acc[k] = ld_chunk_nt<T>(ar, soff[k]);
+        }
+        if (a.V != nullptr) {
+            const VT* vb = a.V + rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                if (k * kBlock < (S::TW >> a.lognb)) st.v[k] = T(vb[voff[k]]);
+        }
+    }
+    // Hand a set to LDS: ring row into slot, per-step rows into their buffers.
+    __device__ __forceinline__ void commit(const Set& st, int slot) const {
+        u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
+#pragma unroll
+        for (int k = 0; k < S::RCH; ++k)
+            if (k * kBlock < nch && tid + k * kBlock < nch) d[tid + k * kBlock] = st.ring[k];
+        if constexpr (NTR > 0) {
+#pragma unroll
+            for (int h = 0; h < NTR; ++h) {
+                u32x4* ds = reinterpret_cast<u32x4*>(tra + h * S::TW);
+#pragma unroll
+                for (int k = 0; k < S::TCH; ++k) ds[tid + k * kBlock] = st.side[h][k];
+            }
+        }
+        u32x4* dz = reinterpret_cast<u32x4*>(zl);
+#pragma unroll
+        for (int k = 0; k < S::TCH; ++k) dz[tid + k * kBlock] = st.z[k];
+        if constexpr (ACC) {
+            u32x4* da = reinterpret_cast<u32x4*>(al);
+#pragma unroll
+            for (int k = 0; k < S::TCH; ++k) da[tid + k * kBlock] = st.acc[k];
+        }
+        if (a.V != nullptr) {
+            const int nrow = S::TW >> a.lognb;
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                if (tid + k * kBlock < nrow) vl[tid + k * kBlock] = st.v[k];
+        }
+    }
+    // Ring row (m, ww) alone into a slot (walk prologue).
+    __device__ __forceinline__ void ring_now(u32x4 (&r)[S::RCH], int ww, int slot) const {
         const cplx<T>* rp = row_ptr(m, ww);
 #pragma unroll
         for (int k = 0; k < S::RCH; ++k)
             if (k * kBlock < nch) r[k] = ld_chunk<T>(rp, roff[k]);
-    }
-    __device__ __forceinline__ void store_ring(int slot, const u32x4 (&r)[S::RCH]) const {
         u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
 #pragma unroll
         for (int k = 0; k < S::RCH; ++k)
             if (k * kBlock < nch && tid + k * kBlock < nch) d[tid + k * kBlock] = r[k];
     }
-    __device__ __forceinline__ void load_side(int ww, u32x4 (&r)[NTR > 0 ? NTR : 1][S::TCH]) const {
-        if constexpr (NTR > 0) {
-#pragma unroll
-            for (int h = 0; h < NTR; ++h) {
-                const cplx<T>* rp = row_ptr(m + (h == 0 ? -1 : 1), ww);
-#pragma unroll
-                for (int k = 0; k < S::TCH; ++k) r[h][k] = ld_chunk<T>(rp, soff[k]);
-            }
-        }
-    }
-    __device__ __forceinline__ void store_side(const u32x4 (&r)[NTR > 0 ? NTR : 1][S::TCH]) const {
-        if constexpr (NTR > 0) {
-#pragma unroll
-            for (int h = 0; h < NTR; ++h) {
-                u32x4* d = reinterpret_cast<u32x4*>(tra + h * S::TW);
-#pragma unroll
-                for (int k = 0; k < S::TCH; ++k) d[tid + k * kBlock] = r[h][k];
-            }
-        }
-    }
-    // Field of the tile's orbital rows (TW / nb of them) in row ww.
-    __device__ __forceinline__ void load_field(int ww, T (&v)[E]) const {
-        if (a.V == nullptr) return;
-        const int64_t r = row_of(m, ww);
-        const VT* vb = a.V + r * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
-#pragma unroll
-        for (int k = 0; k < E; ++k)
-            if (k * kBlock < (S::TW >> a.lognb)) v[k] = T(vb[voff[k]]);
-    }
-    __device__ __forceinline__ void store_field(const T (&v)[E]) const {
-        if (a.V == nullptr) return;
-        const int nrow = S::TW >> a.lognb;
-#pragma unroll
-        for (int k = 0; k < E; ++k)
-            if (tid + k * kBlock < nrow) vl[tid + k * kBlock] = v[k];
-    }
-    // The lane's z and acc_in elements of row ww.
-    __device__ __forceinline__ void load_lane(int ww, unsigned ep, cplx<T> (&zv)[E], cplx<T> (&av)[E]) const {
-        const int64_t rb = row_of(m, ww) * a.rowel;
-        const cplx<T>* zr = a.zsrc + rb;
-        const cplx<T>* ar = a.asrc + rb;
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            zv[k] = ld_row_nt(zr, eoff[k]);
-            if (ep & EP_ACC_ADD) av[k] = ld_row_nt(ar, eoff[k]);
-        }
-    }
 };
+
+// LDS of a staged workgroup: three ring rows with halo, the side rows of 3D
+// lattices, z (and acc_in) of the tile, and the field of its orbital rows.
+template <class P, typename T, int E>
+__host__ __device__ constexpr size_t staged_lds_bytes_for(int nb, bool acc) {
+    return size_t(3 * (Staged<T, E>::TW + 2 * P::NO * nb) + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
+               Staged<T, E>::ES +
+           size_t(Staged<T, E>::TW / nb) * sizeof(T);
+}
 
 template <class P, typename T, typename VT, int E, unsigned EPM>
 __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, int part, int jb, int G) {
     using S = Staged<T, E>;
-    using Ctx = StagedCtx<P, T, VT, E>;
+    constexpr bool ACC = EPM == 0u || (EPM & EP_ACC_ADD) != 0u;
+    using Ctx = StagedCtx<P, T, VT, E, ACC>;
+    using Set = typename Ctx::Set;
     constexpr int NO = P::NO;
     constexpr int NTR = Ctx::NTR;
     static_assert(P::FAMILY != FAM_GENERIC, "staged sweeps need a compiled family");
@@ -726,9 +774,11 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
     double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
 
-    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, tid, a.st_seg / S::CE, 0};
+    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, a.st_seg / S::CE, 0, 0};
     cx.tra = cx.ring + 3 * a.st_seg;
-    cx.vl = reinterpret_cast<T*>(cx.tra + NTR * S::TW);
+    cx.zl = cx.tra + NTR * S::TW;
+    cx.al = cx.zl + S::TW;
+    cx.vl = reinterpret_cast<T*>(cx.al + (ACC ? S::TW : 0));
 
     // this part's ranges of m and w
     int m0 = 0, m1 = a.st_Lm, wA = 0, wB = a.st_Lw;
@@ -759,44 +809,32 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
         cx.setup(xe0);
         const int wa = wA + wc * a.st_C;
         const int wb = min(wa + a.st_C, wB);
+        cx.wb = wb;
+        const int nsteps = wb - wa;
 
-        // prologue: ring rows wa - 1, wa, wa + 1 in slots 0, 1, 2
-        u32x4 rr[3][S::RCH];
-        u32x4 tr[NTR > 0 ? NTR : 1][S::TCH];
-        T vv[E];
-        cplx<T> zv[E], av[E];
-        cx.load_ring(wa - 1, rr[0]);
-        cx.load_ring(wa, rr[1]);
-        cx.load_ring(wa + 1, rr[2]);
-        cx.load_side(wa, tr);
-        cx.load_field(wa, vv);
-        cx.load_lane(wa, ep, zv, av);
-        cx.store_ring(0, rr[0]);
-        cx.store_ring(1, rr[1]);
-        cx.store_ring(2, rr[2]);
-        cx.store_side(tr);
-        cx.store_field(vv);
+        // prologue: ring rows wa - 1, wa into slots 0, 1; set A = ring row
+        // wa + 1 and the rows of step 0, handed over now; set B = ring row
+        // wa + 2 and the rows of step 1, left in flight
+        Set A, B;
+        cx.ring_now(A.ring, wa - 1, 0);
+        cx.ring_now(B.ring, wa, 1);
+        cx.issue(A, wa + 1, wa);
+        cx.commit(A, 2);
+        if (nsteps > 1) cx.issue(B, wa + 2, wa + 1);
         lds_barrier();
 
-        for (int w = wa; w < wb; ++w) {
-            const int s = w - wa;
-            // prefetch of the next step (unconditional so that the compiler's
-            // wait counts stay exact; after the last step of a walk it reads a
-            // valid row again and nobody uses it)
-            const int wn = w + 1 < wb ? w + 1 : w;
-            cplx<T> zn[E], an[E];
-            cx.load_ring(wn + 1, rr[0]);
-            cx.load_side(wn, tr);
-            cx.load_field(wn, vv);
-            cx.load_lane(wn, ep, zn, an);
-
+        // step s (outer index wa + s): issue `nx` for step s + 2, compute from
+        // LDS, hand `cur` (issued for step s + 1) over, store
+        auto step = [&](int s, Set& nx, const Set& cur) {
+            const int w = wa + s;
+            if (s + 2 < nsteps) cx.issue(nx, w + 3, w + 2);
             const cplx<T>* rm = cx.ring + (s % 3) * a.st_seg + site;
             const cplx<T>* r0 = cx.ring + ((s + 1) % 3) * a.st_seg + site;
             const cplx<T>* rp = cx.ring + ((s + 2) % 3) * a.st_seg + site;
             const int64_t rowi = cx.row_of(cx.m, w);
             const int64_t rb = rowi * a.rowel;
             T yr[E], yi[E];
-            cplx<T> xs_[E];
+            cplx<T> xs_[E], zv[E], av[E];
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int l = tid + k * kBlock;
@@ -834,14 +872,11 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 xs_[k] = xc;
                 yr[k] = hr;
                 yi[k] = hi;
+                zv[k] = cx.zl[l];
+                av[k] = ACC ? cx.al[l] : cplx<T>{T(0), T(0)};
             }
-            // hand the prefetched rows over, then finish the elements (the
-            // stores go out after the LDS writes, so waiting for the
-            // prefetch never waits for them)
             lds_barrier();
-            cx.store_ring(s % 3, rr[0]);
-            cx.store_side(tr);
-            cx.store_field(vv);
+            if (s + 1 < nsteps) cx.commit(cur, (s + 3) % 3);
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int xe = xe0 + tid + k * kBlock;
@@ -851,10 +886,12 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                     epilogue_ep(a, ep, rb + xe, gidx, tid & (a.ggroup - 1), xs_[k], zv[k], av[k], yr[k], yi[k], alT,
                                 gaT, er, ei, e0r, e0i, c, dxx, dxr, dxi, dyy);
                 }
-                zv[k] = zn[k];
-                av[k] = an[k];
             }
             lds_barrier();
+        };
+        for (int s = 0; s < nsteps; s += 2) {
+            step(s, A, B);
+            if (s + 1 < nsteps) step(s + 1, B, A);
         }
     }
 
@@ -901,7 +938,8 @@ __global__ __launch_bounds__(kBlock) void batch_staged_kernel(const KArgs<T, VT>
 }
 
 template <class P, typename T, typename VT, int E, unsigned EPM>
-__global__ __launch_bounds__(kBlock) void staged_kernel(KArgs<T, VT> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_STAGED_WAVES_PER_EU)))
+void staged_kernel(KArgs<T, VT> a) {
     if (a.st_parts == 8)
         staged_block<P, T, VT, E, EPM>(a, blockIdx.x, blockIdx.x & 7, blockIdx.x >> 3, gridDim.x >> 3);
     else
@@ -1012,20 +1050,11 @@ int env_int(const char* name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
-// LDS of a staged workgroup: three ring rows with halo, the side rows of 3D
-// lattices, and the field of the tile's orbital rows.
-template <class P, typename T, int E>
+template <class P, typename T, int E, unsigned EPM>
 size_t staged_lds_bytes(int nb) {
-    using S = Staged<T, E>;
-    const int seg = S::TW + 2 * P::NO * nb;
-    const int ntr = P::DIM == 3 ? 2 : 0;
-    return size_t(3 * seg + ntr * S::TW) * S::ES + size_t(S::TW / nb) * sizeof(T);
+    return staged_lds_bytes_for<P, T, E>(nb, EPM == 0u || (EPM & EP_ACC_ADD) != 0u);
 }
 
-// Geometry of a staged sweep for a target of G8 workgroups per XCD part:
-// walk length, strip height, parts.  Returns the workgroups per part actually
-// useful (at most the items of the largest part).  full_walk: one walk per
-// column (no splitting of the outer axis).
 template <class P, typename T, typename VT, int E>
 int staged_setup(const SweepParams& p, int G8, bool full_walk, KArgs<T, VT>& a) {
     using S = Staged<T, E>;
@@ -1067,7 +1096,7 @@ template <class P, typename T, typename VT, int E, unsigned EPM>
 hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
     KArgs<T, VT> a;
     make_kargs<P, T, VT>(p, false, a);
-    const size_t lds = staged_lds_bytes<P, T, E>(p.nb);
+    const size_t lds = staged_lds_bytes<P, T, E, EPM>(p.nb);
     const void* kern = reinterpret_cast<const void*>(&staged_kernel<P, T, VT, E, EPM>);
     // workgroups resident per CU at this LDS size (cached per size)
     static size_t occ_lds[8] = {};
@@ -1120,14 +1149,14 @@ bool staged_default(const SweepParams& p) {
     return (p.ep & (EP_GTERMS | EP_GRAD)) == 0 && elems >= (int64_t(1) << 20);
 }
 
-// Elements per lane of a staged launch: two for complex64 (16-byte chunks),
-// and for complex128 from nb = 8 on (longer tiles: fewer halo chunks per
-// element, more bytes in flight per workgroup).
+// Elements per lane of a staged launch: one for complex128, two for
+// complex64 (one 16-byte chunk per lane and row either way; longer tiles
+// need more registers than two resident waves per SIMD allow).
 int staged_elems(const SweepParams& p) {
     static const int env_e = env_int("PV_STAGED_E", 0);
     if (p.st_E > 0) return p.st_E;
     if (env_e > 0) return env_e;
-    return p.dtype == 0 && p.nb < 8 ? 1 : 2;
+    return p.dtype == 0 ? 1 : 2;
 }
 
 // Sweep kernel of a launch: the staged kernel for compiled families when the
@@ -1140,7 +1169,7 @@ hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
         static const int env_kernel = env_int("PV_SWEEP", 0);
         const int kind = p.kernel > 0 ? p.kernel : env_kernel;
         const bool aligned = ((reinterpret_cast<uintptr_t>(p.x) | reinterpret_cast<uintptr_t>(p.zero_row)) & 15) == 0;
-        if (aligned && (kind == 2 || (kind == 0 && staged_default(p)))) {
+        if (aligned && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && staged_default(p)))) {
             const int e = staged_elems(p);
             if constexpr (sizeof(T) == 8)
                 return e == 2 ? launch_staged_ep<P, T, VT, 2>(p, num_cus, s) : launch_staged_ep<P, T, VT, 1>(p, num_cus, s);
@@ -1535,6 +1564,7 @@ hipError_t batch_fill_record(const SweepParams& p, int staged, void* dst, int* n
         KArgs<T, VT> a;
         if constexpr (P::FAMILY != FAM_GENERIC) {
             if (staged) {
+                if (P::NO * p.nb > STAGED_MAX_SITE) return hipErrorInvalidValue;
                 make_kargs<P, T, VT>(p, false, a);
                 const int e = staged_elems(p);
                 int G8;
@@ -1567,7 +1597,7 @@ hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* tabl
                 constexpr unsigned KPM = EP_STORE_Y | EP_DOTS;
                 auto go = [&](auto ke) -> hipError_t {
                     constexpr int E = decltype(ke)::value;
-                    const size_t lds = staged_lds_bytes<P, T, E>(p.nb);
+                    const size_t lds = staged_lds_bytes<P, T, E, KPM>(p.nb);
                     if (lds > 65536) {
                         hipError_t e = hipFuncSetAttribute(
                             reinterpret_cast<const void*>(&batch_staged_kernel<P, T, VT, E, KPM>),

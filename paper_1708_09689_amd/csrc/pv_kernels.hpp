@@ -10,6 +10,9 @@
 namespace pv {
 
 constexpr int PV_MAX_NB_K = 64;
+// Largest site (n_orb * nb elements) the staged sweep kernel takes; wider
+// blocks use the direct kernel.
+constexpr int STAGED_MAX_SITE = 128;
 
 // Kernel families: a family fixes the stencil's offsets and the zero / real /
 // imaginary structure of every block at compile time; values stay runtime.
