@@ -352,6 +352,22 @@ def main():
                 print(f"# {dtype} nb={nb}: {m2:.4f} ms/step {variants[-1]['GB/s']} GB/s", file=sys.stderr, flush=True)
                 del s2
                 torch.cuda.empty_cache()
+            # on-the-fly field (counter-based generator in the kernel): no field stream
+            lat.set_random_potential(W.MASTER_SEED + WORKLOAD_INDEX, 2.0)
+            for nb in (1, 4):
+                s2 = Sweep(pv, torch, lat, nb, dtype, dev)
+                m2 = time_steps(torch, s2, 3, 10)
+                b2 = bytes_per_step(lat.n_rows, 0, nb, dtype)
+                variants.append({"dtype": dtype, "nb": nb, "field": "generated in the kernel",
+                                 "ms_per_step": round(m2, 5),
+                                 "GLUP/s": round(lat.n_rows * nb / (m2 * 1e-3) / 1e9, 3),
+                                 "GB/s": round(b2 / (m2 * 1e-3) / 1e9, 1),
+                                 "frac_hbm_peak": round(b2 / (m2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "bytes_per_LUP": round(b2 / (lat.n_rows * nb), 3)})
+                print(f"# {dtype} nb={nb} generated field: {m2:.4f} ms/step {variants[-1]['GB/s']} GB/s",
+                      file=sys.stderr, flush=True)
+                del s2
+                torch.cuda.empty_cache()
 
     configs = {}
     if not args.no_configs:

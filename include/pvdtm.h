@@ -159,6 +159,21 @@ pv_status pv_lattice_info(const pv_lattice *lat, int64_t *n_sites, int64_t *n_ro
 pv_status pv_lattice_set_potential(pv_lattice *lat, const void *V_dev, int rtype);
 
 /*
+ * On-the-fly disorder (Sec. 3.3: random numbers generated inside the kernel
+ * instead of streamed from memory).  The field is never stored: the sweep
+ * kernels evaluate it wherever they need it from a counter-based generator,
+ *     V[i] = W * (u_i - 1/2),  u_i = (s_i >> 11) * 2^-53,
+ *     s_i  = output number i + 1 of SplitMix64 (Steele, Lea, Flood 2014)
+ *            seeded with `seed`,
+ * i the site index (PV_POT_SITE) or the orbital row (PV_POT_ORBITAL).  The
+ * value is the same in every sweep and independent of the traversal order;
+ * it saves the field's 8 / (n_orb nb) bytes per row update.  Replaces any
+ * previous field (pv_lattice_set_potential replaces this one in turn).
+ * Gradients with respect to the field are still returned per site / row.
+ */
+pv_status pv_lattice_set_random_potential(pv_lattice *lat, uint64_t seed, double W);
+
+/*
  * One fused sweep (Sec. 3.2 listing), per column c of the nb-wide blocks:
  *     y[:, c] = alpha[c] * (H x[:, c] - beta[c] x[:, c]) + gamma[c] * z[:, c]
  * gamma[c] == 0 means z is not read (z may be NULL then for all columns).

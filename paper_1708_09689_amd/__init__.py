@@ -62,6 +62,7 @@ SIGNATURES = {
     "pv_lattice_destroy": (None, [_vp]),
     "pv_lattice_info": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _ip]),
     "pv_lattice_set_potential": (_i, [_vp, _vp, _i]),
+    "pv_lattice_set_random_potential": (_i, [_vp, ctypes.c_uint64, _d]),
     "pv_spmmv_workspace_size": (_sz, [_vp, _i, _i]),
     "pv_spmmv": (_i, [_vp, _i, _i, _vp, _vp, _vp, _dp, _dp, _dp, _u, _vp, _vp, _sz, _vp]),
     "pv_kpm_workspace_size": (_sz, [_vp, _i, _i, _i]),
@@ -247,6 +248,12 @@ class Lattice:
             raise TypeError("V must be float64 or float32")
         _check(lib().pv_lattice_set_potential(self.handle, ctypes.c_void_p(V.data_ptr()), rt))
         self._V = V
+
+    def set_random_potential(self, seed: int, W: float):
+        """pv_lattice_set_random_potential: on-the-fly field W (u_i - 1/2) from
+        the counter-based generator seeded with `seed` (no array is stored)."""
+        _check(lib().pv_lattice_set_random_potential(self.handle, int(seed) & ((1 << 64) - 1), float(W)))
+        self._V = None
 
 
 def pv_lattice_create(L, periodic, stencil, check_hermitian=True) -> Lattice:

@@ -87,9 +87,12 @@ struct pv_lattice {
     double* d_coef = nullptr;
     int* d_offs = nullptr;
     void* d_zero = nullptr;                            // one x-row of zeros (widest block)
-    // borrowed field
+    // borrowed field, or the parameters of the on-the-fly field
     const void* V = nullptr;
     int vtype = 0;
+    int rng_on = 0;
+    uint64_t rng_seed = 0;
+    double rng_W = 0.0;
     // launch shapes per (dtype, log2 nb)
     pv_tuning tune[2][7] = {};
 };
@@ -226,7 +229,11 @@ pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     p.vtype = l->vtype;
     p.n_orb = l->n_orb;
     p.n_terms = l->n_terms;
-    p.pot_mode = l->V ? l->pot_mode : 0;
+    const bool field = l->V != nullptr || l->rng_on;
+    p.pot_mode = field ? l->pot_mode : 0;
+    p.field = !field ? 0 : (l->rng_on ? 2 : 1);
+    p.rng_seed = l->rng_seed;
+    p.rng_W = l->rng_W;
     for (int d = 0; d < 3; ++d) {
         p.L[d] = l->L[d];
         p.periodic[d] = l->periodic[d];
@@ -582,6 +589,19 @@ extern "C" pv_status pv_lattice_set_potential(pv_lattice* l, const void* V, int 
         return fail(PV_ERR_INVALID_ARG, "potential pointer misaligned");
     l->V = V;
     l->vtype = rtype;
+    l->rng_on = 0;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_lattice_set_random_potential(pv_lattice* l, uint64_t seed, double W) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if (l->pot_mode == PV_POT_NONE) return fail(PV_ERR_INVALID_ARG, "lattice was created with PV_POT_NONE");
+    if (!std::isfinite(W)) return fail(PV_ERR_INVALID_ARG, "W must be finite");
+    l->V = nullptr;
+    l->vtype = PV_F64;
+    l->rng_on = 1;
+    l->rng_seed = seed;
+    l->rng_W = W;
     return PV_OK;
 }
 
@@ -958,7 +978,7 @@ std::string tune_key(const pv_lattice* l, int dtype, int nb) {
     char buf[512];
     std::snprintf(buf, sizeof buf, "family=%d orb=%d L=%lldx%lldx%lld bc=%d%d%d nb=%d dtype=%d vtype=%d dev=%s cus=%d",
                   l->family, l->n_orb, (long long)l->L[0], (long long)l->L[1], (long long)l->L[2], l->periodic[0],
-                  l->periodic[1], l->periodic[2], nb, dtype, l->V ? l->vtype : -1, arch.c_str(), cus);
+                  l->periodic[1], l->periodic[2], nb, dtype, l->rng_on ? 2 : (l->V ? l->vtype : -1), arch.c_str(), cus);
     return buf;
 }
 
@@ -1561,8 +1581,11 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
         uint64_t ab[2];
         std::memcpy(&ab[0], &a[i], 8);
         std::memcpy(&ab[1], &b[i], 8);
+        uint64_t rw;
+        std::memcpy(&rw, &B->lats[i]->rng_W, 8);
         key.insert(key.end(), {(uint64_t)(uintptr_t)r[i], ab[0], ab[1], (uint64_t)(uintptr_t)B->lats[i]->V,
-                               (uint64_t)B->lats[i]->vtype, (uint64_t)(uintptr_t)B->lats[i]->d_coef});
+                               (uint64_t)B->lats[i]->vtype, (uint64_t)(uintptr_t)B->lats[i]->d_coef,
+                               (uint64_t)B->lats[i]->rng_on, B->lats[i]->rng_seed, rw});
     }
     if (B->exec && key == B->key) {
         PV_HIP(hipGraphLaunch(B->exec, s));

@@ -89,6 +89,9 @@ struct KArgs {
     const cplx<T>* zsrc;    // z, or x when no column reads z (a valid dummy)
     const cplx<T>* asrc;    // acc_in, or x when not accumulating
     const VT* V;
+    int field;              // 0 none, 1 stored array V, 2 counter-based generator
+    uint64_t rng_seed;
+    double rng_W;
     const cplx<T>* gw0;     // adjoint terms: w_{k-1}, w_k, w_{k+1} (or NULL)
     const cplx<T>* gw1;
     const cplx<T>* gw2;
@@ -126,6 +129,28 @@ __device__ __forceinline__ void mac(T& ar, T& ai, unsigned char k, T cr, T ci, c
     if (k == CR) { ar += cr * v.re; ai += cr * v.im; }
     else if (k == CI) { ar -= ci * v.im; ai += ci * v.re; }
     else if (k == CC) { ar += cr * v.re - ci * v.im; ai += cr * v.im + ci * v.re; }
+}
+
+// Counter-based generator of the on-the-fly field (SplitMix64, Steele, Lea
+// and Flood 2014): output i + 1 of the stream seeded with `seed`, i.e. the
+// mixing function applied to seed + (i + 1) * golden gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// On-site field value at index i (site, or orbital row for per-orbital
+// fields): the stored array, or W (u - 1/2) with u the generator's top 53
+// bits times 2^-53 -- u - 1/2 is exact, so the value is one rounded product.
+template <typename T, typename VT>
+__device__ __forceinline__ T field_at(const KArgs<T, VT>& a, int64_t i) {
+    if (a.field == 2) {
+        const double u = double(splitmix64_at(a.rng_seed, uint64_t(i)) >> 11) * 0x1.0p-53;
+        return T(a.rng_W * (u - 0.5));
+    }
+    return T(a.V[i]);
 }
 
 // Slots of a compiled family: for block t (t == NT: off-diagonal part of the
@@ -409,9 +434,9 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
         cplx<T> av{T(0), T(0)};
         if (a.ep & EP_ACC_ADD) av = ld_row_nt(a.acc_in + rb, off0);
         T vs = T(0);
-        if (a.V != nullptr) {
-            const VT* vrow = a.V + (int64_t)row * a.Lx * (a.pot_mode == 1 ? 1 : NO);
-            vs = T(a.pot_mode == 1 ? vrow[x] : vrow[x * NO + o]);
+        if (a.field != 0) {
+            const int64_t vs0 = (int64_t)row * a.Lx * (a.pot_mode == 1 ? 1 : NO);
+            vs = field_at(a, a.pot_mode == 1 ? vs0 + x : vs0 + x * NO + o);
         }
         T hr, hi;
         const T d = dgr - beT + vs;
@@ -612,6 +637,7 @@ struct StagedCtx {
     uint32_t roff[S::RCH];
     uint32_t soff[S::TCH];
     uint32_t voff[E];
+    int vshift;      // element -> field entry: log2 of elements per site or per orbital row
 
     __device__ __forceinline__ int64_t row_of(int mm, int ww) const {
         return P::DIM == 3 ? (int64_t)ww * a.Ly + mm : (int64_t)ww;
@@ -649,12 +675,14 @@ struct StagedCtx {
             const int g = xe0 + (tid + k * kBlock) * S::CE;
             soff[k] = uint32_t(g < rowel ? g : rowel - S::CE) * S::ES;
         }
-        const int rowlen = a.Lx * P::NO;
+        // field entries of the tile: one per site (site field) or per orbital
+        // row, clamped into the lattice row
+        const int vlen = a.pot_mode == 1 ? a.Lx : a.Lx * P::NO;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            int r = (xe0 >> a.lognb) + tid + k * kBlock;   // orbital row inside the lattice row
-            if (r >= rowlen) r = rowlen - 1;
-            voff[k] = uint32_t(a.pot_mode == 1 ? r / P::NO : r);
+            int r = (xe0 >> vshift) + tid + k * kBlock;
+            if (r >= vlen) r = vlen - 1;
+            voff[k] = uint32_t(r);
         }
     }
     // Issue the loads of ring row (m, w_ring) and of the per-step rows of
@@ -682,11 +710,11 @@ struct StagedCtx {
 #pragma unroll
             for (int k = 0; k < S::TCH; ++k) st.acc[k] = ld_chunk_nt<T>(ar, soff[k]);
         }
-        if (a.V != nullptr) {
-            const VT* vb = a.V + rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
+        if (a.field != 0) {
+            const int64_t vb = rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
 #pragma unroll
             for (int k = 0; k < E; ++k)
-                if (k * kBlock < (S::TW >> a.lognb)) st.v[k] = T(vb[voff[k]]);
+                if (k * kBlock < (S::TW >> vshift)) st.v[k] = field_at(a, vb + voff[k]);
         }
     }
     // Hand a set to LDS: ring row into slot, per-step rows into their buffers.
@@ -711,8 +739,8 @@ struct StagedCtx {
 #pragma unroll
             for (int k = 0; k < S::TCH; ++k) da[tid + k * kBlock] = st.acc[k];
         }
-        if (a.V != nullptr) {
-            const int nrow = S::TW >> a.lognb;
+        if (a.field != 0) {
+            const int nrow = S::TW >> vshift;
 #pragma unroll
             for (int k = 0; k < E; ++k)
                 if (tid + k * kBlock < nrow) vl[tid + k * kBlock] = st.v[k];
@@ -775,6 +803,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
 
     Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, a.st_seg / S::CE, 0, 0};
+    cx.vshift = a.pot_mode == 1 ? a.logsite : a.lognb;
     cx.tra = cx.ring + 3 * a.st_seg;
     cx.zl = cx.tra + NTR * S::TW;
     cx.al = cx.zl + S::TW;
@@ -842,7 +871,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 const int x = xe >> a.logsite;
                 const bool xlo = a.px || x > 0, xhi = a.px || x < a.Lx - 1;
                 const cplx<T> xc = r0[l];
-                const T vs = a.V != nullptr ? cx.vl[l >> a.lognb] : T(0);
+                const T vs = a.field != 0 ? cx.vl[l >> cx.vshift] : T(0);
                 const T d = dgr - beT + vs;
                 T hr = d * xc.re - dgi * xc.im;
                 T hi = d * xc.im + dgi * xc.re;
@@ -986,6 +1015,9 @@ void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
     a.zsrc = a.z ? a.z : a.x;
     a.asrc = ((p.ep & EP_ACC_ADD) && a.acc_in) ? a.acc_in : a.x;
     a.V = static_cast<const VT*>(p.V);
+    a.field = p.field;
+    a.rng_seed = p.rng_seed;
+    a.rng_W = p.rng_W;
     a.gw0 = static_cast<const cplx<T>*>(p.gw[0]);
     a.gw1 = static_cast<const cplx<T>*>(p.gw[1]);
     a.gw2 = static_cast<const cplx<T>*>(p.gw[2]);

@@ -52,7 +52,10 @@ struct SweepParams {
     void* y;
     const void* acc_in;
     void* acc_out;
-    const void* V;        // NULL = no field
+    const void* V;        // stored field (field == 1)
+    int field;            // 0 none, 1 stored array V, 2 counter-based generator
+    uint64_t rng_seed;    // field == 2: V[i] = rng_W (u_i - 1/2), u_i from SplitMix64 output i + 1
+    double rng_W;
     const void* gw[3];    // adjoint terms (EP_GTERMS / EP_GRAD)
     const double* gcoef;  // device [3][nb] complex
     double* grad;         // device gradient, n_sites (grad_mode 1) or n_rows (grad_mode 2)

@@ -204,3 +204,17 @@ def test_tuning_set_get_and_validation(lib):
         pv.pv_lattice_set_tuning(lat, pv.PV_C128, 3, sh)                    # nb not a power of two
     pv.pv_lattice_set_tuning(lat, pv.PV_C128, 4, None)
     assert pv.pv_lattice_get_tuning(lat, pv.PV_C128, 4)["kernel"] == 0
+
+
+def test_random_potential_validation(lib):
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0])
+    lat = pv.Lattice((4, 4, 4), (1, 1, 1), st)
+    lat.set_random_potential(2**64 - 1, 2.0)          # any 64-bit seed
+    with pytest.raises(pv.PvError):
+        lat.set_random_potential(1, float("nan"))
+    s0 = dict(st)
+    s0["pot_mode"] = pv.PV_POT_NONE
+    lat0 = pv.Lattice((4, 4, 4), (1, 1, 1), s0)
+    with pytest.raises(pv.PvError) as e:
+        lat0.set_random_potential(1, 1.0)
+    assert e.value.status == 1
