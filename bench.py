@@ -289,6 +289,35 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     return out
 
 
+def bench_weyl_spectral(pv, torch, W, dev, nk=64, M=256):
+    """A(k, E) of a disordered Weyl semimetal along k_x (k_y = k_z = 0), the
+    Fermi-arc setup of the paper's Weyl figure: 256 x 32 x 32 sites, periodic
+    x, y, open z, box disorder of strength 2, test states on the z = 0
+    surface; nk momenta x 2 orbitals as Bloch columns in blocks of 32, M
+    moments each (complex128)."""
+    import math
+    st = pv.pv_model_stencil(pv.PV_MODEL_WEYL, [math.pi / 2])
+    lat = pv.Lattice((256, 32, 32), (1, 1, 0), st)
+    lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 2.0, W.generator(5, W.STREAM_POTENTIAL))).to(dev))
+    kx = 2 * math.pi * np.arange(nk) / 256
+    ks = np.array([[k, 0.0, 0.0] for k in kx for _ in (0, 1)])
+    nu = [n for _ in kx for n in (0, 1)]
+    a = 7.5
+    blocks = [(ks[i:i + 32], nu[i:i + 32]) for i in range(0, len(nu), 32)]
+    R = [pv.pv_bloch_block(lat, k, n, layer=(2, 0)) for k, n in blocks]
+    pv.pv_kpm_moments(lat, R[0], M, a, 0.0)
+    mus = []
+    ms = _timed(torch, lambda: mus.extend(pv.pv_kpm_moments(lat, r, M, a, 0.0) for r in R), 1)
+    mu = torch.cat(mus[-len(R):]).cpu().numpy()
+    E = np.array([0.0])
+    A0 = [float(pv.pv_kpm_spectral_function(mu[2 * i:2 * i + 2], E, a, 0.0, 32.0)[0]) for i in range(nk)]
+    lups = lat.n_rows * 32 * (M // 2) * len(R)
+    return {"workload": f"Weyl 256x32x32 (periodic x,y, open z), W=2, surface Bloch states, {nk} k_x x 2 orbitals, "
+                        f"M={M}, complex128, blocks of 32",
+            "ms_total": round(ms, 2), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
+            "A_E0_along_kx_first8": [round(v, 4) for v in A0[:8]]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,7 +405,8 @@ def main():
                          ("filter_sweeps_ti256", lambda: bench_filter(pv, torch, lat, dev)),
                          ("chebtp_graphene1024", lambda: bench_chebtp_graphene(pv, torch, W, dev)),
                          ("batched_kpm_96", lambda: bench_batch(pv, torch, W, dev)),
-                         ("adjoint", lambda: bench_adjoint(pv, torch, W, dev))):
+                         ("adjoint", lambda: bench_adjoint(pv, torch, W, dev)),
+                         ("weyl_spectral", lambda: bench_weyl_spectral(pv, torch, W, dev))):
             t0 = time.perf_counter()
             configs[name] = fn()
             torch.cuda.empty_cache()

@@ -207,6 +207,28 @@ pv_status pv_kpm_dos(int M, const double *mu, double a, double b, int nE, const 
                      double *rho);
 
 /*
+ * Momentum-resolved spectral function (Sec. 2.2, Eq. ak) by KPM with Bloch
+ * start columns.  pv_bloch_block writes the block
+ *     out[s][o][c] = exp(i k_c . r_s)  if o == orbital[c] and r_s lies in
+ *                                      the layer, else 0,
+ * r_s = (x, y, z) the site's integer coordinates, k: host [nb][3] (radians
+ * per lattice unit), orbital: host [nb] in [0, n_orb).  layer_axis = -1 puts
+ * the state on every site; 0, 1 or 2 restricts it to the sites whose
+ * coordinate along that axis equals layer_index (a test state on one
+ * surface, as for the Fermi arcs of Sec. 4.3).  out: device block of dtype,
+ * n_rows x nb.  With mu = pv_kpm_moments of that block,
+ * pv_kpm_spectral_function returns on the host
+ *     A(E) = norm * sum_c rho_c(E),
+ * rho_c the Jackson-damped reconstruction of column c (as pv_kpm_dos).
+ * norm = n_rows / (number of sites carrying the state) makes A integrate to
+ * the number of columns: the spectral weight per site of Eq. ak.
+ */
+pv_status pv_bloch_block(pv_lattice *lat, int dtype, int nb, const double *k, const int *orbital,
+                         int layer_axis, int64_t layer_index, void *out, void *stream);
+pv_status pv_kpm_spectral_function(int nb, int M, const double *mu, double a, double b, double norm,
+                                   int nE, const double *E, double *A);
+
+/*
  * Chebyshev series applied to a block (Sec. 4.1 and 4.2):
  *     Y = sum_{k=0}^{K} coef[k] T_k(H~) X,   coef: host complex [K+1] (re, im)
  * using K fused sweeps whose epilogue accumulates coef[k] * w_k.  X and Y

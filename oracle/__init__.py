@@ -25,6 +25,8 @@ kpm          Chebyshev moments (direct and via the product doubling), Jackson
 chebtp       Bessel J_k by Miller's backward recurrence, Chebyshev time
              propagation (Sec. 4.1, Eq. U_1)
 chebfd       Chebyshev filter diagonalisation with Rayleigh-Ritz (Sec. 4.2)
+spectral     momentum-resolved spectral function A(k, E) from Bloch start
+             vectors (Sec. 2.2, Eq. ak)
 rng          counter-based (SplitMix64) on-the-fly disorder field (Sec. 3.3)
 adjoint      discrete adjoints of the KPM moments and of the Chebyshev time
              propagation with respect to the on-site potential, and central

@@ -90,6 +90,8 @@ SIGNATURES = {
     "pv_kpm_moments_vjp": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_cheb_propagate_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
+    "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
     "pv_lattice_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_lattice_get_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_autotune_workspace_size": (_sz, [_vp, _i, _i]),
@@ -365,6 +367,36 @@ def pv_stream_copy(src, dst):
         raise ValueError("dst too small")
     _check(lib().pv_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, _stream()))
     return dst
+
+
+def pv_bloch_block(lat, k, orbital, layer=None, dtype=PV_C128, out=None, device="cuda"):
+    """Bloch start columns exp(i k_c . r) on orbital[c] (optionally one layer:
+    (axis, index)); k: [nb][3]; returns the device block [n_rows, nb]."""
+    torch = _torch()
+    k = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1, 3))
+    orb = np.ascontiguousarray(np.asarray(orbital, dtype=np.int32).reshape(-1))
+    nb = k.shape[0]
+    if orb.size != nb:
+        raise ValueError("k and orbital need the same number of columns")
+    if out is None:
+        out = torch.empty((lat.n_rows, nb), dtype=torch.complex128 if dtype == PV_C128 else torch.complex64,
+                          device=device)
+    axis, index = (-1, 0) if layer is None else layer
+    _check(lib().pv_bloch_block(lat.handle, dtype, nb, _dptr(k), orb.ctypes.data_as(_ip), axis, index,
+                                _vec(out, "out", lat.n_rows, nb, dtype), _stream()))
+    return out
+
+
+def pv_kpm_spectral_function(mu, E, a: float, b: float, norm: float) -> np.ndarray:
+    """A(E) = norm * sum_c rho_c(E) from host moments mu [nb][M]."""
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64))
+    if mu.ndim == 1:
+        mu = mu[None, :]
+    E = np.ascontiguousarray(np.asarray(E, dtype=np.float64))
+    A = np.zeros(E.size)
+    _check(lib().pv_kpm_spectral_function(mu.shape[0], mu.shape[1], _dptr(mu), a, b, norm, E.size, _dptr(E),
+                                          _dptr(A)))
+    return A
 
 
 def pv_lattice_set_tuning(lat, dtype: int, nb: int, tuning=None):

@@ -748,6 +748,48 @@ extern "C" pv_status pv_kpm_dos(int M, const double* mu, double a, double b, int
     return PV_OK;
 }
 
+extern "C" pv_status pv_kpm_spectral_function(int nb, int M, const double* mu, double a, double b, double norm,
+                                              int nE, const double* E, double* A) {
+    if (nb < 1 || M < 1 || !mu || nE < 0 || (nE && (!E || !A)) || !(a > 0.0) || !std::isfinite(norm))
+        return fail(PV_ERR_INVALID_ARG, "pv_kpm_spectral_function: bad arguments");
+    std::vector<double> rho(nE > 0 ? nE : 1);
+    for (int e = 0; e < nE; ++e) A[e] = 0.0;
+    for (int c = 0; c < nb; ++c) {
+        pv_status st = pv_kpm_dos(M, mu + (size_t)c * M, a, b, nE, E, rho.data());
+        if (st != PV_OK) return st;
+        for (int e = 0; e < nE; ++e) A[e] += norm * rho[e];
+    }
+    return PV_OK;
+}
+
+extern "C" pv_status pv_bloch_block(pv_lattice* l, int dtype, int nb, const double* k, const int* orbital,
+                                    int layer_axis, int64_t layer_index, void* out, void* stream) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "dtype must be PV_C128 or PV_C64");
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if ((st = check_vec(out, dtype, "out")) != PV_OK) return st;
+    if (!k || !orbital) return fail(PV_ERR_INVALID_ARG, "k and orbital are required host arrays [nb]");
+    if (layer_axis < -1 || layer_axis > 2) return fail(PV_ERR_INVALID_ARG, "layer_axis must be -1, 0, 1 or 2");
+    if (layer_axis >= 0 && (layer_index < 0 || layer_index >= l->L[layer_axis]))
+        return fail(PV_ERR_INVALID_ARG, "layer_index %lld outside the lattice", (long long)layer_index);
+    pv::BlochCols cols{};
+    for (int c = 0; c < nb; ++c) {
+        if (orbital[c] < 0 || orbital[c] >= l->n_orb)
+            return fail(PV_ERR_INVALID_ARG, "orbital[%d] = %d outside [0, %d)", c, orbital[c], l->n_orb);
+        for (int d = 0; d < 3; ++d) {
+            if (!std::isfinite(k[3 * c + d])) return fail(PV_ERR_INVALID_ARG, "k[%d] is not finite", c);
+            cols.k[c][d] = k[3 * c + d];
+        }
+        cols.orb[c] = orbital[c];
+    }
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    PV_HIP(pv::launch_bloch(dtype, l->n_sites, l->n_orb, nb, int(l->L[0]), int(l->L[1]), cols, layer_axis,
+                            layer_index, out, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Chebyshev series / propagation
 // ---------------------------------------------------------------------------

@@ -1073,7 +1073,7 @@ void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
         a.fd_slab = make_fastdiv(uint32_t(a.ntx) * uint32_t(p.L[1]) * uint32_t(p.L[2]));
         a.fd_pf = make_fastdiv(uint32_t(a.ntx) * uint32_t(p.L[1]));
         a.ntiles = int64_t(a.ntx) * p.L[1] * p.L[2];
-        a.tpb = p.tpb > 0 ? p.tpb : 4;
+        a.tpb = p.tpb > 0 ? p.tpb : tiles_per_block(a.ntiles);
     }
 }
 
@@ -1447,7 +1447,42 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const u32x4* __restrict__ 
     }
 }
 
+// Bloch start columns (one element per lane).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void bloch_kernel(cplx<T>* __restrict__ out, int64_t n, int n_orb, int nb,
+                                                     int Lx, int Ly, BlochCols cols, int axis, int64_t index) {
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const int c = int(e % nb);
+        const int64_t r = e / nb;
+        const int o = int(r % n_orb);
+        const int64_t s = r / n_orb;
+        const int64_t x = s % Lx, y = (s / Lx) % Ly, z = s / ((int64_t)Lx * Ly);
+        const int64_t coord = axis == 0 ? x : (axis == 1 ? y : z);
+        double re = 0.0, im = 0.0;
+        if (o == cols.orb[c] && (axis < 0 || coord == index)) {
+            const double ph = cols.k[c][0] * double(x) + cols.k[c][1] * double(y) + cols.k[c][2] * double(z);
+            sincos(ph, &im, &re);
+        }
+        out[e] = cplx<T>{T(re), T(im)};
+    }
+}
+
 }  // namespace
+
+static int elementwise_grid(int64_t n);
+
+hipError_t launch_bloch(int dtype, int64_t n_sites, int n_orb, int nb, int Lx, int Ly, const BlochCols& cols,
+                        int axis, int64_t index, void* out, hipStream_t s) {
+    const int64_t n = n_sites * n_orb * nb;
+    const int g = elementwise_grid(n);
+    if (dtype == 0)
+        hipLaunchKernelGGL(bloch_kernel<double>, dim3(g), dim3(kBlock), 0, s, static_cast<cplx<double>*>(out), n,
+                           n_orb, nb, Lx, Ly, cols, axis, index);
+    else
+        hipLaunchKernelGGL(bloch_kernel<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cplx<float>*>(out), n,
+                           n_orb, nb, Lx, Ly, cols, axis, index);
+    return hipGetLastError();
+}
 
 int64_t sweep_grid_max(const int64_t L[3], int n_orb, int nb) {
     const int64_t rowel = L[0] * n_orb * nb;

@@ -100,6 +100,15 @@ hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X,
                          int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
+// Bloch start columns: out[s][o][c] = exp(i k_c . r_s) for o == orb[c] on
+// the sites of the layer (axis < 0: all sites), else 0.
+struct BlochCols {
+    double k[64][3];
+    int orb[64];
+};
+hipError_t launch_bloch(int dtype, int64_t n_sites, int n_orb, int nb, int Lx, int Ly, const BlochCols& cols,
+                        int axis, int64_t index, void* out, hipStream_t s);
+
 // Batched sweeps: one argument record per instance (built on the host with
 // batch_fill_record from that instance's launch description), a table of
 // records in device memory, and per-workgroup instance maps.  staged: every

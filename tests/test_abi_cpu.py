@@ -218,3 +218,12 @@ def test_random_potential_validation(lib):
     with pytest.raises(pv.PvError) as e:
         lat0.set_random_potential(1, 1.0)
     assert e.value.status == 1
+
+
+def test_spectral_function_matches_oracle(lib):
+    from oracle import spectral
+    g = np.random.default_rng(5)
+    mu = np.concatenate([np.full((3, 1), 0.5), 0.2 * g.standard_normal((3, 47)) / np.arange(1, 48)], axis=1)
+    E = np.linspace(-6.5, 6.5, 77)
+    A = pv.pv_kpm_spectral_function(mu, E, 7.0, 0.1, 2.0)
+    assert np.abs(A - spectral.spectral_function(mu, E, 7.0, 0.1, 2.0)).max() < 1e-13
