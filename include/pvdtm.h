@@ -135,6 +135,28 @@ int pv_version(void);
  *   PV_MODEL_WEYL       Sec. 2.3 Eq. (TB_H_wsm); params {k0}
  * On return *n_terms, *n_orb, *dim and *pot_mode describe the model.
  */
+/*
+ * Stencil description language (Sec. 3.2): parse the text of a DSL program
+ * into the same descriptor arrays as pv_model_stencil (same capacities).
+ * Statements: dim, size, n_coeff_const, n_coeff_variable, n_coeff_rand,
+ * coeff_const_default, and "nn d0 d1 [d2]" followed by one row line per
+ * orbital with entries "col|value" or "col|type|arg" (type f fixed, c
+ * constant coefficient, v variable per site, r random per site).  Entry
+ * (k, q) of the block at offset d adds value * x[s + d][q] to y[s][k].
+ * Values may be complex ("0.5i", "1-2i"; an extension of the paper's real
+ * coefficients).  Constant coefficients take coeff_const[idx] when idx <
+ * n_const, else the coeff_const_default values.  Per-site coefficients are
+ * accepted on the on-site diagonal only: *pot_mode = PV_POT_SITE (one index
+ * for all orbitals) or PV_POT_ORBITAL (index k on row k), and *field_kind =
+ * 1 for v (attach an array with pv_lattice_set_potential) or 2 for r (use
+ * pv_lattice_set_random_potential); 0 without per-site coefficients.
+ * Syntax errors return PV_ERR_INVALID_ARG with the line number in
+ * pv_last_error(); shapes the kernels do not support, PV_ERR_UNSUPPORTED.
+ */
+pv_status pv_dsl_stencil(const char *text, const double *coeff_const, int n_const, int *dim,
+                         int *n_orb, int *n_terms, int *offsets, double *blocks, double *onsite,
+                         int *pot_mode, int *field_kind);
+
 typedef enum pv_model {
     PV_MODEL_TI = 0, PV_MODEL_GRAPHENE2 = 1, PV_MODEL_GRAPHENE4 = 2, PV_MODEL_WEYL = 3
 } pv_model;

@@ -92,6 +92,7 @@ SIGNATURES = {
     "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
     "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
+    "pv_dsl_stencil": (_i, [ctypes.c_char_p, _dp, _i, _ip, _ip, _ip, _ip, _dp, _dp, _ip, _ip]),
     "pv_lattice_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_lattice_get_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_autotune_workspace_size": (_sz, [_vp, _i, _i]),
@@ -189,6 +190,26 @@ def pv_model_stencil(model: int, params=None) -> dict:
     e = onsite[: no * no * 2].reshape(no, no, 2)
     return {"dim": dim.value, "n_orb": no, "offsets": offs[: 3 * nt].reshape(nt, 3).copy(),
             "blocks": b[..., 0] + 1j * b[..., 1], "onsite": e[..., 0] + 1j * e[..., 1], "pot_mode": pot.value}
+
+
+def pv_dsl_stencil(text: str, coeff_const=None) -> dict:
+    """Parse a DSL program (Sec. 3.2) into a stencil dict (as pv_model_stencil),
+    plus "field": 0 none, 1 variable (array), 2 random (on the fly)."""
+    cc = None if coeff_const is None else np.ascontiguousarray(np.asarray(coeff_const, dtype=np.float64))
+    dim, n_orb, n_terms, pot, fk = (ctypes.c_int() for _ in range(5))
+    offs = np.zeros(PV_MAX_TERMS * 3, dtype=np.int32)
+    blocks = np.zeros(PV_MAX_TERMS * PV_MAX_ORB * PV_MAX_ORB * 2)
+    onsite = np.zeros(PV_MAX_ORB * PV_MAX_ORB * 2)
+    _check(lib().pv_dsl_stencil(text.encode(), None if cc is None else _dptr(cc), 0 if cc is None else cc.size,
+                                ctypes.byref(dim), ctypes.byref(n_orb), ctypes.byref(n_terms),
+                                offs.ctypes.data_as(_ip), _dptr(blocks), _dptr(onsite), ctypes.byref(pot),
+                                ctypes.byref(fk)))
+    no, nt = n_orb.value, n_terms.value
+    b = blocks[: nt * no * no * 2].reshape(nt, no, no, 2)
+    e = onsite[: no * no * 2].reshape(no, no, 2)
+    return {"dim": dim.value, "n_orb": no, "offsets": offs[: 3 * nt].reshape(nt, 3).copy(),
+            "blocks": b[..., 0] + 1j * b[..., 1], "onsite": e[..., 0] + 1j * e[..., 1], "pot_mode": pot.value,
+            "field": fk.value}
 
 
 class Lattice:

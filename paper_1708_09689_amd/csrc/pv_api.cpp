@@ -306,6 +306,9 @@ pv_status fill_traversal(pv_lattice* l, int dtype, int nb, pv::SweepParams& p) {
 // ---------------------------------------------------------------------------
 // error helpers
 // ---------------------------------------------------------------------------
+// Error reporting for the other translation units of the library.
+pv_status pv_fail_status(pv_status st, const char* msg) { return fail(st, "%s", msg); }
+
 extern "C" const char* pv_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char* pv_status_string(pv_status s) {

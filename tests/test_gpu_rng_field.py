@@ -83,3 +83,21 @@ def test_gradient_with_generated_field():
     g = host(pv.pv_kpm_moments_vjp(c.lat, dev(r), 32, 7.0, 0.0, dev(gbar), ckpt_every=8))
     ref = adjoint.kpm_vjp(c.H, 4, "site", r, 32, 7.0, 0.0, gbar)
     assert np.abs(g - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_dsl_program_end_to_end():
+    """A DSL program with random per-site coefficients (the Weyl model file of
+    the DSL tests) drives the KPM on the GPU with the on-the-fly field."""
+    import os
+    from oracle import lattice, models
+    text = open(os.path.join(os.path.dirname(__file__), "golden", "dsl", "weyl.dsl")).read()
+    st = pv.pv_dsl_stencil(text)
+    assert st["field"] == 2
+    L = (10, 6, 5)
+    lat = pv.Lattice(L, (1, 1, 0), st)
+    lat.set_random_potential(SEED + 7, 1.5)
+    olat = lattice.Lattice(L, (1, 1, 0), 2)
+    H = hamiltonian.assemble(models.weyl_semimetal(), olat, rng.field(SEED + 7, 1.5, olat.n_sites))
+    r = W.random_phase_block(olat.n_rows, 4, W.generator(7, W.STREAM_VECTORS))
+    mu = host(pv.pv_kpm_moments(lat, dev(r), 64, 7.5, 0.0))
+    assert np.abs(mu - kpm.moments_doubling(H, r, 64, 7.5, 0.0)).max() < 1e-12
