@@ -321,6 +321,39 @@ pv_status pv_chebfd_filter_coefficients(double lam_l, double lam_r, double a, do
 pv_status pv_host_heev(int n, const double *A, double *w, double *V);
 
 /*
+ * trLanczosFD (Sec. 4.2, Tab. fd_cases): thick-restart block Lanczos with
+ * polynomial filtering (Li, Xi, Vecharynski, Yang, Saad, SIAM J. Sci.
+ * Comput. 2016) for the eigenpairs of H inside [lam_l, lam_r].
+ *   filter  p(x) = sum_k g_k (2 - delta_k0) T_k(x_c) T_k(x) / norm, the
+ *           Jackson-damped delta peak at the window centre x_c (scaled units
+ *           x = (E - b)/a), p(x_c) = 1; tau = min(p(x_l), p(x_r)).
+ *           pv_trlanczos_filter returns coef[K+1] and tau (host only).
+ *   solver  block Lanczos on p(H~) with blocks of nbl columns (each step =
+ *           one Chebyshev series of degree `degree` on nbl columns; nbl >= 2
+ *           resolves the Kramers pairs of the TI), full reorthogonalisation
+ *           (FP64 Gram, twice), Cholesky QR (twice) of every new block, a
+ *           basis of m vectors; after m vectors the Ritz vectors of p(H~)
+ *           with values above tau, rounded up to whole blocks, are kept
+ *           (thick restart).  Converged when every kept pair above tau has
+ *           ||H u - theta u|| <= tol and their number did not change since
+ *           the previous restart; the pairs returned are those with theta
+ *           inside the window.
+ * v0: device start block [n_rows][nbl] (not modified).  Outputs (host):
+ * theta and res [m] (the first *n_found entries, theta ascending),
+ * *restarts; the first min(*n_found, n_out) Ritz vectors into X
+ * [n_rows][n_out] (n_out a power of two <= PV_MAX_NB, or 0 with X NULL).
+ * PV_ERR_NOT_CONVERGED after max_restarts with the current pairs returned.
+ * nbl a power of two <= 32, m a multiple of nbl, 2 nbl <= m, m + nbl <= 1024.
+ */
+pv_status pv_trlanczos_filter(double lam_l, double lam_r, double a, double b, int K, double *coef,
+                              double *tau);
+size_t pv_trlanczos_workspace_size(const pv_lattice *lat, int dtype, int nbl, int m);
+pv_status pv_trlanczos_fd(pv_lattice *lat, int dtype, double a, double b, double lam_l, double lam_r,
+                          int degree, int nbl, int m, double tol, int max_restarts, const void *v0,
+                          int n_out, void *X, double *theta, double *res, int *n_found, int *restarts,
+                          void *work, size_t work_bytes, void *stream);
+
+/*
  * Gradients with respect to the on-site field V (discrete adjoints of the
  * recurrences above; a and b are fixed numbers, not differentiated).
  *

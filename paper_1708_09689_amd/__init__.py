@@ -93,6 +93,10 @@ SIGNATURES = {
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
     "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
     "pv_dsl_stencil": (_i, [ctypes.c_char_p, _dp, _i, _ip, _ip, _ip, _ip, _dp, _dp, _ip, _ip]),
+    "pv_trlanczos_filter": (_i, [_d, _d, _d, _d, _i, _dp, _dp]),
+    "pv_trlanczos_workspace_size": (_sz, [_vp, _i, _i, _i]),
+    "pv_trlanczos_fd": (_i, [_vp, _i, _d, _d, _d, _d, _i, _i, _i, _d, _i, _vp, _i, _vp, _dp, _dp, _ip, _ip, _vp,
+                             _sz, _vp]),
     "pv_lattice_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_lattice_get_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_autotune_workspace_size": (_sz, [_vp, _i, _i]),
@@ -190,6 +194,36 @@ def pv_model_stencil(model: int, params=None) -> dict:
     e = onsite[: no * no * 2].reshape(no, no, 2)
     return {"dim": dim.value, "n_orb": no, "offsets": offs[: 3 * nt].reshape(nt, 3).copy(),
             "blocks": b[..., 0] + 1j * b[..., 1], "onsite": e[..., 0] + 1j * e[..., 1], "pot_mode": pot.value}
+
+
+def pv_trlanczos_filter(lam_l, lam_r, a, b, K):
+    coef = np.zeros(K + 1)
+    tau = ctypes.c_double()
+    _check(lib().pv_trlanczos_filter(lam_l, lam_r, a, b, K, _dptr(coef), ctypes.byref(tau)))
+    return coef, tau.value
+
+
+def pv_trlanczos_fd(lat, V0, a, b, lam_l, lam_r, degree, m, tol, max_restarts=60, n_out=0, raise_unconverged=True):
+    """Eigenpairs in [lam_l, lam_r] by filtered thick-restart block Lanczos;
+    V0: device start block [n_rows, nbl].  Returns (theta, res, X or None, restarts)."""
+    torch = _torch()
+    dt = _dtype_code(V0)
+    nbl = V0.numel() // lat.n_rows
+    ws = _workspace(lib().pv_trlanczos_workspace_size(lat.handle, dt, nbl, m), V0.device)
+    th, rs = np.zeros(m), np.zeros(m)
+    nf, nr = ctypes.c_int(), ctypes.c_int()
+    X = None
+    if n_out:
+        X = torch.empty((lat.n_rows, n_out), dtype=V0.dtype, device=V0.device)
+    st = lib().pv_trlanczos_fd(lat.handle, dt, a, b, lam_l, lam_r, degree, nbl, m, tol, max_restarts,
+                               _vec(V0, "V0", lat.n_rows, nbl), n_out,
+                               None if X is None else ctypes.c_void_p(X.data_ptr()), _dptr(th), _dptr(rs),
+                               ctypes.byref(nf), ctypes.byref(nr), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                               _stream())
+    if st != 0 and (raise_unconverged or st != 9):
+        _check(st)
+    n = nf.value
+    return th[:n].copy(), rs[:n].copy(), X, nr.value
 
 
 def pv_dsl_stencil(text: str, coeff_const=None) -> dict:

@@ -1448,6 +1448,334 @@ extern "C" pv_status pv_chebfd(pv_lattice* l, int dtype, int bw, int nblk, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Thick-restart Lanczos with polynomial filtering (trLanczosFD, Sec. 4.2; the
+// method of Li, Xi, Vecharynski, Yang and Saad, SIAM J. Sci. Comput. 2016)
+// ---------------------------------------------------------------------------
+extern "C" pv_status pv_trlanczos_filter(double lam_l, double lam_r, double a, double b, int K, double* coef,
+                                         double* tau) {
+    if (K < 1 || !coef || !tau || !(a > 0.0)) return fail(PV_ERR_INVALID_ARG, "bad filter arguments");
+    const double xl = (lam_l - b) / a, xr = (lam_r - b) / a;
+    if (!(xl > -1.0 && xl < xr && xr < 1.0)) return fail(PV_ERR_INVALID_ARG, "window must lie inside the scaled spectrum");
+    const double xc = 0.5 * (xl + xr), tc = std::acos(xc);
+    // Jackson-damped Chebyshev expansion of a delta peak at xc (N = K + 1 terms)
+    const int N = K + 1;
+    const double q = M_PI / (N + 1);
+    for (int k = 0; k <= K; ++k) {
+        const double g = ((N - k + 1) * std::cos(q * k) + std::sin(q * k) / std::tan(q)) / (N + 1);
+        coef[k] = g * (k == 0 ? 1.0 : 2.0) * std::cos(k * tc);
+    }
+    auto eval = [&](double x) {
+        double t0 = 1.0, t1 = x, acc = coef[0] + coef[1] * x;
+        for (int k = 2; k <= K; ++k) {
+            const double t2 = 2.0 * x * t1 - t0;
+            acc += coef[k] * t2;
+            t0 = t1;
+            t1 = t2;
+        }
+        return acc;
+    };
+    const double pc = eval(xc);
+    if (!(pc > 0.0)) return fail(PV_ERR_INVALID_ARG, "degenerate filter");
+    for (int k = 0; k <= K; ++k) coef[k] /= pc;
+    *tau = std::min(eval(xl), eval(xr));
+    return PV_OK;
+}
+
+namespace {
+
+constexpr int kTrBw = 32;   // columns per basis block
+
+struct TrLayout {
+    int nblk;
+    size_t vbl, vbw;
+    size_t V, U, HU, S0, Wv, T1, S1, S2, gp, sp, h, D, total;
+};
+
+TrLayout tr_layout(const pv_lattice* l, int dtype, int nbl, int m) {
+    TrLayout L{};
+    L.nblk = (m + nbl + kTrBw - 1) / kTrBw;
+    L.vbl = vec_bytes(l, dtype, nbl);
+    L.vbw = vec_bytes(l, dtype, kTrBw);
+    size_t off = 0;
+    L.V = off; off += L.vbw * L.nblk;
+    L.U = off; off += L.vbw * L.nblk;
+    L.HU = off; off += L.vbw;
+    L.S0 = off; off += L.vbl;
+    L.Wv = off; off += L.vbl;
+    L.T1 = off; off += L.vbl;
+    L.S1 = off; off += L.vbl;
+    L.S2 = off; off += L.vbl;
+    L.gp = off; off += pv_gram_workspace_size(l->n_rows, kTrBw, kTrBw);
+    L.sp = off; off += pv_spmmv_workspace_size(l, dtype, kTrBw);
+    L.h = off; off += align_up((size_t)kTrBw * kTrBw * 2 * sizeof(double));
+    L.D = off; off += align_up((size_t)kTrBw * 4 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+bool tr_shape_ok(int nbl, int m) {
+    return is_pow2(nbl) && nbl <= kTrBw && m % nbl == 0 && m >= 2 * nbl && m + nbl <= 1024;
+}
+
+}  // namespace
+
+extern "C" size_t pv_trlanczos_workspace_size(const pv_lattice* l, int dtype, int nbl, int m) {
+    if (!l || !tr_shape_ok(nbl, m) || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    return tr_layout(l, dtype, nbl, m).total;
+}
+
+extern "C" pv_status pv_trlanczos_fd(pv_lattice* l, int dtype, double a, double b, double lam_l, double lam_r,
+                                     int degree, int nbl, int m, double tol, int max_restarts, const void* v0,
+                                     int n_out, void* X, double* theta, double* res, int* n_found, int* restarts,
+                                     void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if (!tr_shape_ok(nbl, m))
+        return fail(PV_ERR_INVALID_ARG, "need nbl a power of two <= %d, m a multiple of nbl, 2 nbl <= m, m + nbl <= 1024",
+                    kTrBw);
+    if ((st = check_series_args(l, dtype, nbl, a, b)) != PV_OK) return st;
+    if ((st = check_vec(v0, dtype, "v0")) != PV_OK) return st;
+    if (degree < 1 || !(tol > 0.0) || max_restarts < 1)
+        return fail(PV_ERR_INVALID_ARG, "need degree >= 1, tol > 0, max_restarts >= 1");
+    if (n_out < 0 || (n_out > 0 && (!is_pow2(n_out) || n_out > PV_MAX_NB)))
+        return fail(PV_ERR_INVALID_ARG, "n_out must be 0 or a power of two <= %d", PV_MAX_NB);
+    if (n_out > 0 && (st = check_vec(X, dtype, "X")) != PV_OK) return st;
+    if (!theta || !res || !n_found || !restarts) return fail(PV_ERR_INVALID_ARG, "NULL output");
+    std::vector<double> fc(degree + 1);
+    double tau = 0.0;
+    if ((st = pv_trlanczos_filter(lam_l, lam_r, a, b, degree, fc.data(), &tau)) != PV_OK) return st;
+    const TrLayout Lw = tr_layout(l, dtype, nbl, m);
+    if (!work || work_bytes < Lw.total) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, Lw.total);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(work);
+    const int64_t rows = l->n_rows;
+    auto vblk = [&](size_t base, int i) { return static_cast<void*>(w + base + Lw.vbw * i); };
+    void* S0 = w + Lw.S0;
+    void* Wv = w + Lw.Wv;
+    void* T1 = w + Lw.T1;
+    double* hd = reinterpret_cast<double*>(w + Lw.h);
+    double* Dd = reinterpret_cast<double*>(w + Lw.D);
+    const size_t gp_bytes = Lw.sp - Lw.gp;
+    std::vector<double> coef(2 * (degree + 1), 0.0);
+    for (int k = 0; k <= degree; ++k) coef[2 * k] = fc[k];
+
+    // host copy of a device complex matrix [r][c]
+    auto fetch = [&](int r, int c, std::vector<pvd::cd>& out) -> pv_status {
+        std::vector<double> v((size_t)r * c * 2);
+        PV_HIP(hipMemcpyAsync(v.data(), hd, v.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        PV_HIP(hipStreamSynchronize(s));
+        out.resize((size_t)r * c);
+        for (size_t i = 0; i < out.size(); ++i) out[i] = pvd::cd(v[2 * i], v[2 * i + 1]);
+        return PV_OK;
+    };
+    auto upload = [&](const std::vector<pvd::cd>& M) -> pv_status {
+        std::vector<double> v(M.size() * 2);
+        for (size_t i = 0; i < M.size(); ++i) {
+            v[2 * i] = M[i].real();
+            v[2 * i + 1] = M[i].imag();
+        }
+        PV_HIP(hipMemcpyAsync(hd, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        PV_HIP(hipStreamSynchronize(s));   // v goes out of scope
+        return PV_OK;
+    };
+    // dst = src R^{-1} with src = Q R (Cholesky QR of nbl columns); R returned
+    auto cholqr = [&](const void* src, void* dst, std::vector<pvd::cd>& R) -> pv_status {
+        pv_status e = pv_gram(dtype, rows, nbl, nbl, src, src, hd, w + Lw.gp, gp_bytes, stream);
+        if (e != PV_OK) return e;
+        if ((e = fetch(nbl, nbl, R)) != PV_OK) return e;
+        if (!pvd::cholesky_upper(nbl, R)) return fail(PV_ERR_NOT_CONVERGED, "Lanczos block lost rank");
+        std::vector<pvd::cd> Ri;
+        pvd::invert_upper(nbl, R, Ri);
+        if ((e = upload(Ri)) != PV_OK) return e;
+        return pv_block_rotate(dtype, rows, nbl, nbl, src, hd, 0, dst, stream);
+    };
+    auto matmul = [&](const std::vector<pvd::cd>& A, const std::vector<pvd::cd>& B2, int n) {
+        std::vector<pvd::cd> C((size_t)n * n, pvd::cd(0, 0));
+        for (int i = 0; i < n; ++i)
+            for (int kk = 0; kk < n; ++kk)
+                for (int j = 0; j < n; ++j) C[(size_t)i * n + j] += A[(size_t)i * n + kk] * B2[(size_t)kk * n + j];
+        return C;
+    };
+    // orthonormal basis of src into S0 (two Cholesky QR passes); B = R2 R1
+    auto orthonormalise = [&](const void* src, std::vector<pvd::cd>& B) -> pv_status {
+        std::vector<pvd::cd> R1, R2;
+        pv_status e = cholqr(src, T1, R1);
+        if (e != PV_OK) return e;
+        if ((e = cholqr(T1, S0, R2)) != PV_OK) return e;
+        B = matmul(R2, R1, nbl);
+        return PV_OK;
+    };
+    auto put_cols = [&](const void* src, int j0) -> pv_status {
+        PV_HIP(pv::launch_column_copy(dtype, rows, nbl, src, nbl, 0, vblk(Lw.V, j0 / kTrBw), kTrBw, j0 % kTrBw,
+                                      1.0, 0.0, s));
+        return PV_OK;
+    };
+
+    PV_HIP(pv::launch_zero(w + Lw.V, Lw.vbw * Lw.nblk, s));
+    std::vector<pvd::cd> B;
+    if ((st = orthonormalise(v0, B)) != PV_OK) return st;
+    if ((st = put_cols(S0, 0)) != PV_OK) return st;
+
+    int k = 0, last = -1, it = 0;
+    std::vector<double> kept, mu, th, rr;
+    std::vector<pvd::cd> S, Y;      // restart couplings [nbl][k]; Ritz vectors of the projected matrix
+    std::vector<int> keep;
+    int nk = 0;
+    bool converged = false;
+    for (it = 1; it <= max_restarts; ++it) {
+        std::vector<pvd::cd> T((size_t)m * m, pvd::cd(0, 0));
+        for (int i = 0; i < k; ++i) T[(size_t)i * m + i] = kept[i];
+        for (int r = 0; r < nbl; ++r)
+            for (int i = 0; i < k; ++i) {
+                T[(size_t)(k + r) * m + i] = S[(size_t)r * k + i];
+                T[(size_t)i * m + k + r] = std::conj(S[(size_t)r * k + i]);
+            }
+        for (int j0 = k; j0 < m; j0 += nbl) {
+            const int j1 = j0 + nbl;
+            // Wv = p(H~) V_j   (V_j is in S0)
+            if ((st = run_series(l, dtype, nbl, a, b, degree, coef.data(), S0, Wv, Wv, w + Lw.S1, w + Lw.S2, s)) !=
+                PV_OK)
+                return st;
+            // full reorthogonalisation against the basis columns < j1, twice;
+            // the first pass yields the diagonal block A_j
+            std::vector<pvd::cd> Aj((size_t)nbl * nbl);
+            for (int pass = 0; pass < 2; ++pass)
+                for (int bb = 0; bb * kTrBw < j1; ++bb) {
+                    if ((st = pv_gram(dtype, rows, kTrBw, nbl, vblk(Lw.V, bb), Wv, hd, w + Lw.gp, gp_bytes,
+                                      stream)) != PV_OK)
+                        return st;
+                    std::vector<pvd::cd> h;
+                    if ((st = fetch(kTrBw, nbl, h)) != PV_OK) return st;
+                    for (int r = 0; r < kTrBw; ++r) {
+                        const int col = bb * kTrBw + r;
+                        for (int c = 0; c < nbl; ++c) {
+                            pvd::cd& v = h[(size_t)r * nbl + c];
+                            if (col >= j1) v = 0.0;
+                            else if (pass == 0 && col >= j0) Aj[(size_t)(col - j0) * nbl + c] = v;
+                            v = -v;
+                        }
+                    }
+                    if ((st = upload(h)) != PV_OK) return st;
+                    if ((st = pv_block_rotate(dtype, rows, kTrBw, nbl, vblk(Lw.V, bb), hd, 1, Wv, stream)) != PV_OK)
+                        return st;
+                }
+            for (int r = 0; r < nbl; ++r)
+                for (int c = 0; c < nbl; ++c)
+                    T[(size_t)(j0 + r) * m + j0 + c] = 0.5 * (Aj[(size_t)r * nbl + c] + std::conj(Aj[(size_t)c * nbl + r]));
+            if ((st = orthonormalise(Wv, B)) != PV_OK) return st;
+            if (j1 < m)
+                for (int r = 0; r < nbl; ++r)
+                    for (int c = 0; c < nbl; ++c) {
+                        T[(size_t)(j1 + r) * m + j0 + c] = B[(size_t)r * nbl + c];
+                        T[(size_t)(j0 + c) * m + j1 + r] = std::conj(B[(size_t)r * nbl + c]);
+                    }
+            if ((st = put_cols(S0, j1)) != PV_OK) return st;
+        }
+        // Ritz pairs of p(H~); keep those above the threshold, rounded up to
+        // whole blocks with the next largest ones
+        pvd::heev_jacobi(m, T, mu, Y);
+        int nw = 0;
+        for (int i = 0; i < m; ++i)
+            if (mu[i] > tau) ++nw;
+        nk = std::min((nw + nbl - 1) / nbl * nbl, m - nbl);
+        keep.resize(nk);
+        for (int i = 0; i < nk; ++i) keep[i] = m - nk + i;
+        // U = V Y_keep
+        const int ukb = (nk + kTrBw - 1) / kTrBw;
+        for (int cb = 0; cb < ukb; ++cb)
+            for (int bb = 0; bb * kTrBw < m; ++bb) {
+                std::vector<pvd::cd> q((size_t)kTrBw * kTrBw, pvd::cd(0, 0));
+                for (int r = 0; r < kTrBw; ++r)
+                    for (int c = 0; c < kTrBw; ++c) {
+                        const int row = bb * kTrBw + r, col = cb * kTrBw + c;
+                        if (row < m && col < nk) q[(size_t)r * kTrBw + c] = Y[(size_t)row * m + keep[col]];
+                    }
+                if ((st = upload(q)) != PV_OK) return st;
+                if ((st = pv_block_rotate(dtype, rows, kTrBw, kTrBw, vblk(Lw.V, bb), hd, bb > 0, vblk(Lw.U, cb),
+                                          stream)) != PV_OK)
+                    return st;
+            }
+        // Rayleigh quotients and residuals with respect to H
+        th.assign(nk, 0.0);
+        rr.assign(nk, 0.0);
+        {
+            const std::vector<double> one(kTrBw, 1.0), zero(kTrBw, 0.0);
+            const size_t spb = pv_spmmv_workspace_size(l, dtype, kTrBw);
+            for (int cb = 0; cb < ukb; ++cb) {
+                if ((st = pv_spmmv(l, dtype, kTrBw, vblk(Lw.U, cb), nullptr, w + Lw.HU, one.data(), zero.data(),
+                                   zero.data(), 0, nullptr, w + Lw.sp, spb, stream)) != PV_OK)
+                    return st;
+                if ((st = pv_gram(dtype, rows, kTrBw, kTrBw, vblk(Lw.U, cb), w + Lw.HU, hd, w + Lw.gp, gp_bytes,
+                                  stream)) != PV_OK)
+                    return st;
+                std::vector<pvd::cd> g;
+                if ((st = fetch(kTrBw, kTrBw, g)) != PV_OK) return st;
+                std::vector<double> sh(kTrBw, 0.0);
+                for (int c = 0; c < kTrBw && cb * kTrBw + c < nk; ++c)
+                    sh[c] = th[cb * kTrBw + c] = g[(size_t)c * kTrBw + c].real();
+                if ((st = pv_spmmv(l, dtype, kTrBw, vblk(Lw.U, cb), nullptr, w + Lw.HU, one.data(), sh.data(),
+                                   zero.data(), PV_DOT_YY, Dd, w + Lw.sp, spb, stream)) != PV_OK)
+                    return st;
+                std::vector<double> d((size_t)kTrBw * 4);
+                PV_HIP(hipMemcpyAsync(d.data(), Dd, d.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+                PV_HIP(hipStreamSynchronize(s));
+                for (int c = 0; c < kTrBw && cb * kTrBw + c < nk; ++c)
+                    rr[cb * kTrBw + c] = std::sqrt(std::max(d[c * 4 + 3], 0.0));
+            }
+        }
+        bool all = nw > 0;
+        for (int i = 0; i < nk; ++i)
+            if (mu[keep[i]] > tau && !(rr[i] <= tol)) all = false;
+        if (all && nw == last) {
+            converged = true;
+            break;
+        }
+        last = nw;
+        if (it == max_restarts) break;
+        // thick restart: V[:, :nk] = U, the next block (in S0) after it, and
+        // the couplings B_last Y[last block rows, keep]
+        for (int cb = 0; cb < ukb; ++cb)
+            PV_HIP(hipMemcpyAsync(vblk(Lw.V, cb), vblk(Lw.U, cb), Lw.vbw, hipMemcpyDeviceToDevice, s));
+        if ((st = put_cols(S0, nk)) != PV_OK) return st;
+        kept.assign(nk, 0.0);
+        S.assign((size_t)nbl * nk, pvd::cd(0, 0));
+        for (int i = 0; i < nk; ++i) {
+            kept[i] = mu[keep[i]];
+            for (int r = 0; r < nbl; ++r)
+                for (int c = 0; c < nbl; ++c)
+                    S[(size_t)r * nk + i] += B[(size_t)r * nbl + c] * Y[(size_t)(m - nbl + c) * m + keep[i]];
+        }
+        k = nk;
+    }
+    if (it > max_restarts) it = max_restarts;
+    // the pairs above the threshold with theta inside the window (eigenvalues
+    // just outside can pass the threshold), ascending; Ritz vectors into X
+    std::vector<int> order;
+    for (int i = 0; i < nk; ++i)
+        if (mu[keep[i]] > tau && th[i] >= lam_l && th[i] <= lam_r) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return th[i] < th[j]; });
+    const int nf = int(order.size());
+    for (int i = 0; i < nf; ++i) {
+        theta[i] = th[order[i]];
+        res[i] = rr[order[i]];
+    }
+    if (n_out > 0) {
+        PV_HIP(pv::launch_zero(X, vec_bytes(l, dtype, n_out), s));
+        for (int i = 0; i < nf && i < n_out; ++i) {
+            const int src = order[i];
+            PV_HIP(pv::launch_column_copy(dtype, rows, 1, vblk(Lw.U, src / kTrBw), kTrBw, src % kTrBw, X, n_out, i,
+                                          1.0, 0.0, s));
+        }
+    }
+    PV_HIP(hipStreamSynchronize(s));
+    *n_found = nf;
+    *restarts = it;
+    if (!converged)
+        return fail(PV_ERR_NOT_CONVERGED, "%d Ritz pairs in the window, not all converged after %d restarts", nf, it);
+    return PV_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Batched KPM over independent lattices, captured into a HIP graph
 // ---------------------------------------------------------------------------
 struct pv_batch {

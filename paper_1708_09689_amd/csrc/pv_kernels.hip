@@ -1447,6 +1447,18 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const u32x4* __restrict__ 
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void column_copy_kernel(const cplx<T>* __restrict__ src, int src_ld,
+                                                           int src_col, cplx<T>* __restrict__ dst, int dst_ld,
+                                                           int dst_col, int ncols, int64_t n, double re, double im) {
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t r = e / ncols;
+        const int c = int(e - r * ncols);
+        const cplx<T> v = src[r * src_ld + src_col + c];
+        dst[r * dst_ld + dst_col + c] = cplx<T>{T(re * v.re - im * v.im), T(re * v.im + im * v.re)};
+    }
+}
+
 // Bloch start columns (one element per lane).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bloch_kernel(cplx<T>* __restrict__ out, int64_t n, int n_orb, int nb,
@@ -1470,6 +1482,21 @@ __global__ __launch_bounds__(kBlock) void bloch_kernel(cplx<T>* __restrict__ out
 }  // namespace
 
 static int elementwise_grid(int64_t n);
+
+hipError_t launch_column_copy(int dtype, int64_t rows, int ncols, const void* src, int src_ld, int src_col,
+                              void* dst, int dst_ld, int dst_col, double re, double im, hipStream_t s) {
+    const int64_t n = rows * ncols;
+    const int g = elementwise_grid(n);
+    if (dtype == 0)
+        hipLaunchKernelGGL(column_copy_kernel<double>, dim3(g), dim3(kBlock), 0, s,
+                           static_cast<const cplx<double>*>(src), src_ld, src_col, static_cast<cplx<double>*>(dst),
+                           dst_ld, dst_col, ncols, n, re, im);
+    else
+        hipLaunchKernelGGL(column_copy_kernel<float>, dim3(g), dim3(kBlock), 0, s,
+                           static_cast<const cplx<float>*>(src), src_ld, src_col, static_cast<cplx<float>*>(dst),
+                           dst_ld, dst_col, ncols, n, re, im);
+    return hipGetLastError();
+}
 
 hipError_t launch_bloch(int dtype, int64_t n_sites, int n_orb, int nb, int Lx, int Ly, const BlochCols& cols,
                         int axis, int64_t index, void* out, hipStream_t s) {

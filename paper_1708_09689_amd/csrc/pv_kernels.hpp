@@ -100,6 +100,12 @@ hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X,
                          int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
+// dst[r][dst_col + c] = (re + i im) * src[r][src_col + c] for r < rows,
+// c < ncols, blocks of widths src_ld and dst_ld (columns moved between
+// blocks, scaled).
+hipError_t launch_column_copy(int dtype, int64_t rows, int ncols, const void* src, int src_ld, int src_col,
+                              void* dst, int dst_ld, int dst_col, double re, double im, hipStream_t s);
+
 // Bloch start columns: out[s][o][c] = exp(i k_c . r_s) for o == orb[c] on
 // the sites of the layer (axis < 0: all sites), else 0.
 struct BlochCols {

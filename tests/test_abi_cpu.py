@@ -227,3 +227,11 @@ def test_spectral_function_matches_oracle(lib):
     E = np.linspace(-6.5, 6.5, 77)
     A = pv.pv_kpm_spectral_function(mu, E, 7.0, 0.1, 2.0)
     assert np.abs(A - spectral.spectral_function(mu, E, 7.0, 0.1, 2.0)).max() < 1e-13
+
+
+def test_trlanczos_filter_matches_oracle(lib):
+    from oracle import trlanczos
+    for (l, r, a, b, K) in [(0.9, 1.3, 7.0, 0.1, 150), (-0.2, 0.2, 6.0, 0.0, 40), (2.0, 2.5, 3.1, 0.05, 300)]:
+        c, tau = pv.pv_trlanczos_filter(l, r, a, b, K)
+        rc, rtau = trlanczos.delta_filter(l, r, a, b, K)
+        assert np.abs(c - rc).max() < 1e-13 and abs(tau - rtau) < 1e-13
