@@ -318,6 +318,42 @@ def bench_weyl_spectral(pv, torch, W, dev, nk=64, M=256):
             "A_E0_along_kx_first8": [round(v, 4) for v in A0[:8]]}
 
 
+def bench_fd(pv, torch, W, dev, half=0.05):
+    """Interior eigenpairs near E = 0 of a TI slab like the paper's filter
+    diagonalisation test cases: 240 x 240 x 6 sites, periodic x, y, open z
+    (surface states in the bulk gap), W = 1, a = 6: trLanczosFD (block size 4)
+    and ChebFD (64 search vectors) on the same window, complex128."""
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lat = pv.Lattice((240, 240, 6), (1, 1, 0), st)
+    lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(6, W.STREAM_POTENTIAL))).to(dev))
+    a = 6.0
+    V0 = torch.from_numpy(W.gaussian_block(lat.n_rows, 4, W.generator(6, W.STREAM_VECTORS))).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, res, _, it = pv.pv_trlanczos_fd(lat, V0, a, 0.0, -half, half, 400, 160, 1e-9 * a, max_restarts=40,
+                                        raise_unconverged=False)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t0
+    out = {"workload": f"TI 240x240x6 (periodic x,y, open z), W=1, window |E| < {half}, complex128",
+           "trlanczos": {"pairs": int(th.size), "restarts": it, "seconds": round(t_tr, 2),
+                         "max_residual": float(res.max()) if th.size else None,
+                         "theta_range": [float(th.min()), float(th.max())] if th.size else None}}
+    print(f"# trlanczos: {json.dumps(out['trlanczos'])}", file=sys.stderr, flush=True)
+    if th.size:
+        ns = max(64, -(-(3 * int(th.size) // 2) // 32) * 32)          # search space ~1.5x the pairs
+        X = torch.from_numpy(W.gaussian_block(lat.n_rows, ns, W.generator(6, W.STREAM_VECTORS, 1))).to(dev)
+        t0 = time.perf_counter()
+        thf, resf, nconv, itf = pv.pv_chebfd(lat, X, 32, a, 0.0, -half, half, 600, int(th.size), 1e-9 * a,
+                                             max_iter=40, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_fd = time.perf_counter() - t0
+        thf = np.sort(thf[: th.size])
+        out["chebfd"] = {"search_vectors": ns, "converged": int(nconv), "iterations": itf, "seconds": round(t_fd, 2),
+                         "max_abs_theta_diff_vs_trlanczos": float(np.abs(thf - th).max())}
+        out["chebfd_over_trlanczos_time"] = round(t_fd / t_tr, 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +365,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the per-workload measurements")
+    ap.add_argument("--fd", action="store_true", help="also run the interior-eigenvalue comparison (slow)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -412,6 +449,10 @@ def main():
             torch.cuda.empty_cache()
             print(f"# {name} done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         set_field(args.dtype)
+    if args.fd:
+        t0 = time.perf_counter()
+        configs["interior_eigenpairs"] = bench_fd(pv, torch, W, dev)
+        print(f"# interior_eigenpairs done in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(args.nb)
 
