@@ -17,6 +17,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -32,11 +33,11 @@ WORKLOAD_INDEX = 2            # seeds of the 256x256x64 TI workload
 A_SCALE, B_SHIFT = 7.0, 0.0
 
 
-# HBM-side bytes per Chebyshev-step launch of the staged sweep kernel as built
-# now, from FETCH_SIZE / WRITE_SIZE counters scaled by the copy-kernel factors
-# (profiles/staged_kernel_ti256x256x64_*_counters.txt); (dtype, nb) pairs
-# without a counter run report null.
-COUNTED_TRAFFIC = {("c128", 32): 30_707_000_000, ("c64", 16): 9_312_000_000}
+# HBM-side bytes per Chebyshev-step launch of the sweep kernel as built now,
+# from FETCH_SIZE / WRITE_SIZE counters scaled by the copy-kernel factors
+# (profiles/*_counters.txt), with the launch shape the counters were taken
+# with; other shapes and (dtype, nb) pairs without a counter run report null.
+COUNTED_TRAFFIC = {}
 
 
 def bytes_per_step(n_rows: int, n_sites: int, nb: int, dtype: str) -> int:
@@ -47,11 +48,18 @@ def bytes_per_step(n_rows: int, n_sites: int, nb: int, dtype: str) -> int:
     return 3 * n_rows * nb * e + n_sites * v
 
 
+TUNE_CACHE = os.path.join(tempfile.gettempdir(), "pvdtm_bench_tune.jsonl")
+
+
 class Sweep:
-    """State of one (dtype, nb) Chebyshev recurrence on the benchmark lattice."""
+    """State of one (dtype, nb) Chebyshev recurrence on the benchmark lattice.
+    The launch shape comes from the library's autotuner (cached per device in
+    a temporary file), as a user of the library would run it."""
 
     def __init__(self, pv, torch, lat, nb, dtype, dev):
         self.pv, self.torch, self.lat, self.nb, self.dtype = pv, torch, lat, nb, dtype
+        code = pv.PV_C128 if dtype == "c128" else pv.PV_C64
+        self.shape, self.tune_ms = pv.pv_autotune(lat, nb, code, cache_path=TUNE_CACHE)
         import workloads as W
         self.w0 = W.random_phase_device(lat.n_rows, nb, 10 * WORKLOAD_INDEX + nb, dev,
                                         "complex128" if dtype == "c128" else "complex64")
@@ -394,7 +402,8 @@ def main():
     set_field(args.dtype)
     sw = Sweep(pv, torch, lat, args.nb, args.dtype, dev)
     ms = time_steps(torch, sw, args.warmup, args.steps)
-    print(f"# headline {args.dtype} nb={args.nb}: {ms:.4f} ms/step", file=sys.stderr, flush=True)
+    print(f"# headline {args.dtype} nb={args.nb}: {ms:.4f} ms/step, shape {sw.shape}", file=sys.stderr, flush=True)
+    shape = sw.shape
     nbytes = bytes_per_step(lat.n_rows, lat.n_sites, args.nb, args.dtype)
     glups = lat.n_rows * args.nb / (ms * 1e-3) / 1e9
     achieved = nbytes / (ms * 1e-3) / 1e9
@@ -409,7 +418,7 @@ def main():
                 s2 = Sweep(pv, torch, lat, nb, dtype, dev)
                 m2 = time_steps(torch, s2, 3, 10)
                 b2 = bytes_per_step(lat.n_rows, lat.n_sites, nb, dtype)
-                variants.append({"dtype": dtype, "nb": nb, "ms_per_step": round(m2, 5),
+                variants.append({"dtype": dtype, "nb": nb, "shape": s2.shape, "ms_per_step": round(m2, 5),
                                  "GLUP/s": round(lat.n_rows * nb / (m2 * 1e-3) / 1e9, 3),
                                  "site_GLUP/s": round(lat.n_sites * nb / (m2 * 1e-3) / 1e9, 3),
                                  "GB/s": round(b2 / (m2 * 1e-3) / 1e9, 1),
@@ -475,8 +484,11 @@ def main():
                    "a": A_SCALE, "b": B_SHIFT, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": COUNTED_TRAFFIC.get((args.dtype, args.nb)),
-                     "kernel": "staged_kernel<PatTI> (Chebyshev step, fused dots) + reduce_dots_kernel",
+                     "traffic": (COUNTED_TRAFFIC[(args.dtype, args.nb)][1]
+                                 if COUNTED_TRAFFIC.get((args.dtype, args.nb), (None,))[0] == shape else None),
+                     "kernel": ("staged_kernel<PatTI>" if shape["kernel"] == 2 else "sweep_kernel<PatTI>")
+                               + " (Chebyshev step, fused dots) + reduce_dots_kernel",
+                     "launch_shape": shape,
                      "bytes_per_launch": nbytes},
         "copy_probe_GBs": None if copy_gbs is None else round(copy_gbs, 1),
         "frac_of_copy_probe": None if copy_gbs is None else round(achieved / copy_gbs, 4),

@@ -976,8 +976,9 @@ void staged_kernel(KArgs<T, VT> a) {
 }
 
 // Tiles per workgroup: enough workgroups to keep every CU busy for several
-// rounds (>= 64 per CU), at most 16 tiles each (bounds the partial-dot
-// buffer).  PV_TILES_PER_BLOCK overrides it for tuning runs.
+// rounds (>= 32 per CU), at most 64 tiles each (fewer workgroups also means
+// fewer partial dot products to reduce).  PV_TILES_PER_BLOCK overrides it
+// for tuning runs.
 int tiles_per_block(int64_t ntiles) {
     static int forced = -2;
     if (forced == -2) {
@@ -985,9 +986,9 @@ int tiles_per_block(int64_t ntiles) {
         forced = e ? atoi(e) : -1;
     }
     if (forced > 0) return forced;
-    int64_t tpb = ntiles / (256 * 64);
+    int64_t tpb = ntiles / (256 * 32);
     if (tpb < 1) tpb = 1;
-    if (tpb > 16) tpb = 16;
+    if (tpb > 64) tpb = 64;
     return int(tpb);
 }
 
