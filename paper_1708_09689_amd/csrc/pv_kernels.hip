@@ -608,7 +608,7 @@ __device__ __forceinline__ u32x4 ld_chunk_nt(const void* base, uint32_t boff) {
 
 // One step's worth of rows in flight: ring row with halo, side rows, z and
 // acc_in chunks, field values.
-template <class P, typename T, int E>
+template <class P, typename T, typename VT, int E>
 struct StagedSet {
     using S = Staged<T, E>;
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
@@ -616,20 +616,21 @@ struct StagedSet {
     u32x4 side[NTR > 0 ? NTR : 1][S::TCH];
     u32x4 z[S::TCH];
     u32x4 acc[S::TCH];
-    T v[E];
+    VT v[E];          // stored field entries (converted when handed to LDS)
+    int64_t vrow;     // first field entry of the set's row
 };
 
 template <class P, typename T, typename VT, int E, bool ACC>
 struct StagedCtx {
     using S = Staged<T, E>;
-    using Set = StagedSet<P, T, E>;
+    using Set = StagedSet<P, T, VT, E>;
     static constexpr int NTR = Set::NTR;
     const KArgs<T, VT>& a;
     cplx<T>* ring;   // [3][seg]
     cplx<T>* tra;    // [NTR][TW]
     cplx<T>* zl;     // [TW]
     cplx<T>* al;     // [TW] (ACC only)
-    T* vl;           // [TW / nb]
+    T* vl;           // [E kBlock]
     int tid, nch, m, wb;
     // per walk: byte offsets inside a row of this lane's ring chunks (x
     // wrapped; open boundaries are applied when computing), row chunks and
@@ -643,19 +644,19 @@ struct StagedCtx {
         return P::DIM == 3 ? (int64_t)ww * a.Ly + mm : (int64_t)ww;
     }
     // Row (mm, ww) after wrapping periodic dimensions; -1 when an open
-    // boundary drops it.
+    // boundary drops it.  Integer selects (no boolean state across blocks),
+    // so the row arithmetic stays in scalar registers.
     __device__ __forceinline__ int64_t row_idx(int mm, int ww) const {
-        bool ok = true;
-        if (ww < 0 || ww >= a.st_Lw) {
-            ok = a.st_pw;
-            ww += ww < 0 ? a.st_Lw : -a.st_Lw;
-            if (ww >= a.st_Lw) ww %= a.st_Lw;   // w + 3 on a lattice of few planes
-        }
-        if (mm < 0 || mm >= a.st_Lm) {
-            ok = ok && a.st_pm;
-            mm += mm < 0 ? a.st_Lm : -a.st_Lm;
-        }
-        return ok ? row_of(mm, ww) : -1;
+        const int Lw = a.st_Lw, Lm = a.st_Lm;
+        const int wout = int(ww < 0) | int(ww >= Lw);
+        const int mout = int(mm < 0) | int(mm >= Lm);
+        const int dead = (wout & (a.st_pw ^ 1)) | (mout & (a.st_pm ^ 1));
+        ww += ww < 0 ? Lw : 0;
+        ww -= ww >= Lw ? Lw : 0;
+        if (ww >= Lw) ww %= Lw;   // w + 3 on a lattice of few planes
+        mm += mm < 0 ? Lm : 0;
+        mm -= mm >= Lm ? Lm : 0;
+        return dead ? int64_t(-1) : row_of(mm, ww);
     }
     __device__ __forceinline__ const cplx<T>* row_ptr(int mm, int ww) const {
         const int64_t r = row_idx(mm, ww);
@@ -663,9 +664,13 @@ struct StagedCtx {
     }
     __device__ __forceinline__ void setup(int xe0) {
         const int rowel = a.rowel;
+        // chunks past the ring row (tile + halo) repeat its last chunk: every
+        // lane loads and stores every chunk without branches, and the
+        // repeated addresses add no traffic
 #pragma unroll
         for (int k = 0; k < S::RCH; ++k) {
-            int g = xe0 - a.st_site + (tid + k * kBlock) * S::CE;
+            const int q = tid + k * kBlock;
+            int g = xe0 - a.st_site + (q < nch ? q : nch - 1) * S::CE;
             if (g < 0) g += rowel;
             if (g >= rowel) g %= rowel;
             roff[k] = uint32_t(g) * S::ES;
@@ -686,12 +691,13 @@ struct StagedCtx {
         }
     }
     // Issue the loads of ring row (m, w_ring) and of the per-step rows of
-    // outer index w_row (clamped to the walk) into the set.
+    // outer index w_row (clamped to the walk) into the set.  Every load is
+    // unconditional (branch-free code lets the compiler wait for exactly
+    // the loads a hand-over needs, keeping the next step's loads in flight).
     __device__ __forceinline__ void issue(Set& st, int w_ring, int w_row) const {
         const cplx<T>* rp = row_ptr(m, w_ring);
 #pragma unroll
-        for (int k = 0; k < S::RCH; ++k)
-            if (k * kBlock < nch) st.ring[k] = ld_chunk<T>(rp, roff[k]);
+        for (int k = 0; k < S::RCH; ++k) st.ring[k] = ld_chunk<T>(rp, roff[k]);
         const int wr = w_row < wb ? w_row : wb - 1;
         if constexpr (NTR > 0) {
 #pragma unroll
@@ -710,19 +716,18 @@ struct StagedCtx {
 #pragma unroll
             for (int k = 0; k < S::TCH; ++k) st.acc[k] = ld_chunk_nt<T>(ar, soff[k]);
         }
-        if (a.field != 0) {
-            const int64_t vb = rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
+        // stored field entries (a row of the zero row's bytes when the field
+        // is absent or generated; those values are not used)
+        st.vrow = rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
+        const VT* vp = a.field == 1 ? a.V + st.vrow : reinterpret_cast<const VT*>(a.zero_row);
 #pragma unroll
-            for (int k = 0; k < E; ++k)
-                if (k * kBlock < (S::TW >> vshift)) st.v[k] = field_at(a, vb + voff[k]);
-        }
+        for (int k = 0; k < E; ++k) st.v[k] = vp[voff[k]];
     }
     // Hand a set to LDS: ring row into slot, per-step rows into their buffers.
     __device__ __forceinline__ void commit(const Set& st, int slot) const {
         u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
 #pragma unroll
-        for (int k = 0; k < S::RCH; ++k)
-            if (k * kBlock < nch && tid + k * kBlock < nch) d[tid + k * kBlock] = st.ring[k];
+        for (int k = 0; k < S::RCH; ++k) d[tid + k * kBlock] = st.ring[k];
         if constexpr (NTR > 0) {
 #pragma unroll
             for (int h = 0; h < NTR; ++h) {
@@ -739,33 +744,37 @@ struct StagedCtx {
 #pragma unroll
             for (int k = 0; k < S::TCH; ++k) da[tid + k * kBlock] = st.acc[k];
         }
-        if (a.field != 0) {
-            const int nrow = S::TW >> vshift;
+        if (a.field == 2) {
 #pragma unroll
-            for (int k = 0; k < E; ++k)
-                if (tid + k * kBlock < nrow) vl[tid + k * kBlock] = st.v[k];
+            for (int k = 0; k < E; ++k) vl[tid + k * kBlock] = field_at(a, st.vrow + voff[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < E; ++k) vl[tid + k * kBlock] = T(st.v[k]);
         }
     }
     // Ring row (m, ww) alone into a slot (walk prologue).
     __device__ __forceinline__ void ring_now(u32x4 (&r)[S::RCH], int ww, int slot) const {
         const cplx<T>* rp = row_ptr(m, ww);
 #pragma unroll
-        for (int k = 0; k < S::RCH; ++k)
-            if (k * kBlock < nch) r[k] = ld_chunk<T>(rp, roff[k]);
+        for (int k = 0; k < S::RCH; ++k) r[k] = ld_chunk<T>(rp, roff[k]);
         u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
 #pragma unroll
-        for (int k = 0; k < S::RCH; ++k)
-            if (k * kBlock < nch && tid + k * kBlock < nch) d[tid + k * kBlock] = r[k];
+        for (int k = 0; k < S::RCH; ++k) d[tid + k * kBlock] = r[k];
     }
 };
 
-// LDS of a staged workgroup: three ring rows with halo, the side rows of 3D
-// lattices, z (and acc_in) of the tile, and the field of its orbital rows.
+// LDS of a staged workgroup: three ring rows with halo (slots padded to
+// whole chunks per lane), the side rows of 3D lattices, z (and acc_in) of
+// the tile, and the field of its orbital rows (padded to E per lane).
+template <typename T, int E>
+__host__ __device__ constexpr int staged_seg() {
+    return Staged<T, E>::RCH * kBlock * Staged<T, E>::CE;
+}
 template <class P, typename T, int E>
-__host__ __device__ constexpr size_t staged_lds_bytes_for(int nb, bool acc) {
-    return size_t(3 * (Staged<T, E>::TW + 2 * P::NO * nb) + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
+__host__ __device__ constexpr size_t staged_lds_bytes_for(bool acc) {
+    return size_t(3 * staged_seg<T, E>() + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
                Staged<T, E>::ES +
-           size_t(Staged<T, E>::TW / nb) * sizeof(T);
+           size_t(E * kBlock) * sizeof(T);
 }
 
 template <class P, typename T, typename VT, int E, unsigned EPM>
@@ -802,7 +811,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
     double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
 
-    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, a.st_seg / S::CE, 0, 0};
+    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, (S::TW + 2 * site) / S::CE, 0, 0};
     cx.vshift = a.pot_mode == 1 ? a.logsite : a.lognb;
     cx.tra = cx.ring + 3 * a.st_seg;
     cx.zl = cx.tra + NTR * S::TW;
@@ -849,14 +858,16 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
         cx.ring_now(B.ring, wa, 1);
         cx.issue(A, wa + 1, wa);
         cx.commit(A, 2);
-        if (nsteps > 1) cx.issue(B, wa + 2, wa + 1);
+        cx.issue(B, wa + 2, wa + 1);
         lds_barrier();
 
         // step s (outer index wa + s): issue `nx` for step s + 2, compute from
-        // LDS, hand `cur` (issued for step s + 1) over, store
+        // LDS, hand `cur` (issued for step s + 1) over, store.  Issue and
+        // hand-over run on every step; past the walk they fetch rows read two
+        // steps earlier (cache hits) and fill a ring slot nobody reads.
         auto step = [&](int s, Set& nx, const Set& cur) {
             const int w = wa + s;
-            if (s + 2 < nsteps) cx.issue(nx, w + 3, w + 2);
+            cx.issue(nx, s + 2 < nsteps ? w + 3 : w + 1, w + 2);
             const cplx<T>* rm = cx.ring + (s % 3) * a.st_seg + site;
             const cplx<T>* r0 = cx.ring + ((s + 1) % 3) * a.st_seg + site;
             const cplx<T>* rp = cx.ring + ((s + 2) % 3) * a.st_seg + site;
@@ -905,7 +916,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 av[k] = ACC ? cx.al[l] : cplx<T>{T(0), T(0)};
             }
             lds_barrier();
-            if (s + 1 < nsteps) cx.commit(cur, (s + 3) % 3);
+            cx.commit(cur, (s + 3) % 3);
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int xe = xe0 + tid + k * kBlock;
@@ -918,10 +929,12 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
             }
             lds_barrier();
         };
-        for (int s = 0; s < nsteps; s += 2) {
+        int s = 0;
+        for (; s + 1 < nsteps; s += 2) {
             step(s, A, B);
-            if (s + 1 < nsteps) step(s + 1, B, A);
+            step(s + 1, B, A);
         }
+        if (s < nsteps) step(s, A, B);
     }
 
     if (ep & EP_DOTS) {
@@ -1085,14 +1098,15 @@ int env_int(const char* name, int dflt) {
 
 template <class P, typename T, int E, unsigned EPM>
 size_t staged_lds_bytes(int nb) {
-    return staged_lds_bytes_for<P, T, E>(nb, EPM == 0u || (EPM & EP_ACC_ADD) != 0u);
+    (void)nb;
+    return staged_lds_bytes_for<P, T, E>(EPM == 0u || (EPM & EP_ACC_ADD) != 0u);
 }
 
 template <class P, typename T, typename VT, int E>
 int staged_setup(const SweepParams& p, int G8, bool full_walk, KArgs<T, VT>& a) {
     using S = Staged<T, E>;
     a.st_site = P::NO * p.nb;
-    a.st_seg = S::TW + 2 * a.st_site;
+    a.st_seg = staged_seg<T, E>();   // ring slot; its first TW + 2 site elements hold the row
     a.st_nxs = (a.rowel + S::TW - 1) / S::TW;
     if (P::DIM == 3) {
         a.st_Lm = a.Ly; a.st_Lw = a.Lz; a.st_pm = a.py; a.st_pw = a.pz;
