@@ -426,9 +426,6 @@ pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
  *   tiles_per_group  direct: row tiles per workgroup, up to 64 (values below
  *                    the default are raised to it)
  *   slab_rows        direct: y rows per slab of the sweep order
- *   tile_cols        staged: block columns per tile, a power of two (0 or
- *                    >= nb: all nb; raised to one 16-byte chunk; sweeps with
- *                    the field gradient keep all nb)
  * The shape changes speed only: every shape computes the same result up to
  * the summation order of the fused dot products.
  */
@@ -440,7 +437,6 @@ typedef struct pv_tuning {
     int groups_per_xcd;
     int tiles_per_group;
     int slab_rows;
-    int tile_cols;
 } pv_tuning;
 
 /* Set (t != NULL) or reset to defaults (t == NULL) the shape used for

@@ -297,7 +297,6 @@ pv_status fill_traversal(pv_lattice* l, int dtype, int nb, pv::SweepParams& p) {
     p.st_C = t.walk_planes;
     p.st_Bm = t.strip_rows;
     p.st_G8 = t.groups_per_xcd;
-    p.st_cw = t.tile_cols;
     p.zero_row = l->d_zero;
     return PV_OK;
 }
@@ -1009,8 +1008,6 @@ pv_status check_tuning(int dtype, const pv_tuning& t) {
         return fail(PV_ERR_INVALID_ARG, "tuning.groups_per_xcd = %d (0..256)", t.groups_per_xcd);
     if (t.tiles_per_group < 0 || t.tiles_per_group > 64)
         return fail(PV_ERR_INVALID_ARG, "tuning.tiles_per_group = %d (0..64)", t.tiles_per_group);
-    if (t.tile_cols < 0 || t.tile_cols > 64 || (t.tile_cols & (t.tile_cols - 1)) != 0)
-        return fail(PV_ERR_INVALID_ARG, "tuning.tile_cols = %d (0 or a power of two up to 64)", t.tile_cols);
     return PV_OK;
 }
 
@@ -1030,13 +1027,12 @@ std::string tune_key(const pv_lattice* l, int dtype, int nb) {
     return buf;
 }
 
-constexpr int kNumTuneFields = 8;
-const char* const kTuneFields[kNumTuneFields] = {"kernel",         "elems_per_lane",  "walk_planes", "strip_rows",
-                                                 "groups_per_xcd", "tiles_per_group", "slab_rows",   "tile_cols"};
+const char* const kTuneFields[7] = {"kernel",          "elems_per_lane",  "walk_planes", "strip_rows",
+                                    "groups_per_xcd", "tiles_per_group", "slab_rows"};
 
 int* tune_field(pv_tuning& t, int i) {
-    int* f[kNumTuneFields] = {&t.kernel,         &t.elems_per_lane,  &t.walk_planes, &t.strip_rows,
-                              &t.groups_per_xcd, &t.tiles_per_group, &t.slab_rows,   &t.tile_cols};
+    int* f[7] = {&t.kernel, &t.elems_per_lane, &t.walk_planes, &t.strip_rows,
+                 &t.groups_per_xcd, &t.tiles_per_group, &t.slab_rows};
     return f[i];
 }
 
@@ -1052,7 +1048,7 @@ bool cache_lookup(const char* path, const std::string& key, pv_tuning& t) {
         if (!std::strstr(line, want.c_str())) continue;
         pv_tuning r{};
         bool ok = true;
-        for (int i = 0; i < kNumTuneFields && ok; ++i) {
+        for (int i = 0; i < 7 && ok; ++i) {
             const std::string name = std::string("\"") + kTuneFields[i] + "\": ";
             const char* q = std::strstr(line, name.c_str());
             if (!q) { ok = false; break; }
@@ -1072,7 +1068,7 @@ void cache_append(const char* path, const std::string& key, const pv_tuning& t, 
     if (!f) return;
     std::fprintf(f, "{\"key\": \"%s\"", key.c_str());
     pv_tuning c = t;
-    for (int i = 0; i < kNumTuneFields; ++i) std::fprintf(f, ", \"%s\": %d", kTuneFields[i], *tune_field(c, i));
+    for (int i = 0; i < 7; ++i) std::fprintf(f, ", \"%s\": %d", kTuneFields[i], *tune_field(c, i));
     std::fprintf(f, ", \"ms\": %.6f}\n", ms);
     std::fclose(f);
 }
@@ -1185,30 +1181,22 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
             best = t;
         }
     };
-    // 1. kernel and elements per lane at default shapes, the staged kernel
-    // with all nb columns per tile and with 256-byte column runs (shorter
-    // runs cost more HBM efficiency than their smaller x halo saves)
+    // 1. kernel and elements per lane at default shapes
     pv_tuning t{};
     t.kernel = 1;
     consider(t);
     const bool compiled = l->family != pv::FAM_GENERIC;
-    const int run_cols = dtype == PV_C128 ? 16 : 32;
     if (compiled) {
         const int es[2] = {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4};
-        for (int e : es)
-            for (int cw : {0, run_cols}) {
-                if (cw >= nb) continue;
-                t = pv_tuning{};
-                t.kernel = 2;
-                t.elems_per_lane = e;
-                t.tile_cols = cw;
-                consider(t);
-            }
+        for (int e : es) {
+            t = pv_tuning{};
+            t.kernel = 2;
+            t.elems_per_lane = e;
+            consider(t);
+        }
     }
     if (best.kernel == 2) {
-        // 2. longer column runs, 3. strip height, 4. planes per walk,
-        // 5. workgroups per XCD
-        for (int v = 2 * run_cols; v < nb; v <<= 1) { t = best; t.tile_cols = v; consider(t); }
+        // 2. strip height, 3. planes per walk, 4. workgroups per XCD
         for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
         const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
         for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
@@ -1818,7 +1806,6 @@ pv::SweepParams batch_params(const pv_batch* B, int i, int dtype, int nb) {
     const pv_tuning& t = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
     p.kernel = t.kernel;
     p.st_E = t.elems_per_lane;
-    p.st_cw = t.tile_cols;
     return p;
 }
 
@@ -1960,7 +1947,7 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     const pv_tuning& t0 = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
     std::vector<uint64_t> key = {(uint64_t)dtype, (uint64_t)nb, (uint64_t)M, (uint64_t)(uintptr_t)work,
                                  (uint64_t)work_bytes, (uint64_t)L.staged, (uint64_t)t0.kernel,
-                                 (uint64_t)t0.elems_per_lane, (uint64_t)t0.tile_cols};
+                                 (uint64_t)t0.elems_per_lane};
     char* const mu_ws = static_cast<char*>(work) + L.moments;
     const size_t mu_bytes = (size_t)n * nb * M * sizeof(double);
     for (int i = 0; i < n; ++i) {

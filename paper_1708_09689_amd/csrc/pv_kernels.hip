@@ -119,9 +119,7 @@ struct KArgs {
     unsigned ep;
     // staged traversal (staged_kernel): column tiles of one row walked along
     // the outer dimension w; m is the middle dimension (y in 3D, none in 2D)
-    int st_site, st_seg, st_nxs;   // elements per site, ring slot length, x tiles per row
-    int st_cw, st_logcw, st_ncb;   // block columns per tile (a power of two dividing nb), blocks of them
-    int st_tsite, st_logtsite;     // elements per site inside a tile (n_orb * st_cw)
+    int st_site, st_seg, st_nxs;   // elements per site, ring row length, column tiles per row
     int st_Lm, st_Lw, st_pm, st_pw;
     int st_C, st_Bm, st_parts;     // planes per walk, strip height, 8 XCD parts or 1
 };
@@ -574,19 +572,12 @@ void batch_sweep_kernel(const KArgs<T, VT>* __restrict__ table, const int* __res
 // other set (issued one step earlier) to LDS behind a barrier that waits for
 // LDS operations only, so loads and y stores stay in flight across steps.
 //
-// A tile may hold only cw of the nb block columns (a power of two, at least
-// one 16-byte chunk): its elements run over (site, orbital, column) with cw
-// columns, so a tile spans nb / cw times as many sites and its x halo (one
-// site each side) costs that much less; every cw-column run of a site's
-// orbital row is one contiguous piece of the row in HBM.
-//
 // Walks are items of an XCD part (8 parts: split along m when the lattice has
 // at least 8 middle rows, along w otherwise).  Items are numbered walk chunk
-// first, then strips of st_Bm middle rows, then x tile, then m, then column
-// block; the G workgroups of a part take items j, j + G, ... so the
-// workgroups resident on one XCD walk a compact block of neighbouring columns
-// side by side and read each other's rows (m -+ 1, w) and x halos from the
-// same L2, all column blocks of a row at once.
+// first, then strips of st_Bm middle rows, then x tile, then m; the G
+// workgroups of a part take items j, j + G, ... so the workgroups resident on
+// one XCD walk a compact block of neighbouring columns side by side and read
+// each other's rows (m -+ 1, w) and x halos from the same L2.
 // ---------------------------------------------------------------------------
 template <typename T, int E>
 struct Staged {
@@ -647,21 +638,7 @@ struct StagedCtx {
     uint32_t roff[S::RCH];
     uint32_t soff[S::TCH];
     uint32_t voff[E];
-    int vshift;      // tile element -> field entry: log2 of tile elements per site or per orbital row
-    // row element and site of the lane's element k: (xg0, x0) of the tile
-    // plus a per-lane part (tile elements kBlock apart are whole sites apart)
-    int xg0, x0, lane_e, lane_s;
-    __device__ __forceinline__ int elem_of(int k) const {
-        return xg0 + k * ((kBlock >> a.st_logcw) * a.nb) + lane_e;
-    }
-    __device__ __forceinline__ int site_of(int k) const { return x0 + k * (kBlock >> a.st_logtsite) + lane_s; }
-    // Row element of tile element i (negative or past the row for halo
-    // elements): tile elements run over (site, orbital, column) with cw
-    // columns starting at the tile's first column, row elements over (site,
-    // orbital, column) with nb columns.
-    __device__ __forceinline__ int row_elem(int i) const {
-        return xg0 + (i >> a.st_logcw) * a.nb + (i & (a.st_cw - 1));
-    }
+    int vshift;      // element -> field entry: log2 of elements per site or per orbital row
 
     __device__ __forceinline__ int64_t row_of(int mm, int ww) const {
         return P::DIM == 3 ? (int64_t)ww * a.Ly + mm : (int64_t)ww;
@@ -685,35 +662,30 @@ struct StagedCtx {
         const int64_t r = row_idx(mm, ww);
         return r >= 0 ? a.x + r * a.rowel : a.zero_row;
     }
-    // Tile of sites [x0, x0 + TW / tsite) and columns [c0, c0 + cw).
-    __device__ __forceinline__ void setup(int x0_, int c0) {
+    __device__ __forceinline__ void setup(int xe0) {
         const int rowel = a.rowel;
-        x0 = x0_;
-        xg0 = x0 * a.st_site + c0;
         // chunks past the ring row (tile + halo) repeat its last chunk: every
         // lane loads and stores every chunk without branches, and the
         // repeated addresses add no traffic
 #pragma unroll
         for (int k = 0; k < S::RCH; ++k) {
             const int q = tid + k * kBlock;
-            int g = row_elem((q < nch ? q : nch - 1) * S::CE - a.st_tsite);
+            int g = xe0 - a.st_site + (q < nch ? q : nch - 1) * S::CE;
             if (g < 0) g += rowel;
             if (g >= rowel) g %= rowel;
             roff[k] = uint32_t(g) * S::ES;
         }
 #pragma unroll
         for (int k = 0; k < S::TCH; ++k) {
-            const int i = (tid + k * kBlock) * S::CE;
-            const int g = x0 + (i >> a.st_logtsite) < a.Lx ? row_elem(i) : rowel - S::CE;
-            soff[k] = uint32_t(g) * S::ES;
+            const int g = xe0 + (tid + k * kBlock) * S::CE;
+            soff[k] = uint32_t(g < rowel ? g : rowel - S::CE) * S::ES;
         }
         // field entries of the tile: one per site (site field) or per orbital
         // row, clamped into the lattice row
         const int vlen = a.pot_mode == 1 ? a.Lx : a.Lx * P::NO;
-        const int v0 = a.pot_mode == 1 ? x0 : x0 * P::NO;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            int r = v0 + tid + k * kBlock;
+            int r = (xe0 >> vshift) + tid + k * kBlock;
             if (r >= vlen) r = vlen - 1;
             voff[k] = uint32_t(r);
         }
@@ -793,22 +765,16 @@ struct StagedCtx {
 
 // LDS of a staged workgroup: three ring rows with halo (slots padded to
 // whole chunks per lane), the side rows of 3D lattices, z (and acc_in) of
-// the tile, the field of its orbital rows (padded to E per lane) and, when
-// the block columns are split over tiles (cw < nb), per-wave dot sums of
-// every column.
+// the tile, and the field of its orbital rows (padded to E per lane).
 template <typename T, int E>
 __host__ __device__ constexpr int staged_seg() {
     return Staged<T, E>::RCH * kBlock * Staged<T, E>::CE;
 }
 template <class P, typename T, int E>
-__host__ __device__ constexpr size_t staged_red_offset(bool acc) {
-    return (size_t(3 * staged_seg<T, E>() + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
-                Staged<T, E>::ES +
-            size_t(E * kBlock) * sizeof(T) + 15) / 16 * 16;
-}
-template <class P, typename T, int E>
-__host__ __device__ constexpr size_t staged_lds_bytes_for(int nb, int cw, bool acc) {
-    return staged_red_offset<P, T, E>(acc) + (cw < nb ? size_t(kBlock / 64) * nb * 4 * sizeof(double) : 0);
+__host__ __device__ constexpr size_t staged_lds_bytes_for(bool acc) {
+    return size_t(3 * staged_seg<T, E>() + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
+               Staged<T, E>::ES +
+           size_t(E * kBlock) * sizeof(T);
 }
 
 template <class P, typename T, typename VT, int E, unsigned EPM>
@@ -824,28 +790,17 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     const unsigned ep = EPM ? EPM : a.ep;
     const int tid = threadIdx.x;
     const int nb = a.nb;
-    const int cw = a.st_cw;
-    const int cl = tid & (cw - 1);
-    const int o = (tid >> a.st_logcw) & (NO - 1);
+    const int c = tid & (nb - 1);
+    const int o = (tid >> a.lognb) & (NO - 1);
     const int site = a.st_site;
-    const int tsite = a.st_tsite;
 
-    // column parameters, reloaded when the tile's column block changes
-    int c = cl;
-    T alT, beT, gaT;
-    auto columns = [&](int cc) {
-        c = cc;
-        double al = a.alpha, be = a.beta, ga = a.gamma;
-        if (a.colp != nullptr) {
-            al = a.colp[3 * cc];
-            be = a.colp[3 * cc + 1];
-            ga = a.colp[3 * cc + 2];
-        }
-        alT = T(al);
-        beT = T(be);
-        gaT = T(ga);
-    };
-    columns(cl);
+    double al = a.alpha, be = a.beta, ga = a.gamma;
+    if (a.colp != nullptr) {
+        al = a.colp[3 * c];
+        be = a.colp[3 * c + 1];
+        ga = a.colp[3 * c + 2];
+    }
+    const T alT = T(al), beT = T(be), gaT = T(ga);
     const T er = T(a.eta_re), ei = T(a.eta_im), e0r = T(a.eta0_re), e0i = T(a.eta0_im);
     const T dgr = T(a.coef[(((size_t)P::NT * NO + o) * NO + o) * 2]);
     const T dgi = T(a.coef[(((size_t)P::NT * NO + o) * NO + o) * 2 + 1]);
@@ -853,13 +808,11 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     constexpr int NS = SL.n;
     T cre[NS], cim[NS];
     int dq[NS];
-    slot_coefficients<P, T, NS>(a.coef, o, cw, cre, cim, dq);
+    slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
     double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
 
-    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, (S::TW + 2 * tsite) / S::CE, 0, 0};
-    cx.lane_e = (tid >> a.st_logcw) * nb + cl;
-    cx.lane_s = tid >> a.st_logtsite;
-    cx.vshift = a.pot_mode == 1 ? a.st_logtsite : a.st_logcw;
+    Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, (S::TW + 2 * site) / S::CE, 0, 0};
+    cx.vshift = a.pot_mode == 1 ? a.logsite : a.lognb;
     cx.tra = cx.ring + 3 * a.st_seg;
     cx.zl = cx.tra + NTR * S::TW;
     cx.al = cx.zl + S::TW;
@@ -879,57 +832,19 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     const int nm = m1 - m0, nW = wB - wA;
     const int nwc = nW > 0 ? (nW + a.st_C - 1) / a.st_C : 0;
     const int bms = min(a.st_Bm, nm);
-    const int ncb = a.st_ncb;
-    const int per_wc = nm * a.st_nxs * ncb;
+    const int per_wc = nm * a.st_nxs;
     const int items = nwc * per_wc;
-    const int spt = S::TW >> a.st_logtsite;   // sites per tile
-
-    // Split columns: each wave keeps the dot sums of every column in LDS and
-    // adds its lanes' sums there whenever its tiles move to another column
-    // block (the lanes of one column first summed with a fixed xor tree).
-    const bool dots = (ep & EP_DOTS) != 0u;
-    auto wave_red = [&]() {
-        return reinterpret_cast<double*>(smem + staged_red_offset<P, T, E>(ACC)) + (tid >> 6) * nb * 4;
-    };
-    if (dots && ncb > 1) {
-        double* cred = wave_red();
-        for (int i = tid & 63; i < nb * 4; i += 64) cred[i] = 0.0;
-        __syncthreads();
-    }
-    auto flush = [&](int cc0) {
-        for (int mm = cw; mm < 64; mm <<= 1) {
-            dxx += __shfl_xor(dxx, mm);
-            dxr += __shfl_xor(dxr, mm);
-            dxi += __shfl_xor(dxi, mm);
-            dyy += __shfl_xor(dyy, mm);
-        }
-        if ((tid & 63) < cw) {
-            double* q = wave_red() + (cc0 + (tid & 63)) * 4;
-            q[0] += dxx;
-            q[1] += dxr;
-            q[2] += dxi;
-            q[3] += dyy;
-        }
-        dxx = dxr = dxi = dyy = 0.0;
-    };
-    int cb_cur = 0;
 
     for (int j = jb; j < items; j += G) {
         const int wc = j / per_wc;
-        const int rc = j - wc * per_wc;
-        const int cb = rc & (ncb - 1);
-        const int rem = rc >> (a.lognb - a.st_logcw);
+        const int rem = j - wc * per_wc;
         const int ms = (rem / (bms * a.st_nxs)) * bms;
         const int bm = min(bms, nm - ms);
         const int r2 = rem - ms * a.st_nxs;
         const int xs = r2 / bm;
         cx.m = m0 + ms + (r2 - xs * bm);
-        if (cb != cb_cur) {
-            if (dots) flush(cb_cur * cw);
-            cb_cur = cb;
-            columns(cb * cw + cl);
-        }
-        cx.setup(xs * spt, cb * cw);
+        const int xe0 = xs * S::TW;
+        cx.setup(xe0);
         const int wa = wA + wc * a.st_C;
         const int wb = min(wa + a.st_C, wB);
         cx.wb = wb;
@@ -953,9 +868,9 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
         auto step = [&](int s, Set& nx, const Set& cur) {
             const int w = wa + s;
             cx.issue(nx, s + 2 < nsteps ? w + 3 : w + 1, w + 2);
-            const cplx<T>* rm = cx.ring + (s % 3) * a.st_seg + tsite;
-            const cplx<T>* r0 = cx.ring + ((s + 1) % 3) * a.st_seg + tsite;
-            const cplx<T>* rp = cx.ring + ((s + 2) % 3) * a.st_seg + tsite;
+            const cplx<T>* rm = cx.ring + (s % 3) * a.st_seg + site;
+            const cplx<T>* r0 = cx.ring + ((s + 1) % 3) * a.st_seg + site;
+            const cplx<T>* rp = cx.ring + ((s + 2) % 3) * a.st_seg + site;
             const int64_t rowi = cx.row_of(cx.m, w);
             const int64_t rb = rowi * a.rowel;
             T yr[E], yi[E];
@@ -963,7 +878,8 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int l = tid + k * kBlock;
-                const int x = cx.site_of(k);
+                const int xe = xe0 + l;
+                const int x = xe >> a.logsite;
                 const bool xlo = a.px || x > 0, xhi = a.px || x < a.Lx - 1;
                 const cplx<T> xc = r0[l];
                 const T vs = a.field != 0 ? cx.vl[l >> cx.vshift] : T(0);
@@ -983,7 +899,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                         constexpr int dw = P::DIM == 3 ? P::off[tt][2] : P::off[tt][1];
                         if constexpr (dm == 0) {
                             const cplx<T>* rw = dw < 0 ? rm : (dw > 0 ? rp : r0);
-                            v = rw[l + dx * tsite + dq[jx]];
+                            v = rw[l + dx * site + dq[jx]];
                             if constexpr (dx < 0) v = zero_unless(xlo, v);
                             if constexpr (dx > 0) v = zero_unless(xhi, v);
                         } else {
@@ -1003,14 +919,12 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
             cx.commit(cur, (s + 3) % 3);
 #pragma unroll
             for (int k = 0; k < E; ++k) {
-                const int x = cx.site_of(k);
-                if (x < a.Lx) {
-                    // the field gradient (gidx, lane group) needs whole sites
-                    // per tile, which the host guarantees (cw == nb) for it
-                    const int64_t st = rowi * a.Lx + x;
+                const int xe = xe0 + tid + k * kBlock;
+                if (xe < a.rowel) {
+                    const int64_t st = rowi * a.Lx + (xe >> a.logsite);
                     const int64_t gidx = a.ggroup == nb ? st * NO + o : st;
-                    epilogue_ep(a, ep, rb + cx.elem_of(k), gidx, tid & (a.ggroup - 1), xs_[k], zv[k], av[k], yr[k],
-                                yi[k], alT, gaT, er, ei, e0r, e0i, c, dxx, dxr, dxi, dyy);
+                    epilogue_ep(a, ep, rb + xe, gidx, tid & (a.ggroup - 1), xs_[k], zv[k], av[k], yr[k], yi[k], alT,
+                                gaT, er, ei, e0r, e0i, c, dxx, dxr, dxi, dyy);
                 }
             }
             lds_barrier();
@@ -1023,16 +937,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
         if (s < nsteps) step(s, A, B);
     }
 
-    if (dots && ncb > 1) {
-        flush(cb_cur * cw);
-        __syncthreads();
-        if (tid < nb * 4) {
-            const double* r0 = reinterpret_cast<const double*>(smem + staged_red_offset<P, T, E>(ACC));
-            double sum = 0.0;
-            for (int wv = 0; wv < kBlock / 64; ++wv) sum += r0[wv * nb * 4 + tid];
-            a.partials[(size_t)b_out * nb * 4 + tid] = sum;
-        }
-    } else if (dots) {
+    if (ep & EP_DOTS) {
         for (int mm = nb; mm < 64; mm <<= 1) {
             dxx += __shfl_xor(dxx, mm);
             dxr += __shfl_xor(dxr, mm);
@@ -1191,38 +1096,18 @@ int env_int(const char* name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
-// Block columns per staged tile: p.st_cw when it is a power of two below nb
-// (raised to one 16-byte chunk), else all nb.  The field gradient (EP_GRAD)
-// sums whole sites or orbital rows inside a tile and keeps nb.
-int staged_cols(const SweepParams& p, int elem_bytes) {
-    int cw = p.st_cw;
-    if (cw <= 0 || cw >= p.nb || (cw & (cw - 1)) != 0 || (p.ep & EP_GRAD) != 0) return p.nb;
-    if (cw * elem_bytes < 16) cw = 16 / elem_bytes;
-    return cw < p.nb ? cw : p.nb;
-}
-
 template <class P, typename T, int E, unsigned EPM>
-size_t staged_lds_bytes(const SweepParams& p) {
-    return staged_lds_bytes_for<P, T, E>(p.nb, staged_cols(p, int(sizeof(cplx<T>))),
-                                         EPM == 0u || (EPM & EP_ACC_ADD) != 0u);
+size_t staged_lds_bytes(int nb) {
+    (void)nb;
+    return staged_lds_bytes_for<P, T, E>(EPM == 0u || (EPM & EP_ACC_ADD) != 0u);
 }
 
 template <class P, typename T, typename VT, int E>
 int staged_setup(const SweepParams& p, int G8, bool full_walk, KArgs<T, VT>& a) {
     using S = Staged<T, E>;
-    const int cw = staged_cols(p, S::ES);
-    int lcw = 0;
-    while ((1 << lcw) < cw) ++lcw;
-    a.st_cw = cw;
-    a.st_logcw = lcw;
-    a.st_ncb = p.nb / cw;
-    a.st_tsite = P::NO * cw;
-    static_assert(P::NO == 2 || P::NO == 4, "compiled families have 2 or 4 orbitals");
-    a.st_logtsite = lcw + (P::NO == 4 ? 2 : 1);
     a.st_site = P::NO * p.nb;
-    a.st_seg = staged_seg<T, E>();   // ring slot; its first TW + 2 tsite elements hold the row
-    const int spt = S::TW / a.st_tsite;
-    a.st_nxs = (a.Lx + spt - 1) / spt;
+    a.st_seg = staged_seg<T, E>();   // ring slot; its first TW + 2 site elements hold the row
+    a.st_nxs = (a.rowel + S::TW - 1) / S::TW;
     if (P::DIM == 3) {
         a.st_Lm = a.Ly; a.st_Lw = a.Lz; a.st_pm = a.py; a.st_pw = a.pz;
     } else {
@@ -1232,7 +1117,7 @@ int staged_setup(const SweepParams& p, int G8, bool full_walk, KArgs<T, VT>& a) 
     const bool split_m = a.st_Lm >= 8;
     const int nm = split_m ? (a.st_Lm + 7) / 8 : a.st_Lm;
     const int nW = split_m ? a.st_Lw : (a.st_Lw + 7) / 8;
-    const int cols = nm * a.st_nxs * a.st_ncb;
+    const int cols = nm * a.st_nxs;
     if (nW < 1) {
         a.st_C = 1;
     } else if (p.st_C > 0) {
@@ -1246,12 +1131,10 @@ int staged_setup(const SweepParams& p, int G8, bool full_walk, KArgs<T, VT>& a) 
     }
     const int items = nW < 1 ? 1 : ((nW + a.st_C - 1) / a.st_C) * cols;
     if (G8 > items) G8 = items;
-    // about square blocks of (m, x tile) positions, each with all its column blocks
-    const int gp = G8 / a.st_ncb > 1 ? G8 / a.st_ncb : 1;
-    int bx = int(std::lround(std::sqrt(double(gp) * a.st_tsite / S::TW)));
+    int bx = int(std::lround(std::sqrt(double(G8) * a.st_site / S::TW)));
     if (bx > a.st_nxs) bx = a.st_nxs;
     if (bx < 1) bx = 1;
-    a.st_Bm = p.st_Bm > 0 ? p.st_Bm : (gp / bx > 1 ? gp / bx : 1);
+    a.st_Bm = p.st_Bm > 0 ? p.st_Bm : (G8 / bx > 1 ? G8 / bx : 1);
     a.st_parts = 8;
     return G8;
 }
@@ -1260,7 +1143,7 @@ template <class P, typename T, typename VT, int E, unsigned EPM>
 hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
     KArgs<T, VT> a;
     make_kargs<P, T, VT>(p, false, a);
-    const size_t lds = staged_lds_bytes<P, T, E, EPM>(p);
+    const size_t lds = staged_lds_bytes<P, T, E, EPM>(p.nb);
     const void* kern = reinterpret_cast<const void*>(&staged_kernel<P, T, VT, E, EPM>);
     // workgroups resident per CU at this LDS size (cached per size)
     static size_t occ_lds[8] = {};
@@ -1823,7 +1706,7 @@ hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* tabl
                 constexpr unsigned KPM = EP_STORE_Y | EP_DOTS;
                 auto go = [&](auto ke) -> hipError_t {
                     constexpr int E = decltype(ke)::value;
-                    const size_t lds = staged_lds_bytes<P, T, E, KPM>(p);
+                    const size_t lds = staged_lds_bytes<P, T, E, KPM>(p.nb);
                     if (lds > 65536) {
                         hipError_t e = hipFuncSetAttribute(
                             reinterpret_cast<const void*>(&batch_staged_kernel<P, T, VT, E, KPM>),

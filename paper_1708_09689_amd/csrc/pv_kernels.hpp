@@ -70,7 +70,6 @@ struct SweepParams {
     int kernel;             // 0 = choose, 1 = direct, 2 = staged
     int st_E, st_C, st_Bm, st_G8;   // staged kernel: elements per lane, planes per walk,
                                     // strip height, workgroups per XCD (0 = heuristic)
-    int st_cw;                      // staged kernel: block columns per tile (0 = all nb)
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;

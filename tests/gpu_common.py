@@ -54,15 +54,3 @@ def host(t):
 
 def rel_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-
-
-# Launch shapes of the parity cases: 1 the direct kernel, 2 the staged kernel,
-# 3 the staged kernel with the block columns split over tiles (nb / 4 per
-# tile, at least one 16-byte chunk; all nb for nb = 1).
-SHAPE_KINDS = [1, 2, 3]
-
-
-def shape(kind, nb):
-    if kind == 3:
-        return {"kernel": 2, "tile_cols": max(nb // 4, 1)}
-    return {"kernel": kind}

@@ -76,9 +76,8 @@ def test_batched_equals_single_lattice_path():
 
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
 def test_batched_direct_and_staged_kernels_agree(dtype):
-    """Lattice 0's tuning selects the kernel (and the staged tile's block
-    columns) of the whole batch; all give the same moments up to the
-    summation order of the dots."""
+    """Lattice 0's tuning selects the kernel of the whole batch; both give the
+    same moments up to the summation order of the dots."""
     vd = np.float64 if dtype == np.complex128 else np.float32
     cases, rs, a, b = instances(dtype, vd, nb=8)
     code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
@@ -88,10 +87,7 @@ def test_batched_direct_and_staged_kernels_agree(dtype):
     mu_s = host(pv.pv_batch_kpm_moments(batch, rd, 48, a, b)).copy()
     pv.pv_lattice_set_tuning(cases[0].lat, code, 8, {"kernel": 1})
     mu_d = host(pv.pv_batch_kpm_moments(batch, rd, 48, a, b)).copy()
-    pv.pv_lattice_set_tuning(cases[0].lat, code, 8, {"kernel": 2, "tile_cols": 2})
-    mu_c = host(pv.pv_batch_kpm_moments(batch, rd, 48, a, b)).copy()
     pv.pv_lattice_set_tuning(cases[0].lat, code, 8, None)
-    assert batch.stats()[0] == 3          # every shape change forced a new capture
+    assert batch.stats()[0] == 2          # the kernel change forced a new capture
     tol = 1e-13 if dtype == np.complex128 else 1e-6
     assert np.abs(mu_s - mu_d).max() < tol
-    assert np.abs(mu_c - mu_d).max() < tol

@@ -1,5 +1,5 @@
 """Launch shapes of the sweep (direct / staged kernels, elements per lane,
-block columns per tile, strip, walk and workgroup counts) and the autotuner.
+strip, walk and workgroup counts) and the autotuner.
 
 Every shape runs the same per-element arithmetic (the stencil slots in the
 same order), so y is bitwise identical across shapes; the fused dot products
@@ -25,17 +25,12 @@ SHAPES_C128 = [
     {"kernel": 2, "elems_per_lane": 2},
     {"kernel": 2, "elems_per_lane": 1, "strip_rows": 3, "walk_planes": 2, "groups_per_xcd": 5},
     {"kernel": 2, "elems_per_lane": 2, "strip_rows": 1, "walk_planes": 1, "groups_per_xcd": 1},
-    {"kernel": 2, "elems_per_lane": 1, "tile_cols": 1},
-    {"kernel": 2, "elems_per_lane": 1, "tile_cols": 8},
-    {"kernel": 2, "elems_per_lane": 2, "tile_cols": 2, "strip_rows": 3, "walk_planes": 2, "groups_per_xcd": 5},
 ]
 SHAPES_C64 = [
     {"kernel": 1},
     {"kernel": 2, "elems_per_lane": 2},
     {"kernel": 2, "elems_per_lane": 4},
     {"kernel": 2, "elems_per_lane": 2, "strip_rows": 5, "walk_planes": 3, "groups_per_xcd": 3},
-    {"kernel": 2, "elems_per_lane": 2, "tile_cols": 1},        # raised to one 16-byte chunk (2 columns)
-    {"kernel": 2, "elems_per_lane": 4, "tile_cols": 4, "groups_per_xcd": 3},
 ]
 
 CASES = [
