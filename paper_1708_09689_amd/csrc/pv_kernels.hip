@@ -163,6 +163,7 @@ struct Slots {
     int t[MAX] = {};
     unsigned char kind[MAX] = {};
     signed char q[MAX][4] = {};
+    bool same[MAX] = {};   // every row's entry sits in its own orbital (orbital offset 0)
     constexpr Slots() {
         constexpr int NO = P::NO;
         for (int tt = 0; tt <= P::NT; ++tt)
@@ -186,6 +187,9 @@ struct Slots {
                                 ++cnt;
                             }
                     }
+                    same[n] = true;
+                    for (int o = 0; o < NO; ++o)
+                        if (q[n][o] >= 0 && q[n][o] != o) same[n] = false;
                     ++n;
                 }
             }
@@ -606,24 +610,31 @@ __device__ __forceinline__ u32x4 ld_chunk_nt(const void* base, uint32_t boff) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(reinterpret_cast<const char*>(base) + boff));
 }
 
-// One step's worth of rows in flight: ring row with halo, side rows, z and
-// acc_in chunks, field values.
+// One step's worth of rows in flight: ring row with halo, z and acc_in
+// chunks, field values.  (The side rows of 3D lattices, mostly L2 hits, are
+// loaded one step ahead into a single set of their own.)
 template <class P, typename T, typename VT, int E>
 struct StagedSet {
     using S = Staged<T, E>;
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
     u32x4 ring[S::RCH];
-    u32x4 side[NTR > 0 ? NTR : 1][S::TCH];
     u32x4 z[S::TCH];
     u32x4 acc[S::TCH];
     VT v[E];          // stored field entries (converted when handed to LDS)
     int64_t vrow;     // first field entry of the set's row
 };
 
+template <class P, typename T, int E>
+struct StagedSide {
+    static constexpr int NTR = P::DIM == 3 ? 2 : 0;
+    u32x4 side[NTR > 0 ? NTR : 1][Staged<T, E>::TCH];
+};
+
 template <class P, typename T, typename VT, int E, bool ACC>
 struct StagedCtx {
     using S = Staged<T, E>;
     using Set = StagedSet<P, T, VT, E>;
+    using Side = StagedSide<P, T, E>;
     static constexpr int NTR = Set::NTR;
     const KArgs<T, VT>& a;
     cplx<T>* ring;   // [3][seg]
@@ -699,14 +710,6 @@ struct StagedCtx {
 #pragma unroll
         for (int k = 0; k < S::RCH; ++k) st.ring[k] = ld_chunk<T>(rp, roff[k]);
         const int wr = w_row < wb ? w_row : wb - 1;
-        if constexpr (NTR > 0) {
-#pragma unroll
-            for (int h = 0; h < NTR; ++h) {
-                const cplx<T>* sp = row_ptr(m + (h == 0 ? -1 : 1), wr);
-#pragma unroll
-                for (int k = 0; k < S::TCH; ++k) st.side[h][k] = ld_chunk<T>(sp, soff[k]);
-            }
-        }
         const int64_t rw = row_of(m, wr);
         const cplx<T>* zr = a.zsrc + rw * a.rowel;
 #pragma unroll
@@ -723,19 +726,33 @@ struct StagedCtx {
 #pragma unroll
         for (int k = 0; k < E; ++k) st.v[k] = vp[voff[k]];
     }
-    // Hand a set to LDS: ring row into slot, per-step rows into their buffers.
-    __device__ __forceinline__ void commit(const Set& st, int slot) const {
-        u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
+    // Side rows (m -+ 1, w_row), w_row clamped to the walk (3D lattices).
+    __device__ __forceinline__ void issue_side(Side& sd, int w_row) const {
+        if constexpr (NTR > 0) {
+            const int wr = w_row < wb ? w_row : wb - 1;
 #pragma unroll
-        for (int k = 0; k < S::RCH; ++k) d[tid + k * kBlock] = st.ring[k];
+            for (int h = 0; h < NTR; ++h) {
+                const cplx<T>* sp = row_ptr(m + (h == 0 ? -1 : 1), wr);
+#pragma unroll
+                for (int k = 0; k < S::TCH; ++k) sd.side[h][k] = ld_chunk<T>(sp, soff[k]);
+            }
+        }
+    }
+    __device__ __forceinline__ void commit_side(const Side& sd) const {
         if constexpr (NTR > 0) {
 #pragma unroll
             for (int h = 0; h < NTR; ++h) {
                 u32x4* ds = reinterpret_cast<u32x4*>(tra + h * S::TW);
 #pragma unroll
-                for (int k = 0; k < S::TCH; ++k) ds[tid + k * kBlock] = st.side[h][k];
+                for (int k = 0; k < S::TCH; ++k) ds[tid + k * kBlock] = sd.side[h][k];
             }
         }
+    }
+    // Hand a set to LDS: ring row into slot, per-step rows into their buffers.
+    __device__ __forceinline__ void commit(const Set& st, int slot) const {
+        u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
+#pragma unroll
+        for (int k = 0; k < S::RCH; ++k) d[tid + k * kBlock] = st.ring[k];
         u32x4* dz = reinterpret_cast<u32x4*>(zl);
 #pragma unroll
         for (int k = 0; k < S::TCH; ++k) dz[tid + k * kBlock] = st.z[k];
@@ -794,8 +811,10 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     const int o = (tid >> a.lognb) & (NO - 1);
     const int site = a.st_site;
 
+    // per-column alpha, beta, gamma only in the run-time epilogue (the
+    // specialised ones are launched with uniform values)
     double al = a.alpha, be = a.beta, ga = a.gamma;
-    if (a.colp != nullptr) {
+    if (EPM == 0u && a.colp != nullptr) {
         al = a.colp[3 * c];
         be = a.colp[3 * c + 1];
         ga = a.colp[3 * c + 2];
@@ -854,19 +873,24 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
         // wa + 1 and the rows of step 0, handed over now; set B = ring row
         // wa + 2 and the rows of step 1, left in flight
         Set A, B;
+        typename Ctx::Side SD;
         cx.ring_now(A.ring, wa - 1, 0);
         cx.ring_now(B.ring, wa, 1);
+        cx.issue_side(SD, wa);
         cx.issue(A, wa + 1, wa);
         cx.commit(A, 2);
+        cx.commit_side(SD);
         cx.issue(B, wa + 2, wa + 1);
         lds_barrier();
 
-        // step s (outer index wa + s): issue `nx` for step s + 2, compute from
-        // LDS, hand `cur` (issued for step s + 1) over, store.  Issue and
-        // hand-over run on every step; past the walk they fetch rows read two
-        // steps earlier (cache hits) and fill a ring slot nobody reads.
+        // step s (outer index wa + s): issue the side rows of step s + 1 and
+        // `nx` for step s + 2, compute from LDS, hand `cur` (issued for step
+        // s + 1) and the side rows over, store.  Issue and hand-over run on
+        // every step; past the walk they fetch rows read two steps earlier
+        // (cache hits) and fill buffers nobody reads.
         auto step = [&](int s, Set& nx, const Set& cur) {
             const int w = wa + s;
+            cx.issue_side(SD, w + 1);
             cx.issue(nx, s + 2 < nsteps ? w + 3 : w + 1, w + 2);
             const cplx<T>* rm = cx.ring + (s % 3) * a.st_seg + site;
             const cplx<T>* r0 = cx.ring + ((s + 1) % 3) * a.st_seg + site;
@@ -889,9 +913,10 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 sfor<NS>([&](auto jj) {
                     constexpr int jx = decltype(jj)::value;
                     constexpr int t = SL.t[jx];
+                    const int dqj = SL.same[jx] ? 0 : dq[jx];   // constant 0 for own-orbital slots
                     cplx<T> v;
                     if constexpr (t == P::NT) {
-                        v = r0[l + dq[jx]];
+                        v = r0[l + dqj];
                     } else {
                         constexpr int tt = t < P::NT ? t : 0;
                         constexpr int dx = P::off[tt][0];
@@ -899,12 +924,12 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                         constexpr int dw = P::DIM == 3 ? P::off[tt][2] : P::off[tt][1];
                         if constexpr (dm == 0) {
                             const cplx<T>* rw = dw < 0 ? rm : (dw > 0 ? rp : r0);
-                            v = rw[l + dx * site + dq[jx]];
+                            v = rw[l + dx * site + dqj];
                             if constexpr (dx < 0) v = zero_unless(xlo, v);
                             if constexpr (dx > 0) v = zero_unless(xhi, v);
                         } else {
                             static_assert(dx == 0 && dw == 0, "side rows carry no x or w offset");
-                            v = cx.tra[(dm < 0 ? 0 : S::TW) + l + dq[jx]];
+                            v = cx.tra[(dm < 0 ? 0 : S::TW) + l + dqj];
                         }
                     }
                     mac<T>(hr, hi, SL.kind[jx], cre[jx], cim[jx], v);
@@ -917,6 +942,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
             }
             lds_barrier();
             cx.commit(cur, (s + 3) % 3);
+            cx.commit_side(SD);
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int xe = xe0 + tid + k * kBlock;
@@ -982,10 +1008,9 @@ __global__ __launch_bounds__(kBlock) void batch_staged_kernel(const KArgs<T, VT>
 template <class P, typename T, typename VT, int E, unsigned EPM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_STAGED_WAVES_PER_EU)))
 void staged_kernel(KArgs<T, VT> a) {
-    if (a.st_parts == 8)
-        staged_block<P, T, VT, E, EPM>(a, blockIdx.x, blockIdx.x & 7, blockIdx.x >> 3, gridDim.x >> 3);
-    else
-        staged_block<P, T, VT, E, EPM>(a, blockIdx.x, 0, blockIdx.x, gridDim.x);
+    const bool p8 = a.st_parts == 8;
+    const int b = blockIdx.x, g = gridDim.x;
+    staged_block<P, T, VT, E, EPM>(a, b, p8 ? (b & 7) : 0, p8 ? (b >> 3) : b, p8 ? (g >> 3) : g);
 }
 
 // Tiles per workgroup: enough workgroups to keep every CU busy for several
@@ -1180,8 +1205,8 @@ hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
 template <class P, typename T, typename VT, int E>
 hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
     constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD;
-    if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
-    if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
+    if (p.ep == KPM && p.colp == nullptr) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
+    if (p.ep == SERIES && p.colp == nullptr) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
     return launch_staged<P, T, VT, E, 0u>(p, num_cus, s);
 }
 
