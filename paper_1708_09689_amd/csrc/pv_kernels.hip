@@ -619,7 +619,6 @@ struct StagedSet {
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
     u32x4 ring[S::RCH];
     u32x4 z[S::TCH];
-    u32x4 acc[S::TCH];
     VT v[E];          // stored field entries (converted when handed to LDS)
     int64_t vrow;     // first field entry of the set's row
 };
@@ -628,6 +627,7 @@ template <class P, typename T, int E>
 struct StagedSide {
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
     u32x4 side[NTR > 0 ? NTR : 1][Staged<T, E>::TCH];
+    u32x4 acc[Staged<T, E>::TCH];
 };
 
 template <class P, typename T, typename VT, int E, bool ACC>
@@ -714,11 +714,6 @@ struct StagedCtx {
         const cplx<T>* zr = a.zsrc + rw * a.rowel;
 #pragma unroll
         for (int k = 0; k < S::TCH; ++k) st.z[k] = ld_chunk_nt<T>(zr, soff[k]);
-        if constexpr (ACC) {
-            const cplx<T>* ar = a.asrc + rw * a.rowel;
-#pragma unroll
-            for (int k = 0; k < S::TCH; ++k) st.acc[k] = ld_chunk_nt<T>(ar, soff[k]);
-        }
         // stored field entries (a row of the zero row's bytes when the field
         // is absent or generated; those values are not used)
         st.vrow = rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
@@ -728,6 +723,12 @@ struct StagedCtx {
     }
     // Side rows (m -+ 1, w_row), w_row clamped to the walk (3D lattices).
     __device__ __forceinline__ void issue_side(Side& sd, int w_row) const {
+        if constexpr (ACC) {
+            const int wr = w_row < wb ? w_row : wb - 1;
+            const cplx<T>* ar = a.asrc + row_of(m, wr) * a.rowel;
+#pragma unroll
+            for (int k = 0; k < S::TCH; ++k) sd.acc[k] = ld_chunk_nt<T>(ar, soff[k]);
+        }
         if constexpr (NTR > 0) {
             const int wr = w_row < wb ? w_row : wb - 1;
 #pragma unroll
@@ -739,6 +740,11 @@ struct StagedCtx {
         }
     }
     __device__ __forceinline__ void commit_side(const Side& sd) const {
+        if constexpr (ACC) {
+            u32x4* da = reinterpret_cast<u32x4*>(al);
+#pragma unroll
+            for (int k = 0; k < S::TCH; ++k) da[tid + k * kBlock] = sd.acc[k];
+        }
         if constexpr (NTR > 0) {
 #pragma unroll
             for (int h = 0; h < NTR; ++h) {
@@ -756,11 +762,6 @@ struct StagedCtx {
         u32x4* dz = reinterpret_cast<u32x4*>(zl);
 #pragma unroll
         for (int k = 0; k < S::TCH; ++k) dz[tid + k * kBlock] = st.z[k];
-        if constexpr (ACC) {
-            u32x4* da = reinterpret_cast<u32x4*>(al);
-#pragma unroll
-            for (int k = 0; k < S::TCH; ++k) da[tid + k * kBlock] = st.acc[k];
-        }
         if (a.field == 2) {
 #pragma unroll
             for (int k = 0; k < E; ++k) vl[tid + k * kBlock] = field_at(a, st.vrow + voff[k]);
