@@ -1201,13 +1201,17 @@ hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
 }
 
 // Epilogue specialisations of the staged kernel: the Chebyshev step with
-// fused dots (KPM), the series step (propagation, filters), and every other
-// combination with the flags read at run time.
+// fused dots (KPM), the series step (propagation, filters), the plain sweep
+// or Chebyshev step without dots, and every other combination with the
+// flags read at run time.
 template <class P, typename T, typename VT, int E>
 hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
-    constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD;
-    if (p.ep == KPM && p.colp == nullptr) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
-    if (p.ep == SERIES && p.colp == nullptr) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
+    constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD, PLAIN = EP_STORE_Y;
+    if (p.colp == nullptr) {
+        if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
+        if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
+        if (p.ep == PLAIN) return launch_staged<P, T, VT, E, PLAIN>(p, num_cus, s);
+    }
     return launch_staged<P, T, VT, E, 0u>(p, num_cus, s);
 }
 
