@@ -440,14 +440,19 @@ typedef struct pv_tuning {
 } pv_tuning;
 
 /* Set (t != NULL) or reset to defaults (t == NULL) the shape used for
- * (dtype, nb); PV_ERR_INVALID_ARG for values outside the ranges above. */
+ * (dtype, nb), by every sweep including series steps (this drops a series
+ * shape the autotuner chose); get returns the shape of the Chebyshev step.
+ * PV_ERR_INVALID_ARG for values outside the ranges above. */
 pv_status pv_lattice_set_tuning(pv_lattice *lat, int dtype, int nb, const pv_tuning *t);
 pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tuning *t);
 
 /*
  * Autotuner: times candidate shapes of one Chebyshev step (sweep with fused
  * dots and its reduction) on the stream's device and applies the fastest to
- * the lattice for (dtype, nb).  cache_path names a JSON-lines file (NULL:
+ * the lattice for (dtype, nb); then, separately, those of one series step
+ * (the accumulating sweep of pv_cheb_series, pv_cheb_propagate, pv_chebfd
+ * and pv_trlanczos_fd, whose extra stream changes the best shape), applied
+ * to that step only.  cache_path names a JSON-lines file (NULL:
  * the PV_TUNE_CACHE environment variable, else no cache); an entry whose key
  * (stencil family, orbitals, extents, boundary conditions, nb, dtype, field
  * type, device architecture and CU count) matches is applied without timing,

@@ -95,6 +95,7 @@ struct pv_lattice {
     double rng_W = 0.0;
     // launch shapes per (dtype, log2 nb)
     pv_tuning tune[2][7] = {};
+    pv_tuning tune_acc[2][7] = {};   // series steps (autotuned); kernel 0 = follow tune
 };
 
 namespace {
@@ -297,6 +298,12 @@ pv_status fill_traversal(pv_lattice* l, int dtype, int nb, pv::SweepParams& p) {
     p.st_C = t.walk_planes;
     p.st_Bm = t.strip_rows;
     p.st_G8 = t.groups_per_xcd;
+    const pv_tuning& ta = l->tune_acc[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    p.acc_kernel = ta.kernel;
+    p.acc_E = ta.elems_per_lane;
+    p.acc_C = ta.walk_planes;
+    p.acc_Bm = ta.strip_rows;
+    p.acc_G8 = ta.groups_per_xcd;
     p.zero_row = l->d_zero;
     return PV_OK;
 }
@@ -1036,9 +1043,10 @@ int* tune_field(pv_tuning& t, int i) {
     return f[i];
 }
 
-// Cache lines: {"key": "...", "kernel": k, ..., "ms": t}.  Returns true and
-// fills t for the last line whose key matches.
-bool cache_lookup(const char* path, const std::string& key, pv_tuning& t) {
+// Cache lines: {"key": "...", "kernel": k, ..., "acc_kernel": k, ..., "ms": t}
+// (the Chebyshev-step shape, then the series-step shape).  Returns true and
+// fills t, ta for the last line whose key matches and that holds both.
+bool cache_lookup(const char* path, const std::string& key, pv_tuning& t, pv_tuning& ta) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     bool found = false;
@@ -1046,16 +1054,18 @@ bool cache_lookup(const char* path, const std::string& key, pv_tuning& t) {
     const std::string want = "\"key\": \"" + key + "\"";
     while (std::fgets(line, sizeof line, f)) {
         if (!std::strstr(line, want.c_str())) continue;
-        pv_tuning r{};
+        pv_tuning r[2] = {};
         bool ok = true;
-        for (int i = 0; i < 7 && ok; ++i) {
-            const std::string name = std::string("\"") + kTuneFields[i] + "\": ";
-            const char* q = std::strstr(line, name.c_str());
-            if (!q) { ok = false; break; }
-            *tune_field(r, i) = int(std::strtol(q + name.size(), nullptr, 10));
-        }
+        for (int h = 0; h < 2 && ok; ++h)
+            for (int i = 0; i < 7 && ok; ++i) {
+                const std::string name = std::string("\"") + (h ? "acc_" : "") + kTuneFields[i] + "\": ";
+                const char* q = std::strstr(line, name.c_str());
+                if (!q) { ok = false; break; }
+                *tune_field(r[h], i) = int(std::strtol(q + name.size(), nullptr, 10));
+            }
         if (ok) {
-            t = r;
+            t = r[0];
+            ta = r[1];
             found = true;
         }
     }
@@ -1063,12 +1073,14 @@ bool cache_lookup(const char* path, const std::string& key, pv_tuning& t) {
     return found;
 }
 
-void cache_append(const char* path, const std::string& key, const pv_tuning& t, double ms) {
+void cache_append(const char* path, const std::string& key, const pv_tuning& t, const pv_tuning& ta, double ms) {
     FILE* f = std::fopen(path, "a");
     if (!f) return;
     std::fprintf(f, "{\"key\": \"%s\"", key.c_str());
-    pv_tuning c = t;
-    for (int i = 0; i < 7; ++i) std::fprintf(f, ", \"%s\": %d", kTuneFields[i], *tune_field(c, i));
+    pv_tuning c[2] = {t, ta};
+    for (int h = 0; h < 2; ++h)
+        for (int i = 0; i < 7; ++i)
+            std::fprintf(f, ", \"%s%s\": %d", h ? "acc_" : "", kTuneFields[i], *tune_field(c[h], i));
     std::fprintf(f, ", \"ms\": %.6f}\n", ms);
     std::fclose(f);
 }
@@ -1083,6 +1095,7 @@ extern "C" pv_status pv_lattice_set_tuning(pv_lattice* l, int dtype, int nb, con
     pv_tuning z{};
     if (t && (st = check_tuning(dtype, *t)) != PV_OK) return st;
     l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)] = t ? *t : z;
+    l->tune_acc[dtype == PV_C128 ? 0 : 1][log2_nb(nb)] = z;   // series steps follow the set shape
     return PV_OK;
 }
 
@@ -1097,7 +1110,7 @@ extern "C" pv_status pv_lattice_get_tuning(const pv_lattice* l, int dtype, int n
 
 extern "C" size_t pv_autotune_workspace_size(const pv_lattice* l, int dtype, int nb) {
     if (!l || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
-    return 2 * vec_bytes(l, dtype, nb) + partial_bytes(l, nb) + align_up(sizeof(double) * 4 * nb);
+    return 3 * vec_bytes(l, dtype, nb) + partial_bytes(l, nb) + align_up(sizeof(double) * 4 * nb);
 }
 
 extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* cache_path, void* work,
@@ -1112,45 +1125,63 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!cache_path) cache_path = std::getenv("PV_TUNE_CACHE");
     const std::string key = tune_key(l, dtype, nb);
-    pv_tuning best{};
-    if (cache_path && cache_lookup(cache_path, key, best) && check_tuning(dtype, best) == PV_OK) {
-        l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)] = best;
-        if (out) *out = best;
-        if (ms_out) *ms_out = 0.0;
-        return PV_OK;
+    const int di = dtype == PV_C128 ? 0 : 1, ni = log2_nb(nb);
+    pv_tuning& slot = l->tune[di][ni];
+    pv_tuning& slot_acc = l->tune_acc[di][ni];
+    {
+        pv_tuning c{}, ca{};
+        if (cache_path && cache_lookup(cache_path, key, c, ca) && check_tuning(dtype, c) == PV_OK &&
+            check_tuning(dtype, ca) == PV_OK) {
+            slot = c;
+            slot_acc = ca;
+            if (out) *out = c;
+            if (ms_out) *ms_out = 0.0;
+            return PV_OK;
+        }
     }
 
-    // buffers: x = 0, y = 0; the step y = 2 H~ x - y with fused dots
+    // buffers: x = y = acc = 0; the Chebyshev step y = 2 H~ x - y with fused
+    // dots, and the series step y = 2 H~ x - y, acc += eta y
     char* w = static_cast<char*>(work);
     const size_t vb = vec_bytes(l, dtype, nb);
     void* x = w;
     void* y = w + vb;
-    double* part = reinterpret_cast<double*>(w + 2 * vb);
-    double* dots = reinterpret_cast<double*>(w + 2 * vb + partial_bytes(l, nb));
-    PV_HIP(pv::launch_zero(w, 2 * vb, s));
+    void* acc = w + 2 * vb;
+    double* part = reinterpret_cast<double*>(w + 3 * vb);
+    double* dots = reinterpret_cast<double*>(w + 3 * vb + partial_bytes(l, nb));
+    PV_HIP(pv::launch_zero(w, 3 * vb, s));
     hipEvent_t e0, e1;
     PV_HIP(hipEventCreate(&e0));
     PV_HIP(hipEventCreate(&e1));
-    pv_tuning& slot = l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
-    const pv_tuning saved = slot;
+    const pv_tuning saved = slot, saved_acc = slot_acc;
+    bool series = false;   // which step the candidates are timed on
     auto run = [&](int reps) -> hipError_t {
         for (int r = 0; r < reps; ++r) {
             pv::SweepParams p = base_params(l, dtype, nb);
             fill_traversal(l, dtype, nb, p);
             p.x = x; p.z = y; p.y = y;
             p.alpha = 2.0 / 8.0; p.beta = 0.0; p.gamma = -1.0;
-            p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
-            p.partials = part;
-            hipError_t e = pv::launch_sweep(p, num_cus(), s);
-            if (e == hipSuccess) e = pv::launch_reduce_dots(part, p.grid, nb, 0, dots, 0, 0, 0.0, s);
-            if (e != hipSuccess) return e;
+            if (series) {
+                p.ep = pv::EP_STORE_Y | pv::EP_ACC_ADD;
+                p.acc_in = acc;
+                p.acc_out = acc;
+                p.eta_re = 0.5;
+                p.eta_im = 0.25;
+                if (hipError_t e = pv::launch_sweep(p, num_cus(), s); e != hipSuccess) return e;
+            } else {
+                p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
+                p.partials = part;
+                hipError_t e = pv::launch_sweep(p, num_cus(), s);
+                if (e == hipSuccess) e = pv::launch_reduce_dots(part, p.grid, nb, 0, dots, 0, 0, 0.0, s);
+                if (e != hipSuccess) return e;
+            }
         }
         return hipSuccess;
     };
     // time of one step under shape t (milliseconds); warm-up first, then
     // enough repetitions for about 20 ms
     auto measure = [&](const pv_tuning& t, double& ms) -> hipError_t {
-        slot = t;
+        (series ? slot_acc : slot) = t;
         hipError_t e = run(1);
         if (e != hipSuccess) return e;
         if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
@@ -1170,48 +1201,62 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         ms = double(tt) / reps;
         return hipSuccess;
     };
-    double best_ms = 1e300;
     hipError_t herr = hipSuccess;
-    auto consider = [&](const pv_tuning& t) {
-        if (herr != hipSuccess) return;
-        double ms = 0;
-        herr = measure(t, ms);
-        if (herr == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = t;
+    const bool compiled = l->family != pv::FAM_GENERIC;
+    const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
+    // coordinate search: 1. kernel and elements per lane at default shapes;
+    // for the staged winner 2. strip height, 3. planes per walk, 4. workgroups
+    // per XCD; for the direct winner, tiles per workgroup
+    auto search = [&](pv_tuning& best, double& best_ms) {
+        best = pv_tuning{};
+        best_ms = 1e300;
+        auto consider = [&](const pv_tuning& t) {
+            if (herr != hipSuccess) return;
+            double ms = 0;
+            herr = measure(t, ms);
+            if (herr == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        };
+        pv_tuning t{};
+        t.kernel = 1;
+        consider(t);
+        if (compiled) {
+            const int es[2] = {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4};
+            for (int e : es) {
+                t = pv_tuning{};
+                t.kernel = 2;
+                t.elems_per_lane = e;
+                consider(t);
+            }
+        }
+        if (best.kernel == 2) {
+            for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
+            for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
+            for (int v : {32, 64, 96, 128}) { t = best; t.groups_per_xcd = v; consider(t); }
+        } else {
+            for (int v : {32, 64}) { t = best; t.tiles_per_group = v; consider(t); }
         }
     };
-    // 1. kernel and elements per lane at default shapes
-    pv_tuning t{};
-    t.kernel = 1;
-    consider(t);
-    const bool compiled = l->family != pv::FAM_GENERIC;
-    if (compiled) {
-        const int es[2] = {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4};
-        for (int e : es) {
-            t = pv_tuning{};
-            t.kernel = 2;
-            t.elems_per_lane = e;
-            consider(t);
-        }
-    }
-    if (best.kernel == 2) {
-        // 2. strip height, 3. planes per walk, 4. workgroups per XCD
-        for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
-        const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
-        for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
-        for (int v : {32, 64, 96, 128}) { t = best; t.groups_per_xcd = v; consider(t); }
-    } else {
-        for (int v : {32, 64}) { t = best; t.tiles_per_group = v; consider(t); }
+    pv_tuning best{}, best_acc{};
+    double best_ms = 0.0, best_acc_ms = 0.0;
+    search(best, best_ms);
+    if (herr == hipSuccess) {
+        slot = best;
+        series = true;
+        search(best_acc, best_acc_ms);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (herr != hipSuccess) {
         slot = saved;
+        slot_acc = saved_acc;
         return hip_fail(herr, "autotune");
     }
     slot = best;
-    if (cache_path) cache_append(cache_path, key, best, best_ms);
+    slot_acc = best_acc;
+    if (cache_path) cache_append(cache_path, key, best, best_acc, best_ms);
     if (out) *out = best;
     if (ms_out) *ms_out = best_ms;
     return PV_OK;

@@ -1212,7 +1212,17 @@ hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
         if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
         if (p.ep == PLAIN) return launch_staged<P, T, VT, E, PLAIN>(p, num_cus, s);
     }
-    return launch_staged<P, T, VT, E, 0u>(p, num_cus, s);
+    if constexpr (sizeof(T) == 8 && E == 2) {
+        // the run-time epilogue at two complex128 elements per lane needs more
+        // than 256 VGPRs: one element per lane, default walk and workgroups
+        SweepParams q = p;
+        q.st_C = q.st_Bm = q.st_G8 = 0;
+        const hipError_t e = launch_staged<P, T, VT, 1, 0u>(q, num_cus, s);
+        p.grid = q.grid;
+        return e;
+    } else {
+        return launch_staged<P, T, VT, E, 0u>(p, num_cus, s);
+    }
 }
 
 // Epilogues the staged kernel takes by default: plain sweeps, the Chebyshev
@@ -1565,6 +1575,19 @@ int64_t sweep_grid_max(const int64_t L[3], int n_orb, int nb) {
 }
 
 hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s) {
+    if ((p.ep & (EP_ACC_ADD | EP_ACC_INIT)) && p.acc_kernel > 0) {
+        // series steps: their own launch shape (an extra stream changes the best one)
+        SweepParams q = p;
+        q.kernel = p.acc_kernel;
+        q.st_E = p.acc_E;
+        q.st_C = p.acc_C;
+        q.st_Bm = p.acc_Bm;
+        q.st_G8 = p.acc_G8;
+        q.acc_kernel = 0;
+        const hipError_t e = launch_sweep(q, num_cus, s);
+        p.grid = q.grid;
+        return e;
+    }
     switch (p.family) {
         case FAM_TI: return launch_family<PatTI>(p, num_cus, s);
         case FAM_GRAPHENE2: return launch_family<PatGraphene2>(p, num_cus, s);

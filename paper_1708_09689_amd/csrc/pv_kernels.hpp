@@ -70,6 +70,9 @@ struct SweepParams {
     int kernel;             // 0 = choose, 1 = direct, 2 = staged
     int st_E, st_C, st_Bm, st_G8;   // staged kernel: elements per lane, planes per walk,
                                     // strip height, workgroups per XCD (0 = heuristic)
+    // launch shape of series steps (EP_ACC_ADD) when acc_kernel > 0, else
+    // the fields above
+    int acc_kernel, acc_E, acc_C, acc_Bm, acc_G8;
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;

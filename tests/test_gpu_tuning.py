@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_1708_09689_amd as pv  # noqa: E402
-from oracle import spmmv  # noqa: E402
+from oracle import chebtp, spmmv  # noqa: E402
 import workloads as W  # noqa: E402
 
 from gpu_common import Case, dev, host, rel_err  # noqa: E402
@@ -109,6 +109,7 @@ def test_autotune_applies_and_caches(tmp_path):
     assert shape["kernel"] in (1, 2)
     lines = cache.read_text().strip().splitlines()
     assert len(lines) == 1 and '"key": "family=1 orb=4 L=24x24x16' in lines[0]
+    assert '"acc_kernel": ' in lines[0]          # the series step's own shape
     # a fresh lattice of the same shape takes the cached entry without timing
     c2 = Case("ti", (24, 24, 16), (1, 1, 1), Wd=1.0)
     shape2, ms2 = pv.pv_autotune(c2.lat, 4, pv.PV_C128, cache_path=str(cache))
@@ -119,3 +120,8 @@ def test_autotune_applies_and_caches(tmp_path):
     y = torch.empty((c2.D, 4), dtype=torch.complex128, device="cuda")
     pv.pv_spmmv(c2.lat, dev(x), y, 0.25, 0.0, 0.0)
     assert rel_err(host(y), spmmv.spmmv(c2.H, x, 0.25, 0.0, 0.0)) < 1e-13
+    # and the oracle's Chebyshev series through the series step's shape
+    g = W.generator(8, 2, 4)
+    coef = g.standard_normal(12) + 1j * g.standard_normal(12)
+    pv.pv_cheb_series(c2.lat, dev(x), y, 7.0, 0.1, coef)
+    assert rel_err(host(y), chebtp.cheb_series(c2.H, x, 7.0, 0.1, coef)) < 1e-12
