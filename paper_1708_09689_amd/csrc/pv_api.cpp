@@ -1214,7 +1214,9 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
             if (herr != hipSuccess) return;
             double ms = 0;
             herr = measure(t, ms);
-            if (herr == hipSuccess && ms < best_ms) {
+            // a candidate must beat the incumbent by 1% (timing noise would
+            // otherwise flip between near-equal shapes from run to run)
+            if (herr == hipSuccess && ms < 0.99 * best_ms) {
                 best_ms = ms;
                 best = t;
             }
