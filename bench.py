@@ -38,7 +38,10 @@ A_SCALE, B_SHIFT = 7.0, 0.0
 # (profiles/*_counters.txt), with the launch shape the counters were taken
 # with; other shapes and (dtype, nb) pairs without a counter run report null.
 _STAGED = {"kernel": 2, "walk_planes": 0, "strip_rows": 0, "groups_per_xcd": 0, "tiles_per_group": 0, "slab_rows": 0}
-COUNTED_TRAFFIC = {}
+COUNTED_TRAFFIC = {
+    ("c128", 32): (dict(_STAGED, elems_per_lane=2, strip_rows=32, groups_per_xcd=32), 35_126_000_000),
+    ("c64", 16): (dict(_STAGED, elems_per_lane=2), 8_198_000_000),
+}
 
 
 def bytes_per_step(n_rows: int, n_sites: int, nb: int, dtype: str) -> int:
