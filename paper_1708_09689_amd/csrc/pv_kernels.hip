@@ -646,10 +646,10 @@ struct StagedCtx {
     // per walk: byte offsets inside a row of this lane's ring chunks (x
     // wrapped; open boundaries are applied when computing), row chunks and
     // field entries (clamped into the row)
-    uint32_t roff[S::RCH];
-    uint32_t soff[S::TCH];
-    uint32_t voff[E];
-    int vshift;      // element -> field entry: log2 of elements per site or per orbital row
+    uint32_t roff[S::RCH] = {};
+    uint32_t soff[S::TCH] = {};
+    uint32_t voff[E] = {};
+    int vshift = 0;  // element -> field entry: log2 of elements per site or per orbital row
 
     __device__ __forceinline__ int64_t row_of(int mm, int ww) const {
         return P::DIM == 3 ? (int64_t)ww * a.Ly + mm : (int64_t)ww;
@@ -994,9 +994,9 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
 // workgroups [inst_block0[i], inst_block0[i+1]), a multiple of 8 starting at
 // a multiple of 8, split into its 8 XCD parts like a single-lattice launch.
 template <class P, typename T, typename VT, int E, unsigned EPM>
-__global__ __launch_bounds__(kBlock) void batch_staged_kernel(const KArgs<T, VT>* __restrict__ table,
-                                                              const int* __restrict__ block_inst,
-                                                              const int* __restrict__ inst_block0) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_STAGED_WAVES_PER_EU)))
+void batch_staged_kernel(const KArgs<T, VT>* __restrict__ table, const int* __restrict__ block_inst,
+                         const int* __restrict__ inst_block0) {
     const int b = blockIdx.x;
     const int i = __builtin_amdgcn_readfirstlane(block_inst[b]);
     const int b0 = __builtin_amdgcn_readfirstlane(inst_block0[i]);
