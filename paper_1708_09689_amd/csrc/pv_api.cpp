@@ -18,6 +18,8 @@
 #include "pv_kernels.hpp"
 #include "pvdtm.h"
 
+static_assert(pv::PV_MAX_TERMS_K == PV_MAX_TERMS, "kernel-side stencil term limit");
+
 namespace {
 
 thread_local std::string g_err;
@@ -155,7 +157,28 @@ void choose_family(pv_lattice& l) {
     if (l.n_terms)
         std::memcpy(l.packed.data(), l.blocks.data(), sizeof(double) * l.n_terms * NO * NO * 2);
     std::memcpy(&l.packed[(size_t)l.n_terms * NO * NO * 2], l.onsite.data(), sizeof(double) * NO * NO * 2);
+    // The generic kernel walks the nonzero entries of each block row:
+    // offsets [n_terms][3], then row starts [(n_terms + 1) NO + 1] and the
+    // column of every entry; the entry values follow the dense blocks in
+    // `packed`.  Term n_terms is the on-site block without its diagonal.
     l.packed_offs = l.offsets;
+    std::vector<int> ptr(1, 0), col;
+    std::vector<double> val;
+    for (int t = 0; t <= l.n_terms; ++t)
+        for (int o = 0; o < NO; ++o) {
+            for (int q = 0; q < NO; ++q) {
+                if (t == l.n_terms && q == o) continue;
+                const double* e = &l.packed[(((size_t)t * NO + o) * NO + q) * 2];
+                if (e[0] == 0.0 && e[1] == 0.0) continue;
+                col.push_back(q);
+                val.push_back(e[0]);
+                val.push_back(e[1]);
+            }
+            ptr.push_back(int(col.size()));
+        }
+    l.packed_offs.insert(l.packed_offs.end(), ptr.begin(), ptr.end());
+    l.packed_offs.insert(l.packed_offs.end(), col.begin(), col.end());
+    l.packed.insert(l.packed.end(), val.begin(), val.end());
 }
 
 pv_status ensure_device(pv_lattice* l) {

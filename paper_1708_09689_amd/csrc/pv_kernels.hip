@@ -410,6 +410,26 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
     int dq[NS > 0 ? NS : 1];
     slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
 
+    // generic stencils: the nonzero entries of every block row (row starts,
+    // columns, values; the host packs them after the offsets and the dense
+    // blocks), staged in LDS once per workgroup
+    constexpr int GMAX = (PV_MAX_TERMS_K + 1) * NO * NO;
+    __shared__ int g_ptr[P::FAMILY == FAM_GENERIC ? (PV_MAX_TERMS_K + 1) * NO + 1 : 1];
+    __shared__ int g_col[P::FAMILY == FAM_GENERIC ? GMAX : 1];
+    __shared__ cplx<T> g_val[P::FAMILY == FAM_GENERIC ? GMAX : 1];
+    if constexpr (P::FAMILY == FAM_GENERIC) {
+        const int nptr = (a.n_terms + 1) * NO + 1;
+        const int* gp = a.offs + 3 * a.n_terms;
+        const int nnz = gp[nptr - 1];
+        const double* gv = a.coef + (size_t)(a.n_terms + 1) * NO * NO * 2;
+        for (int i = tid; i < nptr; i += kBlock) g_ptr[i] = gp[i];
+        for (int i = tid; i < nnz; i += kBlock) {
+            g_col[i] = gp[nptr + i];
+            g_val[i] = cplx<T>{T(gv[2 * i]), T(gv[2 * i + 1])};
+        }
+        __syncthreads();
+    }
+
     constexpr uint32_t ES = sizeof(cplx<T>);
     for (int64_t t = t0; t < t1; ++t) {
         // tile -> (row, x-tile): uniform over the workgroup.  Part k is swept
@@ -478,6 +498,7 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
                 mac<T>(hr, hi, S.kind[j], cre[j], cim[j], nv[j]);
             });
         } else {
+            // nonzero entries only; the loads of a term are issued together
             const int own = xe - o * nb;            // orbital-0 element of this site and column
             for (int tb = 0; tb < a.n_terms; ++tb) {
                 const int dy = a.offs[3 * tb + 1], dz = a.offs[3 * tb + 2];
@@ -486,14 +507,18 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
                 const cplx<T>* prow = rok ? a.x + (int64_t)nrow * a.rowel : a.zero_row;
                 int dxe;
                 const bool ok = x_shift(a, x, a.offs[3 * tb], dxe);
-                const double* cb = a.coef + ((size_t)tb * NO + o) * NO * 2;
-                for (int q = 0; q < NO; ++q)
-                    mac<T>(hr, hi, CC, T(cb[2 * q]), T(cb[2 * q + 1]),
-                           zero_unless(ok, ld_row(prow, uint32_t(own + dxe + q * nb) * ES)));
+                const int e0 = g_ptr[tb * NO + o], ne = g_ptr[tb * NO + o + 1] - e0;
+                cplx<T> v[NO];
+#pragma unroll
+                for (int k = 0; k < NO; ++k)
+                    if (k < ne) v[k] = ld_row(prow, uint32_t(own + dxe + g_col[e0 + k] * nb) * ES);
+#pragma unroll
+                for (int k = 0; k < NO; ++k)
+                    if (k < ne) mac<T>(hr, hi, CC, g_val[e0 + k].re, g_val[e0 + k].im, zero_unless(ok, v[k]));
             }
-            const double* cb = a.coef + ((size_t)a.n_terms * NO + o) * NO * 2;
-            for (int q = 0; q < NO; ++q)
-                if (q != o) mac<T>(hr, hi, CC, T(cb[2 * q]), T(cb[2 * q + 1]), ld_row(xrow, uint32_t(own + q * nb) * ES));
+            const int e0 = g_ptr[a.n_terms * NO + o], e1 = g_ptr[a.n_terms * NO + o + 1];
+            for (int e = e0; e < e1; ++e)
+                mac<T>(hr, hi, CC, g_val[e].re, g_val[e].im, ld_row(xrow, uint32_t(own + g_col[e] * nb) * ES));
         }
         const int64_t site = (int64_t)row * a.Lx + x;
         const int64_t gidx = a.ggroup == nb ? site * NO + o : site;

@@ -10,6 +10,7 @@
 namespace pv {
 
 constexpr int PV_MAX_NB_K = 64;
+constexpr int PV_MAX_TERMS_K = 26;   // neighbour offsets per stencil (the C ABI's limit)
 // Largest site (n_orb * nb elements) the staged sweep kernel takes; wider
 // blocks use the direct kernel.
 constexpr int STAGED_MAX_SITE = 128;

@@ -118,10 +118,35 @@ def test_sweep_is_deterministic():
     assert torch.equal(y1, y2) and torch.equal(d1, d2)
 
 
+def _explicit_matrix(L, per, no, offsets, blocks, E0, V, pot_orbital):
+    """Sparse H straight from a stencil definition: (H x)[s] += B_t x[s + d_t],
+    on-site block plus the field (per orbital row or per site)."""
+    import scipy.sparse as sp
+    from oracle import lattice as olat_mod
+    ol = olat_mod.Lattice(L, per, no)
+    rows, cols, vals = [], [], []
+    s = np.arange(ol.n_sites)
+    for o, B in zip(offsets, blocks):
+        nbr, ok = ol.shift(s, o)
+        for a in range(no):
+            for b in range(no):
+                rows.append(s[ok] * no + a)
+                cols.append(nbr[ok] * no + b)
+                vals.append(np.full(ok.sum(), B[a, b]))
+    for a in range(no):
+        for b in range(no):
+            fv = (V[s * no + a] if pot_orbital else V[s]) if a == b else 0.0
+            rows.append(s * no + a)
+            cols.append(s * no + b)
+            vals.append(np.full(s.size, E0[a, b]) + fv)
+    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(ol.n_rows, ol.n_rows)).tocsr()
+    return ol, H
+
+
 def test_generic_family_random_hermitian_stencil():
     """A stencil with diagonal offsets and dense random blocks (no compiled
     family): generic kernel against the explicit matrix of the same stencil."""
-    import scipy.sparse as sp
     g = np.random.default_rng(11)
     offs = [(1, 0, 0), (0, 1, 0), (1, 1, 0), (1, -1, 1), (0, 0, 1)]
     no = 2
@@ -137,28 +162,49 @@ def test_generic_family_random_hermitian_stencil():
     L, per = (6, 5, 4), (1, 0, 1)
     lat = pv.Lattice(L, per, st)
     assert lat.family == 0
-    from oracle import lattice as olat_mod
-    ol = olat_mod.Lattice(L, per, no)
-    V = W.uniform_potential(ol.n_rows, 1.0, W.generator(3, 1))
+    V = W.uniform_potential(L[0] * L[1] * L[2] * no, 1.0, W.generator(3, 1))
     lat.set_potential(dev(V))
-    # explicit matrix straight from the stencil definition (H x)[s] += B_t x[s + d_t]
-    rows, cols, vals = [], [], []
-    s = np.arange(ol.n_sites)
-    for o, B in zip(offsets, blocks):
-        nbr, ok = ol.shift(s, o)
-        for a in range(no):
-            for b in range(no):
-                rows.append(s[ok] * no + a)
-                cols.append(nbr[ok] * no + b)
-                vals.append(np.full(ok.sum(), B[a, b]))
-    for a in range(no):
-        for b in range(no):
-            rows.append(s * no + a)
-            cols.append(s * no + b)
-            vals.append(np.full(s.size, E0[a, b] + (V[s * no + a] if a == b else 0)))
-    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                      shape=(ol.n_rows, ol.n_rows)).tocsr()
+    ol, H = _explicit_matrix(L, per, no, offsets, blocks, E0, V, True)
     x = W.gaussian_block(ol.n_rows, 8, W.generator(3, 2))
     y = torch.empty((ol.n_rows, 8), dtype=torch.complex128, device="cuda")
     pv.pv_spmmv(lat, dev(x), y, 1.0, 0.3, 0.0)
     assert rel_err(host(y), spmmv.spmmv(H, x, 1.0, 0.3, 0.0)) < 1e-13
+
+
+@pytest.mark.parametrize("no,nb,dtype", [(4, 4, np.complex128), (4, 1, np.complex128), (1, 8, np.complex128),
+                                         (4, 16, np.complex64)])
+def test_generic_family_sparse_blocks(no, nb, dtype):
+    """Generic stencils whose blocks are mostly zero, with rows of different
+    entry counts (some empty) and an on-site block with off-diagonal entries:
+    the kernel walks only the nonzero entries.  Chebyshev step with dots."""
+    g = np.random.default_rng(12 + no + nb)
+    offs = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, -1)]
+    blocks, offsets = [], []
+    for i, o in enumerate(offs):
+        B = (g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))) * (g.random((no, no)) < 0.4)
+        if no > 1:
+            B[i % no, :] = 0.0                       # an empty row
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = (g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))) * (g.random((no, no)) < 0.5)
+    E0 = E0 + E0.conj().T
+    st = {"dim": 3, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    L, per = (7, 5, 4), (1, 1, 0)
+    lat = pv.Lattice(L, per, st)
+    assert lat.family == 0
+    n_sites = L[0] * L[1] * L[2]
+    V = W.uniform_potential(n_sites, 1.0, W.generator(4, 1))
+    vdt = np.float64 if dtype == np.complex128 else np.float32
+    lat.set_potential(dev(V.astype(vdt)))
+    ol, H = _explicit_matrix(L, per, no, offsets, blocks, E0, V.astype(vdt).astype(np.float64), False)
+    x = W.gaussian_block(ol.n_rows, nb, W.generator(4, 2), dtype)
+    z = W.gaussian_block(ol.n_rows, nb, W.generator(4, 3), dtype)
+    y = dev(z.copy())
+    d = host(pv.pv_spmmv(lat, dev(x), y, 0.4, 0.2, -1.0, z=y, dot_flags=7))
+    x64, z64 = x.astype(np.complex128), z.astype(np.complex128)
+    ref = spmmv.spmmv(H, x64, 0.4, 0.2, -1.0, z64)
+    tol = 1e-13 if dtype == np.complex128 else 2e-6
+    assert rel_err(host(y).astype(np.complex128), ref) < tol
+    xx = np.sum(np.abs(x64) ** 2, axis=0)
+    assert np.abs(d[:, 0] - xx).max() < (1e-12 if dtype == np.complex128 else 1e-5) * xx.max()
