@@ -330,6 +330,67 @@ def bench_weyl_spectral(pv, torch, W, dev, nk=64, M=256):
             "A_E0_along_kx_first8": [round(v, 4) for v in A0[:8]]}
 
 
+def _dsl_program(st: dict, extra=()) -> str:
+    """DSL text (Sec. 3.2 format) of a stencil dict plus extra (offset, block)
+    terms, with the per-site field as variable coefficient 0."""
+    def num(z):
+        z = complex(z)
+        if z.imag == 0.0:
+            return repr(z.real)
+        if z.real == 0.0:
+            return f"{z.imag!r}i"
+        return f"{z.real!r}{z.imag:+}i"
+    no = int(st["n_orb"])
+    terms = list(zip([tuple(int(v) for v in o) for o in np.asarray(st["offsets"]).reshape(-1, 3)],
+                     np.asarray(st["blocks"]).reshape(-1, no, no))) + list(extra)
+    out = [f"dim {int(st['dim'])}", f"size {no}", "n_coeff_variable 1"]
+    for off, B in terms:
+        out.append("nn " + " ".join(str(v) for v in off))
+        for k in range(no):
+            out.append(f"l{k}; " + "; ".join(f"{q}|{num(B[k, q])}" for q in range(no) if B[k, q] != 0))
+    out.append("nn 0 0 0")
+    E = np.asarray(st["onsite"]).reshape(no, no)
+    for k in range(no):
+        ent = [f"{q}|{num(E[k, q])}" for q in range(no) if E[k, q] != 0] + [f"{k}|v|0"]
+        out.append(f"l{k}; " + "; ".join(ent))
+    return "\n".join(out) + "\n"
+
+
+def bench_dsl(pv, torch, W, dev, nb=16):
+    """Stencils given as DSL text: the TI program (recognised as the compiled
+    TI family) and the TI plus next-nearest-neighbour hops -(t'/2) G1 along
+    (+-1, +-1, 0), t' = 0.1 (no compiled family: the generic kernel), on the
+    256x256x64 lattice, Chebyshev step with dots, complex128."""
+    ti = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    G1 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
+    nnn = [((1, 1, 0), -0.05 * G1), ((-1, -1, 0), -0.05 * G1), ((1, -1, 0), -0.05 * G1), ((-1, 1, 0), -0.05 * G1)]
+    out = {}
+    for name, text in (("ti", _dsl_program(ti)), ("ti_nnn_generic", _dsl_program(ti, nnn))):
+        st = pv.pv_dsl_stencil(text)
+        lat = pv.Lattice(L_BENCH, (1, 1, 1), st)
+        lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 2.0,
+                                                               W.generator(WORKLOAD_INDEX, W.STREAM_POTENTIAL))).to(dev))
+        w0 = W.random_phase_device(lat.n_rows, nb, 10 * WORKLOAD_INDEX + nb, dev)
+        w1 = torch.empty_like(w0)
+        dots = torch.empty((nb, 4), dtype=torch.float64, device=dev)
+        pv.pv_spmmv(lat, w0, w1, 1.0 / A_SCALE, B_SHIFT, 0.0, nb=nb)
+        state = [w0, w1]
+
+        def step():
+            pv.pv_spmmv(lat, state[1], state[0], 2.0 / A_SCALE, B_SHIFT, -1.0, z=state[0],
+                        dot_flags=pv.PV_DOT_XX | pv.PV_DOT_XY, dots=dots, nb=nb)
+            state.reverse()
+        ms = _timed(torch, step, 10)
+        b = bytes_per_step(lat.n_rows, lat.n_sites, nb, "c128")
+        out[name] = {"family": "compiled TI" if lat.family == 1 else "generic", "terms": int(len(st["offsets"])),
+                     "ms_per_step": round(ms, 4), "GLUP/s": round(lat.n_rows * nb / (ms * 1e-3) / 1e9, 3),
+                     "GB/s": round(b / (ms * 1e-3) / 1e9, 1)}
+        del w0, w1, state
+        torch.cuda.empty_cache()
+    out["workload"] = f"TI 256x256x64 from DSL text, W=2, nb={nb}, complex128, Chebyshev step + dots"
+    return out
+
+
 def bench_fd(pv, torch, W, dev, half=0.05):
     """Interior eigenpairs near E = 0 of a TI slab like the paper's filter
     diagonalisation test cases: 240 x 240 x 6 sites, periodic x, y, open z
@@ -456,7 +517,8 @@ def main():
                          ("chebtp_graphene1024", lambda: bench_chebtp_graphene(pv, torch, W, dev)),
                          ("batched_kpm_96", lambda: bench_batch(pv, torch, W, dev)),
                          ("adjoint", lambda: bench_adjoint(pv, torch, W, dev)),
-                         ("weyl_spectral", lambda: bench_weyl_spectral(pv, torch, W, dev))):
+                         ("weyl_spectral", lambda: bench_weyl_spectral(pv, torch, W, dev)),
+                         ("dsl_stencils", lambda: bench_dsl(pv, torch, W, dev))):
             t0 = time.perf_counter()
             configs[name] = fn()
             torch.cuda.empty_cache()
