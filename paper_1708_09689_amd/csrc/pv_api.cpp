@@ -246,6 +246,18 @@ pv_status check_nb(int nb) {
     return PV_OK;
 }
 
+// A generic stencil fits the staged kernel (rows along z in an LDS ring with
+// an x halo, the y neighbours as side rows) when every offset with a y step
+// has no x or z step.
+int generic_stageable(const pv_lattice* l) {
+    if (l->family != pv::FAM_GENERIC || l->dim != 3) return 0;
+    for (int t = 0; t < l->n_terms; ++t) {
+        const int* d = &l->offsets[3 * t];
+        if (d[1] != 0 && (d[0] != 0 || d[2] != 0)) return 0;
+    }
+    return 1;
+}
+
 pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     pv::SweepParams p{};
     p.family = l->family;
@@ -266,6 +278,7 @@ pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     p.V = l->pot_mode ? l->V : nullptr;
     p.coef = l->d_coef;
     p.offs = l->d_offs;
+    p.generic_stageable = generic_stageable(l);
     return p;
 }
 
@@ -1225,7 +1238,7 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         return hipSuccess;
     };
     hipError_t herr = hipSuccess;
-    const bool compiled = l->family != pv::FAM_GENERIC;
+    const bool compiled = l->family != pv::FAM_GENERIC || generic_stageable(l);
     const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
     // coordinate search: 1. kernel and elements per lane at default shapes;
     // for the staged winner 2. strip height, 3. planes per walk, 4. workgroups

@@ -814,10 +814,25 @@ __host__ __device__ constexpr int staged_seg() {
     return Staged<T, E>::RCH * kBlock * Staged<T, E>::CE;
 }
 template <class P, typename T, int E>
+__host__ __device__ constexpr size_t staged_table_offset(bool acc) {
+    return (size_t(3 * staged_seg<T, E>() + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
+                Staged<T, E>::ES +
+            size_t(E * kBlock) * sizeof(T) + 15) / 16 * 16;
+}
+// Generic stencils also keep their block entries in LDS: values, then
+// offsets, row starts and columns.
+template <class P>
+struct StagedTable {
+    static constexpr int GMAX = (PV_MAX_TERMS_K + 1) * P::NO * P::NO;
+    static constexpr int NPTR = (PV_MAX_TERMS_K + 1) * P::NO + 1;
+    static constexpr int NINT = 3 * PV_MAX_TERMS_K + NPTR + GMAX;
+};
+template <class P, typename T, int E>
 __host__ __device__ constexpr size_t staged_lds_bytes_for(bool acc) {
-    return size_t(3 * staged_seg<T, E>() + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E>::TW) *
-               Staged<T, E>::ES +
-           size_t(E * kBlock) * sizeof(T);
+    return staged_table_offset<P, T, E>(acc) +
+           (P::FAMILY == FAM_GENERIC
+                ? StagedTable<P>::GMAX * sizeof(cplx<T>) + StagedTable<P>::NINT * sizeof(int)
+                : 0);
 }
 
 template <class P, typename T, typename VT, int E, unsigned EPM>
@@ -828,7 +843,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     using Set = typename Ctx::Set;
     constexpr int NO = P::NO;
     constexpr int NTR = Ctx::NTR;
-    static_assert(P::FAMILY != FAM_GENERIC, "staged sweeps need a compiled family");
+    constexpr bool GEN = P::FAMILY == FAM_GENERIC;
     extern __shared__ __align__(16) unsigned char smem[];
     const unsigned ep = EPM ? EPM : a.ep;
     const int tid = threadIdx.x;
@@ -847,14 +862,36 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     }
     const T alT = T(al), beT = T(be), gaT = T(ga);
     const T er = T(a.eta_re), ei = T(a.eta_im), e0r = T(a.eta0_re), e0i = T(a.eta0_im);
-    const T dgr = T(a.coef[(((size_t)P::NT * NO + o) * NO + o) * 2]);
-    const T dgi = T(a.coef[(((size_t)P::NT * NO + o) * NO + o) * 2 + 1]);
+    const int nt_on = GEN ? a.n_terms : P::NT;   // index of the on-site block
+    const T dgr = T(a.coef[(((size_t)nt_on * NO + o) * NO + o) * 2]);
+    const T dgi = T(a.coef[(((size_t)nt_on * NO + o) * NO + o) * 2 + 1]);
     static constexpr Slots<P> SL{};
     constexpr int NS = SL.n;
-    T cre[NS], cim[NS];
-    int dq[NS];
+    T cre[NS > 0 ? NS : 1], cim[NS > 0 ? NS : 1];
+    int dq[NS > 0 ? NS : 1];
     slot_coefficients<P, T, NS>(a.coef, o, nb, cre, cim, dq);
     double dxx = 0.0, dxr = 0.0, dxi = 0.0, dyy = 0.0;
+
+    // generic stencils: offsets and the nonzero entries of every block row
+    // (packed by the host after the offsets and the dense blocks) in LDS
+    using Tab = StagedTable<P>;
+    cplx<T>* g_val = reinterpret_cast<cplx<T>*>(smem + staged_table_offset<P, T, E>(ACC));
+    int* g_off = reinterpret_cast<int*>(g_val + Tab::GMAX);
+    int* g_ptr = g_off + 3 * PV_MAX_TERMS_K;
+    int* g_col = g_ptr + Tab::NPTR;
+    if constexpr (GEN) {
+        const int nptr = (a.n_terms + 1) * NO + 1;
+        const int* gp = a.offs + 3 * a.n_terms;
+        const int nnz = gp[nptr - 1];
+        const double* gv = a.coef + (size_t)(a.n_terms + 1) * NO * NO * 2;
+        for (int i = tid; i < 3 * a.n_terms; i += kBlock) g_off[i] = a.offs[i];
+        for (int i = tid; i < nptr; i += kBlock) g_ptr[i] = gp[i];
+        for (int i = tid; i < nnz; i += kBlock) {
+            g_col[i] = gp[nptr + i];
+            g_val[i] = cplx<T>{T(gv[2 * i]), T(gv[2 * i + 1])};
+        }
+        __syncthreads();
+    }
 
     Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, (S::TW + 2 * site) / S::CE, 0, 0};
     cx.vshift = a.pot_mode == 1 ? a.logsite : a.lognb;
@@ -936,30 +973,48 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 const T d = dgr - beT + vs;
                 T hr = d * xc.re - dgi * xc.im;
                 T hi = d * xc.im + dgi * xc.re;
-                sfor<NS>([&](auto jj) {
-                    constexpr int jx = decltype(jj)::value;
-                    constexpr int t = SL.t[jx];
-                    const int dqj = SL.same[jx] ? 0 : dq[jx];   // constant 0 for own-orbital slots
-                    cplx<T> v;
-                    if constexpr (t == P::NT) {
-                        v = r0[l + dqj];
-                    } else {
-                        constexpr int tt = t < P::NT ? t : 0;
-                        constexpr int dx = P::off[tt][0];
-                        constexpr int dm = P::DIM == 3 ? P::off[tt][1] : 0;
-                        constexpr int dw = P::DIM == 3 ? P::off[tt][2] : P::off[tt][1];
-                        if constexpr (dm == 0) {
-                            const cplx<T>* rw = dw < 0 ? rm : (dw > 0 ? rp : r0);
-                            v = rw[l + dx * site + dqj];
-                            if constexpr (dx < 0) v = zero_unless(xlo, v);
-                            if constexpr (dx > 0) v = zero_unless(xhi, v);
-                        } else {
-                            static_assert(dx == 0 && dw == 0, "side rows carry no x or w offset");
-                            v = cx.tra[(dm < 0 ? 0 : S::TW) + l + dqj];
-                        }
+                if constexpr (GEN) {
+                    // runtime terms: rows (m, w + dw) from the ring with the x
+                    // halo, rows (m -+ 1, w) from the side rows (the host admits
+                    // no offset with a y step and an x or z step)
+                    for (int tb = 0; tb < a.n_terms; ++tb) {
+                        const int dx = g_off[3 * tb], dm = g_off[3 * tb + 1], dw = g_off[3 * tb + 2];
+                        const cplx<T>* rw = dm != 0 ? cx.tra + (dm < 0 ? 0 : S::TW) + l
+                                                    : (dw < 0 ? rm : (dw > 0 ? rp : r0)) + l + dx * site;
+                        const bool ok = dx < 0 ? xlo : (dx > 0 ? xhi : true);
+                        const int e0 = g_ptr[tb * NO + o], e1 = g_ptr[tb * NO + o + 1];
+                        for (int e = e0; e < e1; ++e)
+                            mac<T>(hr, hi, CC, g_val[e].re, g_val[e].im, zero_unless(ok, rw[(g_col[e] - o) * nb]));
                     }
-                    mac<T>(hr, hi, SL.kind[jx], cre[jx], cim[jx], v);
-                });
+                    const int e0 = g_ptr[a.n_terms * NO + o], e1 = g_ptr[a.n_terms * NO + o + 1];
+                    for (int e = e0; e < e1; ++e)
+                        mac<T>(hr, hi, CC, g_val[e].re, g_val[e].im, r0[l + (g_col[e] - o) * nb]);
+                } else {
+                    sfor<NS>([&](auto jj) {
+                        constexpr int jx = decltype(jj)::value;
+                        constexpr int t = SL.t[jx];
+                        const int dqj = SL.same[jx] ? 0 : dq[jx];   // constant 0 for own-orbital slots
+                        cplx<T> v;
+                        if constexpr (t == P::NT) {
+                            v = r0[l + dqj];
+                        } else {
+                            constexpr int tt = t < P::NT ? t : 0;
+                            constexpr int dx = P::off[tt][0];
+                            constexpr int dm = P::DIM == 3 ? P::off[tt][1] : 0;
+                            constexpr int dw = P::DIM == 3 ? P::off[tt][2] : P::off[tt][1];
+                            if constexpr (dm == 0) {
+                                const cplx<T>* rw = dw < 0 ? rm : (dw > 0 ? rp : r0);
+                                v = rw[l + dx * site + dqj];
+                                if constexpr (dx < 0) v = zero_unless(xlo, v);
+                                if constexpr (dx > 0) v = zero_unless(xhi, v);
+                            } else {
+                                static_assert(dx == 0 && dw == 0, "side rows carry no x or w offset");
+                                v = cx.tra[(dm < 0 ? 0 : S::TW) + l + dqj];
+                            }
+                        }
+                        mac<T>(hr, hi, SL.kind[jx], cre[jx], cim[jx], v);
+                    });
+                }
                 xs_[k] = xc;
                 yr[k] = hr;
                 yi[k] = hi;
@@ -1271,17 +1326,21 @@ int staged_elems(const SweepParams& p) {
     return p.dtype == 0 ? 1 : 2;
 }
 
-// Sweep kernel of a launch: the staged kernel for compiled families when the
-// block is 16-byte aligned (its chunk loads), else the direct kernel.
+// Sweep kernel of a launch: the staged kernel for compiled families, and for
+// generic 3D stencils whose offsets with a y step have no x or z step, when
+// the block is 16-byte aligned (its chunk loads); else the direct kernel.
 // p.kernel (or PV_SWEEP) 1 forces direct, 2 staged; p.st_E (or PV_STAGED_E)
 // selects the elements per lane.
 template <class P, typename T, typename VT>
 hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
-    if constexpr (P::FAMILY != FAM_GENERIC) {
+    {
         static const int env_kernel = env_int("PV_SWEEP", 0);
         const int kind = p.kernel > 0 ? p.kernel : env_kernel;
         const bool aligned = ((reinterpret_cast<uintptr_t>(p.x) | reinterpret_cast<uintptr_t>(p.zero_row)) & 15) == 0;
-        if (aligned && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && staged_default(p)))) {
+        // generic stencils default to staged only on 3D lattices (walks along z)
+        const bool can = P::FAMILY != FAM_GENERIC || p.generic_stageable;
+        const bool dflt = staged_default(p) && (P::FAMILY != FAM_GENERIC || p.L[2] > 1);
+        if (can && aligned && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && dflt))) {
             const int e = staged_elems(p);
             if constexpr (sizeof(T) == 8)
                 return e == 2 ? launch_staged_ep<P, T, VT, 2>(p, num_cus, s) : launch_staged_ep<P, T, VT, 1>(p, num_cus, s);

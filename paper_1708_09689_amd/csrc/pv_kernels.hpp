@@ -63,12 +63,14 @@ struct SweepParams {
     double gx, gy;
     int grad_mode;
     const double* coef;   // device: [(n_terms + 1)][n_orb][n_orb][2], onsite last
-    const int* offs;      // device: [n_terms][3] (generic family only)
+    const int* offs;      // device (generic family only): [n_terms][3] offsets, then the
+                          // nonzero entries of every block row (row starts, columns)
     const double* colp;   // device: [nb][3] per-column alpha, beta, gamma or NULL
     const void* zero_row;   // device zeros, >= L[0]*n_orb*nb elements
     int slab_rows;          // rows per y-slab of the sweep order (direct kernel)
     int tpb;                // tiles per workgroup (direct kernel; 0 = heuristic)
     int kernel;             // 0 = choose, 1 = direct, 2 = staged
+    int generic_stageable;  // generic family: every offset with a y step has no x or z step
     int st_E, st_C, st_Bm, st_G8;   // staged kernel: elements per lane, planes per walk,
                                     // strip height, workgroups per XCD (0 = heuristic)
     // launch shape of series steps (EP_ACC_ADD) when acc_kernel > 0, else

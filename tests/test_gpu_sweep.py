@@ -171,14 +171,25 @@ def test_generic_family_random_hermitian_stencil():
     assert rel_err(host(y), spmmv.spmmv(H, x, 1.0, 0.3, 0.0)) < 1e-13
 
 
+GENERIC_OFFSETS = {
+    # a y step together with an x step: direct kernel only
+    "diagonal": [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, -1)],
+    # y steps alone, x and z steps combined: the staged kernel takes it too
+    "stageable": [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, -1), (1, 0, 1)],
+}
+
+
 @pytest.mark.parametrize("no,nb,dtype", [(4, 4, np.complex128), (4, 1, np.complex128), (1, 8, np.complex128),
-                                         (4, 16, np.complex64)])
-def test_generic_family_sparse_blocks(no, nb, dtype):
+                                         (4, 16, np.complex64), (2, 32, np.complex128)])
+@pytest.mark.parametrize("shape", ["diagonal", "stageable"])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel):
     """Generic stencils whose blocks are mostly zero, with rows of different
     entry counts (some empty) and an on-site block with off-diagonal entries:
-    the kernel walks only the nonzero entries.  Chebyshev step with dots."""
+    the kernels walk only the nonzero entries.  Chebyshev step with dots, on
+    the direct kernel and (where the offsets allow it) the staged one."""
     g = np.random.default_rng(12 + no + nb)
-    offs = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, -1)]
+    offs = GENERIC_OFFSETS[shape]
     blocks, offsets = [], []
     for i, o in enumerate(offs):
         B = (g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))) * (g.random((no, no)) < 0.4)
@@ -193,6 +204,8 @@ def test_generic_family_sparse_blocks(no, nb, dtype):
     L, per = (7, 5, 4), (1, 1, 0)
     lat = pv.Lattice(L, per, st)
     assert lat.family == 0
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    pv.pv_lattice_set_tuning(lat, code, nb, {"kernel": kernel})
     n_sites = L[0] * L[1] * L[2]
     V = W.uniform_potential(n_sites, 1.0, W.generator(4, 1))
     vdt = np.float64 if dtype == np.complex128 else np.float32
