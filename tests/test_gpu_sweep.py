@@ -221,3 +221,36 @@ def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel):
     assert rel_err(host(y).astype(np.complex128), ref) < tol
     xx = np.sum(np.abs(x64) ** 2, axis=0)
     assert np.abs(d[:, 0] - xx).max() < (1e-12 if dtype == np.complex128 else 1e-5) * xx.max()
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_generic_stageable_open_x_orbital_field_series(kernel):
+    """Staged generic path with an open x boundary, a per-orbital field and
+    the series epilogue (Chebyshev series of degree 9) against the oracle's
+    series on the explicit matrix."""
+    from oracle import chebtp
+    g = np.random.default_rng(31)
+    no = 2
+    offs = GENERIC_OFFSETS["stageable"]
+    blocks, offsets = [], []
+    for o in offs:
+        B = (g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))) * (g.random((no, no)) < 0.7)
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.3, 0.2 - 0.1j], [0.2 + 0.1j, -0.4]])
+    st = {"dim": 3, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_ORBITAL}
+    L, per = (9, 4, 5), (0, 1, 1)
+    lat = pv.Lattice(L, per, st)
+    assert lat.family == 0
+    nb = 4
+    pv.pv_lattice_set_tuning(lat, pv.PV_C128, nb, {"kernel": kernel})
+    V = W.uniform_potential(L[0] * L[1] * L[2] * no, 1.0, W.generator(5, 1))
+    lat.set_potential(dev(V))
+    ol, H = _explicit_matrix(L, per, no, offsets, blocks, E0, V, True)
+    a = float(np.abs(H).sum(axis=1).max()) * 1.05
+    X = W.gaussian_block(ol.n_rows, nb, W.generator(5, 2))
+    coef = W.generator(5, 3).standard_normal(10) + 1j * W.generator(5, 4).standard_normal(10)
+    Y = torch.empty((ol.n_rows, nb), dtype=torch.complex128, device="cuda")
+    pv.pv_cheb_series(lat, dev(X), Y, a, 0.1, coef)
+    assert rel_err(host(Y), chebtp.cheb_series(H, X, a, 0.1, coef)) < 1e-12
