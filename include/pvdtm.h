@@ -426,6 +426,10 @@ pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
  *   tiles_per_group  direct: row tiles per workgroup, up to 64 (values below
  *                    the default are raised to it)
  *   slab_rows        direct: y rows per slab of the sweep order
+ *   workgroup_size   staged: lanes per workgroup, 256 (0: default) or 512
+ *                    (a tile twice as long: half the relative x halo;
+ *                    compiled stencil families, the Chebyshev, series and
+ *                    plain sweeps)
  * The shape changes speed only: every shape computes the same result up to
  * the summation order of the fused dot products.
  */
@@ -437,6 +441,7 @@ typedef struct pv_tuning {
     int groups_per_xcd;
     int tiles_per_group;
     int slab_rows;
+    int workgroup_size;
 } pv_tuning;
 
 /* Set (t != NULL) or reset to defaults (t == NULL) the shape used for

@@ -48,7 +48,7 @@ class pv_lattice_desc(ctypes.Structure):
 
 class pv_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("kernel", "elems_per_lane", "walk_planes", "strip_rows",
-                                            "groups_per_xcd", "tiles_per_group", "slab_rows")]
+                                            "groups_per_xcd", "tiles_per_group", "slab_rows", "workgroup_size")]
 
 
 TUNING_FIELDS = [f[0] for f in pv_tuning._fields_]

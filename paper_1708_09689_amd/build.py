@@ -9,6 +9,7 @@ paper_1708_09689_amd/lib/libpvdtm.so.
 
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import shutil
@@ -44,14 +45,20 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp"))):
-        obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
-        if verbose:
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in srcs]
+    cmds = [[hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj] for src, obj in zip(srcs, objs)]
+    if verbose:
+        for cmd in cmds:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    # one compiler per translation unit, in parallel (the stencil families
+    # are separate units); MAX_JOBS caps the number of jobs
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1), 16))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for cmd, done in zip(cmds, pool.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds)):
+            if done.returncode != 0:
+                sys.stderr.write(done.stdout + done.stderr)
+                raise subprocess.CalledProcessError(done.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -334,9 +334,11 @@ pv_status fill_traversal(pv_lattice* l, int dtype, int nb, pv::SweepParams& p) {
     p.st_C = t.walk_planes;
     p.st_Bm = t.strip_rows;
     p.st_G8 = t.groups_per_xcd;
+    p.st_nt = t.workgroup_size;
     const pv_tuning& ta = l->tune_acc[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
     p.acc_kernel = ta.kernel;
     p.acc_E = ta.elems_per_lane;
+    p.acc_nt = ta.workgroup_size;
     p.acc_C = ta.walk_planes;
     p.acc_Bm = ta.strip_rows;
     p.acc_G8 = ta.groups_per_xcd;
@@ -1051,6 +1053,8 @@ pv_status check_tuning(int dtype, const pv_tuning& t) {
         return fail(PV_ERR_INVALID_ARG, "tuning.groups_per_xcd = %d (0..256)", t.groups_per_xcd);
     if (t.tiles_per_group < 0 || t.tiles_per_group > 64)
         return fail(PV_ERR_INVALID_ARG, "tuning.tiles_per_group = %d (0..64)", t.tiles_per_group);
+    if (t.workgroup_size != 0 && t.workgroup_size != 256 && t.workgroup_size != 512)
+        return fail(PV_ERR_INVALID_ARG, "tuning.workgroup_size = %d (0, 256 or 512)", t.workgroup_size);
     return PV_OK;
 }
 
@@ -1070,12 +1074,13 @@ std::string tune_key(const pv_lattice* l, int dtype, int nb) {
     return buf;
 }
 
-const char* const kTuneFields[7] = {"kernel",          "elems_per_lane",  "walk_planes", "strip_rows",
-                                    "groups_per_xcd", "tiles_per_group", "slab_rows"};
+constexpr int kNumTuneFields = 8;
+const char* const kTuneFields[kNumTuneFields] = {"kernel",         "elems_per_lane",  "walk_planes", "strip_rows",
+                                                 "groups_per_xcd", "tiles_per_group", "slab_rows",   "workgroup_size"};
 
 int* tune_field(pv_tuning& t, int i) {
-    int* f[7] = {&t.kernel, &t.elems_per_lane, &t.walk_planes, &t.strip_rows,
-                 &t.groups_per_xcd, &t.tiles_per_group, &t.slab_rows};
+    int* f[kNumTuneFields] = {&t.kernel,         &t.elems_per_lane,  &t.walk_planes, &t.strip_rows,
+                              &t.groups_per_xcd, &t.tiles_per_group, &t.slab_rows,   &t.workgroup_size};
     return f[i];
 }
 
@@ -1093,7 +1098,7 @@ bool cache_lookup(const char* path, const std::string& key, pv_tuning& t, pv_tun
         pv_tuning r[2] = {};
         bool ok = true;
         for (int h = 0; h < 2 && ok; ++h)
-            for (int i = 0; i < 7 && ok; ++i) {
+            for (int i = 0; i < kNumTuneFields && ok; ++i) {
                 const std::string name = std::string("\"") + (h ? "acc_" : "") + kTuneFields[i] + "\": ";
                 const char* q = std::strstr(line, name.c_str());
                 if (!q) { ok = false; break; }
@@ -1115,7 +1120,7 @@ void cache_append(const char* path, const std::string& key, const pv_tuning& t, 
     std::fprintf(f, "{\"key\": \"%s\"", key.c_str());
     pv_tuning c[2] = {t, ta};
     for (int h = 0; h < 2; ++h)
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < kNumTuneFields; ++i)
             std::fprintf(f, ", \"%s%s\": %d", h ? "acc_" : "", kTuneFields[i], *tune_field(c[h], i));
     std::fprintf(f, ", \"ms\": %.6f}\n", ms);
     std::fclose(f);
@@ -1270,6 +1275,7 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
             }
         }
         if (best.kernel == 2) {
+            if (l->family != pv::FAM_GENERIC) { t = best; t.workgroup_size = 512; consider(t); }
             for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
             for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
             for (int v : {32, 64, 96, 128}) { t = best; t.groups_per_xcd = v; consider(t); }

@@ -1,0 +1,19 @@
+// Sweep kernels of the ti stencil family (one translation unit per family).
+#include "pv_sweep.hpp"
+
+namespace pv {
+
+hipError_t launch_sweep_ti(SweepParams& p, int num_cus, hipStream_t s) {
+    return launch_family<PatTI>(p, num_cus, s);
+}
+
+hipError_t batch_fill_record_ti(const SweepParams& p, int staged, void* dst, int* nblocks) {
+    return batch_fill_record_fam<PatTI>(p, staged, dst, nblocks);
+}
+
+hipError_t launch_batch_sweep_ti(const SweepParams& p, int staged, const void* table, const int* block_inst,
+                                  const int* inst_block0, int grid, hipStream_t s) {
+    return launch_batch_sweep_fam<PatTI>(p, staged, table, block_inst, inst_block0, grid, s);
+}
+
+}  // namespace pv

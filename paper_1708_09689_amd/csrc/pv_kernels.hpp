@@ -73,9 +73,10 @@ struct SweepParams {
     int generic_stageable;  // generic family: every offset with a y step has no x or z step
     int st_E, st_C, st_Bm, st_G8;   // staged kernel: elements per lane, planes per walk,
                                     // strip height, workgroups per XCD (0 = heuristic)
+    int st_nt;                      // staged kernel: lanes per workgroup (0 = 256, or 512)
     // launch shape of series steps (EP_ACC_ADD) when acc_kernel > 0, else
     // the fields above
-    int acc_kernel, acc_E, acc_C, acc_Bm, acc_G8;
+    int acc_kernel, acc_E, acc_C, acc_Bm, acc_G8, acc_nt;
     double alpha, beta, gamma;
     double eta_re, eta_im, eta0_re, eta0_im;
     unsigned ep;

@@ -54,3 +54,12 @@ def host(t):
 
 def rel_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# Launch shapes of the parity cases: 1 the direct kernel, 2 the staged kernel,
+# 3 the staged kernel with 512 lanes per workgroup (a tile twice as long).
+SHAPE_KINDS = [1, 2, 3]
+
+
+def shape(kind):
+    return {"kernel": 2, "workgroup_size": 512} if kind == 3 else {"kernel": kind}

@@ -188,7 +188,7 @@ def test_chebfd_filter_coefficients_match_oracle(lib):
 def test_tuning_set_get_and_validation(lib):
     lat = pv.Lattice((6, 5, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
     assert pv.pv_lattice_get_tuning(lat, pv.PV_C128, 4) == {k: 0 for k in pv.TUNING_FIELDS}
-    sh = {"kernel": 2, "elems_per_lane": 2, "strip_rows": 8, "walk_planes": 3, "groups_per_xcd": 40}
+    sh = {"kernel": 2, "elems_per_lane": 2, "strip_rows": 8, "walk_planes": 3, "groups_per_xcd": 40, "workgroup_size": 512}
     pv.pv_lattice_set_tuning(lat, pv.PV_C128, 4, sh)
     got = pv.pv_lattice_get_tuning(lat, pv.PV_C128, 4)
     assert all(got[k] == sh.get(k, 0) for k in pv.TUNING_FIELDS)
@@ -196,7 +196,8 @@ def test_tuning_set_get_and_validation(lib):
     assert pv.pv_lattice_get_tuning(lat, pv.PV_C64, 4)["kernel"] == 0       # per dtype
     for bad, dt in [({"kernel": 3}, pv.PV_C128), ({"elems_per_lane": 4}, pv.PV_C128),
                     ({"elems_per_lane": 1}, pv.PV_C64), ({"groups_per_xcd": 257}, pv.PV_C128),
-                    ({"tiles_per_group": 65}, pv.PV_C128), ({"walk_planes": -1}, pv.PV_C128)]:
+                    ({"tiles_per_group": 65}, pv.PV_C128), ({"walk_planes": -1}, pv.PV_C128),
+                    ({"workgroup_size": 128}, pv.PV_C128), ({"workgroup_size": 1024}, pv.PV_C64)]:
         with pytest.raises(pv.PvError) as e:
             pv.pv_lattice_set_tuning(lat, dt, 4, bad)
         assert e.value.status == 1

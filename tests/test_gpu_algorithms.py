@@ -16,7 +16,7 @@ import paper_1708_09689_amd as pv  # noqa: E402
 from oracle import chebtp, kpm  # noqa: E402
 import workloads as W  # noqa: E402
 
-from gpu_common import Case, dev, host, rel_err  # noqa: E402
+from gpu_common import Case, dev, host, rel_err, SHAPE_KINDS, shape  # noqa: E402
 
 
 @pytest.mark.parametrize("name,L,periodic,nb,M", [
@@ -27,10 +27,10 @@ from gpu_common import Case, dev, host, rel_err  # noqa: E402
     ("graphene2", (40, 24), (0, 1), 8, 96),
     ("weyl", (9, 8, 5), (1, 1, 0), 2, 64),
 ])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", SHAPE_KINDS)
 def test_kpm_moments_c128(name, L, periodic, nb, M, kernel):
     c = Case(name, L, periodic, Wd=1.0)
-    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, {"kernel": kernel})
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, shape(kernel))
     r = c.block(nb, kind="phase")
     a = 4.0 if name == "graphene2" else 7.0   # a > ||H||: TI and Weyl spectra reach ~5-6
     mu = host(pv.pv_kpm_moments(c.lat, dev(r), M, a, 0.0))
@@ -59,10 +59,10 @@ def test_kpm_deterministic():
 
 @pytest.mark.parametrize("K", [0, 1, 2, 3, 17])
 @pytest.mark.parametrize("nb", [1, 4])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", SHAPE_KINDS)
 def test_cheb_series_c128(K, nb, kernel):
     c = Case("ti", (9, 7, 6), (1, 1, 0), Wd=1.5)
-    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, {"kernel": kernel})
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, shape(kernel))
     X = c.block(nb)
     g = W.generator(8, 1, K)
     coef = g.standard_normal(K + 1) + 1j * g.standard_normal(K + 1)
@@ -73,10 +73,10 @@ def test_cheb_series_c128(K, nb, kernel):
 
 
 @pytest.mark.parametrize("M", [1, 2, 3, 64])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", SHAPE_KINDS)
 def test_propagate_graphene_c128(M, kernel):
     c = Case("graphene2", (64, 20), (0, 1), Wd=0.2)
-    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, 2, {"kernel": kernel})
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, 2, shape(kernel))
     psi = c.block(2)
     a, b, dt = 3.2, 0.05, 2.0 if M < 64 else 10.0
     t = dev(psi)

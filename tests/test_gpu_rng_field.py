@@ -15,7 +15,7 @@ import paper_1708_09689_amd as pv  # noqa: E402
 from oracle import adjoint, hamiltonian, kpm, rng, spmmv  # noqa: E402
 import workloads as W  # noqa: E402
 
-from gpu_common import Case, dev, host, rel_err  # noqa: E402
+from gpu_common import Case, dev, host, rel_err, SHAPE_KINDS, shape  # noqa: E402
 
 SEED = 0x5EED_1708
 
@@ -36,11 +36,11 @@ def rng_case(name, L, periodic, Wd, seed=SEED):
     ("graphene4", (21, 10), (1, 1)),      # per-orbital field
     ("weyl", (19, 6, 5), (1, 1, 0)),
 ])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", SHAPE_KINDS)
 def test_sweep_with_generated_field(name, L, periodic, kernel):
     nb = 4
     c = rng_case(name, L, periodic, 2.0)
-    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, {"kernel": kernel})
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, shape(kernel))
     x = c.block(nb, seed=1)
     z = c.block(nb, seed=2)
     y = dev(z.copy())

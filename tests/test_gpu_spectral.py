@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 import paper_1708_09689_amd as pv  # noqa: E402
 from oracle import kpm, spectral  # noqa: E402
 
-from gpu_common import Case, dev, host  # noqa: E402
+from gpu_common import Case, dev, host, SHAPE_KINDS, shape  # noqa: E402
 
 K0 = math.pi / 2
 
@@ -37,7 +37,7 @@ def test_bloch_block_matches_oracle(layer, dtype):
     assert np.abs(R.astype(np.complex128) - ref).max() < (1e-13 if dtype == pv.PV_C128 else 1e-6)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", SHAPE_KINDS)
 def test_clean_weyl_bloch_moments_closed_form(kernel):
     L = (16, 10, 8)
     c = Case("weyl", L, (1, 1, 1), with_field=False)
@@ -45,7 +45,7 @@ def test_clean_weyl_bloch_moments_closed_form(kernel):
     ks = [(2 * math.pi * i / L[0], 2 * math.pi * j / L[1], 2 * math.pi * l / L[2]) for (i, j, l) in grid]
     kk = np.array([k for k in ks for _ in (0, 1)])
     nu = [n for _ in ks for n in (0, 1)]
-    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, 8, {"kernel": kernel})
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, 8, shape(kernel))
     R = pv.pv_bloch_block(c.lat, kk, nu)
     M, a = 96, 7.0
     mu = host(pv.pv_kpm_moments(c.lat, R, M, a, 0.0))

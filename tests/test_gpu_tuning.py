@@ -1,5 +1,5 @@
 """Launch shapes of the sweep (direct / staged kernels, elements per lane,
-strip, walk and workgroup counts) and the autotuner.
+lanes per workgroup, strip, walk and workgroup counts) and the autotuner.
 
 Every shape runs the same per-element arithmetic (the stencil slots in the
 same order), so y is bitwise identical across shapes; the fused dot products
@@ -25,12 +25,16 @@ SHAPES_C128 = [
     {"kernel": 2, "elems_per_lane": 2},
     {"kernel": 2, "elems_per_lane": 1, "strip_rows": 3, "walk_planes": 2, "groups_per_xcd": 5},
     {"kernel": 2, "elems_per_lane": 2, "strip_rows": 1, "walk_planes": 1, "groups_per_xcd": 1},
+    {"kernel": 2, "elems_per_lane": 2, "workgroup_size": 512},
+    {"kernel": 2, "elems_per_lane": 1, "workgroup_size": 512, "strip_rows": 3, "walk_planes": 2, "groups_per_xcd": 5},
 ]
 SHAPES_C64 = [
     {"kernel": 1},
     {"kernel": 2, "elems_per_lane": 2},
     {"kernel": 2, "elems_per_lane": 4},
     {"kernel": 2, "elems_per_lane": 2, "strip_rows": 5, "walk_planes": 3, "groups_per_xcd": 3},
+    {"kernel": 2, "elems_per_lane": 4, "workgroup_size": 512},
+    {"kernel": 2, "elems_per_lane": 2, "workgroup_size": 512, "groups_per_xcd": 3},
 ]
 
 CASES = [
