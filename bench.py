@@ -33,14 +33,16 @@ WORKLOAD_INDEX = 2            # seeds of the 256x256x64 TI workload
 A_SCALE, B_SHIFT = 7.0, 0.0
 
 
-# HBM-side bytes per Chebyshev-step launch of the sweep kernel as built now,
-# from FETCH_SIZE / WRITE_SIZE counters scaled by the copy-kernel factors
-# (profiles/*_counters.txt), with the launch shape the counters were taken
-# with; other shapes and (dtype, nb) pairs without a counter run report null.
-_STAGED = {"kernel": 2, "walk_planes": 0, "strip_rows": 0, "groups_per_xcd": 0, "tiles_per_group": 0, "slab_rows": 0}
+# Bytes per Chebyshev-step launch of the sweep kernel as built now that miss
+# L2 (FETCH_SIZE / WRITE_SIZE counters scaled by the copy-kernel factors,
+# profiles/*_counters.txt; the Infinity Cache serves part of them), with the
+# launch shape the counters were taken with; other shapes and (dtype, nb)
+# pairs without a counter run report null.
+_STAGED = {"kernel": 2, "walk_planes": 0, "strip_rows": 0, "groups_per_xcd": 0, "tiles_per_group": 0, "slab_rows": 0,
+           "workgroup_size": 0}
 COUNTED_TRAFFIC = {
-    ("c128", 32): (dict(_STAGED, elems_per_lane=2, strip_rows=32, groups_per_xcd=32), 35_126_000_000),
-    ("c64", 16): (dict(_STAGED, elems_per_lane=2), 8_198_000_000),
+    ("c128", 32): (dict(_STAGED, elems_per_lane=2, strip_rows=32, workgroup_size=512), 35_619_000_000),
+    ("c64", 16): (dict(_STAGED, elems_per_lane=4, workgroup_size=512), 6_970_000_000),
 }
 
 

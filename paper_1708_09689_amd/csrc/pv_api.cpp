@@ -1245,7 +1245,8 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
     hipError_t herr = hipSuccess;
     const bool compiled = l->family != pv::FAM_GENERIC || generic_stageable(l);
     const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
-    // coordinate search: 1. kernel and elements per lane at default shapes;
+    // coordinate search: 1. kernel, elements per lane and lanes per workgroup
+    // at default shapes;
     // for the staged winner 2. strip height, 3. planes per walk, 4. workgroups
     // per XCD; for the direct winner, tiles per workgroup
     auto search = [&](pv_tuning& best, double& best_ms) {
@@ -1266,16 +1267,19 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         t.kernel = 1;
         consider(t);
         if (compiled) {
+            // elements per lane x lanes per workgroup (512 only for compiled families)
             const int es[2] = {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4};
-            for (int e : es) {
-                t = pv_tuning{};
-                t.kernel = 2;
-                t.elems_per_lane = e;
-                consider(t);
-            }
+            for (int wg : {256, 512})
+                for (int e : es) {
+                    if (wg == 512 && l->family == pv::FAM_GENERIC) continue;
+                    t = pv_tuning{};
+                    t.kernel = 2;
+                    t.elems_per_lane = e;
+                    t.workgroup_size = wg == 512 ? 512 : 0;
+                    consider(t);
+                }
         }
         if (best.kernel == 2) {
-            if (l->family != pv::FAM_GENERIC) { t = best; t.workgroup_size = 512; consider(t); }
             for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
             for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
             for (int v : {32, 64, 96, 128}) { t = best; t.groups_per_xcd = v; consider(t); }
