@@ -41,9 +41,17 @@ A_SCALE, B_SHIFT = 7.0, 0.0
 _STAGED = {"kernel": 2, "walk_planes": 0, "strip_rows": 0, "groups_per_xcd": 0, "tiles_per_group": 0, "slab_rows": 0,
            "workgroup_size": 0}
 COUNTED_TRAFFIC = {
-    ("c128", 32): (dict(_STAGED, elems_per_lane=2, strip_rows=32, workgroup_size=512), 35_619_000_000),
-    ("c64", 16): (dict(_STAGED, elems_per_lane=4, workgroup_size=512), 6_970_000_000),
+    ("c128", 32): [(dict(_STAGED, elems_per_lane=2, strip_rows=32, workgroup_size=512), 35_475_000_000),
+                   (dict(_STAGED, elems_per_lane=2, strip_rows=64, workgroup_size=512), 35_557_000_000)],
+    ("c64", 16): [(dict(_STAGED, elems_per_lane=4, workgroup_size=512), 6_968_000_000)],
 }
+
+
+def counted_traffic(dtype: str, nb: int, shape: dict):
+    for sh, nbytes in COUNTED_TRAFFIC.get((dtype, nb), []):
+        if {**_STAGED, "elems_per_lane": 0, **sh} == {**_STAGED, "elems_per_lane": 0, **shape}:
+            return nbytes
+    return None
 
 
 def bytes_per_step(n_rows: int, n_sites: int, nb: int, dtype: str) -> int:
@@ -60,12 +68,17 @@ TUNE_CACHE = os.path.join(tempfile.gettempdir(), "pvdtm_bench_tune.jsonl")
 class Sweep:
     """State of one (dtype, nb) Chebyshev recurrence on the benchmark lattice.
     The launch shape comes from the library's autotuner (cached per device in
-    a temporary file), as a user of the library would run it."""
+    a temporary file), as a user of the library would run it, unless a shape
+    is pinned (fields of pv_tuning; the rest default)."""
 
-    def __init__(self, pv, torch, lat, nb, dtype, dev):
+    def __init__(self, pv, torch, lat, nb, dtype, dev, shape=None):
         self.pv, self.torch, self.lat, self.nb, self.dtype = pv, torch, lat, nb, dtype
         code = pv.PV_C128 if dtype == "c128" else pv.PV_C64
-        self.shape, self.tune_ms = pv.pv_autotune(lat, nb, code, cache_path=TUNE_CACHE)
+        if shape is None:
+            self.shape, self.tune_ms = pv.pv_autotune(lat, nb, code, cache_path=TUNE_CACHE)
+        else:
+            self.shape = {**_STAGED, "elems_per_lane": 0, **shape}
+            pv.pv_lattice_set_tuning(lat, code, nb, self.shape)
         import workloads as W
         self.w0 = W.random_phase_device(lat.n_rows, nb, 10 * WORKLOAD_INDEX + nb, dev,
                                         "complex128" if dtype == "c128" else "complex64")
@@ -446,6 +459,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the per-workload measurements")
     ap.add_argument("--fd", action="store_true", help="also run the interior-eigenvalue comparison (slow)")
+    ap.add_argument("--shape", type=json.loads, default=None,
+                    help="pin the headline launch shape (JSON object of pv_tuning fields) instead of autotuning")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -472,7 +487,7 @@ def main():
 
     # headline
     set_field(args.dtype)
-    sw = Sweep(pv, torch, lat, args.nb, args.dtype, dev)
+    sw = Sweep(pv, torch, lat, args.nb, args.dtype, dev, shape=args.shape)
     ms = time_steps(torch, sw, args.warmup, args.steps)
     print(f"# headline {args.dtype} nb={args.nb}: {ms:.4f} ms/step, shape {sw.shape}", file=sys.stderr, flush=True)
     shape = sw.shape
@@ -557,8 +572,7 @@ def main():
                    "a": A_SCALE, "b": B_SHIFT, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (COUNTED_TRAFFIC[(args.dtype, args.nb)][1]
-                                 if COUNTED_TRAFFIC.get((args.dtype, args.nb), (None,))[0] == shape else None),
+                     "traffic": counted_traffic(args.dtype, args.nb, shape),
                      "kernel": ("staged_kernel<PatTI>" if shape["kernel"] == 2 else "sweep_kernel<PatTI>")
                                + " (Chebyshev step, fused dots) + reduce_dots_kernel",
                      "launch_shape": shape,

@@ -1219,8 +1219,9 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         }
         return hipSuccess;
     };
-    // time of one step under shape t (milliseconds); warm-up first, then
-    // enough repetitions for about 20 ms
+    // time of one step under shape t (milliseconds): warm-up first, then the
+    // fastest of three batches of about 10 ms each (a single short batch lets
+    // clock and co-tenant noise pick a shape that moves more bytes)
     auto measure = [&](const pv_tuning& t, double& ms) -> hipError_t {
         (series ? slot_acc : slot) = t;
         hipError_t e = run(1);
@@ -1231,15 +1232,18 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
         float t1 = 0.f;
         if ((e = hipEventElapsedTime(&t1, e0, e1)) != hipSuccess) return e;
-        int reps = t1 > 0.f ? int(20.0 / t1) : 20;
+        int reps = t1 > 0.f ? int(10.0 / t1) : 10;
         reps = reps < 2 ? 2 : (reps > 50 ? 50 : reps);
-        if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
-        if ((e = run(reps)) != hipSuccess) return e;
-        if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-        float tt = 0.f;
-        if ((e = hipEventElapsedTime(&tt, e0, e1)) != hipSuccess) return e;
-        ms = double(tt) / reps;
+        ms = 1e300;
+        for (int b = 0; b < 3; ++b) {
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+            if ((e = run(reps)) != hipSuccess) return e;
+            if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+            float tt = 0.f;
+            if ((e = hipEventElapsedTime(&tt, e0, e1)) != hipSuccess) return e;
+            if (double(tt) / reps < ms) ms = double(tt) / reps;
+        }
         return hipSuccess;
     };
     hipError_t herr = hipSuccess;
