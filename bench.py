@@ -129,6 +129,26 @@ def copy_probe(pv, torch, dev, nbytes=4 << 30, reps=10) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def triad_probe(pv, torch, dev, nbytes=4 << 30, reps=10) -> float:
+    """Achievable bandwidth of a streaming triad y = x + z (GB/s, two reads +
+    one write: the stream mix of a Chebyshev step without the stencil)."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    z = torch.empty_like(x).fill_(2.0)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        pv.pv_stream_triad(x, z, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pv.pv_stream_triad(x, z, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, z, y
+    return 3.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(nb: int, budget_s: float = 12.0) -> dict:
     """The oracle (scipy CSR SpMMV + numpy dots, one thread) on a bounded
     sample of the same workload: the same x-y planes, 4 of the 64 z-layers."""
@@ -484,6 +504,7 @@ def main():
         lat.set_potential(V64 if dtype == "c128" else V32)
 
     copy_gbs = None if args.no_copy else copy_probe(pv, torch, dev)
+    triad_gbs = None if args.no_copy else triad_probe(pv, torch, dev)
 
     # headline
     set_field(args.dtype)
@@ -579,6 +600,8 @@ def main():
                      "bytes_per_launch": nbytes},
         "copy_probe_GBs": None if copy_gbs is None else round(copy_gbs, 1),
         "frac_of_copy_probe": None if copy_gbs is None else round(achieved / copy_gbs, 4),
+        "triad_probe_GBs": None if triad_gbs is None else round(triad_gbs, 1),
+        "frac_of_triad_probe": None if triad_gbs is None else round(achieved / triad_gbs, 4),
         "variants": variants,
         "workloads": configs,
         "cpu_baseline": cpu,

@@ -411,6 +411,13 @@ pv_status pv_batch_stats(const pv_batch *batch, int *captures, int *replays);
  * multiple of 16), a plain streaming copy kernel. */
 pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/* Second bandwidth reference with the stream mix of one Chebyshev step (two
+ * reads, one write): y = x + z elementwise over FP64 values; x, z and y are
+ * device buffers of `bytes` each (a multiple of 16, 16-byte aligned), y may
+ * alias neither input.  PV_ERR_INVALID_ARG on a null or misaligned pointer
+ * or size. */
+pv_status pv_stream_triad(const void *x, const void *z, void *y, size_t bytes, void *stream);
+
 /*
  * Launch shape of the stencil sweep for one (dtype, nb) of a lattice -- the
  * GPU counterpart of the cache-blocking choices of Sec. 3.1 (layer

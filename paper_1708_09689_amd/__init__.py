@@ -77,6 +77,7 @@ SIGNATURES = {
     "pv_gram": (_i, [_i, _i64, _i, _i, _vp, _vp, _vp, _vp, _sz, _vp]),
     "pv_block_rotate": (_i, [_i, _i64, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "pv_stream_copy": (_i, [_vp, _vp, _sz, _vp]),
+    "pv_stream_triad": (_i, [_vp, _vp, _vp, _sz, _vp]),
     "pv_chebfd_workspace_size": (_sz, [_vp, _i, _i, _i]),
     "pv_chebfd": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _i, _vp, _dp, _dp, _ip, _ip, _vp, _sz, _vp]),
     "pv_chebfd_filter_coefficients": (_i, [_d, _d, _d, _d, _i, _dp]),
@@ -422,6 +423,20 @@ def pv_stream_copy(src, dst):
         raise ValueError("dst too small")
     _check(lib().pv_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, _stream()))
     return dst
+
+
+def pv_stream_triad(x, z, y):
+    """y = x + z over float64 tensors of equal size (bandwidth reference)."""
+    import torch
+    for t in (x, z, y):
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("triad takes contiguous float64 tensors")
+    if not (x.numel() == z.numel() == y.numel()):
+        raise ValueError("triad operands differ in size")
+    n = x.numel() * 8
+    _check(lib().pv_stream_triad(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                 ctypes.c_void_p(y.data_ptr()), n, _stream()))
+    return y
 
 
 def pv_bloch_block(lat, k, orbital, layer=None, dtype=PV_C128, out=None, device="cuda"):

@@ -1037,6 +1037,16 @@ extern "C" pv_status pv_stream_copy(const void* src, void* dst, size_t bytes, vo
     return PV_OK;
 }
 
+extern "C" pv_status pv_stream_triad(const void* x, const void* z, void* y, size_t bytes, void* stream) {
+    if (!x || !z || !y || bytes % 16 ||
+        (reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(y)) % 16)
+        return fail(PV_ERR_INVALID_ARG, "triad needs 16-byte aligned pointers and size");
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    PV_HIP(pv::launch_triad(x, z, y, bytes, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Launch shapes and the autotuner
 // ---------------------------------------------------------------------------

@@ -227,6 +227,28 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const u32x4* __restrict__ 
     }
 }
 
+// Streaming triad over FP64 pairs: y = x + z, the stream mix of one
+// Chebyshev step (two reads, one write) without the stencil.
+using f64x2 = double __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(kBlock) void triad_kernel(const f64x2* __restrict__ x, const f64x2* __restrict__ z,
+                                                       f64x2* __restrict__ y, int64_t n) {
+    const int64_t chunk = 4 * (int64_t)kBlock;
+    for (int64_t base = blockIdx.x * chunk; base < n; base += (int64_t)gridDim.x * chunk) {
+        f64x2 a[4], b[4];
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            if (i < n) {
+                a[k] = __builtin_nontemporal_load(x + i);
+                b[k] = __builtin_nontemporal_load(z + i);
+            }
+        }
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            if (i < n) __builtin_nontemporal_store(a[k] + b[k], y + i);
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void column_copy_kernel(const cplx<T>* __restrict__ src, int src_ld,
                                                            int src_col, cplx<T>* __restrict__ dst, int dst_ld,
@@ -395,6 +417,16 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
     if (g < 1) g = 1;
     hipLaunchKernelGGL(copy_kernel, dim3(int(g)), dim3(kBlock), 0, s, static_cast<const u32x4*>(src),
                        static_cast<u32x4*>(dst), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_triad(const void* x, const void* z, void* y, size_t bytes, hipStream_t s) {
+    const int64_t n = int64_t(bytes / 16);
+    int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(triad_kernel, dim3(int(g)), dim3(kBlock), 0, s, static_cast<const f64x2*>(x),
+                       static_cast<const f64x2*>(z), static_cast<f64x2*>(y), n);
     return hipGetLastError();
 }
 

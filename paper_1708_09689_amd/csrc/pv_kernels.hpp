@@ -106,6 +106,7 @@ int gram_grid(int64_t rows, int num_cus);
 hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q,
                          int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_triad(const void* x, const void* z, void* y, size_t bytes, hipStream_t s);
 
 // dst[r][dst_col + c] = (re + i im) * src[r][src_col + c] for r < rows,
 // c < ncols, blocks of widths src_ld and dst_ld (columns moved between

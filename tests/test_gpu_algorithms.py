@@ -137,3 +137,14 @@ def test_stream_copy():
     pv.pv_stream_copy(a, b)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n", [2, 1 << 20, (1 << 20) + 2 * 1000 + 2])
+def test_stream_triad(n):
+    # ragged tail past the last whole 4-chunk block; IEEE addition is exact to compare
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    z = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.full_like(x, float("nan"))
+    pv.pv_stream_triad(x, z, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y.cpu(), x.cpu() + z.cpu())
