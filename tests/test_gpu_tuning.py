@@ -77,6 +77,25 @@ def test_shapes_c128_identical_and_match_oracle(name, L, periodic, nb):
 
 
 @pytest.mark.parametrize("name,L,periodic", CASES)
+@pytest.mark.parametrize("nb", [4, 16])
+def test_shapes_c128_uniform_coefficients(name, L, periodic, nb):
+    """Uniform alpha, beta, gamma take the specialised epilogues (per-column
+    ones take the run-time epilogue): every shape gives the same y as the
+    direct kernel, which matches the oracle, and dots within rounding."""
+    c = Case(name, L, periodic, Wd=2.0, seed=nb + 11)
+    x = c.block(nb, seed=3)
+    z = c.block(nb, seed=4)
+    outs, dots = run_shapes(c, SHAPES_C128, pv.PV_C128, nb, dev(x), dev(z), 0.7, -0.2, -1.0)
+    ref = spmmv.spmmv(c.H, x, 0.7, -0.2, -1.0, z)
+    assert rel_err(outs[0], ref) < 1e-13
+    dref = np.stack([np.einsum("ij,ij->j", x.conj(), x).real, (x.conj() * ref).sum(0).real,
+                     (x.conj() * ref).sum(0).imag, np.einsum("ij,ij->j", ref.conj(), ref).real], axis=1)
+    for o, d in zip(outs, dots):
+        assert np.array_equal(o, outs[0])
+        assert np.abs(d - dref).max() <= 1e-11 * np.abs(dref).max()
+
+
+@pytest.mark.parametrize("name,L,periodic", CASES)
 @pytest.mark.parametrize("nb", [1, 8])
 def test_shapes_c64_identical(name, L, periodic, nb):
     c = Case(name, L, periodic, Wd=2.0, seed=nb + 5, vdtype=np.float32)
