@@ -395,17 +395,19 @@ def bench_dsl(pv, torch, W, dev, nb=16):
     """Stencils given as DSL text, on the 256x256x64 lattice, Chebyshev step
     with dots, complex128: the TI program (recognised as the compiled TI
     family); the TI plus next-nearest-neighbour hops -(t'/2) G1, t' = 0.1,
-    along (+-1, 0, +-1) (no compiled family; the staged generic kernel takes
-    it) and along (+-1, +-1, 0) (a y step with an x step: the direct generic
-    kernel)."""
+    along (+-1, 0, +-1) and along (+-1, +-1, 0) (no compiled family; the
+    staged generic kernel takes both) and along (0, +-1, +-1) (a y step with
+    a z step: the direct generic kernel)."""
     ti = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
     G1 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
     h = -0.05 * G1
     xz = [((1, 0, 1), h), ((-1, 0, -1), h), ((1, 0, -1), h), ((-1, 0, 1), h)]
     xy = [((1, 1, 0), h), ((-1, -1, 0), h), ((1, -1, 0), h), ((-1, 1, 0), h)]
+    yz = [((0, 1, 1), h), ((0, -1, -1), h), ((0, 1, -1), h), ((0, -1, 1), h)]
     out = {}
     for name, text in (("ti", _dsl_program(ti)), ("ti_nnn_xz_generic_staged", _dsl_program(ti, xz)),
-                       ("ti_nnn_xy_generic_direct", _dsl_program(ti, xy))):
+                       ("ti_nnn_xy_generic_staged", _dsl_program(ti, xy)),
+                       ("ti_nnn_yz_generic_direct", _dsl_program(ti, yz))):
         st = pv.pv_dsl_stencil(text)
         lat = pv.Lattice(L_BENCH, (1, 1, 1), st)
         lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 2.0,

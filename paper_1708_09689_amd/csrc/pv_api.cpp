@@ -246,16 +246,27 @@ pv_status check_nb(int nb) {
     return PV_OK;
 }
 
-// A generic stencil fits the staged kernel (rows along z in an LDS ring with
-// an x halo, the y neighbours as side rows) when every offset with a y step
-// has no x or z step.
+// A generic stencil fits the staged kernel (rows along z in an LDS ring,
+// the y neighbours in the plane as side rows, both with an x halo) when no
+// offset has both a y and a z step.
 int generic_stageable(const pv_lattice* l) {
     if (l->family != pv::FAM_GENERIC || l->dim != 3) return 0;
     for (int t = 0; t < l->n_terms; ++t) {
         const int* d = &l->offsets[3 * t];
-        if (d[1] != 0 && (d[0] != 0 || d[2] != 0)) return 0;
+        if (d[1] != 0 && d[2] != 0) return 0;
     }
     return 1;
+}
+
+// The staged kernel then loads the y neighbours' rows with the x halo too
+// when some offset has both a y and an x step.
+int generic_side_halo(const pv_lattice* l) {
+    if (!generic_stageable(l)) return 0;
+    for (int t = 0; t < l->n_terms; ++t) {
+        const int* d = &l->offsets[3 * t];
+        if (d[1] != 0 && d[0] != 0) return 1;
+    }
+    return 0;
 }
 
 pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
@@ -279,6 +290,7 @@ pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     p.coef = l->d_coef;
     p.offs = l->d_offs;
     p.generic_stageable = generic_stageable(l);
+    p.generic_side_halo = generic_side_halo(l);
     return p;
 }
 

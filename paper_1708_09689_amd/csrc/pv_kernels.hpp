@@ -70,7 +70,8 @@ struct SweepParams {
     int slab_rows;          // rows per y-slab of the sweep order (direct kernel)
     int tpb;                // tiles per workgroup (direct kernel; 0 = heuristic)
     int kernel;             // 0 = choose, 1 = direct, 2 = staged
-    int generic_stageable;  // generic family: every offset with a y step has no x or z step
+    int generic_stageable;  // generic family: no offset has both a y and a z step
+    int generic_side_halo;  // generic family: some offset has both a y and an x step
     int st_E, st_C, st_Bm, st_G8;   // staged kernel: elements per lane, planes per walk,
                                     // strip height, workgroups per XCD (0 = heuristic)
     int st_nt;                      // staged kernel: lanes per workgroup (0 = 256, or 512)

@@ -200,12 +200,23 @@ struct Slots {
 };
 
 // Generic family descriptor: NO orbitals, runtime offsets, dense blocks.
-template <int NO_>
+// SH: the staged kernel loads the side rows with the x halo (stencils with
+// hops that have a y and an x step).
+template <int NO_, bool SH = false>
 struct PatGeneric {
     static constexpr int FAMILY = FAM_GENERIC, NO = NO_, NT = 0, DIM = 3;
+    static constexpr bool SIDE_HALO = SH;
     static constexpr int off[1][3] = {{0, 0, 0}};
     static constexpr unsigned char code[1][NO_][NO_] = {};   // no compiled slots
 };
+
+template <class P>
+constexpr bool side_halo() {
+    if constexpr (P::FAMILY == FAM_GENERIC)
+        return P::SIDE_HALO;
+    else
+        return false;
+}
 
 template <typename T>
 __device__ __forceinline__ cplx<T> ld_nt(const cplx<T>* p) {
@@ -653,10 +664,16 @@ struct StagedSet {
     int64_t vrow;     // first field entry of the set's row
 };
 
+// Side rows hold the tile, or for generic stencils with hops that have a y
+// and an x step the tile with the one-site x halo of ring rows.
 template <class P, typename T, int E, int NT>
 struct StagedSide {
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
-    u32x4 side[NTR > 0 ? NTR : 1][Staged<T, E, NT>::TCH];
+    static constexpr bool HALO = side_halo<P>();
+    static constexpr int SCH = HALO ? Staged<T, E, NT>::RCH : Staged<T, E, NT>::TCH;   // chunks per lane
+    static constexpr int SLEN = HALO ? Staged<T, E, NT>::RCH * NT * Staged<T, E, NT>::CE
+                                     : Staged<T, E, NT>::TW;                         // LDS elements per row
+    u32x4 side[NTR > 0 ? NTR : 1][SCH];
     u32x4 acc[Staged<T, E, NT>::TCH];
 };
 
@@ -668,7 +685,7 @@ struct StagedCtx {
     static constexpr int NTR = Set::NTR;
     const KArgs<T, VT>& a;
     cplx<T>* ring;   // [3][seg]
-    cplx<T>* tra;    // [NTR][TW]
+    cplx<T>* tra;    // [NTR][Side::SLEN]
     cplx<T>* zl;     // [TW]
     cplx<T>* al;     // [TW] (ACC only)
     T* vl;           // [E S::NTH]
@@ -764,8 +781,13 @@ struct StagedCtx {
 #pragma unroll
             for (int h = 0; h < NTR; ++h) {
                 const cplx<T>* sp = row_ptr(m + (h == 0 ? -1 : 1), wr);
+                if constexpr (Side::HALO) {
 #pragma unroll
-                for (int k = 0; k < S::TCH; ++k) sd.side[h][k] = ld_chunk<T>(sp, soff[k]);
+                    for (int k = 0; k < Side::SCH; ++k) sd.side[h][k] = ld_chunk<T>(sp, roff[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < Side::SCH; ++k) sd.side[h][k] = ld_chunk<T>(sp, soff[k]);
+                }
             }
         }
     }
@@ -778,9 +800,9 @@ struct StagedCtx {
         if constexpr (NTR > 0) {
 #pragma unroll
             for (int h = 0; h < NTR; ++h) {
-                u32x4* ds = reinterpret_cast<u32x4*>(tra + h * S::TW);
+                u32x4* ds = reinterpret_cast<u32x4*>(tra + h * Side::SLEN);
 #pragma unroll
-                for (int k = 0; k < S::TCH; ++k) ds[tid + k * S::NTH] = sd.side[h][k];
+                for (int k = 0; k < Side::SCH; ++k) ds[tid + k * S::NTH] = sd.side[h][k];
             }
         }
     }
@@ -820,7 +842,8 @@ __host__ __device__ constexpr int staged_seg() {
 }
 template <class P, typename T, int E, int NT>
 __host__ __device__ constexpr size_t staged_table_offset(bool acc) {
-    return (size_t(3 * staged_seg<T, E, NT>() + ((P::DIM == 3 ? 2 : 0) + 1 + (acc ? 1 : 0)) * Staged<T, E, NT>::TW) *
+    return (size_t(3 * staged_seg<T, E, NT>() + (P::DIM == 3 ? 2 : 0) * StagedSide<P, T, E, NT>::SLEN +
+                   (1 + (acc ? 1 : 0)) * Staged<T, E, NT>::TW) *
                 Staged<T, E, NT>::ES +
             size_t(E * NT) * sizeof(T) + 15) / 16 * 16;
 }
@@ -901,7 +924,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     Ctx cx{a, reinterpret_cast<cplx<T>*>(smem), nullptr, nullptr, nullptr, nullptr, tid, (S::TW + 2 * site) / S::CE, 0, 0};
     cx.vshift = a.pot_mode == 1 ? a.logsite : a.lognb;
     cx.tra = cx.ring + 3 * a.st_seg;
-    cx.zl = cx.tra + NTR * S::TW;
+    cx.zl = cx.tra + NTR * Ctx::Side::SLEN;
     cx.al = cx.zl + S::TW;
     cx.vl = reinterpret_cast<T*>(cx.al + (ACC ? S::TW : 0));
 
@@ -979,13 +1002,15 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 T hr = d * xc.re - dgi * xc.im;
                 T hi = d * xc.im + dgi * xc.re;
                 if constexpr (GEN) {
-                    // runtime terms: rows (m, w + dw) from the ring with the x
-                    // halo, rows (m -+ 1, w) from the side rows (the host admits
-                    // no offset with a y step and an x or z step)
+                    // runtime terms: rows (m, w + dw) from the ring, rows
+                    // (m -+ 1, w) from the side rows, both with the x halo (the
+                    // host admits no offset with both a y and a z step)
                     for (int tb = 0; tb < a.n_terms; ++tb) {
                         const int dx = g_off[3 * tb], dm = g_off[3 * tb + 1], dw = g_off[3 * tb + 2];
-                        const cplx<T>* rw = dm != 0 ? cx.tra + (dm < 0 ? 0 : S::TW) + l
-                                                    : (dw < 0 ? rm : (dw > 0 ? rp : r0)) + l + dx * site;
+                        // side rows start at the tile (no halo) or one site before it
+                        constexpr int side0 = Ctx::Side::HALO ? 1 : 0;
+                        const cplx<T>* rw = (dm != 0 ? cx.tra + (dm < 0 ? 0 : Ctx::Side::SLEN) + side0 * site
+                                                     : (dw < 0 ? rm : (dw > 0 ? rp : r0))) + l + dx * site;
                         const bool ok = dx < 0 ? xlo : (dx > 0 ? xhi : true);
                         const int e0 = g_ptr[tb * NO + o], e1 = g_ptr[tb * NO + o + 1];
                         for (int e = e0; e < e1; ++e)
@@ -1295,10 +1320,12 @@ template <class P, typename T, typename VT, int E>
 hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
     constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD, PLAIN = EP_STORE_Y;
     if (p.colp == nullptr) {
-        if (p.st_nt == 512 && P::FAMILY != FAM_GENERIC) {
-            if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM, 512>(p, num_cus, s);
-            if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES, 512>(p, num_cus, s);
-            if (p.ep == PLAIN) return launch_staged<P, T, VT, E, PLAIN, 512>(p, num_cus, s);
+        if constexpr (P::FAMILY != FAM_GENERIC) {
+            if (p.st_nt == 512) {
+                if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM, 512>(p, num_cus, s);
+                if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES, 512>(p, num_cus, s);
+                if (p.ep == PLAIN) return launch_staged<P, T, VT, E, PLAIN, 512>(p, num_cus, s);
+            }
         }
         if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
         if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
@@ -1338,8 +1365,13 @@ int staged_elems(const SweepParams& p) {
     return p.dtype == 0 ? 1 : 2;
 }
 
+template <class X>
+struct Tag {
+    using type = X;
+};
+
 // Sweep kernel of a launch: the staged kernel for compiled families, and for
-// generic 3D stencils whose offsets with a y step have no x or z step, when
+// generic 3D stencils with no offset that has both a y and a z step, when
 // the block is 16-byte aligned (its chunk loads); else the direct kernel.
 // p.kernel (or PV_SWEEP) 1 forces direct, 2 staged; p.st_E (or PV_STAGED_E)
 // selects the elements per lane.
@@ -1354,10 +1386,19 @@ hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
         const bool dflt = staged_default(p) && (P::FAMILY != FAM_GENERIC || p.L[2] > 1);
         if (can && aligned && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && dflt))) {
             const int e = staged_elems(p);
-            if constexpr (sizeof(T) == 8)
-                return e == 2 ? launch_staged_ep<P, T, VT, 2>(p, num_cus, s) : launch_staged_ep<P, T, VT, 1>(p, num_cus, s);
-            else
-                return e == 4 ? launch_staged_ep<P, T, VT, 4>(p, num_cus, s) : launch_staged_ep<P, T, VT, 2>(p, num_cus, s);
+            auto staged = [&](auto pt) -> hipError_t {
+                using Q = typename decltype(pt)::type;
+                if constexpr (sizeof(T) == 8)
+                    return e == 2 ? launch_staged_ep<Q, T, VT, 2>(p, num_cus, s)
+                                  : launch_staged_ep<Q, T, VT, 1>(p, num_cus, s);
+                else
+                    return e == 4 ? launch_staged_ep<Q, T, VT, 4>(p, num_cus, s)
+                                  : launch_staged_ep<Q, T, VT, 2>(p, num_cus, s);
+            };
+            if constexpr (P::FAMILY == FAM_GENERIC) {
+                if (p.generic_side_halo) return staged(Tag<PatGeneric<P::NO, true>>{});
+            }
+            return staged(Tag<P>{});
         }
     }
     (void)num_cus;
@@ -1378,11 +1419,6 @@ hipError_t launch_family(SweepParams& p, int num_cus, hipStream_t s) {
     return launch_typed<P, float, float>(p, num_cus, s);
 }
 
-
-template <class X>
-struct Tag {
-    using type = X;
-};
 
 // Calls f(Tag<T>, Tag<VT>) for the vector and field types of a launch.
 template <class F>

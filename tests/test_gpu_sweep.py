@@ -172,22 +172,26 @@ def test_generic_family_random_hermitian_stencil():
 
 
 GENERIC_OFFSETS = {
-    # a y step together with an x step: direct kernel only
-    "diagonal": [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, -1)],
+    # a y step together with a z step: direct kernel only
+    "diagonal": [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (1, 0, -1)],
     # y steps alone, x and z steps combined: the staged kernel takes it too
     "stageable": [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, -1), (1, 0, 1)],
+    # y steps with x steps (side rows with the x halo) and x with z steps
+    "xy": [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, -1, 0), (1, 0, 1)],
 }
 
 
 @pytest.mark.parametrize("no,nb,dtype", [(4, 4, np.complex128), (4, 1, np.complex128), (1, 8, np.complex128),
                                          (4, 16, np.complex64), (2, 32, np.complex128)])
-@pytest.mark.parametrize("shape", ["diagonal", "stageable"])
+@pytest.mark.parametrize("shape", ["diagonal", "stageable", "xy"])
 @pytest.mark.parametrize("kernel", [1, 2])
-def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel):
+@pytest.mark.parametrize("per", [(1, 1, 0), (0, 0, 1)])
+def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel, per):
     """Generic stencils whose blocks are mostly zero, with rows of different
     entry counts (some empty) and an on-site block with off-diagonal entries:
     the kernels walk only the nonzero entries.  Chebyshev step with dots, on
-    the direct kernel and (where the offsets allow it) the staged one."""
+    the direct kernel and (where the offsets allow it) the staged one, with
+    open and periodic x and y boundaries."""
     g = np.random.default_rng(12 + no + nb)
     offs = GENERIC_OFFSETS[shape]
     blocks, offsets = [], []
@@ -201,7 +205,7 @@ def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel):
     E0 = E0 + E0.conj().T
     st = {"dim": 3, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
           "pot_mode": pv.PV_POT_SITE}
-    L, per = (7, 5, 4), (1, 1, 0)
+    L = (7, 5, 4)
     lat = pv.Lattice(L, per, st)
     assert lat.family == 0
     code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
@@ -224,14 +228,15 @@ def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel):
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
-def test_generic_stageable_open_x_orbital_field_series(kernel):
+@pytest.mark.parametrize("shape", ["stageable", "xy"])
+def test_generic_stageable_open_x_orbital_field_series(kernel, shape):
     """Staged generic path with an open x boundary, a per-orbital field and
     the series epilogue (Chebyshev series of degree 9) against the oracle's
     series on the explicit matrix."""
     from oracle import chebtp
     g = np.random.default_rng(31)
     no = 2
-    offs = GENERIC_OFFSETS["stageable"]
+    offs = GENERIC_OFFSETS[shape]
     blocks, offsets = [], []
     for o in offs:
         B = (g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))) * (g.random((no, no)) < 0.7)
