@@ -424,8 +424,10 @@ pv_status pv_stream_triad(const void *x, const void *z, void *y, size_t bytes, v
  * conditions, blocking factor).  Zero fields take the library's defaults.
  *   kernel           0 choose, 1 direct (every neighbour load goes through the
  *                    caches; any stencil), 2 staged (LDS ring of rows along
- *                    the outer lattice axis; compiled stencil families with
- *                    16-byte aligned blocks, otherwise direct is used)
+ *                    the outer lattice axis; compiled stencil families, and
+ *                    generic 3D stencils with no offset that has both a y
+ *                    and a z step, with 16-byte aligned blocks; otherwise
+ *                    direct is used)
  *   elems_per_lane   staged: 1 or 2 (complex128), 2 or 4 (complex64)
  *   walk_planes      staged: outer-axis planes per walk of a workgroup
  *   strip_rows       staged: middle-axis rows per strip of the work order
