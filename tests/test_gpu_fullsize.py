@@ -1,6 +1,7 @@
 """Parity at the full benchmark size: TI 256 x 256 x 64 periodic (D =
 16,777,216 rows), W = 2, the Chebyshev step with fused dots in the launch
-configuration the benchmark times.
+configurations the benchmark times: the autotuner's shape (as bench.py
+obtains it) and every shape whose traffic bench.py reports.
 
 The oracle cannot assemble H at this size, so the output is checked on
 sampled sites: the oracle builds the explicit rows of H for those sites, the
@@ -16,6 +17,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+import bench  # noqa: E402
 import paper_1708_09689_amd as pv  # noqa: E402
 from oracle import hamiltonian, lattice, models  # noqa: E402
 import workloads as W  # noqa: E402
@@ -36,8 +38,14 @@ def sampled_sites(olat):
     return np.unique(np.concatenate([rnd, corners, faces, tiles]).astype(np.int64))
 
 
-@pytest.mark.parametrize("dtype,nb", [("c128", 32), ("c64", 16)])
-def test_fullsize_chebyshev_step_sampled(dtype, nb):
+def launch_shapes(dtype, nb):
+    """None (the autotuner's choice) and the shapes with counted traffic."""
+    return [None] + [sh for sh, _ in bench.COUNTED_TRAFFIC.get((dtype, nb), [])]
+
+
+@pytest.mark.parametrize("dtype,nb,k", [("c128", 32, k) for k in range(len(launch_shapes("c128", 32)))] +
+                                       [("c64", 16, k) for k in range(len(launch_shapes("c64", 16)))])
+def test_fullsize_chebyshev_step_sampled(dtype, nb, k):
     dev = torch.device("cuda:0")
     c128 = dtype == "c128"
     model = models.topological_insulator(1.0, 2.0)
@@ -46,6 +54,13 @@ def test_fullsize_chebyshev_step_sampled(dtype, nb):
     lat = pv.Lattice(L, (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0]))
     Vd = torch.from_numpy(V if c128 else V.astype(np.float32)).to(dev)
     lat.set_potential(Vd)
+    code = pv.PV_C128 if c128 else pv.PV_C64
+    shape = launch_shapes(dtype, nb)[k]
+    if shape is None:
+        shape, _ = pv.pv_autotune(lat, nb, code)
+    else:
+        pv.pv_lattice_set_tuning(lat, code, nb, shape)
+    assert pv.pv_lattice_get_tuning(lat, code, nb) == {**{f: 0 for f in pv.TUNING_FIELDS}, **shape}
     tname = "complex128" if c128 else "complex64"
     x = W.random_phase_device(lat.n_rows, nb, 900 + nb, dev, tname)
     y = W.random_phase_device(lat.n_rows, nb, 901 + nb, dev, tname)
