@@ -733,8 +733,15 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
 extern "C" size_t pv_kpm_workspace_size(const pv_lattice* l, int dtype, int nb, int M) {
     (void)M;
     if (!l || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
-    return partial_bytes(l, nb) + 2 * vec_bytes(l, dtype, nb);
+    return 2 * partial_bytes(l, nb) + 2 * vec_bytes(l, dtype, nb);
 }
+
+namespace {
+// Blocks up to this many elements fold each step's moment reduction into the
+// next sweep (one launch per step instead of two; their steps are short
+// enough for launch latency to matter).
+constexpr int64_t kFuseReductionElems = int64_t(1) << 22;
+}  // namespace
 
 extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
                                     double* mu, void* work, size_t work_bytes, void* stream) {
@@ -751,14 +758,34 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     if ((st = ensure_device(l)) != PV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(work);
-    double* partials = reinterpret_cast<double*>(w);
-    void* A = w + partial_bytes(l, nb);
+    double* part[2] = {reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb))};
+    void* A = w + 2 * partial_bytes(l, nb);
     void* B = static_cast<char*>(A) + vec_bytes(l, dtype, nb);
     pv::SweepParams p = base_params(l, dtype, nb);
     if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
-    p.partials = partials;
     p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
     const double invD = 1.0 / double(l->n_rows);
+    const bool fuse = l->n_rows * int64_t(nb) <= kFuseReductionElems;
+    // step n's dots go to part[n % 2]; its moments come from the reduction
+    // folded into sweep n + 1, or from a reduction launch of their own
+    int last_grid = 0;
+    auto step_sweep = [&](int n) -> hipError_t {
+        p.partials = part[n % 2];
+        p.red_src = nullptr;
+        if (fuse && n > 0) {
+            p.red_src = part[(n - 1) % 2];
+            p.red_out = mu;
+            p.red_grid = last_grid;
+            p.red_mode = n == 1 ? 1 : 2;
+            p.red_M = M;
+            p.red_step = n - 1;
+            p.red_invD = invD;
+        }
+        hipError_t e = pv::launch_sweep(p, num_cus(), s);
+        if (e == hipSuccess && !fuse) e = pv::launch_reduce_dots(p.partials, p.grid, nb, n == 0 ? 1 : 2, mu, M, n, invD, s);
+        last_grid = p.grid;
+        return e;
+    };
     // w_1 = H~ w_0
     p.x = r;
     p.y = A;
@@ -766,8 +793,7 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     p.alpha = 1.0 / a;
     p.beta = b;
     p.gamma = 0.0;
-    PV_HIP(pv::launch_sweep(p, num_cus(), s));
-    PV_HIP(pv::launch_reduce_dots(partials, p.grid, nb, 1, mu, M, 0, invD, s));
+    PV_HIP(step_sweep(0));
     const void* prev = r;
     void* cur = A;
     p.alpha = 2.0 / a;
@@ -777,11 +803,13 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
         p.x = cur;
         p.z = prev;
         p.y = next;
-        PV_HIP(pv::launch_sweep(p, num_cus(), s));
-        PV_HIP(pv::launch_reduce_dots(partials, p.grid, nb, 2, mu, M, n, invD, s));
+        PV_HIP(step_sweep(n));
         prev = cur;
         cur = next;
     }
+    const int n_last = M / 2 - 1;
+    if (fuse)
+        PV_HIP(pv::launch_reduce_dots(part[n_last % 2], last_grid, nb, n_last == 0 ? 1 : 2, mu, M, n_last, invD, s));
     return PV_OK;
 }
 

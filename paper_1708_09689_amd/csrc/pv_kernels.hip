@@ -9,46 +9,11 @@ namespace {
 
 // ------------------------------------------------------------------ reductions
 
-__global__ __launch_bounds__(kBlock) void reduce_dots_kernel(const double* __restrict__ partials,
-                                                             int grid, int nb, int mode, double* out,
-                                                             int M, int step, double inv_D) {
-    const int c = blockIdx.x;
-    const int tid = threadIdx.x;
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int b = tid; b < grid; b += kBlock) {
-        const double* q = partials + ((size_t)b * nb + c) * 4;
-        s0 += q[0];
-        s1 += q[1];
-        s2 += q[2];
-        s3 += q[3];
-    }
-    __shared__ double sh[4][kBlock];
-    sh[0][tid] = s0;
-    sh[1][tid] = s1;
-    sh[2][tid] = s2;
-    sh[3][tid] = s3;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w)
-            for (int k = 0; k < 4; ++k) sh[k][tid] += sh[k][tid + w];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const double xx = sh[0][0], xr = sh[1][0], xi = sh[2][0], yy = sh[3][0];
-        if (mode == 0) {
-            out[c * 4 + 0] = xx;
-            out[c * 4 + 1] = xr;
-            out[c * 4 + 2] = xi;
-            out[c * 4 + 3] = yy;
-        } else if (mode == 1) {
-            out[(size_t)c * M + 0] = xx * inv_D;
-            out[(size_t)c * M + 1] = xr * inv_D;
-        } else {
-            double* mu = out + (size_t)c * M;
-            mu[2 * step] = 2.0 * xx * inv_D - mu[0];
-            mu[2 * step + 1] = 2.0 * xr * inv_D - mu[1];
-        }
-    }
+// One wave per block column: the fixed-order reduction shared with the
+// reduction folded into a sweep.
+__global__ __launch_bounds__(64) void reduce_dots_kernel(const double* __restrict__ partials, int grid, int nb,
+                                                         int mode, double* out, int M, int step, double inv_D) {
+    reduce_column_wave(partials, grid, nb, blockIdx.x, mode, out, M, step, inv_D, threadIdx.x);
 }
 
 // Per-instance fixed-order reduction of a batched sweep: workgroup
@@ -347,8 +312,8 @@ hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s) {
 
 hipError_t launch_reduce_dots(const double* partials, int grid, int nb, int mode, double* out, int M,
                               int step, double inv_D, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_dots_kernel, dim3(nb), dim3(kBlock), 0, s, partials, grid, nb, mode, out,
-                       M, step, inv_D);
+    hipLaunchKernelGGL(reduce_dots_kernel, dim3(nb), dim3(64), 0, s, partials, grid, nb, mode, out, M, step,
+                       inv_D);
     return hipGetLastError();
 }
 

@@ -83,6 +83,13 @@ struct SweepParams {
     unsigned ep;
     double* partials;     // [grid][nb][4] when EP_DOTS
     int grid;             // set by launch_sweep: number of workgroups
+    // reduction of the previous sweep's partials (red_grid rows) into
+    // red_out, by the first wave of workgroup 0 before its tiles (modes of
+    // launch_reduce_dots); NULL red_src: none
+    const double* red_src;
+    double* red_out;
+    int red_grid, red_mode, red_M, red_step;
+    double red_invD;
 };
 
 // Number of workgroups a sweep of an nb-wide block over the lattice uses

@@ -106,6 +106,10 @@ struct KArgs {
     const int* offs;
     const double* colp;
     double* partials;
+    const double* red_src;   // previous sweep's partials reduced at the start (or NULL)
+    double* red_out;
+    int red_grid, red_mode, red_M, red_step;
+    double red_invD;
     int64_t n_elem, ntiles;
     int tpb;
     // traversal: XCD part k (rows y in [Ly k/8, Ly (k+1)/8), all z) is swept
@@ -392,6 +396,54 @@ __device__ __forceinline__ void slot_coefficients(const double* coef, int o, int
 // The work of one workgroup: tiles [t0, t1) of the part of the lattice made of
 // rows y in [y0, y0 + ny) (all z), swept slab by slab; partial dots go to
 // partials[b_out].
+// Fixed-order sum over the partial rows of block column c by one wave
+// (lane-strided sums, then an xor tree); lane 0 stores the result: mode 0
+// the four dots, mode 1 mu_0 and mu_1 (divided by D), mode 2 the moments
+// mu_2step = 2 xx / D - mu_0 and mu_2step+1 = 2 xy / D - mu_1.
+__device__ __forceinline__ void reduce_column_wave(const double* __restrict__ partials, int grid, int nb, int c,
+                                                  int mode, double* out, int M, int step, double inv_D, int lane) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int b = lane; b < grid; b += 64) {
+        const double* q = partials + ((size_t)b * nb + c) * 4;
+        s0 += q[0];
+        s1 += q[1];
+        s2 += q[2];
+        s3 += q[3];
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        s0 += __shfl_xor(s0, m);
+        s1 += __shfl_xor(s1, m);
+        s2 += __shfl_xor(s2, m);
+        s3 += __shfl_xor(s3, m);
+    }
+    if (lane == 0) {
+        if (mode == 0) {
+            out[c * 4 + 0] = s0;
+            out[c * 4 + 1] = s1;
+            out[c * 4 + 2] = s2;
+            out[c * 4 + 3] = s3;
+        } else if (mode == 1) {
+            out[(size_t)c * M + 0] = s0 * inv_D;
+            out[(size_t)c * M + 1] = s1 * inv_D;
+        } else {
+            double* mu = out + (size_t)c * M;
+            mu[2 * step] = 2.0 * s0 * inv_D - mu[0];
+            mu[2 * step + 1] = 2.0 * s1 * inv_D - mu[1];
+        }
+    }
+}
+
+// The previous sweep's reduction, folded into this one: the first wave of
+// workgroup 0 reduces every column before its tiles.  The partials were
+// written by the previous launch, so they are complete and visible.
+template <typename T, typename VT>
+__device__ __forceinline__ void fused_reduction(const KArgs<T, VT>& a, int b_out, int tid) {
+    if (a.red_src != nullptr && b_out == 0 && tid < 64)
+        for (int c = 0; c < a.nb; ++c)
+            reduce_column_wave(a.red_src, a.red_grid, a.nb, c, a.red_mode, a.red_out, a.red_M, a.red_step,
+                               a.red_invD, tid);
+}
+
 template <class P, typename T, typename VT>
 __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, int y0, int ny, int64_t t0,
                                             int64_t t1) {
@@ -400,6 +452,7 @@ __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, in
     const int nb = a.nb;
     const int c = tid & (nb - 1);
     const int o = (tid >> a.lognb) & (NO - 1);
+    fused_reduction(a, b_out, tid);
 
     double al = a.alpha, be = a.beta, ga = a.gamma;
     if (a.colp != nullptr) {
@@ -879,6 +932,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     const int c = tid & (nb - 1);
     const int o = (tid >> a.lognb) & (NO - 1);
     const int site = a.st_site;
+    fused_reduction(a, b_out, tid);
 
     // per-column alpha, beta, gamma only in the run-time epilogue (the
     // specialised ones are launched with uniform values)
@@ -1182,6 +1236,13 @@ void make_kargs(const SweepParams& p, bool whole_part, KArgs<T, VT>& a) {
     a.offs = p.offs;
     a.colp = p.colp;
     a.partials = p.partials;
+    a.red_src = p.red_src;
+    a.red_out = p.red_out;
+    a.red_grid = p.red_grid;
+    a.red_mode = p.red_mode;
+    a.red_M = p.red_M;
+    a.red_step = p.red_step;
+    a.red_invD = p.red_invD;
     a.Lx = int(p.L[0]);
     a.Ly = int(p.L[1]);
     a.Lz = int(p.L[2]);

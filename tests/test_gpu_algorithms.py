@@ -49,6 +49,26 @@ def test_kpm_moments_c64_stated_error():
     assert np.abs(mu - ref).max() < 1e-4
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_kpm_folded_and_separate_reductions_agree(kernel):
+    """Blocks of up to 2^22 elements fold each step's moment reduction into
+    the next sweep; larger ones reduce in a launch of their own.  On TI 64^3
+    (D = 2^20 rows) nb = 1 takes the first path and nb = 8 the second: the
+    shared column's moments agree to rounding, and mu_0 = 1."""
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lat = pv.Lattice((64, 64, 64), (1, 1, 1), st)
+    lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(1, 1))).to("cuda"))
+    r8 = W.random_phase_device(lat.n_rows, 8, 77, torch.device("cuda"))
+    r1 = r8[:, :1].contiguous()
+    for nb in (1, 8):
+        pv.pv_lattice_set_tuning(lat, pv.PV_C128, nb, {"kernel": kernel})
+    M = 24
+    mu1 = host(pv.pv_kpm_moments(lat, r1, M, 7.0, 0.0))
+    mu8 = host(pv.pv_kpm_moments(lat, r8, M, 7.0, 0.0))
+    assert np.abs(mu1[0] - mu8[0]).max() < 1e-13
+    assert np.abs(mu8[:, 0] - 1.0).max() < 1e-14 and abs(mu1[0, 0] - 1.0) < 1e-14
+
+
 def test_kpm_deterministic():
     c = Case("ti", (10, 9, 8), (1, 1, 1))
     r = dev(c.block(4, kind="phase"))
