@@ -172,9 +172,16 @@ def cpu_baseline(nb: int, budget_s: float = 12.0) -> dict:
         if el > budget_s:
             break
     glups = olat.n_rows * nb * sweeps / el / 1e9
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(glups, 5), "unit": "GLUP/s", "cores": 1, "kind": "oracle",
             "sample": f"TI {L[0]}x{L[1]}x{L[2]} periodic (4 of 64 z-layers), W=2, nb={nb}, complex128, "
-                      f"{sweeps} Chebyshev sweeps + dots in {el:.1f} s, scipy CSR + numpy, 1 thread"}
+                      f"{sweeps} Chebyshev sweeps + dots in {el:.1f} s, scipy CSR + numpy, 1 thread",
+            "host": f"{os.cpu_count()} logical CPUs visible, {model}"}
 
 
 def _timed(torch, fn, reps=1):
@@ -579,6 +586,7 @@ def main():
     out = {
         "metric": METRIC,
         "value": round(glups, 3),
+        "site_GLUP/s": round(lat.n_sites * args.nb / (ms * 1e-3) / 1e9, 3),
         "unit": "GLUP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -596,6 +604,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": counted_traffic(args.dtype, args.nb, shape),
+                     "traffic_GBs": (None if counted_traffic(args.dtype, args.nb, shape) is None else
+                                     round(counted_traffic(args.dtype, args.nb, shape) / (ms * 1e-3) / 1e9, 1)),
                      "kernel": ("staged_kernel<PatTI>" if shape["kernel"] == 2 else "sweep_kernel<PatTI>")
                                + " (Chebyshev step, fused dots) + reduce_dots_kernel",
                      "launch_shape": shape,
