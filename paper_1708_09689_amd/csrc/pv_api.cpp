@@ -211,11 +211,10 @@ pv_status ensure_device(pv_lattice* l) {
 // is kept near PV_SLAB_BYTES (default 2 MiB) so the +-z neighbour rows of a
 // plane are still in that XCD's 4 MiB L2 when the next plane is swept.
 int slab_rows(const pv_lattice* l, int dtype, int nb) {
-    static long long target = -1;
-    if (target < 0) {
+    static const long long target = [] {
         const char* e = getenv("PV_SLAB_BYTES");
-        target = e ? atoll(e) : (2ll << 20);
-    }
+        return e ? atoll(e) : (2ll << 20);
+    }();
     const long long site = (long long)l->n_orb * nb * (dtype == PV_C128 ? 16 : 8);
     const long long ny_max = (l->L[1] + 7) / 8;
     long long by = target / (l->L[0] * site);

@@ -1185,11 +1185,10 @@ void staged_kernel(KArgs<T, VT> a) {
 // fewer partial dot products to reduce).  PV_TILES_PER_BLOCK overrides it
 // for tuning runs.
 int tiles_per_block(int64_t ntiles) {
-    static int forced = -2;
-    if (forced == -2) {
+    static const int forced = [] {
         const char* e = getenv("PV_TILES_PER_BLOCK");
-        forced = e ? atoi(e) : -1;
-    }
+        return e ? atoi(e) : -1;
+    }();
     if (forced > 0) return forced;
     int64_t tpb = ntiles / (256 * 32);
     if (tpb < 1) tpb = 1;
@@ -1199,13 +1198,12 @@ int tiles_per_block(int64_t ntiles) {
 
 template <class P, typename T, typename VT>
 int occupancy_blocks() {
-    static int cached = -1;
-    if (cached < 0) {
+    static const int cached = [] {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<P, T, VT>, kBlock, 0) != hipSuccess || n < 1)
             n = 1;
-        cached = n;
-    }
+        return n;
+    }();
     return cached;
 }
 
@@ -1295,9 +1293,9 @@ int env_int(const char* name, int dflt) {
     return e ? atoi(e) : dflt;
 }
 
+// LDS of a staged kernel instance (independent of nb: tiles are elements)
 template <class P, typename T, int E, unsigned EPM, int NT = kBlock>
-size_t staged_lds_bytes(int nb) {
-    (void)nb;
+size_t staged_lds_bytes() {
     return staged_lds_bytes_for<P, T, E, NT>(EPM == 0u || (EPM & EP_ACC_ADD) != 0u);
 }
 
@@ -1342,29 +1340,24 @@ template <class P, typename T, typename VT, int E, unsigned EPM, int NT = kBlock
 hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
     KArgs<T, VT> a;
     make_kargs<P, T, VT>(p, false, a);
-    const size_t lds = staged_lds_bytes<P, T, E, EPM, NT>(p.nb);
-    const void* kern = reinterpret_cast<const void*>(&staged_kernel<P, T, VT, E, EPM, NT>);
-    // workgroups resident per CU at this LDS size (cached per size)
-    static size_t occ_lds[8] = {};
-    static int occ_n[8] = {};
-    int occ = 0;
-    for (int i = 0; i < 8; ++i)
-        if (occ_lds[i] == lds) occ = occ_n[i];
-    if (occ == 0) {
-        if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-            if (e != hipSuccess) return e;
+    // LDS size and workgroups resident per CU: fixed per kernel instance,
+    // set up once (thread-safe initialisation of the local static)
+    static const std::pair<hipError_t, int> occ_res = [] {
+        const size_t bytes = staged_lds_bytes<P, T, E, EPM, NT>();
+        if (bytes > 65536) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&staged_kernel<P, T, VT, E, EPM, NT>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+            if (e != hipSuccess) return std::make_pair(e, 0);
         }
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, staged_kernel<P, T, VT, E, EPM, NT>, NT, lds) !=
-                hipSuccess || occ < 1)
-            occ = 1;
-        for (int i = 0; i < 8; ++i)
-            if (occ_lds[i] == 0) {
-                occ_lds[i] = lds;
-                occ_n[i] = occ;
-                break;
-            }
-    }
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, staged_kernel<P, T, VT, E, EPM, NT>, NT, bytes) !=
+                hipSuccess || n < 1)
+            n = 1;
+        return std::make_pair(hipSuccess, n);
+    }();
+    if (occ_res.first != hipSuccess) return occ_res.first;
+    const int occ = occ_res.second;
+    const size_t lds = staged_lds_bytes<P, T, E, EPM, NT>();
     int G8 = p.st_G8 > 0 ? p.st_G8 : (num_cus >= 8 ? num_cus / 8 : 1) * occ;
     if (G8 > 256) G8 = 256;
     G8 = staged_setup<P, T, VT, E, NT>(p, G8, false, a);
@@ -1536,7 +1529,7 @@ hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* 
                 constexpr unsigned KPM = EP_STORE_Y | EP_DOTS;
                 auto go = [&](auto ke) -> hipError_t {
                     constexpr int E = decltype(ke)::value;
-                    const size_t lds = staged_lds_bytes<P, T, E, KPM>(p.nb);
+                    const size_t lds = staged_lds_bytes<P, T, E, KPM>();
                     if (lds > 65536) {
                         hipError_t e = hipFuncSetAttribute(
                             reinterpret_cast<const void*>(&batch_staged_kernel<P, T, VT, E, KPM>),

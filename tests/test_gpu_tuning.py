@@ -148,3 +148,44 @@ def test_autotune_applies_and_caches(tmp_path):
     coef = g.standard_normal(12) + 1j * g.standard_normal(12)
     pv.pv_cheb_series(c2.lat, dev(x), y, 7.0, 0.1, coef)
     assert rel_err(host(y), chebtp.cheb_series(c2.H, x, 7.0, 0.1, coef)) < 1e-12
+
+
+def test_concurrent_host_threads():
+    """Four host threads, each with its own lattice, stream and block width,
+    sweep at the same time (the launchers' one-time set-up is shared): every
+    result equals the one computed alone."""
+    import threading
+    cases = [("ti", (20, 9, 6), (1, 1, 1), 4), ("ti", (17, 8, 7), (1, 0, 1), 16),
+             ("weyl", (11, 6, 5), (1, 1, 0), 8), ("graphene2", (40, 12), (0, 1), 2)]
+    setups = []
+    for i, (name, L, per, nb) in enumerate(cases):
+        c = Case(name, L, per, Wd=1.0, seed=40 + i)
+        setups.append((c, nb, dev(c.block(nb, seed=1)), dev(c.block(nb, seed=2))))
+
+    def run(c, nb, x, z):
+        y = z.clone()
+        d = pv.pv_spmmv(c.lat, x, y, 0.3, 0.1, -1.0, z=y, dot_flags=3)
+        torch.cuda.current_stream().synchronize()
+        return host(y), host(d)
+
+    alone = [run(*s) for s in setups]
+    out = [None] * len(setups)
+    errs = []
+
+    def worker(k):
+        try:
+            with torch.cuda.stream(torch.cuda.Stream()):
+                for _ in range(5):
+                    out[k] = run(*setups[k])
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(len(setups))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for (y0, d0), (y1, d1) in zip(alone, out):
+        assert np.array_equal(y0, y1)
+        assert np.array_equal(d0, d1)
