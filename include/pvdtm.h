@@ -36,6 +36,11 @@
  * minimum size.  Too small a workspace gives PV_ERR_WORKSPACE.
  * Determinism.  Reductions use fixed-order two-pass sums (no floating-point
  * atomics): repeated calls with the same inputs give bitwise equal results.
+ * Threads.  Calls from several host threads may run at once on different
+ * objects, or on one lattice or batch when none of them changes it
+ * (set_potential, set_random_potential, set_tuning, autotune and the batch
+ * calls, which rebuild their graph, change it); the caller serialises
+ * changes of an object against every other use of it.
  */
 #ifndef PVDTM_H
 #define PVDTM_H
