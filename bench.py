@@ -41,9 +41,9 @@ A_SCALE, B_SHIFT = 7.0, 0.0
 _STAGED = {"kernel": 2, "walk_planes": 0, "strip_rows": 0, "groups_per_xcd": 0, "tiles_per_group": 0, "slab_rows": 0,
            "workgroup_size": 0}
 COUNTED_TRAFFIC = {
-    ("c128", 32): [(dict(_STAGED, elems_per_lane=2, strip_rows=32, workgroup_size=512), 35_475_000_000),
-                   (dict(_STAGED, elems_per_lane=2, strip_rows=64, workgroup_size=512), 35_557_000_000)],
-    ("c64", 16): [(dict(_STAGED, elems_per_lane=4, workgroup_size=512), 6_968_000_000)],
+    ("c128", 32): [(dict(_STAGED, elems_per_lane=2, strip_rows=32, workgroup_size=512), 35_685_000_000),
+                   (dict(_STAGED, elems_per_lane=2, strip_rows=64, workgroup_size=512), 35_700_000_000)],
+    ("c64", 16): [(dict(_STAGED, elems_per_lane=4, workgroup_size=512), 6_957_000_000)],
 }
 
 
@@ -230,12 +230,15 @@ def bench_chebtp_graphene(pv, torch, W, dev, steps=5):
     lat.set_potential(torch.from_numpy(W.dot_array_potential(Li, Lj)).to(dev))
     psi = torch.from_numpy(W.gaussian_wave_packet(Li, Lj, i0=200, width=50, energy=0.2).reshape(-1, 1)).to(dev)
     pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, 1)
-    ms = _timed(torch, lambda: pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, steps)) / steps
+    # median of three runs of `steps` time steps (one run is ~10 ms)
+    runs = sorted(_timed(torch, lambda: pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, steps)) / steps
+                  for _ in range(3))
+    ms = runs[1]
     norm = float(torch.linalg.vector_norm(psi).item())
     lups = lat.n_rows * 64
     by = lat.n_rows * (4 * 16) + lat.n_sites * 8   # x, z, acc in/out (+y) per sweep, field
     return {"workload": "graphene 1024x1024 cells x 2 sites, open x / periodic y, dot array, packet; "
-                        f"{steps} time steps of dt=10, M=64, complex128",
+                        f"runs of {steps} time steps of dt=10 (median of 3), M=64, complex128",
             "ms_per_time_step": round(ms, 4), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
             "norm_after": round(norm, 12), "approx_GB/s": round(by * 64 / (ms * 1e-3) / 1e9, 1),
             "note": "working set ~170 MB: largely resident in the 256 MB Infinity Cache"}
@@ -533,7 +536,7 @@ def main():
             set_field(dtype)
             for nb in (1, 4, 16, 32):
                 s2 = Sweep(pv, torch, lat, nb, dtype, dev)
-                m2 = time_steps(torch, s2, 3, 10)
+                m2 = time_steps(torch, s2, 3, 20)
                 b2 = bytes_per_step(lat.n_rows, lat.n_sites, nb, dtype)
                 variants.append({"dtype": dtype, "nb": nb, "shape": s2.shape, "ms_per_step": round(m2, 5),
                                  "GLUP/s": round(lat.n_rows * nb / (m2 * 1e-3) / 1e9, 3),
@@ -548,7 +551,7 @@ def main():
             lat.set_random_potential(W.MASTER_SEED + WORKLOAD_INDEX, 2.0)
             for nb in (1, 4):
                 s2 = Sweep(pv, torch, lat, nb, dtype, dev)
-                m2 = time_steps(torch, s2, 3, 10)
+                m2 = time_steps(torch, s2, 3, 20)
                 b2 = bytes_per_step(lat.n_rows, 0, nb, dtype)
                 variants.append({"dtype": dtype, "nb": nb, "field": "generated in the kernel",
                                  "ms_per_step": round(m2, 5),
@@ -583,6 +586,18 @@ def main():
 
     cpu = None if args.no_cpu else cpu_baseline(args.nb)
 
+    # the metric's comparisons in one place: FP64 vs FP32 vectors at the
+    # headline block width, forward vs forward + adjoint
+    parts = {"fp64": {"GLUP/s": round(glups, 3), "frac_hbm_peak": round(achieved / HBM_PEAK_GBS, 4)}}
+    v32 = [v for v in variants if v["dtype"] == "c64" and v["nb"] == args.nb and "field" not in v]
+    if v32:
+        parts["fp32_vectors_fp64_dots"] = {"GLUP/s": v32[0]["GLUP/s"], "frac_hbm_peak": v32[0]["frac_hbm_peak"]}
+    if "adjoint" in configs:
+        ti = configs["adjoint"]["ti"]
+        parts["forward_vs_forward_plus_adjoint"] = {"workload": ti["workload"], "fwd_GLUP/s": ti["fwd_GLUP/s"],
+                                                    "fwd+adj_GLUP/s": ti["fwd+adj_GLUP/s"],
+                                                    "grad_over_fwd": ti["grad_over_fwd"]}
+
     out = {
         "metric": METRIC,
         "value": round(glups, 3),
@@ -614,6 +629,7 @@ def main():
         "frac_of_copy_probe": None if copy_gbs is None else round(achieved / copy_gbs, 4),
         "triad_probe_GBs": None if triad_gbs is None else round(triad_gbs, 1),
         "frac_of_triad_probe": None if triad_gbs is None else round(achieved / triad_gbs, 4),
+        "metric_parts": parts,
         "variants": variants,
         "workloads": configs,
         "cpu_baseline": cpu,
