@@ -259,6 +259,29 @@ def bench_filter(pv, torch, lat, dev, nb=32, K=8):
             "GB/s": round(by / (ms * 1e-3) / 1e9, 1), "bytes_per_LUP": 80}
 
 
+def bench_plain(pv, torch, lat, dev):
+    """The plain stencil SpMMV y = alpha (H x - beta x) on the 256x256x64 TI
+    (gamma = 0: y is written only), complex128, in the launch shape the
+    lattice holds for that block width (the autotuner's, when the variants
+    ran first): two vector streams and the field."""
+    import workloads as W
+    out = {}
+    for nb in (4, 32):
+        x = W.random_phase_device(lat.n_rows, nb, 78, dev)
+        y = torch.empty_like(x)
+        pv.pv_spmmv(lat, x, y, 1.0 / A_SCALE, B_SHIFT, 0.0, nb=nb)
+        ms = _timed(torch, lambda: pv.pv_spmmv(lat, x, y, 1.0 / A_SCALE, B_SHIFT, 0.0, nb=nb), 20)
+        by = lat.n_rows * nb * 16 * 2 + lat.n_sites * 8
+        out[f"nb{nb}"] = {"ms_per_sweep": round(ms, 4), "GLUP/s": round(lat.n_rows * nb / (ms * 1e-3) / 1e9, 3),
+                          "GB/s": round(by / (ms * 1e-3) / 1e9, 1),
+                          "bytes_per_LUP": round(by / (lat.n_rows * nb), 3),
+                          "shape": {k: v for k, v in pv.pv_lattice_get_tuning(lat, pv.PV_C128, nb).items() if v}}
+        del x, y
+        torch.cuda.empty_cache()
+    out["workload"] = "TI 256x256x64, W=2, complex128, y = alpha (H - beta) x"
+    return out
+
+
 def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16, loop_M=64):
     """96 TI disorder realisations, L ~ U{24..96}, W ~ U[0.5, 3], 16 random-phase
     columns, M = 1024: one graph-captured batched launch per step with
@@ -569,6 +592,7 @@ def main():
         set_field("c128")
         for name, fn in (("kpm_ti16", lambda: bench_kpm16(pv, torch, W, dev)),
                          ("filter_sweeps_ti256", lambda: bench_filter(pv, torch, lat, dev)),
+                         ("plain_spmmv_ti256", lambda: bench_plain(pv, torch, lat, dev)),
                          ("chebtp_graphene1024", lambda: bench_chebtp_graphene(pv, torch, W, dev)),
                          ("batched_kpm_96", lambda: bench_batch(pv, torch, W, dev)),
                          ("adjoint", lambda: bench_adjoint(pv, torch, W, dev)),
