@@ -36,6 +36,7 @@ enum : unsigned {
     EP_DOTS = 8u,        // per-block partial dots (xx, Re xy, Im xy, yy)
     EP_GTERMS = 16u,     // y += sum_j gcoef[j][c] gw_j (adjoint source terms)
     EP_GRAD = 32u,       // grad += gx Re(conj(x) gw_1) + gy Re(conj(y) gw_0) per site/row
+    EP_NO_Z = 64u,       // launch-internal: gamma = 0, z is neither loaded nor staged
 };
 
 struct SweepParams {

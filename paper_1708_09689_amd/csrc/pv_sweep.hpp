@@ -730,7 +730,8 @@ struct StagedSide {
     u32x4 acc[Staged<T, E, NT>::TCH];
 };
 
-template <class P, typename T, typename VT, int E, bool ACC, int NT>
+// ZL: the step reads z (every epilogue but the plain sweep with gamma = 0)
+template <class P, typename T, typename VT, int E, bool ACC, int NT, bool ZL = true>
 struct StagedCtx {
     using S = Staged<T, E, NT>;
     using Set = StagedSet<P, T, VT, E, NT>;
@@ -812,8 +813,10 @@ struct StagedCtx {
         const int wr = w_row < wb ? w_row : wb - 1;
         const int64_t rw = row_of(m, wr);
         const cplx<T>* zr = a.zsrc + rw * a.rowel;
+        if constexpr (ZL) {
 #pragma unroll
-        for (int k = 0; k < S::TCH; ++k) st.z[k] = ld_chunk_nt<T>(zr, soff[k]);
+            for (int k = 0; k < S::TCH; ++k) st.z[k] = ld_chunk_nt<T>(zr, soff[k]);
+        }
         // stored field entries (a row of the zero row's bytes when the field
         // is absent or generated; those values are not used)
         st.vrow = rw * a.Lx * (a.pot_mode == 1 ? 1 : P::NO);
@@ -864,9 +867,11 @@ struct StagedCtx {
         u32x4* d = reinterpret_cast<u32x4*>(ring + slot * a.st_seg);
 #pragma unroll
         for (int k = 0; k < S::RCH; ++k) d[tid + k * S::NTH] = st.ring[k];
-        u32x4* dz = reinterpret_cast<u32x4*>(zl);
+        if constexpr (ZL) {
+            u32x4* dz = reinterpret_cast<u32x4*>(zl);
 #pragma unroll
-        for (int k = 0; k < S::TCH; ++k) dz[tid + k * S::NTH] = st.z[k];
+            for (int k = 0; k < S::TCH; ++k) dz[tid + k * S::NTH] = st.z[k];
+        }
         if (a.field == 2) {
 #pragma unroll
             for (int k = 0; k < E; ++k) vl[tid + k * S::NTH] = field_at(a, st.vrow + voff[k]);
@@ -920,7 +925,8 @@ template <class P, typename T, typename VT, int E, unsigned EPM, int NT>
 __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, int part, int jb, int G) {
     using S = Staged<T, E, NT>;
     constexpr bool ACC = EPM == 0u || (EPM & EP_ACC_ADD) != 0u;
-    using Ctx = StagedCtx<P, T, VT, E, ACC, NT>;
+    constexpr bool ZL = (EPM & EP_NO_Z) == 0u;
+    using Ctx = StagedCtx<P, T, VT, E, ACC, NT, ZL>;
     using Set = typename Ctx::Set;
     constexpr int NO = P::NO;
     constexpr int NTR = Ctx::NTR;
@@ -1102,7 +1108,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 xs_[k] = xc;
                 yr[k] = hr;
                 yi[k] = hi;
-                zv[k] = cx.zl[l];
+                zv[k] = ZL ? cx.zl[l] : cplx<T>{T(0), T(0)};
                 av[k] = ACC ? cx.al[l] : cplx<T>{T(0), T(0)};
             }
             lds_barrier();
@@ -1368,8 +1374,8 @@ hipError_t launch_staged(SweepParams& p, int num_cus, hipStream_t s) {
 
 // Epilogue specialisations of the staged kernel: the Chebyshev step with
 // fused dots (KPM), the series step (propagation, filters), the plain sweep
-// or Chebyshev step without dots, and every other combination with the
-// flags read at run time.
+// or Chebyshev step without dots (with gamma = 0: no z stream at all), and
+// every other combination with the flags read at run time.
 template <class P, typename T, typename VT, int E>
 hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
     constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD, PLAIN = EP_STORE_Y;
@@ -1378,12 +1384,16 @@ hipError_t launch_staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
             if (p.st_nt == 512) {
                 if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM, 512>(p, num_cus, s);
                 if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES, 512>(p, num_cus, s);
-                if (p.ep == PLAIN) return launch_staged<P, T, VT, E, PLAIN, 512>(p, num_cus, s);
+                if (p.ep == PLAIN)
+                    return p.gamma == 0.0 ? launch_staged<P, T, VT, E, PLAIN | EP_NO_Z, 512>(p, num_cus, s)
+                                          : launch_staged<P, T, VT, E, PLAIN, 512>(p, num_cus, s);
             }
         }
         if (p.ep == KPM) return launch_staged<P, T, VT, E, KPM>(p, num_cus, s);
         if (p.ep == SERIES) return launch_staged<P, T, VT, E, SERIES>(p, num_cus, s);
-        if (p.ep == PLAIN) return launch_staged<P, T, VT, E, PLAIN>(p, num_cus, s);
+        if (p.ep == PLAIN)
+            return p.gamma == 0.0 ? launch_staged<P, T, VT, E, PLAIN | EP_NO_Z>(p, num_cus, s)
+                                  : launch_staged<P, T, VT, E, PLAIN>(p, num_cus, s);
     }
     if constexpr (sizeof(T) == 8 && E == 2) {
         // the run-time epilogue at two complex128 elements per lane needs more

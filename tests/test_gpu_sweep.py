@@ -108,6 +108,24 @@ def test_per_column_and_gamma_zero_semantics():
     assert rel_err(out, spmmv.spmmv(c.H, x, alpha, beta, 0.0)) < 1e-13
 
 
+@pytest.mark.parametrize("name,L,periodic", [("ti", (21, 6, 5), (1, 1, 1)), ("ti", (9, 7, 6), (0, 1, 0)),
+                                             ("weyl", (13, 5, 4), (1, 0, 1)), ("graphene2", (37, 11), (0, 1))])
+@pytest.mark.parametrize("nb", [1, 4, 16])
+@pytest.mark.parametrize("sh", [{"kernel": 1}, {"kernel": 2}, {"kernel": 2, "elems_per_lane": 2},
+                                {"kernel": 2, "elems_per_lane": 2, "workgroup_size": 512}])
+def test_plain_sweep_gamma_zero_uniform(name, L, periodic, nb, sh):
+    """Uniform alpha, beta and gamma = 0 take the plain staged kernel that
+    loads no z: y starts as NaN and must come out as alpha (H x - beta x)."""
+    c = Case(name, L, periodic, Wd=1.5, seed=nb)
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, sh)
+    x = c.block(nb, seed=5)
+    y = dev(np.full((c.D, nb), np.nan + 0j))
+    pv.pv_spmmv(c.lat, dev(x), y, 0.6, -0.3, 0.0)
+    out = host(y)
+    assert np.isfinite(out).all()
+    assert rel_err(out, spmmv.spmmv(c.H, x, 0.6, -0.3, 0.0)) < 1e-13
+
+
 def test_sweep_is_deterministic():
     c = Case("ti", (33, 17, 9), (1, 1, 1))
     x = dev(c.block(4))
