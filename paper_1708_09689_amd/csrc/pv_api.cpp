@@ -1305,13 +1305,14 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
     auto search = [&](pv_tuning& best, double& best_ms) {
         best = pv_tuning{};
         best_ms = 1e300;
-        auto consider = [&](const pv_tuning& t) {
+        // a candidate must beat the incumbent by 1% (timing noise would
+        // otherwise flip between near-equal shapes from run to run), plus
+        // `extra`, the fraction of the step's bytes it moves on top
+        auto consider = [&](const pv_tuning& t, double extra = 0.0) {
             if (herr != hipSuccess) return;
             double ms = 0;
             herr = measure(t, ms);
-            // a candidate must beat the incumbent by 1% (timing noise would
-            // otherwise flip between near-equal shapes from run to run)
-            if (herr == hipSuccess && ms < 0.99 * best_ms) {
+            if (herr == hipSuccess && ms < (0.99 - extra) * best_ms) {
                 best_ms = ms;
                 best = t;
             }
@@ -1334,7 +1335,14 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         }
         if (best.kernel == 2) {
             for (int v : {4, 8, 16, 32, 64}) { t = best; t.strip_rows = v; consider(t); }
-            for (int v : {8, 16, 32}) if (v < lw) { t = best; t.walk_planes = v; consider(t); }
+            // a walk of v planes re-reads two ring rows that a whole walk
+            // reads once per lw planes: x is one of about three streams
+            for (int v : {8, 16, 32})
+                if (v < lw) {
+                    t = best;
+                    t.walk_planes = v;
+                    consider(t, (2.0 / v - 2.0 / lw) / 3.0);
+                }
             for (int v : {32, 64, 96, 128}) { t = best; t.groups_per_xcd = v; consider(t); }
         } else {
             for (int v : {32, 64}) { t = best; t.tiles_per_group = v; consider(t); }
