@@ -4,6 +4,7 @@ full (as the autotuner returns it) or with the defaults left out (as it is
 pinned on the command line), and nothing else."""
 
 import os
+import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -37,3 +38,10 @@ def test_counted_traffic_is_null_for_other_shapes():
     shape["groups_per_xcd"] = 17
     assert bench.counted_traffic(dtype, nb, full(shape)) is None
     assert bench.counted_traffic(dtype, nb + 1, full(entries[0][0])) is None
+
+
+def test_bench_refuses_several_gpus():
+    """One GPU only: --gpus above 1 exits with a message before touching a GPU."""
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert out.returncode != 0 and "one GPU" in out.stderr
