@@ -1945,7 +1945,7 @@ struct pv_batch {
 namespace {
 
 struct BatchLayout {
-    size_t tables, block_inst, inst_block0, invD, partials, moments, vecs, total;
+    size_t tables, block_inst, inst_block0, invD, partials, partial_stride, moments, vecs, total;
     std::vector<size_t> vec_off;  // per instance: A at vec_off[i], B at vec_off[i] + vb_i
     std::vector<int> nblocks;
     int total_blocks;
@@ -2010,7 +2010,10 @@ pv_status batch_layout(const pv_batch* B, int dtype, int nb, int M, int staged, 
     L.block_inst = off; off += align_up(sizeof(int) * cap);
     L.inst_block0 = off; off += align_up(sizeof(int) * (n + 1));
     L.invD = off; off += align_up(sizeof(double) * n);
-    L.partials = off; off += align_up((size_t)cap * nb * 4 * sizeof(double));
+    // two partial buffers: step n writes buffer n % 2 while its sweep folds
+    // in the reduction of step n - 1 from the other
+    L.partials = off; off += 2 * align_up((size_t)cap * nb * 4 * sizeof(double));
+    L.partial_stride = align_up((size_t)cap * nb * 4 * sizeof(double));
     L.moments = off; off += align_up((size_t)n * nb * M * sizeof(double));
     L.vecs = off;
     L.vec_off.resize(n);
@@ -2142,7 +2145,20 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
             pv::SweepParams p = batch_params(B, i, dtype, nb);
             p.zero_row = l->d_zero;
             p.slab_rows = slab_rows(l, dtype, nb);
-            p.partials = reinterpret_cast<double*>(w + L.partials);
+            // variants 0 and 2 run even steps, 1 and 3 odd ones: dots into
+            // buffer v % 2; every step after the first folds in the previous
+            // step's reduction (this instance's rows of the other buffer)
+            double* part[2] = {reinterpret_cast<double*>(w + L.partials),
+                               reinterpret_cast<double*>(w + L.partials + L.partial_stride)};
+            p.partials = part[v & 1];
+            if (v > 0) {
+                p.red_src = part[(v & 1) ^ 1] + (size_t)inst_block0[i] * nb * 4;
+                p.red_out = reinterpret_cast<double*>(mu_ws) + (size_t)i * nb * M;
+                p.red_grid = L.nblocks[i];
+                p.red_mode = v == 1 ? 1 : 2;
+                p.red_M = M;
+                p.red_invD = invD[i];
+            }
             p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
             p.beta = b[i];
             if (v == 0) {          // w_1 = H~ w_0
@@ -2170,7 +2186,8 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     const int* d_bi = reinterpret_cast<const int*>(w + L.block_inst);
     const int* d_i0 = reinterpret_cast<const int*>(w + L.inst_block0);
     const double* d_invD = reinterpret_cast<const double*>(w + L.invD);
-    const double* d_part = reinterpret_cast<const double*>(w + L.partials);
+    const double* d_part[2] = {reinterpret_cast<const double*>(w + L.partials),
+                               reinterpret_cast<const double*>(w + L.partials + L.partial_stride)};
     const int vtype = (dtype == PV_C128) ? 0 : B->lats[0]->vtype;
     for (int i = 1; i < n; ++i)
         if (dtype != PV_C128 && B->lats[i]->vtype != vtype && (B->lats[i]->V || B->lats[0]->V))
@@ -2180,14 +2197,17 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     p0.ep = pv::EP_STORE_Y | pv::EP_DOTS;
     PV_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
+    // one launch per step (each folds in the previous step's moments), then
+    // the last step's reduction
     for (int step = 0; step < M / 2 && e == hipSuccess; ++step) {
         const int v = step == 0 ? 0 : (step == 1 ? 1 : (step % 2 == 0 ? 2 : 3));
         e = pv::launch_batch_sweep(p0, L.staged, w + L.tables + (size_t)v * n * rb, d_bi, d_i0, L.total_blocks,
-                                   B->cap);
-        if (e == hipSuccess)
-            e = pv::launch_batch_reduce(d_part, d_i0, n, nb, step == 0 ? 1 : 2, reinterpret_cast<double*>(mu_ws), M,
-                                        step, d_invD, B->cap);
+                                   step - 1, B->cap);
     }
+    const int last = M / 2 - 1;
+    if (e == hipSuccess)
+        e = pv::launch_batch_reduce(d_part[last & 1], d_i0, n, nb, last == 0 ? 1 : 2,
+                                    reinterpret_cast<double*>(mu_ws), M, last, d_invD, B->cap);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {

@@ -23,11 +23,14 @@ hipError_t batch_fill_record_generic(const SweepParams& p, int staged, void* dst
 }
 
 hipError_t launch_batch_sweep_generic(const SweepParams& p, int staged, const void* table, const int* block_inst,
-                                      const int* inst_block0, int grid, hipStream_t s) {
+                                      const int* inst_block0, int grid, int red_step, hipStream_t s) {
     switch (p.n_orb) {
-        case 1: return launch_batch_sweep_fam<PatGeneric<1>>(p, staged, table, block_inst, inst_block0, grid, s);
-        case 2: return launch_batch_sweep_fam<PatGeneric<2>>(p, staged, table, block_inst, inst_block0, grid, s);
-        case 4: return launch_batch_sweep_fam<PatGeneric<4>>(p, staged, table, block_inst, inst_block0, grid, s);
+        case 1: return launch_batch_sweep_fam<PatGeneric<1>>(p, staged, table, block_inst, inst_block0, grid, red_step,
+                                                             s);
+        case 2: return launch_batch_sweep_fam<PatGeneric<2>>(p, staged, table, block_inst, inst_block0, grid, red_step,
+                                                             s);
+        case 4: return launch_batch_sweep_fam<PatGeneric<4>>(p, staged, table, block_inst, inst_block0, grid, red_step,
+                                                             s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -12,8 +12,8 @@ hipError_t batch_fill_record_graphene4(const SweepParams& p, int staged, void* d
 }
 
 hipError_t launch_batch_sweep_graphene4(const SweepParams& p, int staged, const void* table, const int* block_inst,
-                                  const int* inst_block0, int grid, hipStream_t s) {
-    return launch_batch_sweep_fam<PatGraphene4>(p, staged, table, block_inst, inst_block0, grid, s);
+                                  const int* inst_block0, int grid, int red_step, hipStream_t s) {
+    return launch_batch_sweep_fam<PatGraphene4>(p, staged, table, block_inst, inst_block0, grid, red_step, s);
 }
 
 }  // namespace pv

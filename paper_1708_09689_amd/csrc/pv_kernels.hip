@@ -16,45 +16,18 @@ __global__ __launch_bounds__(64) void reduce_dots_kernel(const double* __restric
     reduce_column_wave(partials, grid, nb, blockIdx.x, mode, out, M, step, inv_D, threadIdx.x);
 }
 
-// Per-instance fixed-order reduction of a batched sweep: workgroup
+// Per-instance fixed-order reduction of a batched sweep: one wave per
 // (instance i, column c) sums the partials of the instance's workgroups
 // [inst_block0[i], inst_block0[i+1]) and updates mu[i][c][.] (modes 1, 2 of
-// reduce_dots_kernel).
-__global__ __launch_bounds__(kBlock) void batch_reduce_kernel(const double* __restrict__ partials,
-                                                              const int* __restrict__ inst_block0, int nb,
-                                                              int mode, double* mu, int M, int step,
-                                                              const double* __restrict__ invD) {
+// reduce_dots_kernel), in the order of the reduction folded into a sweep.
+__global__ __launch_bounds__(64) void batch_reduce_kernel(const double* __restrict__ partials,
+                                                          const int* __restrict__ inst_block0, int nb, int mode,
+                                                          double* mu, int M, int step,
+                                                          const double* __restrict__ invD) {
     const int i = blockIdx.x / nb, c = blockIdx.x % nb;
     const int b0 = inst_block0[i], b1 = inst_block0[i + 1];
-    const int tid = threadIdx.x;
-    double s0 = 0, s1 = 0;
-    for (int b = b0 + tid; b < b1; b += kBlock) {
-        const double* q = partials + ((size_t)b * nb + c) * 4;
-        s0 += q[0];
-        s1 += q[1];
-    }
-    __shared__ double sh[2][kBlock];
-    sh[0][tid] = s0;
-    sh[1][tid] = s1;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-            sh[0][tid] += sh[0][tid + w];
-            sh[1][tid] += sh[1][tid + w];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double* m = mu + ((size_t)i * nb + c) * M;
-        const double xx = sh[0][0], xr = sh[1][0], d = invD[i];
-        if (mode == 1) {
-            m[0] = xx * d;
-            m[1] = xr * d;
-        } else {
-            m[2 * step] = 2.0 * xx * d - m[0];
-            m[2 * step + 1] = 2.0 * xr * d - m[1];
-        }
-    }
+    reduce_column_wave(partials + (size_t)b0 * nb * 4, b1 - b0, nb, c, mode, mu + (size_t)i * nb * M, M, step,
+                       invD[i], threadIdx.x);
 }
 
 template <typename T>
@@ -414,20 +387,23 @@ hipError_t batch_fill_record(const SweepParams& p, int staged, void* dst, int* n
 }
 
 hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* table, const int* block_inst,
-                              const int* inst_block0, int grid, hipStream_t s) {
+                              const int* inst_block0, int grid, int red_step, hipStream_t s) {
+    const void* t = table;
+    const int* bi = block_inst;
+    const int* i0 = inst_block0;
     switch (p.family) {
-        case FAM_TI: return launch_batch_sweep_ti(p, staged, table, block_inst, inst_block0, grid, s);
-        case FAM_GRAPHENE2: return launch_batch_sweep_graphene2(p, staged, table, block_inst, inst_block0, grid, s);
-        case FAM_GRAPHENE4: return launch_batch_sweep_graphene4(p, staged, table, block_inst, inst_block0, grid, s);
-        case FAM_WEYL: return launch_batch_sweep_weyl(p, staged, table, block_inst, inst_block0, grid, s);
-        default: return launch_batch_sweep_generic(p, staged, table, block_inst, inst_block0, grid, s);
+        case FAM_TI: return launch_batch_sweep_ti(p, staged, t, bi, i0, grid, red_step, s);
+        case FAM_GRAPHENE2: return launch_batch_sweep_graphene2(p, staged, t, bi, i0, grid, red_step, s);
+        case FAM_GRAPHENE4: return launch_batch_sweep_graphene4(p, staged, t, bi, i0, grid, red_step, s);
+        case FAM_WEYL: return launch_batch_sweep_weyl(p, staged, t, bi, i0, grid, red_step, s);
+        default: return launch_batch_sweep_generic(p, staged, t, bi, i0, grid, red_step, s);
     }
 }
 
 hipError_t launch_batch_reduce(const double* partials, const int* inst_block0, int n_inst, int nb, int mode,
                                double* mu, int M, int step, const double* invD, hipStream_t s) {
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(n_inst * nb), dim3(kBlock), 0, s, partials, inst_block0, nb, mode,
-                       mu, M, step, invD);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(n_inst * nb), dim3(64), 0, s, partials, inst_block0, nb, mode, mu,
+                       M, step, invD);
     return hipGetLastError();
 }
 

@@ -144,8 +144,10 @@ size_t batch_record_bytes();
 // dst = 0 (bytes a multiple of 4)
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
 hipError_t batch_fill_record(const SweepParams& p, int staged, void* dst, int* nblocks);
+// red_step: the moment step the records' folded reductions write (their
+// red_* fields say what to reduce; see SweepParams)
 hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* table, const int* block_inst,
-                              const int* inst_block0, int grid, hipStream_t s);
+                              const int* inst_block0, int grid, int red_step, hipStream_t s);
 hipError_t launch_batch_reduce(const double* partials, const int* inst_block0, int n_inst, int nb, int mode,
                                double* mu, int M, int step, const double* invD, hipStream_t s);
 

@@ -434,11 +434,12 @@ __device__ __forceinline__ void reduce_column_wave(const double* __restrict__ pa
 }
 
 // The previous sweep's reduction, folded into this one: the first wave of
-// workgroup 0 reduces every column before its tiles.  The partials were
-// written by the previous launch, so they are complete and visible.
+// the leading workgroup (workgroup 0, or an instance's first in a batched
+// launch) reduces every column before its tiles.  The partials were written
+// by the previous launch, so they are complete and visible.
 template <typename T, typename VT>
-__device__ __forceinline__ void fused_reduction(const KArgs<T, VT>& a, int b_out, int tid) {
-    if (a.red_src != nullptr && b_out == 0 && tid < 64)
+__device__ __forceinline__ void fused_reduction(const KArgs<T, VT>& a, bool lead, int tid) {
+    if (a.red_src != nullptr && lead && tid < 64)
         for (int c = 0; c < a.nb; ++c)
             reduce_column_wave(a.red_src, a.red_grid, a.nb, c, a.red_mode, a.red_out, a.red_M, a.red_step,
                                a.red_invD, tid);
@@ -446,13 +447,13 @@ __device__ __forceinline__ void fused_reduction(const KArgs<T, VT>& a, int b_out
 
 template <class P, typename T, typename VT>
 __device__ __forceinline__ void sweep_block(const KArgs<T, VT>& a, int b_out, int y0, int ny, int64_t t0,
-                                            int64_t t1) {
+                                            int64_t t1, bool lead) {
     constexpr int NO = P::NO;
     const int tid = threadIdx.x;
     const int nb = a.nb;
     const int c = tid & (nb - 1);
     const int o = (tid >> a.lognb) & (NO - 1);
-    fused_reduction(a, b_out, tid);
+    fused_reduction(a, lead, tid);
 
     double al = a.alpha, be = a.beta, ga = a.gamma;
     if (a.colp != nullptr) {
@@ -634,25 +635,27 @@ void sweep_kernel(KArgs<T, VT> a) {
     const int64_t ntl = (int64_t)a.ntx * ny * a.Lz;
     const int64_t t0 = (int64_t)(b >> 3) * a.tpb;
     const int64_t t1 = min(t0 + a.tpb, ntl);
-    sweep_block<P, T, VT>(a, b, y0, ny, t0, t1);
+    sweep_block<P, T, VT>(a, b, y0, ny, t0, t1, b == 0);
 }
 
 // One sweep over a batch of independent lattices of the same family in a
 // single launch: workgroup b serves instance block_inst[b], whose argument
 // record (geometry, buffers, scale and shift) is table[instance]; each
 // instance's workgroups are consecutive and cover its tiles in order.
+// red_step: the step whose moments the records' folded reduction writes.
 template <class P, typename T, typename VT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_SWEEP_WAVES_PER_EU)))
 void batch_sweep_kernel(const KArgs<T, VT>* __restrict__ table, const int* __restrict__ block_inst,
-                        const int* __restrict__ inst_block0) {
+                        const int* __restrict__ inst_block0, int red_step) {
     const int b = blockIdx.x;
     const int i = __builtin_amdgcn_readfirstlane(block_inst[b]);
     const int lb = b - __builtin_amdgcn_readfirstlane(inst_block0[i]);
-    const KArgs<T, VT> a = table[i];
+    KArgs<T, VT> a = table[i];
+    a.red_step = red_step;
     const int64_t ntl = (int64_t)a.ntx * a.Ly * a.Lz;
     const int64_t t0 = (int64_t)lb * a.tpb;
     const int64_t t1 = min(t0 + a.tpb, ntl);
-    sweep_block<P, T, VT>(a, b, 0, a.Ly, t0, t1);
+    sweep_block<P, T, VT>(a, b, 0, a.Ly, t0, t1, lb == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -938,7 +941,7 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
     const int c = tid & (nb - 1);
     const int o = (tid >> a.lognb) & (NO - 1);
     const int site = a.st_site;
-    fused_reduction(a, b_out, tid);
+    fused_reduction(a, part == 0 && jb == 0, tid);
 
     // per-column alpha, beta, gamma only in the run-time epilogue (the
     // specialised ones are launched with uniform values)
@@ -1166,12 +1169,13 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
 template <class P, typename T, typename VT, int E, unsigned EPM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_STAGED_WAVES_PER_EU)))
 void batch_staged_kernel(const KArgs<T, VT>* __restrict__ table, const int* __restrict__ block_inst,
-                         const int* __restrict__ inst_block0) {
+                         const int* __restrict__ inst_block0, int red_step) {
     const int b = blockIdx.x;
     const int i = __builtin_amdgcn_readfirstlane(block_inst[b]);
     const int b0 = __builtin_amdgcn_readfirstlane(inst_block0[i]);
     const int b1 = __builtin_amdgcn_readfirstlane(inst_block0[i + 1]);
-    const KArgs<T, VT> a = table[i];
+    KArgs<T, VT> a = table[i];
+    a.red_step = red_step;
     const int lb = b - b0;
     staged_block<P, T, VT, E, EPM, kBlock>(a, b, lb & 7, lb >> 3, (b1 - b0) >> 3);
 }
@@ -1530,7 +1534,7 @@ hipError_t batch_fill_record_fam(const SweepParams& p, int staged, void* dst, in
 // One step of a batched sweep: every instance's workgroups in one launch.
 template <class P>
 hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* table, const int* block_inst,
-                                  const int* inst_block0, int grid, hipStream_t s) {
+                                  const int* inst_block0, int grid, int red_step, hipStream_t s) {
     return dispatch_types(p.dtype, p.vtype, [&](auto tt, auto tv) -> hipError_t {
         using T = typename decltype(tt)::type;
         using VT = typename decltype(tv)::type;
@@ -1547,7 +1551,7 @@ hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* 
                         if (e != hipSuccess) return e;
                     }
                     hipLaunchKernelGGL((batch_staged_kernel<P, T, VT, E, KPM>), dim3(grid), dim3(kBlock), lds, s,
-                                       static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0);
+                                       static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0, red_step);
                     return hipGetLastError();
                 };
                 if (p.ep != KPM) return hipErrorInvalidValue;
@@ -1559,7 +1563,7 @@ hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* 
             }
         }
         hipLaunchKernelGGL((batch_sweep_kernel<P, T, VT>), dim3(grid), dim3(kBlock), 0, s,
-                           static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0);
+                           static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0, red_step);
         return hipGetLastError();
     });
 }
@@ -1571,7 +1575,8 @@ hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* 
     hipError_t launch_sweep_##name(SweepParams& p, int num_cus, hipStream_t s);                              \
     hipError_t batch_fill_record_##name(const SweepParams& p, int staged, void* dst, int* nblocks);          \
     hipError_t launch_batch_sweep_##name(const SweepParams& p, int staged, const void* table,                \
-                                         const int* block_inst, const int* inst_block0, int grid, hipStream_t s);
+                                         const int* block_inst, const int* inst_block0, int grid, int red_step, \
+                                         hipStream_t s);
 PV_FAMILY_ENTRY_POINTS(ti)
 PV_FAMILY_ENTRY_POINTS(graphene2)
 PV_FAMILY_ENTRY_POINTS(graphene4)
