@@ -245,6 +245,36 @@ def test_generic_family_sparse_blocks(no, nb, dtype, shape, kernel, per):
     assert np.abs(d[:, 0] - xx).max() < (1e-12 if dtype == np.complex128 else 1e-5) * xx.max()
 
 
+@pytest.mark.parametrize("shape", ["diagonal", "stageable", "xy"])
+@pytest.mark.parametrize("nb", [1, 8])
+def test_generic_plain_sweep_gamma_zero(shape, nb):
+    """Generic stencils, uniform coefficients and gamma = 0 on the staged
+    kernel where the offsets allow it (the plain kernel without a z stream,
+    with or without halo side rows): y starts as NaN and is written only."""
+    g = np.random.default_rng(50 + nb)
+    no = 2
+    blocks, offsets = [], []
+    for o in GENERIC_OFFSETS[shape]:
+        B = (g.standard_normal((no, no)) + 1j * g.standard_normal((no, no))) * (g.random((no, no)) < 0.6)
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.1, 0.3j], [-0.3j, -0.2]])
+    st = {"dim": 3, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    L, per = (11, 6, 5), (0, 1, 1)
+    lat = pv.Lattice(L, per, st)
+    pv.pv_lattice_set_tuning(lat, pv.PV_C128, nb, {"kernel": 2})
+    V = W.uniform_potential(L[0] * L[1] * L[2], 1.0, W.generator(6, 1))
+    lat.set_potential(dev(V))
+    ol, H = _explicit_matrix(L, per, no, offsets, blocks, E0, V, False)
+    x = W.gaussian_block(ol.n_rows, nb, W.generator(6, 2))
+    y = dev(np.full((ol.n_rows, nb), np.nan + 0j))
+    pv.pv_spmmv(lat, dev(x), y, 0.8, 0.25, 0.0)
+    out = host(y)
+    assert np.isfinite(out).all()
+    assert rel_err(out, spmmv.spmmv(H, x, 0.8, 0.25, 0.0)) < 1e-13
+
+
 @pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("shape", ["stageable", "xy"])
 def test_generic_stageable_open_x_orbital_field_series(kernel, shape):
