@@ -1065,9 +1065,10 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                 T hr = d * xc.re - dgi * xc.im;
                 T hi = d * xc.im + dgi * xc.re;
                 if constexpr (GEN) {
-                    // runtime terms: rows (m, w + dw) from the ring, rows
-                    // (m -+ 1, w) from the side rows, both with the x halo (the
-                    // host admits no offset with both a y and a z step)
+                    // runtime terms: rows (m, w + dw) from the ring with the x
+                    // halo, rows (m -+ 1, w) from the side rows (with the x halo
+                    // in the instance for hops with a y and an x step; the host
+                    // admits no offset with both a y and a z step)
                     for (int tb = 0; tb < a.n_terms; ++tb) {
                         const int dx = g_off[3 * tb], dm = g_off[3 * tb + 1], dw = g_off[3 * tb + 2];
                         // side rows start at the tile (no halo) or one site before it
