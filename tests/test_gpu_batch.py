@@ -53,6 +53,19 @@ def test_batched_kpm_c128_matches_each_instance_and_replays():
     assert batch.stats() == (2, 2)
 
 
+@pytest.mark.parametrize("M", [2, 6, 10])
+def test_batched_kpm_short_runs(M):
+    """One step (only the final reduction) and odd step counts (the last
+    step's partials in the other buffer of the pair): every instance equals
+    its oracle run."""
+    cases, rs, a, b = instances(nb=2)
+    batch = pv.Batch([c.lat for c in cases])
+    mu = host(pv.pv_batch_kpm_moments(batch, [dev(r) for r in rs], M, a, b))
+    for i, c in enumerate(cases):
+        ref = kpm.moments_doubling(c.H, rs[i], M, a[i], b[i])
+        assert np.abs(mu[i] - ref).max() < 1e-12, (M, i)
+
+
 def test_batched_kpm_c64_stated_error():
     cases, rs, a, b = instances(np.complex64, np.float32, nb=16)
     batch = pv.Batch([c.lat for c in cases])
