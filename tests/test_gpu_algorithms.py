@@ -23,6 +23,8 @@ from gpu_common import Case, dev, host, rel_err, SHAPE_KINDS, shape  # noqa: E40
     ("ti", (16, 16, 16), (1, 1, 1), 1, 128),      # the 16^3 TI KPM workload
     ("ti", (13, 7, 5), (1, 0, 1), 4, 64),
     ("ti", (3, 3, 3), (1, 1, 1), 2, 2),
+    ("ti", (7, 5, 3), (1, 1, 1), 4, 6),           # odd step counts: the last step's
+    ("graphene2", (12, 9), (1, 1), 2, 10),        # partials in the other buffer
     ("ti", (6, 5, 4), (1, 1, 1), 32, 40),
     ("graphene2", (40, 24), (0, 1), 8, 96),
     ("weyl", (9, 8, 5), (1, 1, 0), 2, 64),
