@@ -104,3 +104,26 @@ def test_batched_direct_and_staged_kernels_agree(dtype):
     assert batch.stats()[0] == 2          # the kernel change forced a new capture
     tol = 1e-13 if dtype == np.complex128 else 1e-6
     assert np.abs(mu_s - mu_d).max() < tol
+
+
+@pytest.mark.parametrize("dtype,elems", [(np.complex128, 1), (np.complex128, 2),
+                                         (np.complex64, 2), (np.complex64, 4)])
+def test_batched_staged_elements_per_lane(dtype, elems):
+    """Lattice 0's elements per lane set the staged tile length of the whole
+    batch: every instance equals its oracle run (complex64 vectors and field
+    against the oracle on the FP32-rounded field, to the stated 1e-4)."""
+    vd = np.float64 if dtype == np.complex128 else np.float32
+    cases, rs, a, b = instances(dtype, vd, nb=16)
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    batch = pv.Batch([c.lat for c in cases])
+    pv.pv_lattice_set_tuning(cases[0].lat, code, 16, {"kernel": 2, "elems_per_lane": elems})
+    try:
+        mu = host(pv.pv_batch_kpm_moments(batch, [dev(r) for r in rs], 40, a, b))
+    finally:
+        pv.pv_lattice_set_tuning(cases[0].lat, code, 16, None)
+    import oracle.hamiltonian as oh
+    for i, c in enumerate(cases):
+        H = c.H if dtype == np.complex128 else oh.assemble(c.model, c.olat, c.V.astype(np.float32).astype(np.float64))
+        ref = kpm.moments_doubling(H, rs[i].astype(np.complex128), 40, a[i], b[i])
+        tol = 1e-12 if dtype == np.complex128 else 1e-4
+        assert np.abs(mu[i] - ref).max() < tol, (elems, i)
