@@ -382,6 +382,26 @@ size_t pv_kpm_vjp_workspace_size(const pv_lattice *lat, int dtype, int nb, int M
 pv_status pv_kpm_moments_vjp(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
                              const void *r, const double *gbar, double *gradV, int ckpt_every,
                              void *work, size_t work_bytes, void *stream);
+
+/*
+ * The same gradient split in two calls for a caller that needs the moments
+ * before the cotangent is known (reverse-mode autodiff):
+ * pv_kpm_moments_ckpt computes mu exactly as pv_kpm_moments does and writes
+ * the checkpoint pairs (w_{jC}, w_{jC+1}) into `work` as it goes (sized by
+ * pv_kpm_vjp_workspace_size, with the same ckpt_every);
+ * pv_kpm_moments_vjp_ckpt then runs only the segment recomputation and the
+ * adjoint sweep of pv_kpm_moments_vjp from that workspace.  The caller keeps
+ * `work`, r and the field unchanged between the two calls and passes the
+ * same lat, dtype, nb, M, a, b, r and ckpt_every to both; the result equals
+ * pv_kpm_moments_vjp's.  Asynchronous on the stream (the second call
+ * synchronises once, to read gbar on the host).
+ */
+pv_status pv_kpm_moments_ckpt(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
+                              const void *r, double *mu, int ckpt_every, void *work,
+                              size_t work_bytes, void *stream);
+pv_status pv_kpm_moments_vjp_ckpt(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
+                                  const void *r, const double *gbar, double *gradV, int ckpt_every,
+                                  void *work, size_t work_bytes, void *stream);
 size_t pv_cheb_propagate_vjp_workspace_size(const pv_lattice *lat, int dtype, int nb, int M,
                                             int nsteps);
 pv_status pv_cheb_propagate_vjp(pv_lattice *lat, int dtype, int nb, double a, double b, double dt,

@@ -89,6 +89,8 @@ SIGNATURES = {
     "pv_batch_stats": (_i, [_vp, _ip, _ip]),
     "pv_kpm_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_kpm_moments_vjp": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
+    "pv_kpm_moments_ckpt": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _i, _vp, _sz, _vp]),
+    "pv_kpm_moments_vjp_ckpt": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_cheb_propagate_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
@@ -598,6 +600,35 @@ def pv_kpm_moments_vjp(lat: Lattice, r, M: int, a: float, b: float, gbar, ckpt_e
     return gradV
 
 
+def pv_kpm_moments_ckpt(lat: Lattice, r, M: int, a: float, b: float, ckpt_every: int = 16, nb=None):
+    """(mu, work): the moments of pv_kpm_moments plus a workspace holding the
+    forward checkpoints, for pv_kpm_moments_vjp_ckpt."""
+    torch = _torch()
+    nb = nb if nb is not None else r.numel() // lat.n_rows
+    dt = _dtype_code(r)
+    mu = torch.empty((nb, M), dtype=torch.float64, device=r.device)
+    ws = _workspace(lib().pv_kpm_vjp_workspace_size(lat.handle, dt, nb, M, ckpt_every), r.device)
+    _check(lib().pv_kpm_moments_ckpt(lat.handle, dt, nb, M, a, b, _vec(r, "r", lat.n_rows, nb),
+                                     ctypes.c_void_p(mu.data_ptr()), ckpt_every,
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return mu, ws
+
+
+def pv_kpm_moments_vjp_ckpt(lat: Lattice, r, M: int, a: float, b: float, gbar, work, ckpt_every: int = 16,
+                            gradV=None, nb=None):
+    """dL/dV for L = sum gbar * mu from the checkpoints of pv_kpm_moments_ckpt (same arguments)."""
+    torch = _torch()
+    nb = nb if nb is not None else r.numel() // lat.n_rows
+    dt = _dtype_code(r)
+    if gradV is None:
+        gradV = torch.empty(_grad_len(lat), dtype=torch.float64, device=r.device)
+    gbar = gbar.contiguous()
+    _check(lib().pv_kpm_moments_vjp_ckpt(lat.handle, dt, nb, M, a, b, _vec(r, "r", lat.n_rows, nb),
+                                         ctypes.c_void_p(gbar.data_ptr()), ctypes.c_void_p(gradV.data_ptr()),
+                                         ckpt_every, ctypes.c_void_p(work.data_ptr()), work.numel(), _stream()))
+    return gradV
+
+
 def pv_cheb_propagate_vjp(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, want_psi0bar=True, nb=None):
     """(dL/dV, cotangent of psi0) for psi_T = U^nsteps psi0 and cotangent psibar of psi_T."""
     torch = _torch()
@@ -624,15 +655,17 @@ def _autograd():
         @staticmethod
         def forward(ctx, V, lat, r, M, a, b, ckpt_every):
             lat.set_potential(V.detach())
-            mu = pv_kpm_moments(lat, r, M, a, b)
-            ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, ctx.ck = lat, r, M, a, b, ckpt_every
+            # the forward keeps its checkpoint pairs for the backward
+            mu, work = pv_kpm_moments_ckpt(lat, r, M, a, b, ckpt_every)
+            ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, ctx.ck, ctx.work = lat, r, M, a, b, ckpt_every, work
             ctx.V = V.detach()
             return mu
 
         @staticmethod
         def backward(ctx, gbar):
             ctx.lat.set_potential(ctx.V)
-            g = pv_kpm_moments_vjp(ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, gbar.to(torch.float64), ctx.ck)
+            g = pv_kpm_moments_vjp_ckpt(ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, gbar.to(torch.float64), ctx.work, ctx.ck)
+            ctx.work = None
             return g.to(ctx.V.dtype), None, None, None, None, None, None
 
     class Propagate(torch.autograd.Function):
@@ -659,7 +692,8 @@ def _autograd():
 
 def kpm_moments(V, lat: Lattice, r, M: int, a: float, b: float, ckpt_every: int = 16):
     """Differentiable KPM moments mu(V) (torch.autograd.Function around
-    pv_kpm_moments / pv_kpm_moments_vjp)."""
+    pv_kpm_moments_ckpt / pv_kpm_moments_vjp_ckpt: the forward keeps its
+    checkpoints for the backward)."""
     return _autograd()[0].apply(V, lat, r, M, a, b, ckpt_every)
 
 

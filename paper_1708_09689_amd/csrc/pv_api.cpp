@@ -742,8 +742,9 @@ namespace {
 constexpr int64_t kFuseReductionElems = int64_t(1) << 22;
 }  // namespace
 
-extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
-                                    double* mu, void* work, size_t work_bytes, void* stream) {
+namespace {
+
+pv_status check_kpm_args(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r, const double* mu) {
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
     pv_status st;
     if ((st = check_dtype(l, dtype)) != PV_OK) return st;
@@ -752,14 +753,18 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     if (!mu) return fail(PV_ERR_INVALID_ARG, "mu is NULL");
     if (M < 2 || (M & 1) || M > 65536) return fail(PV_ERR_INVALID_ARG, "M = %d must be even, 2..65536", M);
     if (!(a > 0.0) || !std::isfinite(a) || !std::isfinite(b)) return fail(PV_ERR_INVALID_ARG, "need finite a > 0 and b");
-    const size_t need = pv_kpm_workspace_size(l, dtype, nb, M);
-    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
-    if ((st = ensure_device(l)) != PV_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char* w = static_cast<char*>(work);
-    double* part[2] = {reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb))};
-    void* A = w + 2 * partial_bytes(l, nb);
-    void* B = static_cast<char*>(A) + vec_bytes(l, dtype, nb);
+    return PV_OK;
+}
+
+// The KPM recurrence with fused dots: w_1 = H~ r, w_{n+1} = 2 H~ w_n - w_{n-1}
+// for n < M/2, moments from the per-step dots.  wbuf(k) is the buffer that
+// receives w_k (k >= 1); it never aliases w_k's predecessor w_{k-1} (the
+// sweep's x), and it may alias w_{k-2} (the sweep's z, updated in place).
+template <class WB, class AFTER>
+pv_status kpm_forward(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r, double* mu,
+                      double* part0, double* part1, WB&& wbuf, AFTER&& after, hipStream_t s) {
+    pv_status st;
+    double* part[2] = {part0, part1};
     pv::SweepParams p = base_params(l, dtype, nb);
     if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
     p.ep = pv::EP_STORE_Y | pv::EP_DOTS;
@@ -787,22 +792,24 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     };
     // w_1 = H~ w_0
     p.x = r;
-    p.y = A;
+    p.y = wbuf(1);
     p.z = nullptr;
     p.alpha = 1.0 / a;
     p.beta = b;
     p.gamma = 0.0;
     PV_HIP(step_sweep(0));
+    PV_HIP(after(1, p.y));
     const void* prev = r;
-    void* cur = A;
+    const void* cur = p.y;
     p.alpha = 2.0 / a;
     p.gamma = -1.0;
     for (int n = 1; n < M / 2; ++n) {
-        void* next = (n == 1) ? B : const_cast<void*>(prev);
+        void* next = wbuf(n + 1);
         p.x = cur;
         p.z = prev;
         p.y = next;
         PV_HIP(step_sweep(n));
+        PV_HIP(after(n + 1, next));
         prev = cur;
         cur = next;
     }
@@ -810,6 +817,25 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
     if (fuse)
         PV_HIP(pv::launch_reduce_dots(part[n_last % 2], last_grid, nb, n_last == 0 ? 1 : 2, mu, M, n_last, invD, s));
     return PV_OK;
+}
+
+}  // namespace
+
+extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                                    double* mu, void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if ((st = check_kpm_args(l, dtype, nb, M, a, b, r, mu)) != PV_OK) return st;
+    const size_t need = pv_kpm_workspace_size(l, dtype, nb, M);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    char* w = static_cast<char*>(work);
+    void* A = w + 2 * partial_bytes(l, nb);
+    void* B = static_cast<char*>(A) + vec_bytes(l, dtype, nb);
+    // w_k in A for odd k, in B for even k (w_{k+1} overwrites w_{k-1})
+    return kpm_forward(l, dtype, nb, M, a, b, r, mu, reinterpret_cast<double*>(w),
+                       reinterpret_cast<double*>(w + partial_bytes(l, nb)),
+                       [&](int k) { return (k & 1) ? A : B; }, [](int, const void*) { return hipSuccess; },
+                       static_cast<hipStream_t>(stream));
 }
 
 extern "C" pv_status pv_kpm_dos(int M, const double* mu, double a, double b, int nE, const double* E, double* rho) {
@@ -2269,18 +2295,28 @@ pv_status adjoint_sweep(pv_lattice* l, int dtype, int nb, const void* x, const v
 
 }  // namespace
 
-extern "C" size_t pv_kpm_vjp_workspace_size(const pv_lattice* l, int dtype, int nb, int M, int ckpt) {
-    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || M < 2 || (M & 1) || ckpt < 1 ||
-        (dtype != PV_C128 && dtype != PV_C64))
-        return 0;
+namespace {
+// KPM adjoint workspace: 2J checkpoint vectors (w_{jC}, w_{jC+1}), C segment
+// vectors, two adjoint and two forward vectors, the source-term table, then
+// the dot partials of pv_kpm_moments_ckpt.
+size_t kpm_vjp_core_bytes(const pv_lattice* l, int dtype, int nb, int M, int ckpt) {
     const int N = M / 2, J = (N - 1) / ckpt + 1;
     const size_t vb = vec_bytes(l, dtype, nb);
     return vb * (2 * (size_t)J + ckpt + 2 + 2) + align_up((size_t)(N + 1) * 3 * nb * 2 * sizeof(double));
 }
+}  // namespace
 
-extern "C" pv_status pv_kpm_moments_vjp(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
-                                        const double* gbar, double* gradV, int ckpt, void* work, size_t work_bytes,
-                                        void* stream) {
+extern "C" size_t pv_kpm_vjp_workspace_size(const pv_lattice* l, int dtype, int nb, int M, int ckpt) {
+    if (!l || !is_pow2(nb) || nb > PV_MAX_NB || M < 2 || (M & 1) || ckpt < 1 ||
+        (dtype != PV_C128 && dtype != PV_C64))
+        return 0;
+    return kpm_vjp_core_bytes(l, dtype, nb, M, ckpt) + 2 * partial_bytes(l, nb);
+}
+
+namespace {
+
+pv_status check_kpm_vjp_args(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                             const double* gbar, double* gradV, int ckpt, void* work, size_t work_bytes) {
     pv_status st;
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
     if ((st = check_grad_args(l, dtype, nb, a, b, gradV)) != PV_OK) return st;
@@ -2290,8 +2326,14 @@ extern "C" pv_status pv_kpm_moments_vjp(pv_lattice* l, int dtype, int nb, int M,
     if (ckpt < 1) return fail(PV_ERR_INVALID_ARG, "checkpoint interval must be >= 1");
     const size_t need = pv_kpm_vjp_workspace_size(l, dtype, nb, M, ckpt);
     if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
-    if ((st = ensure_device(l)) != PV_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return ensure_device(l);
+}
+
+// The adjoint sweep; with have_ckpt the checkpoint pairs are already in the
+// workspace (pv_kpm_moments_ckpt) and the forward recurrence is skipped.
+pv_status kpm_vjp_impl(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                       const double* gbar, double* gradV, int ckpt, void* work, hipStream_t s, bool have_ckpt) {
+    pv_status st;
     const int N = M / 2, C = ckpt, J = (N - 1) / C + 1;
     const size_t vb = vec_bytes(l, dtype, nb);
     const double invD = 1.0 / double(l->n_rows);
@@ -2328,24 +2370,26 @@ extern "C" pv_status pv_kpm_moments_vjp(pv_lattice* l, int dtype, int nb, int M,
 
     // forward recurrence, keeping (w_{jC}, w_{jC+1}) for j = 0..J-1
     const unsigned store = pv::EP_STORE_Y;
-    if ((st = adjoint_sweep(l, dtype, nb, r, nullptr, F0, 1.0 / a, b, 0.0, nullptr, nullptr, nullptr, nullptr,
-                            nullptr, 0, 0, store, s)) != PV_OK)
-        return st;
-    PV_HIP(pv::launch_copy(r, ck(0, 0), vbytes, s));
-    PV_HIP(pv::launch_copy(F0, ck(0, 1), vbytes, s));
-    {
-        const void* prev = r;
-        void* cur = F0;
-        for (int k = 1; k <= (J - 1) * C; ++k) {
-            void* next = (k == 1) ? F1 : const_cast<void*>(prev);
-            if ((st = adjoint_sweep(l, dtype, nb, cur, prev, next, 2.0 / a, b, -1.0, nullptr, nullptr, nullptr,
-                                    nullptr, nullptr, 0, 0, store, s)) != PV_OK)
-                return st;
-            prev = cur;
-            cur = next;
-            if (k % C == 0) {
-                PV_HIP(pv::launch_copy(prev, ck(k / C, 0), vbytes, s));
-                PV_HIP(pv::launch_copy(cur, ck(k / C, 1), vbytes, s));
+    if (!have_ckpt) {
+        if ((st = adjoint_sweep(l, dtype, nb, r, nullptr, F0, 1.0 / a, b, 0.0, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, 0, 0, store, s)) != PV_OK)
+            return st;
+        PV_HIP(pv::launch_copy(r, ck(0, 0), vbytes, s));
+        PV_HIP(pv::launch_copy(F0, ck(0, 1), vbytes, s));
+        {
+            const void* prev = r;
+            void* cur = F0;
+            for (int k = 1; k <= (J - 1) * C; ++k) {
+                void* next = (k == 1) ? F1 : const_cast<void*>(prev);
+                if ((st = adjoint_sweep(l, dtype, nb, cur, prev, next, 2.0 / a, b, -1.0, nullptr, nullptr, nullptr,
+                                        nullptr, nullptr, 0, 0, store, s)) != PV_OK)
+                    return st;
+                prev = cur;
+                cur = next;
+                if (k % C == 0) {
+                    PV_HIP(pv::launch_copy(prev, ck(k / C, 0), vbytes, s));
+                    PV_HIP(pv::launch_copy(cur, ck(k / C, 1), vbytes, s));
+                }
             }
         }
     }
@@ -2374,6 +2418,58 @@ extern "C" pv_status pv_kpm_moments_vjp(pv_lattice* l, int dtype, int nb, int M,
         }
     }
     return PV_OK;
+}
+
+}  // namespace
+
+extern "C" pv_status pv_kpm_moments_vjp(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                                        const double* gbar, double* gradV, int ckpt, void* work, size_t work_bytes,
+                                        void* stream) {
+    pv_status st;
+    if ((st = check_kpm_vjp_args(l, dtype, nb, M, a, b, r, gbar, gradV, ckpt, work, work_bytes)) != PV_OK) return st;
+    return kpm_vjp_impl(l, dtype, nb, M, a, b, r, gbar, gradV, ckpt, work, static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" pv_status pv_kpm_moments_ckpt(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
+                                         double* mu, int ckpt, void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if ((st = check_kpm_args(l, dtype, nb, M, a, b, r, mu)) != PV_OK) return st;
+    if (ckpt < 1) return fail(PV_ERR_INVALID_ARG, "checkpoint interval must be >= 1");
+    const size_t need = pv_kpm_vjp_workspace_size(l, dtype, nb, M, ckpt);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int N = M / 2, C = ckpt, J = (N - 1) / C + 1;
+    const size_t vb = vec_bytes(l, dtype, nb);
+    const size_t vbytes = (size_t)l->n_rows * nb * elem_bytes(dtype);
+    char* w = static_cast<char*>(work);
+    auto ck = [&](int j, int which) { return static_cast<void*>(w + vb * (2 * (size_t)j + which)); };
+    char* S = w + vb * 2 * (size_t)J;
+    void* F[2] = {S + vb * (C + 2), S + vb * (C + 3)};
+    char* part = w + kpm_vjp_core_bytes(l, dtype, nb, M, ckpt);
+    PV_HIP(pv::launch_copy(r, ck(0, 0), vbytes, s));
+    // w_k goes straight to its checkpoint slot (jC + rem, rem in {0, 1}),
+    // else to the forward ring by parity; with C = 1, w_k also fills slot
+    // (k - 1, 1)
+    auto wbuf = [&](int k) -> void* {
+        const int j = k / C, rem = k - j * C;
+        if (j < J && rem <= 1) return ck(j, rem);
+        return F[k & 1];
+    };
+    auto after = [&](int k, const void* y) -> hipError_t {
+        if (C == 1 && k - 1 < J) return pv::launch_copy(y, ck(k - 1, 1), vbytes, s);
+        return hipSuccess;
+    };
+    return kpm_forward(l, dtype, nb, M, a, b, r, mu, reinterpret_cast<double*>(part),
+                       reinterpret_cast<double*>(part + partial_bytes(l, nb)), wbuf, after, s);
+}
+
+extern "C" pv_status pv_kpm_moments_vjp_ckpt(pv_lattice* l, int dtype, int nb, int M, double a, double b,
+                                             const void* r, const double* gbar, double* gradV, int ckpt, void* work,
+                                             size_t work_bytes, void* stream) {
+    pv_status st;
+    if ((st = check_kpm_vjp_args(l, dtype, nb, M, a, b, r, gbar, gradV, ckpt, work, work_bytes)) != PV_OK) return st;
+    return kpm_vjp_impl(l, dtype, nb, M, a, b, r, gbar, gradV, ckpt, work, static_cast<hipStream_t>(stream), true);
 }
 
 extern "C" size_t pv_cheb_propagate_vjp_workspace_size(const pv_lattice* l, int dtype, int nb, int M, int nsteps) {

@@ -135,3 +135,52 @@ def test_kpm_and_propagate_vjp_both_kernels(kernel):
     p0_ref, g_ref = adjoint.propagate_vjp(cg.H, 2, "site", psi0, 3.3, 0.05, 4.0, 16, 2, psibar)
     assert rel(host(gv), g_ref) < 1e-10
     assert rel(host(p0), p0_ref) < 1e-10
+
+
+@pytest.mark.parametrize("L,nb,M,ck,kernel,dtype", [
+    ((4, 3, 5), 1, 32, 4, 0, np.complex128),
+    ((3, 3, 3), 2, 2, 1, 0, np.complex128),       # one step, interval 1
+    ((5, 4, 3), 4, 20, 1, 2, np.complex128),      # interval 1: w_k fills two slots
+    ((6, 4, 3), 16, 40, 3, 2, np.complex128),
+    ((5, 5, 4), 4, 64, 16, 1, np.complex128),
+    ((4, 4, 4), 8, 34, 100, 0, np.complex128),    # interval beyond the run: one pair
+    ((6, 5, 4), 8, 48, 5, 0, np.complex64),
+])
+def test_kpm_ckpt_pair_matches_one_call_and_oracle(L, nb, M, ck, kernel, dtype):
+    """pv_kpm_moments_ckpt + pv_kpm_moments_vjp_ckpt: the moments equal
+    pv_kpm_moments', the gradient equals the one-call pv_kpm_moments_vjp's
+    and the oracle's discrete adjoint."""
+    c64 = dtype == np.complex64
+    c = Case("ti", L, (1, 1, 1), Wd=1.0, seed=17, vdtype=np.float32 if c64 else np.float64)
+    code = pv.PV_C64 if c64 else pv.PV_C128
+    if kernel:
+        pv.pv_lattice_set_tuning(c.lat, code, nb, {"kernel": kernel})
+    r = dev(c.block(nb, kind="phase", dtype=dtype))
+    gbar = W.generator(9, W.STREAM_COTANGENT, nb).standard_normal((nb, M))
+    mu_ck, work = pv.pv_kpm_moments_ckpt(c.lat, r, M, 7.0, 0.1, ckpt_every=ck)
+    mu = pv.pv_kpm_moments(c.lat, r, M, 7.0, 0.1)
+    assert np.abs(host(mu_ck) - host(mu)).max() < 1e-15
+    g_ck = host(pv.pv_kpm_moments_vjp_ckpt(c.lat, r, M, 7.0, 0.1, dev(gbar), work, ckpt_every=ck))
+    g_one = host(pv.pv_kpm_moments_vjp(c.lat, r, M, 7.0, 0.1, dev(gbar), ckpt_every=ck))
+    assert rel(g_ck, g_one) < (1e-6 if c64 else 1e-13)
+    H = oh.assemble(c.model, c.olat, c.V.astype(np.float32).astype(np.float64)) if c64 else c.H
+    ref = adjoint.kpm_vjp(H, 4, "site", host(r).astype(np.complex128), M, 7.0, 0.1, gbar)
+    assert rel(g_ck, ref) < (1e-3 if c64 else 1e-10)
+
+
+def test_kpm_ckpt_pair_separate_reductions_full_block():
+    """TI 64^3, nb = 8 (2^23 elements: each step's moments reduce in a launch
+    of their own) on the staged kernel: the two-call gradient equals the
+    one-call gradient, and the moments equal pv_kpm_moments'."""
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lat = pv.Lattice((64, 64, 64), (1, 1, 1), st)
+    V = torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(4, W.STREAM_POTENTIAL))).to("cuda")
+    lat.set_potential(V)
+    r = W.random_phase_device(lat.n_rows, 8, 400, "cuda")
+    gbar = torch.from_numpy(W.generator(4, W.STREAM_COTANGENT).standard_normal((8, 32))).to("cuda")
+    mu_ck, work = pv.pv_kpm_moments_ckpt(lat, r, 32, 7.0, 0.0, ckpt_every=6)
+    mu = pv.pv_kpm_moments(lat, r, 32, 7.0, 0.0)
+    assert float((mu_ck - mu).abs().max()) < 1e-15
+    g_ck = pv.pv_kpm_moments_vjp_ckpt(lat, r, 32, 7.0, 0.0, gbar, work, ckpt_every=6)
+    g_one = pv.pv_kpm_moments_vjp(lat, r, 32, 7.0, 0.0, gbar, ckpt_every=6)
+    assert float((g_ck - g_one).abs().max() / g_one.abs().max()) < 1e-13
