@@ -354,6 +354,14 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, ckpt)
     ms_cb = _timed(torch, lambda: pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, ckpt), 2)
     del work
+    # memory-rich variant: one segment (ckpt_every = M/2), every w_k kept by
+    # the forward (M/2 + 6 vectors, 18 GB here), no recompute
+    _, work = pv.pv_kpm_moments_ckpt(lat, r, M, 7.0, 0.0, M // 2)
+    ms_af = _timed(torch, lambda: pv.pv_kpm_moments_ckpt(lat, r, M, 7.0, 0.0, M // 2), 2)
+    pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, M // 2)
+    ms_ab = _timed(torch, lambda: pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, M // 2), 2)
+    del work
+    torch.cuda.empty_cache()
     lups = lat.n_rows * 8 * (M // 2)
     out = {"ti": {"workload": "TI 64^3, W=1, nb=8, M=256, checkpoint every 16, complex128",
                   "fwd_ms": round(ms_f, 3), "fwd_GLUP/s": round(lups / (ms_f * 1e-3) / 1e9, 3),
@@ -361,6 +369,10 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
                   "fwd_ckpt_ms": round(ms_cf, 3), "adj_from_ckpt_ms": round(ms_cb, 3),
                   "fwd+adj_GLUP/s": round(lups / ((ms_cf + ms_cb) * 1e-3) / 1e9, 3),
                   "fwd+adj_over_fwd": round((ms_cf + ms_cb) / ms_f, 2),
+                  "keep_all": {"fwd_ms": round(ms_af, 3), "adj_ms": round(ms_ab, 3),
+                               "fwd+adj_GLUP/s": round(lups / ((ms_af + ms_ab) * 1e-3) / 1e9, 3),
+                               "fwd+adj_over_fwd": round((ms_af + ms_ab) / ms_f, 2),
+                               "note": "ckpt_every = M/2: the forward keeps every w_k, the adjoint recomputes none"},
                   "note": "GLUP/s counted on the forward's LUPs. fwd+adj: the forward keeping its checkpoints "
                           "(fwd_ckpt_ms) then recompute + adjoint from them (adj_from_ckpt_ms), as autograd runs "
                           "them; grad_ms: the one-call gradient (its own checkpointed forward + recompute + adjoint)"}}

@@ -393,8 +393,11 @@ pv_status pv_kpm_moments_vjp(pv_lattice *lat, int dtype, int nb, int M, double a
  * adjoint sweep of pv_kpm_moments_vjp from that workspace.  The caller keeps
  * `work`, r and the field unchanged between the two calls and passes the
  * same lat, dtype, nb, M, a, b, r and ckpt_every to both; the result equals
- * pv_kpm_moments_vjp's.  Asynchronous on the stream (the second call
- * synchronises once, to read gbar on the host).
+ * pv_kpm_moments_vjp's, and the second call may be repeated (other
+ * cotangents) on the same workspace.  With ckpt_every >= M/2 the forward
+ * keeps every w_k (M/2 + 6 vectors of workspace) and the adjoint recomputes
+ * none.  Asynchronous on the stream (the second call synchronises once, to
+ * read gbar on the host).
  */
 pv_status pv_kpm_moments_ckpt(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
                               const void *r, double *mu, int ckpt_every, void *work,

@@ -2405,7 +2405,9 @@ pv_status kpm_vjp_impl(pv_lattice* l, int dtype, int nb, int M, double a, double
             if (i == j * C + 1) return ck(j, 1);
             return S + vb * (size_t)(i - j * C - 2);
         };
-        for (int i = j * C + 2; i <= std::min(k_hi + 1, N); ++i)
+        // (with one segment, pv_kpm_moments_ckpt left w_2..w_N in place)
+        const bool stored = have_ckpt && J == 1;
+        for (int i = j * C + 2; !stored && i <= std::min(k_hi + 1, N); ++i)
             if ((st = adjoint_sweep(l, dtype, nb, wv(i - 1), wv(i - 2), wv(i), 2.0 / a, b, -1.0, nullptr, nullptr,
                                     nullptr, nullptr, nullptr, 0, 0, store, s)) != PV_OK)
                 return st;
@@ -2448,12 +2450,14 @@ extern "C" pv_status pv_kpm_moments_ckpt(pv_lattice* l, int dtype, int nb, int M
     void* F[2] = {S + vb * (C + 2), S + vb * (C + 3)};
     char* part = w + kpm_vjp_core_bytes(l, dtype, nb, M, ckpt);
     PV_HIP(pv::launch_copy(r, ck(0, 0), vbytes, s));
-    // w_k goes straight to its checkpoint slot (jC + rem, rem in {0, 1}),
-    // else to the forward ring by parity; with C = 1, w_k also fills slot
-    // (k - 1, 1)
+    // w_k goes straight to its checkpoint slot (jC + rem, rem in {0, 1});
+    // with one segment (C >= M/2) w_2..w_N go to the segment slots, where
+    // the adjoint reads them without recomputing; else to the forward ring
+    // by parity.  With C = 1, w_k also fills slot (k - 1, 1).
     auto wbuf = [&](int k) -> void* {
         const int j = k / C, rem = k - j * C;
         if (j < J && rem <= 1) return ck(j, rem);
+        if (J == 1) return S + vb * (size_t)(k - 2);
         return F[k & 1];
     };
     auto after = [&](int k, const void* y) -> hipError_t {

@@ -143,7 +143,9 @@ def test_kpm_and_propagate_vjp_both_kernels(kernel):
     ((5, 4, 3), 4, 20, 1, 2, np.complex128),      # interval 1: w_k fills two slots
     ((6, 4, 3), 16, 40, 3, 2, np.complex128),
     ((5, 5, 4), 4, 64, 16, 1, np.complex128),
-    ((4, 4, 4), 8, 34, 100, 0, np.complex128),    # interval beyond the run: one pair
+    ((4, 4, 4), 8, 34, 100, 0, np.complex128),    # one segment: every w_k kept, no recompute
+    ((5, 4, 4), 4, 30, 15, 2, np.complex128),     # one segment at exactly C = M/2
+    ((5, 4, 4), 4, 30, 14, 2, np.complex128),     # two segments, the second of one step
     ((6, 5, 4), 8, 48, 5, 0, np.complex64),
 ])
 def test_kpm_ckpt_pair_matches_one_call_and_oracle(L, nb, M, ck, kernel, dtype):
@@ -163,6 +165,9 @@ def test_kpm_ckpt_pair_matches_one_call_and_oracle(L, nb, M, ck, kernel, dtype):
     g_ck = host(pv.pv_kpm_moments_vjp_ckpt(c.lat, r, M, 7.0, 0.1, dev(gbar), work, ckpt_every=ck))
     g_one = host(pv.pv_kpm_moments_vjp(c.lat, r, M, 7.0, 0.1, dev(gbar), ckpt_every=ck))
     assert rel(g_ck, g_one) < (1e-6 if c64 else 1e-13)
+    # the checkpoints survive the adjoint: a second call gives the same gradient
+    g_ck2 = host(pv.pv_kpm_moments_vjp_ckpt(c.lat, r, M, 7.0, 0.1, dev(gbar), work, ckpt_every=ck))
+    assert np.array_equal(g_ck, g_ck2)
     H = oh.assemble(c.model, c.olat, c.V.astype(np.float32).astype(np.float64)) if c64 else c.H
     ref = adjoint.kpm_vjp(H, 4, "site", host(r).astype(np.complex128), M, 7.0, 0.1, gbar)
     assert rel(g_ck, ref) < (1e-3 if c64 else 1e-10)
