@@ -413,6 +413,25 @@ pv_status pv_cheb_propagate_vjp(pv_lattice *lat, int dtype, int nb, double a, do
                                 void *stream);
 
 /*
+ * The propagation gradient split in two calls, for reverse-mode autodiff:
+ * pv_cheb_propagate_keep writes psiT = U(dt)^nsteps psi0 (psiT must not
+ * alias psi0; psi0 is not modified) and keeps psi_1..psi_{nsteps-1} in
+ * `work` (sized by pv_cheb_propagate_vjp_workspace_size);
+ * pv_cheb_propagate_vjp_keep then runs only the reverse steps of
+ * pv_cheb_propagate_vjp from those states.  The caller keeps `work`, psi0
+ * and the field unchanged between the calls and passes the same arguments
+ * to both; the second call may be repeated (other cotangents).  Results
+ * equal pv_cheb_propagate's and pv_cheb_propagate_vjp's.
+ */
+pv_status pv_cheb_propagate_keep(pv_lattice *lat, int dtype, int nb, double a, double b, double dt,
+                                 int M, int nsteps, const void *psi0, void *psiT, void *work,
+                                 size_t work_bytes, void *stream);
+pv_status pv_cheb_propagate_vjp_keep(pv_lattice *lat, int dtype, int nb, double a, double b,
+                                     double dt, int M, int nsteps, const void *psi0,
+                                     const void *psibar, void *psi0bar, double *gradV, void *work,
+                                     size_t work_bytes, void *stream);
+
+/*
  * Batched KPM over independent lattices (disorder realisations, possibly of
  * different sizes) of one stencil family: every Chebyshev step of all
  * instances is ONE kernel launch (each workgroup serves one instance, argument

@@ -93,6 +93,8 @@ SIGNATURES = {
     "pv_kpm_moments_vjp_ckpt": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_cheb_propagate_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pv_cheb_propagate_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "pv_cheb_propagate_vjp_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
     "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
     "pv_dsl_stencil": (_i, [ctypes.c_char_p, _dp, _i, _ip, _ip, _ip, _ip, _dp, _dp, _ip, _ip]),
@@ -646,6 +648,37 @@ def pv_cheb_propagate_vjp(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, want_
     return gradV, psi0bar
 
 
+def pv_cheb_propagate_keep(lat: Lattice, psi0, a, b, dt, M, nsteps, nb=None):
+    """(psi_T, work): psi_T = U^nsteps psi0 (psi0 unchanged) plus a workspace
+    holding the intermediate states, for pv_cheb_propagate_vjp_keep."""
+    torch = _torch()
+    nb = nb if nb is not None else psi0.numel() // lat.n_rows
+    dtc = _dtype_code(psi0)
+    psiT = torch.empty_like(psi0)
+    ws = _workspace(lib().pv_cheb_propagate_vjp_workspace_size(lat.handle, dtc, nb, M, nsteps), psi0.device)
+    _check(lib().pv_cheb_propagate_keep(lat.handle, dtc, nb, a, b, dt, M, nsteps, _vec(psi0, "psi0", lat.n_rows, nb),
+                                        _vec(psiT, "psiT", lat.n_rows, nb, dtc), ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel(), _stream()))
+    return psiT, ws
+
+
+def pv_cheb_propagate_vjp_keep(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, work, want_psi0bar=True, nb=None):
+    """pv_cheb_propagate_vjp from the states kept by pv_cheb_propagate_keep (same arguments)."""
+    torch = _torch()
+    nb = nb if nb is not None else psi0.numel() // lat.n_rows
+    dtc = _dtype_code(psi0)
+    gradV = torch.empty(_grad_len(lat), dtype=torch.float64, device=psi0.device)
+    psi0bar = torch.empty_like(psi0) if want_psi0bar else None
+    psibar = psibar.contiguous()
+    _check(lib().pv_cheb_propagate_vjp_keep(lat.handle, dtc, nb, a, b, dt, M, nsteps,
+                                            _vec(psi0, "psi0", lat.n_rows, nb),
+                                            _vec(psibar, "psibar", lat.n_rows, nb, dtc),
+                                            None if psi0bar is None else ctypes.c_void_p(psi0bar.data_ptr()),
+                                            ctypes.c_void_p(gradV.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                                            work.numel(), _stream()))
+    return gradV, psi0bar
+
+
 def _autograd():
     torch = _torch()
 
@@ -665,7 +698,6 @@ def _autograd():
         def backward(ctx, gbar):
             ctx.lat.set_potential(ctx.V)
             g = pv_kpm_moments_vjp_ckpt(ctx.lat, ctx.r, ctx.M, ctx.a, ctx.b, gbar.to(torch.float64), ctx.work, ctx.ck)
-            ctx.work = None
             return g.to(ctx.V.dtype), None, None, None, None, None, None
 
     class Propagate(torch.autograd.Function):
@@ -674,17 +706,23 @@ def _autograd():
         @staticmethod
         def forward(ctx, V, psi0, lat, a, b, dt, M, nsteps):
             lat.set_potential(V.detach())
-            psi = psi0.detach().clone()
-            pv_cheb_propagate(lat, psi, a, b, dt, M, nsteps)
             ctx.lat, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n = lat, a, b, dt, M, nsteps
             ctx.V = V.detach()
-            ctx.psi0 = psi0.detach()
+            ctx.psi0 = psi0.detach().contiguous()
+            if nsteps < 1:
+                ctx.work = None
+                return ctx.psi0.clone()
+            # the forward keeps its intermediate states for the backward
+            psi, ctx.work = pv_cheb_propagate_keep(lat, ctx.psi0, a, b, dt, M, nsteps)
             return psi
 
         @staticmethod
         def backward(ctx, psibar):
+            if ctx.work is None:
+                return torch.zeros_like(ctx.V), psibar, None, None, None, None, None, None
             ctx.lat.set_potential(ctx.V)
-            g, p0 = pv_cheb_propagate_vjp(ctx.lat, ctx.psi0, psibar, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n)
+            g, p0 = pv_cheb_propagate_vjp_keep(ctx.lat, ctx.psi0, psibar, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n,
+                                               ctx.work)
             return g.to(ctx.V.dtype), p0, None, None, None, None, None, None
 
     return KPMMoments, Propagate

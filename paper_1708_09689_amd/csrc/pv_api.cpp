@@ -2483,9 +2483,55 @@ extern "C" size_t pv_cheb_propagate_vjp_workspace_size(const pv_lattice* l, int 
     return vb * ((size_t)nsteps + M + 4) + align_up((size_t)(M + 1) * 3 * nb * 2 * sizeof(double));
 }
 
-extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M,
-                                           int nsteps, const void* psi0, const void* psibar, void* psi0bar,
-                                           double* gradV, void* work, size_t work_bytes, void* stream) {
+namespace {
+
+// Series coefficients of one propagation step: eta_0 = e^{-ibdt} c_0,
+// eta_k = 2 e^{-ibdt} c_k (complex interleaved, k = 0..M).
+std::vector<double> tp_step_coefficients(double a, double b, double dt, int M) {
+    std::vector<double> coef(2 * (M + 1));
+    pv_cheb_tp_coefficients(a, dt, M, coef.data());
+    const std::complex<double> ph = std::exp(std::complex<double>(0.0, -b * dt));
+    for (int k = 0; k <= M; ++k) {
+        std::complex<double> c(coef[2 * k], coef[2 * k + 1]);
+        c *= ph * (k ? 2.0 : 1.0);
+        coef[2 * k] = c.real();
+        coef[2 * k + 1] = c.imag();
+    }
+    return coef;
+}
+
+// Workspace of the propagation adjoint: states psi_1..psi_{nsteps-1} in
+// slots 1..nsteps-1, w_1..w_M, two adjoint and two cotangent vectors, the
+// source-term table.
+struct TpVjpLayout {
+    char* w;
+    size_t vb;
+    int nsteps, M;
+    void* state(int i) const { return w + vb * (size_t)i; }
+    void* wk(int k) const { return w + vb * ((size_t)nsteps + k - 1); }
+    void* L0() const { return w + vb * ((size_t)nsteps + M); }
+};
+
+// The forward of the adjoint: psi_{i+1} = U psi_i for i < n_keep, each kept
+// in its state slot; with out != NULL the last step U psi_{nsteps-1} goes
+// to out.
+pv_status tp_forward_keep(pv_lattice* l, int dtype, int nb, double a, double b, int M, int nsteps, const double* coef,
+                          const void* psi0, void* out, const TpVjpLayout& T, hipStream_t s) {
+    pv_status st;
+    auto psi = [&](int i) -> const void* { return i == 0 ? psi0 : T.state(i); };
+    for (int i = 0; i < nsteps; ++i) {
+        void* dst = i + 1 < nsteps ? T.state(i + 1) : out;
+        if (!dst) break;
+        if ((st = run_series(l, dtype, nb, a, b, M, coef, psi(i), dst, dst, T.wk(1), M >= 2 ? T.wk(2) : T.L0(),
+                             s)) != PV_OK)
+            return st;
+    }
+    return PV_OK;
+}
+
+pv_status check_tp_vjp_args(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M, int nsteps,
+                            const void* psi0, const void* psibar, void* psi0bar, double* gradV, void* work,
+                            size_t work_bytes) {
     pv_status st;
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
     if ((st = check_grad_args(l, dtype, nb, a, b, gradV)) != PV_OK) return st;
@@ -2495,8 +2541,15 @@ extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, dou
     if (M < 1 || nsteps < 1 || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "need M >= 1, nsteps >= 1");
     const size_t need = pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps);
     if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
-    if ((st = ensure_device(l)) != PV_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return ensure_device(l);
+}
+
+// The propagation adjoint; with have_states the states psi_1..psi_{nsteps-1}
+// are already in the workspace (pv_cheb_propagate_keep).
+pv_status tp_vjp_impl(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M, int nsteps,
+                      const void* psi0, const void* psibar, void* psi0bar, double* gradV, void* work, hipStream_t s,
+                      bool have_states) {
+    pv_status st;
     const size_t vb = vec_bytes(l, dtype, nb);
     const size_t vbytes = (size_t)l->n_rows * nb * elem_bytes(dtype);
     char* w = static_cast<char*>(work);
@@ -2508,16 +2561,7 @@ extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, dou
     void* Y1 = w + vb * ((size_t)nsteps + M + 3);
     double* table = reinterpret_cast<double*>(w + vb * ((size_t)nsteps + M + 4));
 
-    // series coefficients of one step: eta_0 = e^{-ibdt} c_0, eta_k = 2 e^{-ibdt} c_k
-    std::vector<double> coef(2 * (M + 1));
-    pv_cheb_tp_coefficients(a, dt, M, coef.data());
-    const std::complex<double> ph = std::exp(std::complex<double>(0.0, -b * dt));
-    for (int k = 0; k <= M; ++k) {
-        std::complex<double> c(coef[2 * k], coef[2 * k + 1]);
-        c *= ph * (k ? 2.0 : 1.0);
-        coef[2 * k] = c.real();
-        coef[2 * k + 1] = c.imag();
-    }
+    const std::vector<double> coef = tp_step_coefficients(a, b, dt, M);
     // adjoint source of lambda_k: conj(eta_k) * Ybar in the third slot
     std::vector<double> tab((size_t)(M + 1) * 3 * nb * 2, 0.0);
     for (int k = 0; k <= M; ++k)
@@ -2531,10 +2575,10 @@ extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, dou
 
     // forward: psi_{i+1} = U psi_i, keep psi_1 .. psi_{nsteps-1}
     auto psi = [&](int i) -> const void* { return i == 0 ? psi0 : state(i); };
-    for (int i = 0; i + 1 < nsteps; ++i)
-        if ((st = run_series(l, dtype, nb, a, b, M, coef.data(), psi(i), state(i + 1), state(i + 1), wk(1),
-                             M >= 2 ? wk(2) : L0, s)) != PV_OK)
-            return st;
+    const TpVjpLayout T{w, vb, nsteps, M};
+    if (!have_states &&
+        (st = tp_forward_keep(l, dtype, nb, a, b, M, nsteps, coef.data(), psi0, nullptr, T, s)) != PV_OK)
+        return st;
 
     PV_HIP(pv::launch_copy(psibar, Y0, vbytes, s));
     void* ybar = Y0;
@@ -2570,4 +2614,47 @@ extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, dou
     }
     if (psi0bar) PV_HIP(pv::launch_copy(ybar, psi0bar, vbytes, s));
     return PV_OK;
+}
+
+}  // namespace
+
+extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M,
+                                           int nsteps, const void* psi0, const void* psibar, void* psi0bar,
+                                           double* gradV, void* work, size_t work_bytes, void* stream) {
+    pv_status st;
+    if ((st = check_tp_vjp_args(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
+                                work_bytes)) != PV_OK)
+        return st;
+    return tp_vjp_impl(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
+                       static_cast<hipStream_t>(stream), false);
+}
+
+extern "C" pv_status pv_cheb_propagate_keep(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M,
+                                            int nsteps, const void* psi0, void* psiT, void* work, size_t work_bytes,
+                                            void* stream) {
+    pv_status st;
+    if ((st = check_series_args(l, dtype, nb, a, b)) != PV_OK) return st;
+    if ((st = check_vec(psi0, dtype, "psi0")) != PV_OK) return st;
+    if ((st = check_vec(psiT, dtype, "psiT")) != PV_OK) return st;
+    if (psiT == psi0) return fail(PV_ERR_INVALID_ARG, "psiT must not alias psi0 (the adjoint reads psi0)");
+    if (M < 1 || nsteps < 1 || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "need M >= 1, nsteps >= 1");
+    const size_t need = pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    const std::vector<double> coef = tp_step_coefficients(a, b, dt, M);
+    const TpVjpLayout T{static_cast<char*>(work), vec_bytes(l, dtype, nb), nsteps, M};
+    return tp_forward_keep(l, dtype, nb, a, b, M, nsteps, coef.data(), psi0, psiT, T,
+                           static_cast<hipStream_t>(stream));
+}
+
+extern "C" pv_status pv_cheb_propagate_vjp_keep(pv_lattice* l, int dtype, int nb, double a, double b, double dt,
+                                                int M, int nsteps, const void* psi0, const void* psibar,
+                                                void* psi0bar, double* gradV, void* work, size_t work_bytes,
+                                                void* stream) {
+    pv_status st;
+    if ((st = check_tp_vjp_args(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
+                                work_bytes)) != PV_OK)
+        return st;
+    return tp_vjp_impl(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
+                       static_cast<hipStream_t>(stream), true);
 }

@@ -189,3 +189,48 @@ def test_kpm_ckpt_pair_separate_reductions_full_block():
     g_ck = pv.pv_kpm_moments_vjp_ckpt(lat, r, 32, 7.0, 0.0, gbar, work, ckpt_every=6)
     g_one = pv.pv_kpm_moments_vjp(lat, r, 32, 7.0, 0.0, gbar, ckpt_every=6)
     assert float((g_ck - g_one).abs().max() / g_one.abs().max()) < 1e-13
+
+
+@pytest.mark.parametrize("M,nsteps,nb", [(1, 1, 1), (1, 3, 2), (16, 1, 1), (24, 3, 4)])
+def test_propagate_keep_pair_matches_one_call_and_oracle(M, nsteps, nb):
+    """pv_cheb_propagate_keep + pv_cheb_propagate_vjp_keep: psi_T equals
+    pv_cheb_propagate's, the gradient and psi0's cotangent equal the
+    one-call pv_cheb_propagate_vjp's and the oracle's; psi0 is unchanged and
+    a second adjoint call gives the same result."""
+    c = Case("graphene2", (20, 8), (0, 1), Wd=0.3, seed=23)
+    psi0_h, psibar_h = c.block(nb, seed=5), c.block(nb, seed=6)
+    psi0, psibar = dev(psi0_h), dev(psibar_h)
+    a, b, dt = 3.3, 0.05, 2.0
+    psiT, work = pv.pv_cheb_propagate_keep(c.lat, psi0, a, b, dt, M, nsteps)
+    assert np.array_equal(host(psi0), psi0_h)
+    ref_T = psi0.clone()
+    pv.pv_cheb_propagate(c.lat, ref_T, a, b, dt, M, nsteps)
+    assert rel(host(psiT), host(ref_T)) < 1e-13
+    g, p0 = pv.pv_cheb_propagate_vjp_keep(c.lat, psi0, psibar, a, b, dt, M, nsteps, work)
+    g1, p01 = pv.pv_cheb_propagate_vjp(c.lat, psi0, psibar, a, b, dt, M, nsteps)
+    assert rel(host(g), host(g1)) < 1e-13 and rel(host(p0), host(p01)) < 1e-13
+    g2, p02 = pv.pv_cheb_propagate_vjp_keep(c.lat, psi0, psibar, a, b, dt, M, nsteps, work)
+    assert np.array_equal(host(g), host(g2)) and np.array_equal(host(p0), host(p02))
+    p0_ref, g_ref = adjoint.propagate_vjp(c.H, 2, "site", psi0_h, a, b, dt, M, nsteps, psibar_h)
+    assert rel(host(g), g_ref) < 1e-10 and rel(host(p0), p0_ref) < 1e-10
+
+
+def test_autograd_backward_twice_with_retained_graph():
+    """Both autograd functions keep their forward workspaces: a second
+    backward through a retained graph accumulates the same gradient again."""
+    c = Case("ti", (4, 4, 3), (1, 1, 1), Wd=1.0, seed=24)
+    r = dev(c.block(2, kind="phase"))
+    V = c.Vd.clone().requires_grad_(True)
+    loss = (pv.kpm_moments(V, c.lat, r, 12, 7.0, 0.0) ** 2).sum()
+    loss.backward(retain_graph=True)
+    g1 = V.grad.clone()
+    loss.backward()
+    assert torch.equal(V.grad, 2 * g1)
+    cg = Case("graphene2", (16, 6), (0, 1), Wd=0.3, seed=25)
+    psi0 = dev(cg.block(1, seed=7))
+    Vg = cg.Vd.clone().requires_grad_(True)
+    T = (pv.cheb_propagate(Vg, psi0, cg.lat, 3.3, 0.05, 2.0, 16, 2).abs() ** 2)[: cg.D // 2].sum()
+    T.backward(retain_graph=True)
+    h1 = Vg.grad.clone()
+    T.backward()
+    assert torch.equal(Vg.grad, 2 * h1)
