@@ -384,18 +384,23 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     region = torch.zeros(lg.n_rows, 1, dtype=torch.bool, device=dev)
     region.view(Lj, Li, 2)[:, 464:, :] = True
 
-    def grad_T():
+    def grad_T(keep_series=False):
         V = Vg.clone().requires_grad_(True)
-        psiT = pv.cheb_propagate(V, psi0, lg, 3.06, 0.05, 10.0, 64, 50)
+        psiT = pv.cheb_propagate(V, psi0, lg, 3.06, 0.05, 10.0, 64, 50, keep_series)
         T = (psiT.abs() ** 2)[region].sum()
         T.backward()
         return T
     grad_T()
     ms_g = _timed(torch, grad_T, 1)
+    # every step's Chebyshev vectors kept (50 * 64 vectors, 27 GB): no recompute
+    grad_T(True)
+    ms_gk = _timed(torch, lambda: grad_T(True), 1)
+    torch.cuda.empty_cache()
     psi = psi0.clone()
     ms_gf = _timed(torch, lambda: pv.pv_cheb_propagate(lg, psi, 3.06, 0.05, 10.0, 64, 50), 1)
     out["graphene"] = {"workload": "graphene 512x512x2, 50 steps dt=10 M=64, dT/dV by autograd",
                        "fwd_ms": round(ms_gf, 2), "fwd+adj_ms": round(ms_g, 2),
+                       "fwd+adj_keep_series_ms": round(ms_gk, 2),
                        "fwd_GLUP/s": round(lg.n_rows * 64 * 50 / (ms_gf * 1e-3) / 1e9, 3)}
     return out
 

@@ -416,20 +416,26 @@ pv_status pv_cheb_propagate_vjp(pv_lattice *lat, int dtype, int nb, double a, do
  * The propagation gradient split in two calls, for reverse-mode autodiff:
  * pv_cheb_propagate_keep writes psiT = U(dt)^nsteps psi0 (psiT must not
  * alias psi0; psi0 is not modified) and keeps psi_1..psi_{nsteps-1} in
- * `work` (sized by pv_cheb_propagate_vjp_workspace_size);
+ * `work`; with keep_series != 0 it also keeps every step's Chebyshev
+ * vectors w_1..w_M (nsteps*M more vectors), so that the adjoint recomputes
+ * none.  `work` is sized by pv_cheb_propagate_keep_workspace_size (with
+ * keep_series = 0 it equals pv_cheb_propagate_vjp_workspace_size).
  * pv_cheb_propagate_vjp_keep then runs only the reverse steps of
- * pv_cheb_propagate_vjp from those states.  The caller keeps `work`, psi0
+ * pv_cheb_propagate_vjp from what was kept.  The caller keeps `work`, psi0
  * and the field unchanged between the calls and passes the same arguments
- * to both; the second call may be repeated (other cotangents).  Results
- * equal pv_cheb_propagate's and pv_cheb_propagate_vjp's.
+ * (keep_series included) to both; the second call may be repeated (other
+ * cotangents).  Results equal pv_cheb_propagate's and
+ * pv_cheb_propagate_vjp's up to rounding.
  */
+size_t pv_cheb_propagate_keep_workspace_size(const pv_lattice *lat, int dtype, int nb, int M,
+                                             int nsteps, int keep_series);
 pv_status pv_cheb_propagate_keep(pv_lattice *lat, int dtype, int nb, double a, double b, double dt,
-                                 int M, int nsteps, const void *psi0, void *psiT, void *work,
-                                 size_t work_bytes, void *stream);
+                                 int M, int nsteps, const void *psi0, void *psiT, int keep_series,
+                                 void *work, size_t work_bytes, void *stream);
 pv_status pv_cheb_propagate_vjp_keep(pv_lattice *lat, int dtype, int nb, double a, double b,
                                      double dt, int M, int nsteps, const void *psi0,
-                                     const void *psibar, void *psi0bar, double *gradV, void *work,
-                                     size_t work_bytes, void *stream);
+                                     const void *psibar, void *psi0bar, double *gradV,
+                                     int keep_series, void *work, size_t work_bytes, void *stream);
 
 /*
  * Batched KPM over independent lattices (disorder realisations, possibly of

@@ -93,8 +93,9 @@ SIGNATURES = {
     "pv_kpm_moments_vjp_ckpt": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_cheb_propagate_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_cheb_propagate_vjp": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
-    "pv_cheb_propagate_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _sz, _vp]),
-    "pv_cheb_propagate_vjp_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pv_cheb_propagate_keep_workspace_size": (_sz, [_vp, _i, _i, _i, _i, _i]),
+    "pv_cheb_propagate_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _i, _vp, _sz, _vp]),
+    "pv_cheb_propagate_vjp_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
     "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
     "pv_dsl_stencil": (_i, [ctypes.c_char_p, _dp, _i, _ip, _ip, _ip, _ip, _dp, _dp, _ip, _ip]),
@@ -648,21 +649,24 @@ def pv_cheb_propagate_vjp(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, want_
     return gradV, psi0bar
 
 
-def pv_cheb_propagate_keep(lat: Lattice, psi0, a, b, dt, M, nsteps, nb=None):
+def pv_cheb_propagate_keep(lat: Lattice, psi0, a, b, dt, M, nsteps, keep_series=False, nb=None):
     """(psi_T, work): psi_T = U^nsteps psi0 (psi0 unchanged) plus a workspace
-    holding the intermediate states, for pv_cheb_propagate_vjp_keep."""
+    holding the intermediate states (and with keep_series every step's
+    Chebyshev vectors), for pv_cheb_propagate_vjp_keep."""
     torch = _torch()
     nb = nb if nb is not None else psi0.numel() // lat.n_rows
     dtc = _dtype_code(psi0)
     psiT = torch.empty_like(psi0)
-    ws = _workspace(lib().pv_cheb_propagate_vjp_workspace_size(lat.handle, dtc, nb, M, nsteps), psi0.device)
+    ks = int(bool(keep_series))
+    ws = _workspace(lib().pv_cheb_propagate_keep_workspace_size(lat.handle, dtc, nb, M, nsteps, ks), psi0.device)
     _check(lib().pv_cheb_propagate_keep(lat.handle, dtc, nb, a, b, dt, M, nsteps, _vec(psi0, "psi0", lat.n_rows, nb),
-                                        _vec(psiT, "psiT", lat.n_rows, nb, dtc), ctypes.c_void_p(ws.data_ptr()),
+                                        _vec(psiT, "psiT", lat.n_rows, nb, dtc), ks, ctypes.c_void_p(ws.data_ptr()),
                                         ws.numel(), _stream()))
     return psiT, ws
 
 
-def pv_cheb_propagate_vjp_keep(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, work, want_psi0bar=True, nb=None):
+def pv_cheb_propagate_vjp_keep(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, work, keep_series=False,
+                               want_psi0bar=True, nb=None):
     """pv_cheb_propagate_vjp from the states kept by pv_cheb_propagate_keep (same arguments)."""
     torch = _torch()
     nb = nb if nb is not None else psi0.numel() // lat.n_rows
@@ -674,8 +678,8 @@ def pv_cheb_propagate_vjp_keep(lat: Lattice, psi0, psibar, a, b, dt, M, nsteps, 
                                             _vec(psi0, "psi0", lat.n_rows, nb),
                                             _vec(psibar, "psibar", lat.n_rows, nb, dtc),
                                             None if psi0bar is None else ctypes.c_void_p(psi0bar.data_ptr()),
-                                            ctypes.c_void_p(gradV.data_ptr()), ctypes.c_void_p(work.data_ptr()),
-                                            work.numel(), _stream()))
+                                            ctypes.c_void_p(gradV.data_ptr()), int(bool(keep_series)),
+                                            ctypes.c_void_p(work.data_ptr()), work.numel(), _stream()))
     return gradV, psi0bar
 
 
@@ -704,26 +708,26 @@ def _autograd():
         """psi_T = U(dt)^nsteps psi0 for the lattice with field V (differentiable in V and psi0)."""
 
         @staticmethod
-        def forward(ctx, V, psi0, lat, a, b, dt, M, nsteps):
+        def forward(ctx, V, psi0, lat, a, b, dt, M, nsteps, keep_series):
             lat.set_potential(V.detach())
-            ctx.lat, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n = lat, a, b, dt, M, nsteps
+            ctx.lat, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n, ctx.ks = lat, a, b, dt, M, nsteps, keep_series
             ctx.V = V.detach()
             ctx.psi0 = psi0.detach().contiguous()
             if nsteps < 1:
                 ctx.work = None
                 return ctx.psi0.clone()
             # the forward keeps its intermediate states for the backward
-            psi, ctx.work = pv_cheb_propagate_keep(lat, ctx.psi0, a, b, dt, M, nsteps)
+            psi, ctx.work = pv_cheb_propagate_keep(lat, ctx.psi0, a, b, dt, M, nsteps, keep_series)
             return psi
 
         @staticmethod
         def backward(ctx, psibar):
             if ctx.work is None:
-                return torch.zeros_like(ctx.V), psibar, None, None, None, None, None, None
+                return torch.zeros_like(ctx.V), psibar, None, None, None, None, None, None, None
             ctx.lat.set_potential(ctx.V)
             g, p0 = pv_cheb_propagate_vjp_keep(ctx.lat, ctx.psi0, psibar, ctx.a, ctx.b, ctx.dt, ctx.M, ctx.n,
-                                               ctx.work)
-            return g.to(ctx.V.dtype), p0, None, None, None, None, None, None
+                                               ctx.work, ctx.ks)
+            return g.to(ctx.V.dtype), p0, None, None, None, None, None, None, None
 
     return KPMMoments, Propagate
 
@@ -735,6 +739,10 @@ def kpm_moments(V, lat: Lattice, r, M: int, a: float, b: float, ckpt_every: int 
     return _autograd()[0].apply(V, lat, r, M, a, b, ckpt_every)
 
 
-def cheb_propagate(V, psi0, lat: Lattice, a: float, b: float, dt: float, M: int, nsteps: int):
-    """Differentiable Chebyshev propagation psi_T(V, psi0)."""
-    return _autograd()[1].apply(V, psi0, lat, a, b, dt, M, nsteps)
+def cheb_propagate(V, psi0, lat: Lattice, a: float, b: float, dt: float, M: int, nsteps: int,
+                   keep_series: bool = False):
+    """Differentiable Chebyshev propagation psi_T(V, psi0).  The forward keeps
+    its time-step states for the backward; with keep_series also every
+    step's Chebyshev vectors (nsteps * M more vectors), and the backward
+    recomputes none."""
+    return _autograd()[1].apply(V, psi0, lat, a, b, dt, M, nsteps, bool(keep_series))

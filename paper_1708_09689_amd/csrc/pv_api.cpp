@@ -957,6 +957,43 @@ pv_status run_series(pv_lattice* l, int dtype, int nb, double a, double b, int K
     return PV_OK;
 }
 
+// The same series with w_k written to wbuf(k) for k = 1..K, the last
+// included (never in place: every w_k stays readable afterwards).
+template <class WB>
+pv_status run_series_keep(pv_lattice* l, int dtype, int nb, double a, double b, int K, const double* coef,
+                          const void* X, void* acc, void* out, WB&& wbuf, hipStream_t s) {
+    pv::SweepParams p = base_params(l, dtype, nb);
+    pv_status st;
+    if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
+    p.x = X;
+    p.y = wbuf(1);
+    p.z = nullptr;
+    p.alpha = 1.0 / a;
+    p.beta = b;
+    p.gamma = 0.0;
+    p.eta0_re = coef[0];
+    p.eta0_im = coef[1];
+    p.eta_re = coef[2];
+    p.eta_im = coef[3];
+    p.acc_out = (K == 1) ? out : acc;
+    p.ep = pv::EP_ACC_INIT | pv::EP_STORE_Y;
+    PV_HIP(pv::launch_sweep(p, num_cus(), s));
+    p.alpha = 2.0 / a;
+    p.gamma = -1.0;
+    for (int k = 2; k <= K; ++k) {
+        p.x = wbuf(k - 1);
+        p.z = k == 2 ? X : wbuf(k - 2);
+        p.y = wbuf(k);
+        p.eta_re = coef[2 * k];
+        p.eta_im = coef[2 * k + 1];
+        p.acc_in = acc;
+        p.acc_out = (k == K) ? out : acc;
+        p.ep = pv::EP_ACC_ADD | pv::EP_STORE_Y;
+        PV_HIP(pv::launch_sweep(p, num_cus(), s));
+    }
+    return PV_OK;
+}
+
 pv_status check_series_args(pv_lattice* l, int dtype, int nb, double a, double b) {
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
     pv_status st;
@@ -2503,35 +2540,41 @@ std::vector<double> tp_step_coefficients(double a, double b, double dt, int M) {
 // Workspace of the propagation adjoint: states psi_1..psi_{nsteps-1} in
 // slots 1..nsteps-1, w_1..w_M, two adjoint and two cotangent vectors, the
 // source-term table.
+// With the series kept, w_k of step i (k = 1..M) follows at series(i, k).
 struct TpVjpLayout {
     char* w;
     size_t vb;
     int nsteps, M;
+    size_t base;   // bytes of the layout without the kept series
     void* state(int i) const { return w + vb * (size_t)i; }
     void* wk(int k) const { return w + vb * ((size_t)nsteps + k - 1); }
     void* L0() const { return w + vb * ((size_t)nsteps + M); }
+    void* series(int i, int k) const { return w + base + vb * ((size_t)i * M + k - 1); }
 };
 
 // The forward of the adjoint: psi_{i+1} = U psi_i for i < n_keep, each kept
 // in its state slot; with out != NULL the last step U psi_{nsteps-1} goes
 // to out.
 pv_status tp_forward_keep(pv_lattice* l, int dtype, int nb, double a, double b, int M, int nsteps, const double* coef,
-                          const void* psi0, void* out, const TpVjpLayout& T, hipStream_t s) {
+                          const void* psi0, void* out, const TpVjpLayout& T, bool keep_series, hipStream_t s) {
     pv_status st;
     auto psi = [&](int i) -> const void* { return i == 0 ? psi0 : T.state(i); };
     for (int i = 0; i < nsteps; ++i) {
         void* dst = i + 1 < nsteps ? T.state(i + 1) : out;
         if (!dst) break;
-        if ((st = run_series(l, dtype, nb, a, b, M, coef, psi(i), dst, dst, T.wk(1), M >= 2 ? T.wk(2) : T.L0(),
-                             s)) != PV_OK)
-            return st;
+        if (keep_series)
+            st = run_series_keep(l, dtype, nb, a, b, M, coef, psi(i), dst, dst,
+                                 [&](int k) { return T.series(i, k); }, s);
+        else
+            st = run_series(l, dtype, nb, a, b, M, coef, psi(i), dst, dst, T.wk(1), M >= 2 ? T.wk(2) : T.L0(), s);
+        if (st != PV_OK) return st;
     }
     return PV_OK;
 }
 
 pv_status check_tp_vjp_args(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M, int nsteps,
                             const void* psi0, const void* psibar, void* psi0bar, double* gradV, void* work,
-                            size_t work_bytes) {
+                            size_t work_bytes, int keep_series) {
     pv_status st;
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
     if ((st = check_grad_args(l, dtype, nb, a, b, gradV)) != PV_OK) return st;
@@ -2539,7 +2582,7 @@ pv_status check_tp_vjp_args(pv_lattice* l, int dtype, int nb, double a, double b
     if ((st = check_vec(psibar, dtype, "psibar")) != PV_OK) return st;
     if (psi0bar && (st = check_vec(psi0bar, dtype, "psi0bar")) != PV_OK) return st;
     if (M < 1 || nsteps < 1 || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "need M >= 1, nsteps >= 1");
-    const size_t need = pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps);
+    const size_t need = pv_cheb_propagate_keep_workspace_size(l, dtype, nb, M, nsteps, keep_series);
     if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
     return ensure_device(l);
 }
@@ -2548,7 +2591,7 @@ pv_status check_tp_vjp_args(pv_lattice* l, int dtype, int nb, double a, double b
 // are already in the workspace (pv_cheb_propagate_keep).
 pv_status tp_vjp_impl(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M, int nsteps,
                       const void* psi0, const void* psibar, void* psi0bar, double* gradV, void* work, hipStream_t s,
-                      bool have_states) {
+                      bool have_states, bool have_series) {
     pv_status st;
     const size_t vb = vec_bytes(l, dtype, nb);
     const size_t vbytes = (size_t)l->n_rows * nb * elem_bytes(dtype);
@@ -2575,9 +2618,9 @@ pv_status tp_vjp_impl(pv_lattice* l, int dtype, int nb, double a, double b, doub
 
     // forward: psi_{i+1} = U psi_i, keep psi_1 .. psi_{nsteps-1}
     auto psi = [&](int i) -> const void* { return i == 0 ? psi0 : state(i); };
-    const TpVjpLayout T{w, vb, nsteps, M};
+    const TpVjpLayout T{w, vb, nsteps, M, pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps)};
     if (!have_states &&
-        (st = tp_forward_keep(l, dtype, nb, a, b, M, nsteps, coef.data(), psi0, nullptr, T, s)) != PV_OK)
+        (st = tp_forward_keep(l, dtype, nb, a, b, M, nsteps, coef.data(), psi0, nullptr, T, false, s)) != PV_OK)
         return st;
 
     PV_HIP(pv::launch_copy(psibar, Y0, vbytes, s));
@@ -2586,15 +2629,17 @@ pv_status tp_vjp_impl(pv_lattice* l, int dtype, int nb, double a, double b, doub
     const unsigned store = pv::EP_STORE_Y;
     for (int i = nsteps - 1; i >= 0; --i) {
         const void* X = psi(i);
-        // recompute w_1 .. w_M of this step
-        auto wv = [&](int k) -> const void* { return k == 0 ? X : wk(k); };
-        if ((st = adjoint_sweep(l, dtype, nb, X, nullptr, wk(1), 1.0 / a, b, 0.0, nullptr, nullptr, nullptr, nullptr,
-                                nullptr, 0, 0, store, s)) != PV_OK)
-            return st;
-        for (int k = 2; k <= M; ++k)
-            if ((st = adjoint_sweep(l, dtype, nb, wv(k - 1), wv(k - 2), wk(k), 2.0 / a, b, -1.0, nullptr, nullptr,
-                                    nullptr, nullptr, nullptr, 0, 0, store, s)) != PV_OK)
+        // w_1 .. w_M of this step: kept by the forward, or recomputed
+        auto wv = [&](int k) -> const void* { return k == 0 ? X : (have_series ? T.series(i, k) : wk(k)); };
+        if (!have_series) {
+            if ((st = adjoint_sweep(l, dtype, nb, X, nullptr, wk(1), 1.0 / a, b, 0.0, nullptr, nullptr, nullptr,
+                                    nullptr, nullptr, 0, 0, store, s)) != PV_OK)
                 return st;
+            for (int k = 2; k <= M; ++k)
+                if ((st = adjoint_sweep(l, dtype, nb, wv(k - 1), wv(k - 2), wk(k), 2.0 / a, b, -1.0, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, 0, 0, store, s)) != PV_OK)
+                    return st;
+        }
         PV_HIP(pv::launch_zero(L0, vb, s));
         PV_HIP(pv::launch_zero(L1, vb, s));
         void* lx = L0;
@@ -2622,39 +2667,47 @@ extern "C" pv_status pv_cheb_propagate_vjp(pv_lattice* l, int dtype, int nb, dou
                                            int nsteps, const void* psi0, const void* psibar, void* psi0bar,
                                            double* gradV, void* work, size_t work_bytes, void* stream) {
     pv_status st;
-    if ((st = check_tp_vjp_args(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
-                                work_bytes)) != PV_OK)
+    if ((st = check_tp_vjp_args(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work, work_bytes,
+                                0)) != PV_OK)
         return st;
     return tp_vjp_impl(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
-                       static_cast<hipStream_t>(stream), false);
+                       static_cast<hipStream_t>(stream), false, false);
+}
+
+extern "C" size_t pv_cheb_propagate_keep_workspace_size(const pv_lattice* l, int dtype, int nb, int M, int nsteps,
+                                                        int keep_series) {
+    const size_t base = pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps);
+    if (base == 0 || !keep_series) return base;
+    return base + vec_bytes(l, dtype, nb) * (size_t)nsteps * (size_t)M;
 }
 
 extern "C" pv_status pv_cheb_propagate_keep(pv_lattice* l, int dtype, int nb, double a, double b, double dt, int M,
-                                            int nsteps, const void* psi0, void* psiT, void* work, size_t work_bytes,
-                                            void* stream) {
+                                            int nsteps, const void* psi0, void* psiT, int keep_series, void* work,
+                                            size_t work_bytes, void* stream) {
     pv_status st;
     if ((st = check_series_args(l, dtype, nb, a, b)) != PV_OK) return st;
     if ((st = check_vec(psi0, dtype, "psi0")) != PV_OK) return st;
     if ((st = check_vec(psiT, dtype, "psiT")) != PV_OK) return st;
     if (psiT == psi0) return fail(PV_ERR_INVALID_ARG, "psiT must not alias psi0 (the adjoint reads psi0)");
     if (M < 1 || nsteps < 1 || !std::isfinite(dt)) return fail(PV_ERR_INVALID_ARG, "need M >= 1, nsteps >= 1");
-    const size_t need = pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps);
+    const size_t need = pv_cheb_propagate_keep_workspace_size(l, dtype, nb, M, nsteps, keep_series);
     if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
     if ((st = ensure_device(l)) != PV_OK) return st;
     const std::vector<double> coef = tp_step_coefficients(a, b, dt, M);
-    const TpVjpLayout T{static_cast<char*>(work), vec_bytes(l, dtype, nb), nsteps, M};
-    return tp_forward_keep(l, dtype, nb, a, b, M, nsteps, coef.data(), psi0, psiT, T,
+    const TpVjpLayout T{static_cast<char*>(work), vec_bytes(l, dtype, nb), nsteps, M,
+                        pv_cheb_propagate_vjp_workspace_size(l, dtype, nb, M, nsteps)};
+    return tp_forward_keep(l, dtype, nb, a, b, M, nsteps, coef.data(), psi0, psiT, T, keep_series != 0,
                            static_cast<hipStream_t>(stream));
 }
 
 extern "C" pv_status pv_cheb_propagate_vjp_keep(pv_lattice* l, int dtype, int nb, double a, double b, double dt,
                                                 int M, int nsteps, const void* psi0, const void* psibar,
-                                                void* psi0bar, double* gradV, void* work, size_t work_bytes,
-                                                void* stream) {
+                                                void* psi0bar, double* gradV, int keep_series, void* work,
+                                                size_t work_bytes, void* stream) {
     pv_status st;
-    if ((st = check_tp_vjp_args(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
-                                work_bytes)) != PV_OK)
+    if ((st = check_tp_vjp_args(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work, work_bytes,
+                                keep_series)) != PV_OK)
         return st;
     return tp_vjp_impl(l, dtype, nb, a, b, dt, M, nsteps, psi0, psibar, psi0bar, gradV, work,
-                       static_cast<hipStream_t>(stream), true);
+                       static_cast<hipStream_t>(stream), true, keep_series != 0);
 }

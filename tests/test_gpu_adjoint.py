@@ -191,8 +191,9 @@ def test_kpm_ckpt_pair_separate_reductions_full_block():
     assert float((g_ck - g_one).abs().max() / g_one.abs().max()) < 1e-13
 
 
-@pytest.mark.parametrize("M,nsteps,nb", [(1, 1, 1), (1, 3, 2), (16, 1, 1), (24, 3, 4)])
-def test_propagate_keep_pair_matches_one_call_and_oracle(M, nsteps, nb):
+@pytest.mark.parametrize("keep_series", [False, True])
+@pytest.mark.parametrize("M,nsteps,nb", [(1, 1, 1), (1, 3, 2), (2, 2, 1), (16, 1, 1), (24, 3, 4)])
+def test_propagate_keep_pair_matches_one_call_and_oracle(M, nsteps, nb, keep_series):
     """pv_cheb_propagate_keep + pv_cheb_propagate_vjp_keep: psi_T equals
     pv_cheb_propagate's, the gradient and psi0's cotangent equal the
     one-call pv_cheb_propagate_vjp's and the oracle's; psi0 is unchanged and
@@ -201,15 +202,15 @@ def test_propagate_keep_pair_matches_one_call_and_oracle(M, nsteps, nb):
     psi0_h, psibar_h = c.block(nb, seed=5), c.block(nb, seed=6)
     psi0, psibar = dev(psi0_h), dev(psibar_h)
     a, b, dt = 3.3, 0.05, 2.0
-    psiT, work = pv.pv_cheb_propagate_keep(c.lat, psi0, a, b, dt, M, nsteps)
+    psiT, work = pv.pv_cheb_propagate_keep(c.lat, psi0, a, b, dt, M, nsteps, keep_series)
     assert np.array_equal(host(psi0), psi0_h)
     ref_T = psi0.clone()
     pv.pv_cheb_propagate(c.lat, ref_T, a, b, dt, M, nsteps)
     assert rel(host(psiT), host(ref_T)) < 1e-13
-    g, p0 = pv.pv_cheb_propagate_vjp_keep(c.lat, psi0, psibar, a, b, dt, M, nsteps, work)
+    g, p0 = pv.pv_cheb_propagate_vjp_keep(c.lat, psi0, psibar, a, b, dt, M, nsteps, work, keep_series)
     g1, p01 = pv.pv_cheb_propagate_vjp(c.lat, psi0, psibar, a, b, dt, M, nsteps)
     assert rel(host(g), host(g1)) < 1e-13 and rel(host(p0), host(p01)) < 1e-13
-    g2, p02 = pv.pv_cheb_propagate_vjp_keep(c.lat, psi0, psibar, a, b, dt, M, nsteps, work)
+    g2, p02 = pv.pv_cheb_propagate_vjp_keep(c.lat, psi0, psibar, a, b, dt, M, nsteps, work, keep_series)
     assert np.array_equal(host(g), host(g2)) and np.array_equal(host(p0), host(p02))
     p0_ref, g_ref = adjoint.propagate_vjp(c.H, 2, "site", psi0_h, a, b, dt, M, nsteps, psibar_h)
     assert rel(host(g), g_ref) < 1e-10 and rel(host(p0), p0_ref) < 1e-10
@@ -234,3 +235,8 @@ def test_autograd_backward_twice_with_retained_graph():
     h1 = Vg.grad.clone()
     T.backward()
     assert torch.equal(Vg.grad, 2 * h1)
+    # keeping every step's Chebyshev vectors gives the same gradient
+    Vk = cg.Vd.clone().requires_grad_(True)
+    Tk = (pv.cheb_propagate(Vk, psi0, cg.lat, 3.3, 0.05, 2.0, 16, 2, keep_series=True).abs() ** 2)[: cg.D // 2].sum()
+    Tk.backward()
+    assert float((Vk.grad - h1).abs().max() / h1.abs().max()) < 1e-12
