@@ -236,3 +236,32 @@ def test_trlanczos_filter_matches_oracle(lib):
         c, tau = pv.pv_trlanczos_filter(l, r, a, b, K)
         rc, rtau = trlanczos.delta_filter(l, r, a, b, K)
         assert np.abs(c - rc).max() < 1e-13 and abs(tau - rtau) < 1e-13
+
+
+def test_gradient_split_entry_points_validate_before_any_launch(lib):
+    """The checkpointing forwards and the adjoints that read their workspace
+    reject bad arguments with a status before touching the device."""
+    lat = pv.Lattice((4, 4, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    other = ctypes.c_void_p(1 << 21)
+    big = 1 << 40
+    # KPM: odd M, interval 0, workspace too small, gbar NULL
+    assert lib.pv_kpm_moments_ckpt(lat.handle, 0, 1, 7, 7.0, 0.0, fake, fake, 4, fake, big, None) == 1
+    assert lib.pv_kpm_moments_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, fake, 0, fake, big, None) == 1
+    assert lib.pv_kpm_moments_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, fake, 4, fake, 16, None) == 4
+    need = lib.pv_kpm_vjp_workspace_size(lat.handle, 0, 1, 8, 4)
+    assert need > 0
+    assert lib.pv_kpm_moments_vjp_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, None, fake, 4, fake, big, None) == 1
+    assert lib.pv_kpm_moments_vjp_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, fake, fake, 4, fake, need - 1, None) == 4
+    # propagation: psiT aliasing psi0, no steps, workspace sized without the kept series
+    assert lib.pv_cheb_propagate_keep(lat.handle, 0, 1, 7.0, 0.0, 1.0, 8, 2, fake, fake, 0, other, big, None) == 1
+    assert b"alias" in lib.pv_last_error()
+    assert lib.pv_cheb_propagate_keep(lat.handle, 0, 1, 7.0, 0.0, 1.0, 8, 0, fake, other, 0, other, big, None) == 1
+    base = lib.pv_cheb_propagate_keep_workspace_size(lat.handle, 0, 1, 8, 3, 0)
+    full = lib.pv_cheb_propagate_keep_workspace_size(lat.handle, 0, 1, 8, 3, 1)
+    assert base == lib.pv_cheb_propagate_vjp_workspace_size(lat.handle, 0, 1, 8, 3)
+    vb = lat.n_rows * 16
+    assert full - base >= 3 * 8 * vb
+    assert lib.pv_cheb_propagate_keep(lat.handle, 0, 1, 7.0, 0.0, 1.0, 8, 3, fake, other, 1, other, base, None) == 4
+    assert lib.pv_cheb_propagate_vjp_keep(lat.handle, 0, 1, 7.0, 0.0, 1.0, 8, 3, fake, fake, None, fake, 1, other,
+                                          base, None) == 4
