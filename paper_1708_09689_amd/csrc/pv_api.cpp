@@ -2494,7 +2494,7 @@ extern "C" pv_status pv_kpm_moments_ckpt(pv_lattice* l, int dtype, int nb, int M
     auto wbuf = [&](int k) -> void* {
         const int j = k / C, rem = k - j * C;
         if (j < J && rem <= 1) return ck(j, rem);
-        if (J == 1) return S + vb * (size_t)(k - 2);
+        if (J == 1 && k >= 2) return S + vb * (size_t)(k - 2);
         return F[k & 1];
     };
     auto after = [&](int k, const void* y) -> hipError_t {
