@@ -2336,10 +2336,11 @@ namespace {
 // KPM adjoint workspace: 2J checkpoint vectors (w_{jC}, w_{jC+1}), C segment
 // vectors, two adjoint and two forward vectors, the source-term table, then
 // the dot partials of pv_kpm_moments_ckpt.
+// Intervals beyond N = M/2 all mean one segment; the layout takes C = min(ckpt, N).
 size_t kpm_vjp_core_bytes(const pv_lattice* l, int dtype, int nb, int M, int ckpt) {
-    const int N = M / 2, J = (N - 1) / ckpt + 1;
+    const int N = M / 2, C = std::min(ckpt, N), J = (N - 1) / C + 1;
     const size_t vb = vec_bytes(l, dtype, nb);
-    return vb * (2 * (size_t)J + ckpt + 2 + 2) + align_up((size_t)(N + 1) * 3 * nb * 2 * sizeof(double));
+    return vb * (2 * (size_t)J + C + 2 + 2) + align_up((size_t)(N + 1) * 3 * nb * 2 * sizeof(double));
 }
 }  // namespace
 
@@ -2371,7 +2372,7 @@ pv_status check_kpm_vjp_args(pv_lattice* l, int dtype, int nb, int M, double a, 
 pv_status kpm_vjp_impl(pv_lattice* l, int dtype, int nb, int M, double a, double b, const void* r,
                        const double* gbar, double* gradV, int ckpt, void* work, hipStream_t s, bool have_ckpt) {
     pv_status st;
-    const int N = M / 2, C = ckpt, J = (N - 1) / C + 1;
+    const int N = M / 2, C = std::min(ckpt, N), J = (N - 1) / C + 1;
     const size_t vb = vec_bytes(l, dtype, nb);
     const double invD = 1.0 / double(l->n_rows);
     char* w = static_cast<char*>(work);
@@ -2478,7 +2479,7 @@ extern "C" pv_status pv_kpm_moments_ckpt(pv_lattice* l, int dtype, int nb, int M
     if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
     if ((st = ensure_device(l)) != PV_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int N = M / 2, C = ckpt, J = (N - 1) / C + 1;
+    const int N = M / 2, C = std::min(ckpt, N), J = (N - 1) / C + 1;
     const size_t vb = vec_bytes(l, dtype, nb);
     const size_t vbytes = (size_t)l->n_rows * nb * elem_bytes(dtype);
     char* w = static_cast<char*>(work);

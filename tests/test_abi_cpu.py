@@ -251,6 +251,9 @@ def test_gradient_split_entry_points_validate_before_any_launch(lib):
     assert lib.pv_kpm_moments_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, fake, 4, fake, 16, None) == 4
     need = lib.pv_kpm_vjp_workspace_size(lat.handle, 0, 1, 8, 4)
     assert need > 0
+    # intervals from M/2 up all mean one segment: the same workspace
+    assert lib.pv_kpm_vjp_workspace_size(lat.handle, 0, 1, 8, 1000) == need
+    assert lib.pv_kpm_vjp_workspace_size(lat.handle, 0, 1, 8, 3) > need
     assert lib.pv_kpm_moments_vjp_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, None, fake, 4, fake, big, None) == 1
     assert lib.pv_kpm_moments_vjp_ckpt(lat.handle, 0, 1, 8, 7.0, 0.0, fake, fake, fake, 4, fake, need - 1, None) == 4
     # propagation: psiT aliasing psi0, no steps, workspace sized without the kept series
