@@ -2438,14 +2438,19 @@ pv_status kpm_vjp_impl(pv_lattice* l, int dtype, int nb, int M, double a, double
     void* lz = L1;   // lambda_{k+2}, overwritten by lambda_k
     for (int j = J - 1; j >= 0; --j) {
         const int k_hi = std::min((j + 1) * C, N);
+        // w_{(j+1)C} and w_{(j+1)C+1} are the next segment's checkpoint pair
         auto wv = [&](int i) -> void* {
             if (i == j * C) return ck(j, 0);
             if (i == j * C + 1) return ck(j, 1);
+            if (j + 1 < J && i == (j + 1) * C) return ck(j + 1, 0);
+            if (j + 1 < J && i == (j + 1) * C + 1) return ck(j + 1, 1);
             return S + vb * (size_t)(i - j * C - 2);
         };
-        // (with one segment, pv_kpm_moments_ckpt left w_2..w_N in place)
+        // recompute the rest (with one segment, pv_kpm_moments_ckpt left
+        // w_2..w_N in place)
         const bool stored = have_ckpt && J == 1;
-        for (int i = j * C + 2; !stored && i <= std::min(k_hi + 1, N); ++i)
+        const int i_hi = (j + 1 < J) ? (j + 1) * C - 1 : std::min(k_hi + 1, N);
+        for (int i = j * C + 2; !stored && i <= i_hi; ++i)
             if ((st = adjoint_sweep(l, dtype, nb, wv(i - 1), wv(i - 2), wv(i), 2.0 / a, b, -1.0, nullptr, nullptr,
                                     nullptr, nullptr, nullptr, 0, 0, store, s)) != PV_OK)
                 return st;
