@@ -240,3 +240,16 @@ def test_autograd_backward_twice_with_retained_graph():
     Tk = (pv.cheb_propagate(Vk, psi0, cg.lat, 3.3, 0.05, 2.0, 16, 2, keep_series=True).abs() ** 2)[: cg.D // 2].sum()
     Tk.backward()
     assert float((Vk.grad - h1).abs().max() / h1.abs().max()) < 1e-12
+
+
+def test_autograd_propagation_without_steps_is_identity():
+    """nsteps = 0: psi_T = psi0, so the field gradient is zero and psi0's
+    cotangent is psi_T's."""
+    cg = Case("graphene2", (12, 6), (0, 1), Wd=0.3, seed=26)
+    psi0 = dev(cg.block(1, seed=8)).requires_grad_(True)
+    V = cg.Vd.clone().requires_grad_(True)
+    psiT = pv.cheb_propagate(V, psi0, cg.lat, 3.3, 0.05, 2.0, 16, 0)
+    assert torch.equal(psiT.detach(), psi0.detach())
+    (psiT.abs() ** 2).sum().backward()
+    assert float(V.grad.abs().max()) == 0.0
+    assert torch.allclose(psi0.grad, 2 * psi0.detach(), rtol=0, atol=1e-15)
