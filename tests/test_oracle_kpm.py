@@ -130,3 +130,58 @@ def test_jackson_and_dos_normalisation():
     integral = (rho * 7.0 * np.sin(th)).sum() * np.pi / n
     assert abs(integral - 1.0) < 1e-12
     assert (rho > -1e-12).all()
+
+
+@pytest.mark.parametrize("M", [2, 16, 64, 257, 1024])
+def test_jackson_factors_are_the_normalised_autocorrelation(M):
+    """Jackson's construction (Weisse et al. 2006, the KPM reference of the
+    paper, Sec. 2.2): g_n is the autocorrelation at lag n of
+    a_k = sin(pi (k + 1)/(M + 1)), k = 0..M-1, divided by its value at lag 0.
+    Built here by brute-force sums over the sequence, independent of the
+    closed form; it fixes every g_n (g_1 = cos(pi/(M + 1)))."""
+    g = kpm.jackson(M)
+    a = np.sin(np.pi * (np.arange(M) + 1) / (M + 1))
+    ac = np.array([sum(a[k] * a[k + n] for k in range(M - n)) for n in range(M)]) / np.dot(a, a)
+    assert np.abs(g - ac).max() < 1e-14
+    if M > 1:
+        assert abs(g[1] - np.cos(np.pi / (M + 1))) < 1e-15
+
+
+@pytest.mark.parametrize("M,tol", [(64, 2e-3), (256, 1.2e-4), (1024, 8e-6)])
+def test_dos_reconstructs_uniform_density(M, tol):
+    """A density uniform on [b - a, b + a] (value 1/(2a)) has the Chebyshev
+    moments mu_n = (1/2) int_{-1}^{1} T_n(x) dx: mu_0 = 1,
+    mu_{2k} = -1/(4k^2 - 1), odd moments 0.  The Jackson-damped series must
+    return 1/(2a) away from the band edges, with an error that falls as 1/M^2
+    (the kernel's resolution pi/M, squared for a smooth density)."""
+    mu = np.zeros(M)
+    mu[0] = 1.0
+    k = np.arange(1, M // 2)
+    mu[2 * k] = -1.0 / (4.0 * k * k - 1.0)
+    a, b = 2.5, 0.3
+    E = b + a * np.linspace(-0.9, 0.9, 181)
+    rho = kpm.dos(mu, E, a, b)
+    assert np.abs(rho * 2 * a - 1.0).max() < tol
+
+
+@pytest.mark.parametrize("x0", [0.0, 0.37, -0.81])
+def test_dos_of_a_delta_peak_has_the_kernels_moments(x0):
+    """A single level at E0 = b + a x0 has moments mu_n = T_n(x0).  Integrals
+    of the reconstructed density against 1, x and x^2 (Gauss-Chebyshev
+    quadrature in E) follow from Chebyshev orthogonality alone:
+    int rho = g_0, <x> = g_1 x0, <x^2> = (g_0 + g_2 T_2(x0))/2.  A dropped
+    factor 2 on the n >= 1 terms, a wrong T_n argument or a wrong a, b
+    mapping breaks one of them; the maximum sits at E0 within the kernel's
+    resolution."""
+    M, a, b = 128, 3.0, -0.4
+    mu = np.cos(np.arange(M) * np.arccos(x0))
+    g = kpm.jackson(M)
+    n = 20000
+    th = (np.arange(n) + 0.5) * np.pi / n
+    x = np.cos(th)
+    rho = kpm.dos(mu, b + a * x, a, b)
+    w = a * np.sin(th) * np.pi / n
+    assert abs((rho * w).sum() - 1.0) < 1e-13
+    assert abs((rho * x * w).sum() - g[1] * x0) < 1e-13
+    assert abs((rho * x * x * w).sum() - 0.5 * (1.0 + g[2] * (2 * x0 * x0 - 1.0))) < 1e-13
+    assert abs(x[np.argmax(rho)] - x0) < np.pi / M
