@@ -557,6 +557,12 @@ extern "C" pv_status pv_lattice_create(const pv_lattice_desc* d, pv_lattice** ou
     const double sites = double(d->L[0]) * double(d->L[1]) * double(d->L[2]);
     if (sites * d->n_orb * PV_MAX_NB * 16.0 > 9.0e18) return fail(PV_ERR_INVALID_ARG, "lattice too large");
     if (sites >= 2147483648.0) return fail(PV_ERR_UNSUPPORTED, "more than 2^31 - 1 sites");
+    // the sweeps address an x row of a block with 32-bit element and byte
+    // offsets: a row of the widest block (PV_MAX_NB complex128 columns) must
+    // stay below 2^31 bytes
+    if (double(d->L[0]) * d->n_orb * PV_MAX_NB * 16.0 >= 2147483648.0)
+        return fail(PV_ERR_UNSUPPORTED, "L[0] * n_orb = %lld: an x row of a %d-column complex128 block exceeds 2^31 bytes",
+                    (long long)d->L[0] * d->n_orb, PV_MAX_NB);
     const int no = d->n_orb;
     for (int t = 0; t < d->n_terms; ++t) {
         const int* o = d->offsets + 3 * t;

@@ -1453,7 +1453,11 @@ hipError_t launch_typed(SweepParams& p, int num_cus, hipStream_t s) {
         // generic stencils default to staged only on 3D lattices (walks along z)
         const bool can = P::FAMILY != FAM_GENERIC || p.generic_stageable;
         const bool dflt = staged_default(p) && (P::FAMILY != FAM_GENERIC || p.L[2] > 1);
-        if (can && aligned && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && dflt))) {
+        // a site must be whole 16-byte chunks: ring rows start one site
+        // before the tile and wrap by whole chunks (complex64 with
+        // n_orb * nb = 1 is half a chunk per site: direct kernel)
+        const bool whole = (P::NO * p.nb * int(sizeof(cplx<T>))) % 16 == 0;
+        if (can && aligned && whole && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && dflt))) {
             const int e = staged_elems(p);
             auto staged = [&](auto pt) -> hipError_t {
                 using Q = typename decltype(pt)::type;
@@ -1510,7 +1514,8 @@ hipError_t batch_fill_record_fam(const SweepParams& p, int staged, void* dst, in
         KArgs<T, VT> a;
         if constexpr (P::FAMILY != FAM_GENERIC) {
             if (staged) {
-                if (P::NO * p.nb > STAGED_MAX_SITE) return hipErrorInvalidValue;
+                if (P::NO * p.nb > STAGED_MAX_SITE || (P::NO * p.nb * int(sizeof(cplx<T>))) % 16 != 0)
+                    return hipErrorInvalidValue;
                 make_kargs<P, T, VT>(p, false, a);
                 const int e = staged_elems(p);
                 int G8;

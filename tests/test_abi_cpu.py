@@ -112,6 +112,24 @@ def test_descriptor_validation(lib):
         pv.Lattice((4, 4, 2), (1, 1, 1), g)
 
 
+def test_x_row_length_limit(lib):
+    """The sweeps address an x row with 32-bit offsets: a lattice whose x row
+    of a PV_MAX_NB-wide complex128 block reaches 2^31 bytes is refused at
+    creation (long ribbons), the longest row below that is accepted."""
+    g = pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0])
+    limit = (1 << 31) // (2 * pv.PV_MAX_NB * 16)      # sites per row with n_orb = 2
+    with pytest.raises(pv.PvError) as e:
+        pv.Lattice((limit, 1), (0, 1), g)
+    assert e.value.status == 2
+    assert b"exceeds 2^31 bytes" in lib.pv_last_error()
+    lat = pv.Lattice((limit - 1, 1), (0, 1), g)
+    assert lat.n_sites == limit - 1
+    ti = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0])
+    with pytest.raises(pv.PvError) as e:
+        pv.Lattice(((1 << 31) // (4 * pv.PV_MAX_NB * 16), 1, 1), (1, 1, 1), ti)
+    assert e.value.status == 2
+
+
 def test_argument_errors_return_before_any_launch(lib):
     lat = pv.Lattice((4, 4, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
     one = np.ones(4)

@@ -307,3 +307,43 @@ def test_generic_stageable_open_x_orbital_field_series(kernel, shape):
     Y = torch.empty((ol.n_rows, nb), dtype=torch.complex128, device="cuda")
     pv.pv_cheb_series(lat, dev(X), Y, a, 0.1, coef)
     assert rel_err(host(Y), chebtp.cheb_series(H, X, a, 0.1, coef)) < 1e-12
+
+
+@pytest.mark.parametrize("nb,dtype", [(1, np.complex64), (2, np.complex64), (1, np.complex128)])
+@pytest.mark.parametrize("per", [(1, 1, 1), (0, 1, 0)])
+@pytest.mark.parametrize("kernel", [0, 2])
+def test_generic_single_orbital_narrow_sites(nb, dtype, per, kernel):
+    """Single-orbital generic stencil (simple-cubic hops with next-nearest x-z
+    hops) with sites narrower than or equal to one 16-byte chunk: complex64
+    at nb = 1 (half a chunk per site, where a staged ring row would start
+    inside a chunk, so the launch takes the direct kernel even when the
+    staged one is requested), complex64 at nb = 2 and complex128 at nb = 1
+    (one chunk per site, staged).  Open and periodic x; Chebyshev step with
+    dots against the oracle on the explicit matrix."""
+    g = np.random.default_rng(70 + nb)
+    no = 1
+    blocks, offsets = [], []
+    for o in GENERIC_OFFSETS["stageable"]:
+        B = g.standard_normal((1, 1)) + 1j * g.standard_normal((1, 1))
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.25]])
+    st = {"dim": 3, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    L = (67, 5, 6)          # ragged: 67 sites per row
+    lat = pv.Lattice(L, per, st)
+    assert lat.family == 0
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    if kernel:
+        pv.pv_lattice_set_tuning(lat, code, nb, {"kernel": kernel})
+    V = W.uniform_potential(L[0] * L[1] * L[2], 1.0, W.generator(7, 1))
+    vdt = np.float64 if dtype == np.complex128 else np.float32
+    lat.set_potential(dev(V.astype(vdt)))
+    ol, H = _explicit_matrix(L, per, no, offsets, blocks, E0, V.astype(vdt).astype(np.float64), False)
+    x = W.gaussian_block(ol.n_rows, nb, W.generator(7, 2), dtype)
+    z = W.gaussian_block(ol.n_rows, nb, W.generator(7, 3), dtype)
+    y = dev(z.copy())
+    pv.pv_spmmv(lat, dev(x), y, 0.4, 0.2, -1.0, z=y, dot_flags=7)
+    ref = spmmv.spmmv(H, x.astype(np.complex128), 0.4, 0.2, -1.0, z.astype(np.complex128))
+    tol = 1e-13 if dtype == np.complex128 else 2e-6
+    assert rel_err(host(y).astype(np.complex128), ref) < tol
