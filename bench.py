@@ -157,6 +157,44 @@ def triad_probe(pv, torch, dev, nbytes=4 << 30, reps=10) -> float:
     return 3.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def read_probe(pv, torch, dev, nbytes=8 << 30, reps=10) -> float:
+    """Achievable bandwidth of a streaming read (GB/s, reads only)."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    sink = torch.empty(pv.PV_STREAM_READ_SINK_BYTES // 4, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        pv.pv_stream_read(x, sink)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pv.pv_stream_read(x, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, sink
+    return nbytes / (ms * 1e-3) / 1e9
+
+
+def memcpy_probe(torch, dev, nbytes=4 << 30, reps=10) -> float:
+    """Device-to-device copy through the runtime (torch's copy_ of contiguous
+    tensors of one dtype: hipMemcpyAsync), GB/s read + write: a copy that is
+    not this library's, as a cross-check of the copy probe."""
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(nb: int, budget_s: float = 12.0) -> dict:
     """The oracle (scipy CSR SpMMV + numpy dots, one thread) on a bounded
     sample of the same workload: the same x-y planes, 4 of the 64 z-layers."""
@@ -576,6 +614,8 @@ def main():
 
     copy_gbs = None if args.no_copy else copy_probe(pv, torch, dev)
     triad_gbs = None if args.no_copy else triad_probe(pv, torch, dev)
+    read_gbs = None if args.no_copy else read_probe(pv, torch, dev)
+    memcpy_gbs = None if args.no_copy else memcpy_probe(torch, dev)
 
     # headline
     set_field(args.dtype)
@@ -689,6 +729,8 @@ def main():
         "frac_of_copy_probe": None if copy_gbs is None else round(achieved / copy_gbs, 4),
         "triad_probe_GBs": None if triad_gbs is None else round(triad_gbs, 1),
         "frac_of_triad_probe": None if triad_gbs is None else round(achieved / triad_gbs, 4),
+        "read_probe_GBs": None if read_gbs is None else round(read_gbs, 1),
+        "memcpy_d2d_GBs": None if memcpy_gbs is None else round(memcpy_gbs, 1),
         "metric_parts": parts,
         "variants": variants,
         "workloads": configs,

@@ -471,6 +471,15 @@ pv_status pv_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
  * or size. */
 pv_status pv_stream_triad(const void *x, const void *z, void *y, size_t bytes, void *stream);
 
+/* Third bandwidth reference, reads only: every 16-byte chunk of x (a device
+ * buffer of `bytes`, a multiple of 16, 16-byte aligned) is loaded once and
+ * folded into a 32-bit XOR per wave, written to `sink` (a device buffer of
+ * PV_STREAM_READ_SINK_BYTES, caller-owned; its contents are a checksum with
+ * no other meaning).  PV_ERR_INVALID_ARG on a null or misaligned pointer or
+ * size. */
+#define PV_STREAM_READ_SINK_BYTES 65536
+pv_status pv_stream_read(const void *x, size_t bytes, void *sink, void *stream);
+
 /*
  * Launch shape of the stencil sweep for one (dtype, nb) of a lattice -- the
  * GPU counterpart of the cache-blocking choices of Sec. 3.1 (layer

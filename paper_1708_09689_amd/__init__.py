@@ -78,6 +78,7 @@ SIGNATURES = {
     "pv_block_rotate": (_i, [_i, _i64, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "pv_stream_copy": (_i, [_vp, _vp, _sz, _vp]),
     "pv_stream_triad": (_i, [_vp, _vp, _vp, _sz, _vp]),
+    "pv_stream_read": (_i, [_vp, _sz, _vp, _vp]),
     "pv_chebfd_workspace_size": (_sz, [_vp, _i, _i, _i]),
     "pv_chebfd": (_i, [_vp, _i, _i, _i, _d, _d, _d, _d, _i, _i, _d, _i, _vp, _dp, _dp, _ip, _ip, _vp, _sz, _vp]),
     "pv_chebfd_filter_coefficients": (_i, [_d, _d, _d, _d, _i, _dp]),
@@ -442,6 +443,20 @@ def pv_stream_triad(x, z, y):
     _check(lib().pv_stream_triad(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(z.data_ptr()),
                                  ctypes.c_void_p(y.data_ptr()), n, _stream()))
     return y
+
+
+PV_STREAM_READ_SINK_BYTES = 65536
+
+
+def pv_stream_read(x, sink):
+    """Reads every byte of the contiguous device tensor x once (bandwidth
+    reference); sink: a device tensor of at least PV_STREAM_READ_SINK_BYTES
+    that receives a checksum per wave."""
+    if not x.is_contiguous() or sink.numel() * sink.element_size() < PV_STREAM_READ_SINK_BYTES:
+        raise ValueError("read probe takes a contiguous tensor and a sink of PV_STREAM_READ_SINK_BYTES")
+    n = x.numel() * x.element_size()
+    _check(lib().pv_stream_read(ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(sink.data_ptr()), _stream()))
+    return sink
 
 
 def pv_bloch_block(lat, k, orbital, layer=None, dtype=PV_C128, out=None, device="cuda"):

@@ -1145,6 +1145,16 @@ extern "C" pv_status pv_stream_copy(const void* src, void* dst, size_t bytes, vo
     return PV_OK;
 }
 
+extern "C" pv_status pv_stream_read(const void* x, size_t bytes, void* sink, void* stream) {
+    static_assert(pv::STREAM_READ_GROUPS * 4 * 4 == PV_STREAM_READ_SINK_BYTES, "sink size");
+    if (!x || !sink || bytes % 16 || reinterpret_cast<uintptr_t>(x) % 16 || reinterpret_cast<uintptr_t>(sink) % 4)
+        return fail(PV_ERR_INVALID_ARG, "read probe needs a 16-byte aligned source and size and a 4-byte aligned sink");
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    PV_HIP(pv::launch_read(x, bytes, sink, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
 extern "C" pv_status pv_stream_triad(const void* x, const void* z, void* y, size_t bytes, void* stream) {
     if (!x || !z || !y || bytes % 16 ||
         (reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(y)) % 16)

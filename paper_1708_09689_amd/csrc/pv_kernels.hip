@@ -187,6 +187,24 @@ __global__ __launch_bounds__(kBlock) void triad_kernel(const f64x2* __restrict__
     }
 }
 
+// Streaming read: every 16-byte chunk of src is loaded once and folded into
+// a per-lane XOR; each wave writes one word (the sink keeps the loads live).
+__global__ __launch_bounds__(kBlock) void read_kernel(const u32x4* __restrict__ src, int64_t n,
+                                                      uint32_t* __restrict__ sink) {
+    const int64_t chunk = 4 * (int64_t)kBlock;
+    uint32_t acc = 0;
+    for (int64_t base = blockIdx.x * chunk; base < n; base += (int64_t)gridDim.x * chunk) {
+        u32x4 r[4];
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = base + k * kBlock + threadIdx.x;
+            r[k] = i < n ? __builtin_nontemporal_load(src + i) : u32x4{0u, 0u, 0u, 0u};
+        }
+        for (int k = 0; k < 4; ++k) acc ^= r[k].x ^ r[k].y ^ r[k].z ^ r[k].w;
+    }
+    for (int d = 32; d > 0; d >>= 1) acc ^= uint32_t(__shfl_xor(int(acc), d));
+    if ((threadIdx.x & 63) == 0) sink[blockIdx.x * (kBlock / 64) + threadIdx.x / 64] = acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void column_copy_kernel(const cplx<T>* __restrict__ src, int src_ld,
                                                            int src_col, cplx<T>* __restrict__ dst, int dst_ld,
@@ -355,6 +373,16 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) 
     if (g < 1) g = 1;
     hipLaunchKernelGGL(copy_kernel, dim3(int(g)), dim3(kBlock), 0, s, static_cast<const u32x4*>(src),
                        static_cast<u32x4*>(dst), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_read(const void* src, size_t bytes, void* sink, hipStream_t s) {
+    const int64_t n = int64_t(bytes / 16);
+    int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
+    if (g > STREAM_READ_GROUPS) g = STREAM_READ_GROUPS;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(read_kernel, dim3(int(g)), dim3(kBlock), 0, s, static_cast<const u32x4*>(src), n,
+                       static_cast<uint32_t*>(sink));
     return hipGetLastError();
 }
 

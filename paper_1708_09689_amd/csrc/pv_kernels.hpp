@@ -116,6 +116,9 @@ hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X,
                          int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_triad(const void* x, const void* z, void* y, size_t bytes, hipStream_t s);
+// workgroups of the read probe (its sink holds one 32-bit word per wave)
+constexpr int STREAM_READ_GROUPS = 4096;
+hipError_t launch_read(const void* src, size_t bytes, void* sink, hipStream_t s);
 
 // dst[r][dst_col + c] = (re + i im) * src[r][src_col + c] for r < rows,
 // c < ncols, blocks of widths src_ld and dst_ld (columns moved between
