@@ -217,6 +217,29 @@ pv_status pv_spmmv(pv_lattice *lat, int dtype, int nb, const void *x, const void
                    void *stream);
 
 /*
+ * pv_spmmv without allocation, for callers that cannot call hipMalloc: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid device
+ * allocation.  Same arguments, semantics and errors as pv_spmmv, without
+ * (work, work_bytes): the partial dot products and the per-column scale
+ * table live in a library-owned static device array of
+ * PV_NOALLOC_SCRATCH_BYTES, one copy per GPU, held until the process ends.
+ * No call allocates or frees device memory.
+ *   - PV_ERR_UNSUPPORTED when pv_spmmv_workspace_size(lat, dtype, nb)
+ *     exceeds PV_NOALLOC_SCRATCH_BYTES.
+ *   - PV_ERR_INVALID_ARG when the lattice has no device tables on the current
+ *     device yet: the first other sweep call there (pv_spmmv, pv_kpm_moments,
+ *     ...) creates them.
+ *   - Every call on one GPU shares that GPU's array and leaves its contents
+ *     behind; calls that overlap on one GPU (several streams or host threads)
+ *     race, so the caller serialises them.  Per-column (non-uniform) alpha,
+ *     beta, gamma synchronise the stream, as in pv_spmmv.
+ */
+#define PV_NOALLOC_SCRATCH_BYTES (64 << 20)
+pv_status pv_spmmv_noalloc(pv_lattice *lat, int dtype, int nb, const void *x, const void *z, void *y,
+                           const double *alpha, const double *beta, const double *gamma, unsigned dot_flags,
+                           double *dots, void *stream);
+
+/*
  * KPM moments (Sec. 2.2 DOS, Sec. 4): for every column c of the start block r
  *     mu[c][n] = Re <r_c, T_n(H~) r_c> / D,  H~ = (H - b)/a,  n = 0..M-1,
  * with D = n_rows, formed from M/2 fused sweeps through

@@ -65,6 +65,7 @@ SIGNATURES = {
     "pv_lattice_set_random_potential": (_i, [_vp, ctypes.c_uint64, _d]),
     "pv_spmmv_workspace_size": (_sz, [_vp, _i, _i]),
     "pv_spmmv": (_i, [_vp, _i, _i, _vp, _vp, _vp, _dp, _dp, _dp, _u, _vp, _vp, _sz, _vp]),
+    "pv_spmmv_noalloc": (_i, [_vp, _i, _i, _vp, _vp, _vp, _dp, _dp, _dp, _u, _vp, _vp]),
     "pv_kpm_workspace_size": (_sz, [_vp, _i, _i, _i]),
     "pv_kpm_moments": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _sz, _vp]),
     "pv_kpm_dos": (_i, [_i, _dp, _d, _d, _i, _dp, _dp]),
@@ -341,6 +342,25 @@ def pv_spmmv(lat: Lattice, x, y, alpha, beta, gamma, z=None, dot_flags: int = 0,
                           _vec(y, "y", lat.n_rows, nb, dt), _dptr(a), _dptr(b), _dptr(g), dot_flags,
                           None if dots is None else ctypes.c_void_p(dots.data_ptr()),
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return dots
+
+
+PV_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def pv_spmmv_noalloc(lat: Lattice, x, y, alpha, beta, gamma, z=None, dot_flags: int = 0, dots=None, nb=None):
+    """pv_spmmv with the library's static scratch instead of a workspace (the
+    library allocates nothing; dots, when requested, is the caller's [nb][4]
+    FP64 device tensor)."""
+    nb = nb if nb is not None else x.numel() // lat.n_rows
+    dt = _dtype_code(x)
+    a = np.broadcast_to(np.asarray(alpha, dtype=np.float64), (nb,)).copy()
+    b = np.broadcast_to(np.asarray(beta, dtype=np.float64), (nb,)).copy()
+    g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (nb,)).copy()
+    _check(lib().pv_spmmv_noalloc(lat.handle, dt, nb, _vec(x, "x", lat.n_rows, nb),
+                                  _vec(z, "z", lat.n_rows, nb, dt), _vec(y, "y", lat.n_rows, nb, dt), _dptr(a),
+                                  _dptr(b), _dptr(g), dot_flags,
+                                  None if dots is None else ctypes.c_void_p(dots.data_ptr()), _stream()))
     return dots
 
 

@@ -679,9 +679,14 @@ extern "C" size_t pv_spmmv_workspace_size(const pv_lattice* l, int dtype, int nb
     return partial_bytes(l, nb) + align_up(sizeof(double) * 3 * nb);
 }
 
-extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y,
-                              const double* alpha, const double* beta, const double* gamma, unsigned dot_flags,
-                              double* dots, void* work, size_t work_bytes, void* stream) {
+namespace {
+
+// Validation and launch of one fused sweep; the partial dot products go to
+// `partials` and non-uniform per-column scales to `colp` (both device
+// memory of the caller's choosing, sized by pv_spmmv_workspace_size).
+pv_status spmmv_check(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y, const double* alpha,
+                      const double* beta, const double* gamma, unsigned dot_flags, double* dots, bool& uniform,
+                      bool& need_z) {
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
     pv_status st;
     if ((st = check_dtype(l, dtype)) != PV_OK) return st;
@@ -689,7 +694,8 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
     if ((st = check_vec(x, dtype, "x")) != PV_OK) return st;
     if ((st = check_vec(y, dtype, "y")) != PV_OK) return st;
     if (!alpha || !beta || !gamma) return fail(PV_ERR_INVALID_ARG, "alpha/beta/gamma must be host arrays [nb]");
-    bool uniform = true, need_z = false;
+    uniform = true;
+    need_z = false;
     for (int c = 0; c < nb; ++c) {
         if (!std::isfinite(alpha[c]) || !std::isfinite(beta[c]) || !std::isfinite(gamma[c]))
             return fail(PV_ERR_INVALID_ARG, "non-finite scale/shift in column %d", c);
@@ -700,10 +706,13 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
     if (x == y || (need_z && x == z)) return fail(PV_ERR_INVALID_ARG, "x must not alias y or z");
     if (dot_flags & ~7u) return fail(PV_ERR_INVALID_ARG, "unknown dot flags 0x%x", dot_flags);
     if (dot_flags && !dots) return fail(PV_ERR_INVALID_ARG, "dots is NULL but dot products were requested");
-    const size_t need = pv_spmmv_workspace_size(l, dtype, nb);
-    if (work_bytes < need || (!work && need)) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
-    if ((st = ensure_device(l)) != PV_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return PV_OK;
+}
+
+pv_status spmmv_launch(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y, const double* alpha,
+                       const double* beta, const double* gamma, unsigned dot_flags, double* dots, bool uniform,
+                       bool need_z, double* partials, double* colp, hipStream_t s) {
+    pv_status st;
     pv::SweepParams p = base_params(l, dtype, nb);
     if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
     p.x = x;
@@ -713,10 +722,8 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
     p.beta = beta[0];
     p.gamma = gamma[0];
     p.ep = pv::EP_STORE_Y | (dot_flags ? pv::EP_DOTS : 0u);
-    char* w = static_cast<char*>(work);
-    p.partials = reinterpret_cast<double*>(w);
+    p.partials = partials;
     if (!uniform) {
-        double* colp = reinterpret_cast<double*>(w + partial_bytes(l, nb));
         std::vector<double> h(3 * nb);
         for (int c = 0; c < nb; ++c) {
             h[3 * c] = alpha[c];
@@ -725,11 +732,91 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
         }
         PV_HIP(hipMemcpyAsync(colp, h.data(), sizeof(double) * 3 * nb, hipMemcpyHostToDevice, s));
         p.colp = colp;
+        PV_HIP(pv::launch_sweep(p, num_cus(), s));
+        PV_HIP(hipStreamSynchronize(s));  // the host staging buffer h goes out of scope
+    } else {
+        PV_HIP(pv::launch_sweep(p, num_cus(), s));
     }
-    PV_HIP(pv::launch_sweep(p, num_cus(), s));
     if (dot_flags) PV_HIP(pv::launch_reduce_dots(p.partials, p.grid, nb, 0, dots, 0, 0, 0.0, s));
-    if (!uniform) PV_HIP(hipStreamSynchronize(s));  // host staging buffer h goes out of scope
     return PV_OK;
+}
+
+}  // namespace
+
+extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y,
+                              const double* alpha, const double* beta, const double* gamma, unsigned dot_flags,
+                              double* dots, void* work, size_t work_bytes, void* stream) {
+    bool uniform, need_z;
+    pv_status st;
+    if ((st = spmmv_check(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z)) != PV_OK)
+        return st;
+    const size_t need = pv_spmmv_workspace_size(l, dtype, nb);
+    if (work_bytes < need || (!work && need)) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    if ((st = ensure_device(l)) != PV_OK) return st;
+    char* w = static_cast<char*>(work);
+    return spmmv_launch(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z,
+                        reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb)),
+                        static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free sweep: the scratch of pv_spmmv (partial dot products,
+// per-column scales) in a static device array, one copy per GPU.
+// ---------------------------------------------------------------------------
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[PV_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch` (looked up once per device,
+// with that device current).  The array's name in host code is a host-side
+// stand-in and is never passed to a kernel or a copy.
+pv_status scratch_of_device(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PV_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PV_OK;
+}
+
+}  // namespace
+
+extern "C" pv_status pv_spmmv_noalloc(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y,
+                                      const double* alpha, const double* beta, const double* gamma,
+                                      unsigned dot_flags, double* dots, void* stream) {
+    bool uniform, need_z;
+    pv_status st;
+    if ((st = spmmv_check(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z)) != PV_OK)
+        return st;
+    const size_t need = pv_spmmv_workspace_size(l, dtype, nb);
+    if (need > (size_t)PV_NOALLOC_SCRATCH_BYTES)
+        return fail(PV_ERR_UNSUPPORTED, "sweep needs %zu bytes of scratch, more than the static %d", need,
+                    PV_NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    {
+        // the lattice's device tables are made (allocated) by the first other
+        // sweep call on this device; this entry point only uses them
+        std::lock_guard<std::mutex> lk(l->mu);
+        if (l->dev != dev || !l->d_coef)
+            return fail(PV_ERR_INVALID_ARG, "lattice has no device tables on device %d: run one other sweep call "
+                                            "(for instance pv_spmmv) on this device first", dev);
+    }
+    void* ptr = nullptr;
+    if ((st = scratch_of_device(dev, &ptr)) != PV_OK) return st;
+    char* w = static_cast<char*>(ptr);
+    return spmmv_launch(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z,
+                        reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb)),
+                        static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------------------

@@ -286,3 +286,21 @@ def test_gradient_split_entry_points_validate_before_any_launch(lib):
     assert lib.pv_cheb_propagate_keep(lat.handle, 0, 1, 7.0, 0.0, 1.0, 8, 3, fake, other, 1, other, base, None) == 4
     assert lib.pv_cheb_propagate_vjp_keep(lat.handle, 0, 1, 7.0, 0.0, 1.0, 8, 3, fake, fake, None, fake, 1, other,
                                           base, None) == 4
+
+
+def test_noalloc_sweep_rejects_oversized_scratch_before_any_device_call(lib):
+    """pv_spmmv_noalloc refuses a sweep whose scratch need exceeds the static
+    array (PV_ERR_UNSUPPORTED), and bad arguments, before touching a device."""
+    lat = pv.Lattice((512, 512, 512), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
+    assert lib.pv_spmmv_workspace_size(lat.handle, 0, 64) > pv.PV_NOALLOC_SCRATCH_BYTES
+    one = np.ones(64)
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    st = lib.pv_spmmv_noalloc(lat.handle, 0, 64, fake, None, ctypes.c_void_p(1 << 21), pv._dptr(one),
+                              pv._dptr(one), pv._dptr(np.zeros(64)), 0, None, None)
+    assert st == 2 and b"static" in lib.pv_last_error()
+    st = lib.pv_spmmv_noalloc(lat.handle, 0, 3, fake, None, ctypes.c_void_p(1 << 21), pv._dptr(one),
+                              pv._dptr(one), pv._dptr(np.zeros(64)), 0, None, None)
+    assert st == 2   # nb not a power of two
+    st = lib.pv_spmmv_noalloc(lat.handle, 0, 1, fake, None, fake, pv._dptr(one), pv._dptr(one),
+                              pv._dptr(np.zeros(64)), 0, None, None)
+    assert st == 1   # x aliases y

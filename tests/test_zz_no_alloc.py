@@ -1,0 +1,75 @@
+"""The allocation-free sweep (pv_spmmv_noalloc) against pv_spmmv, through the
+C ABI: two calls in a row on one GPU's static scratch, the second with a
+smaller block, each compared with pv_spmmv on the same inputs (bitwise: the
+same kernels in the same launch shapes) and with the oracle (complex128,
+1e-13 relative to max|y|; dots 1e-12 relative)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1708_09689_amd as pv  # noqa: E402
+from oracle import spmmv  # noqa: E402
+import workloads as W  # noqa: E402
+
+from gpu_common import Case, dev, host, rel_err  # noqa: E402
+
+
+def _both(c, nb, alpha, beta, gamma, seed):
+    x = c.block(nb, seed=seed)
+    z = c.block(nb, seed=seed + 1)
+    # reference: pv_spmmv with a workspace (y starts as z: in-place recurrence)
+    y_ref = dev(z.copy())
+    d_ref = pv.pv_spmmv(c.lat, dev(x), y_ref, alpha, beta, gamma, z=y_ref, dot_flags=7)
+    # allocation-free call; y starts as z, dots start as NaN (every entry written)
+    y = dev(z.copy())
+    dots = torch.full((nb, 4), float("nan"), dtype=torch.float64, device="cuda")
+    pv.pv_spmmv_noalloc(c.lat, dev(x), y, alpha, beta, gamma, z=y, dot_flags=7, dots=dots)
+    ref = spmmv.spmmv(c.H, x, np.broadcast_to(alpha, (nb,)), np.broadcast_to(beta, (nb,)),
+                      np.broadcast_to(gamma, (nb,)), z)
+    return host(y), host(dots), host(y_ref), host(d_ref), ref, x
+
+
+def test_noalloc_sweep_matches_pv_spmmv_two_calls():
+    # first call: a block of 2^22 elements (staged kernel, 512-lane shape by
+    # default for c128 is not forced: whatever pv_spmmv takes, both take)
+    big = Case("ti", (64, 32, 32), (1, 1, 1), Wd=2.0, seed=3)
+    pv.pv_spmmv(big.lat, dev(big.block(8, seed=9)), torch.empty((big.D, 8), dtype=torch.complex128, device="cuda"),
+                1.0, 0.0, 0.0)   # creates the lattice's device tables (the only allocation)
+    y, d, y_ref, d_ref, ref, x = _both(big, 8, 2.0 / 7.0, 0.1, -1.0, 11)
+    assert np.array_equal(y, y_ref)
+    assert np.array_equal(d, d_ref)
+    assert rel_err(y, ref) < 1e-13
+    xx = np.sum(np.abs(x) ** 2, axis=0)
+    assert np.abs(d[:, 0] - xx).max() < 1e-12 * xx.max()
+    assert np.abs(d[:, 3] - np.sum(np.abs(ref) ** 2, axis=0)).max() < 1e-12 * xx.max() * 10
+
+    # second call, smaller block, per-column scales (scratch holds the table)
+    small = Case("ti", (9, 7, 5), (1, 0, 1), Wd=1.0, seed=4)
+    pv.pv_spmmv(small.lat, dev(small.block(4, seed=2)),
+                torch.empty((small.D, 4), dtype=torch.complex128, device="cuda"), 1.0, 0.0, 0.0)
+    g = W.generator(8, 7, 4)
+    alpha, beta, gamma = 0.5 + g.random(4), g.standard_normal(4), g.standard_normal(4)
+    y, d, y_ref, d_ref, ref, x = _both(small, 4, alpha, beta, gamma, 21)
+    assert np.array_equal(y, y_ref)
+    assert np.array_equal(d, d_ref)
+    assert rel_err(y, ref) < 1e-13
+    assert np.isfinite(d).all()
+
+
+def test_noalloc_sweep_needs_device_tables_and_bounds_scratch():
+    c = Case("ti", (6, 5, 4), (1, 1, 1), Wd=1.0, seed=5)   # no sweep has run on this lattice
+    x = dev(c.block(2, seed=1))
+    y = torch.empty_like(x)
+    with pytest.raises(pv.PvError) as e:
+        pv.pv_spmmv_noalloc(c.lat, x, y, 1.0, 0.0, 0.0)
+    assert e.value.status == 1
+    assert b"no device tables" in pv.lib().pv_last_error()
+    # after one other sweep the same call runs
+    pv.pv_spmmv(c.lat, x, torch.empty_like(x), 1.0, 0.0, 0.0)
+    pv.pv_spmmv_noalloc(c.lat, x, y, 1.0, 0.0, 0.0)
+    assert rel_err(host(y), spmmv.spmmv(c.H, host(x), 1.0, 0.0, 0.0)) < 1e-13
