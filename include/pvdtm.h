@@ -125,6 +125,11 @@ typedef struct pv_batch pv_batch;
 const char *pv_last_error(void);
 const char *pv_status_string(pv_status s);
 int pv_version(void);
+/* Hash of the sources and this header the library was built from (16 hex
+ * digits, "unstamped" for builds that did not set it).  A binding compares it
+ * with the sources it was shipped with, so that structures such as
+ * pv_tuning never cross the interface with two different layouts. */
+const char *pv_source_hash(void);
 
 /*
  * Model stencils (host only, no device use).  Fill the descriptor arrays for

@@ -57,6 +57,7 @@ SIGNATURES = {
     "pv_last_error": (ctypes.c_char_p, []),
     "pv_status_string": (ctypes.c_char_p, [_i]),
     "pv_version": (_i, []),
+    "pv_source_hash": (ctypes.c_char_p, []),
     "pv_model_stencil": (_i, [_i, _dp, _ip, _ip, _ip, _ip, _dp, _dp, _ip]),
     "pv_lattice_create": (_i, [ctypes.POINTER(pv_lattice_desc), ctypes.POINTER(_vp)]),
     "pv_lattice_destroy": (None, [_vp]),
@@ -128,9 +129,21 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1708_09689_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
-            f = getattr(L, name)
+            f = getattr(L, name, None)
+            if f is None:
+                raise RuntimeError(f"{LIB_PATH} lacks {name}: it was built from other sources; rebuild with "
+                                   "`python -m paper_1708_09689_amd.build`")
             f.restype = res
             f.argtypes = args
+        # the structures this module declares (pv_tuning, pv_lattice_desc)
+        # must have the library's layout: refuse a library built from other
+        # sources than the ones shipped beside this module
+        from . import build as _build
+        if os.path.isdir(_build.CSRC):
+            want, have = _build.source_hash(), L.pv_source_hash().decode()
+            if have != want:
+                raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {have}, sources {want}): "
+                                   "rebuild with `python -m paper_1708_09689_amd.build`")
         _lib = L
     return _lib
 

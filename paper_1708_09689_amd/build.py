@@ -34,6 +34,22 @@ HIP_FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the library's sources and C header,
+    stamped into the build and compared by the binding when it loads the
+    library: a library built from other sources is refused."""
+    import hashlib
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")) +
+                   glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(INCLUDE, "*.h")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode() + b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+        h.update(b"\0")
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -47,7 +63,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in srcs]
-    cmds = [[hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj] for src, obj in zip(srcs, objs)]
+    stamp = f'-DPV_SOURCE_HASH="{source_hash()}"'
+    cmds = [[hipcc(), *HIP_FLAGS, stamp, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj] for src, obj in zip(srcs, objs)]
     if verbose:
         for cmd in cmds:
             print(" ".join(cmd), flush=True)

@@ -385,6 +385,11 @@ extern "C" const char* pv_status_string(pv_status s) {
 
 extern "C" int pv_version(void) { return 1; }
 
+#ifndef PV_SOURCE_HASH
+#define PV_SOURCE_HASH "unstamped"
+#endif
+extern "C" const char* pv_source_hash(void) { return PV_SOURCE_HASH; }
+
 // ---------------------------------------------------------------------------
 // model stencils (Sec. 2)
 // ---------------------------------------------------------------------------

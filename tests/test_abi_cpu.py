@@ -304,3 +304,11 @@ def test_noalloc_sweep_rejects_oversized_scratch_before_any_device_call(lib):
     st = lib.pv_spmmv_noalloc(lat.handle, 0, 1, fake, None, fake, pv._dptr(one), pv._dptr(one),
                               pv._dptr(np.zeros(64)), 0, None, None)
     assert st == 1   # x aliases y
+
+
+def test_library_built_from_these_sources(lib):
+    """The loaded library carries the hash of the sources it was built from,
+    and it is the tree's (the binding refuses a stale build, whose structures
+    could differ from the ones it declares)."""
+    from paper_1708_09689_amd import build
+    assert lib.pv_source_hash().decode() == build.source_hash()
