@@ -281,12 +281,22 @@ def bench_chebtp_graphene(pv, torch, W, dev, steps=5):
                   for _ in range(3))
     ms = runs[1]
     norm = float(torch.linalg.vector_norm(psi).item())
+    # the configured run: 200 steps from the initial packet, then 200 back
+    psi0 = torch.from_numpy(W.gaussian_wave_packet(Li, Lj, i0=200, width=50, energy=0.2).reshape(-1, 1)).to(dev)
+    psi = psi0.clone()
+    ms200 = _timed(torch, lambda: pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, 200))
+    n200 = float(torch.linalg.vector_norm(psi).item())
+    pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, -10.0, 64, 200)
+    back = float((torch.linalg.vector_norm(psi - psi0) / torch.linalg.vector_norm(psi0)).item())
     lups = lat.n_rows * 64
     by = lat.n_rows * (4 * 16) + lat.n_sites * 8   # x, z, acc in/out (+y) per sweep, field
     return {"workload": "graphene 1024x1024 cells x 2 sites, open x / periodic y, dot array, packet; "
                         f"runs of {steps} time steps of dt=10 (median of 3), M=64, complex128",
             "ms_per_time_step": round(ms, 4), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
             "norm_after": round(norm, 12), "approx_GB/s": round(by * 64 / (ms * 1e-3) / 1e9, 1),
+            "run_200_steps": {"ms": round(ms200, 2), "norm_minus_1": float(f"{n200 - 1.0:.3g}"),
+                              "back_200_steps_rel_err": float(f"{back:.3g}"),
+                              "note": "200 steps of dt=10 from the packet, then 200 steps of dt=-10"},
             "note": "working set ~170 MB: largely resident in the 256 MB Infinity Cache"}
 
 
@@ -328,11 +338,12 @@ def bench_plain(pv, torch, lat, dev):
     return out
 
 
-def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16, loop_M=64):
+def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16):
     """96 TI disorder realisations, L ~ U{24..96}, W ~ U[0.5, 3], 16 random-phase
     columns, M = 1024: one graph-captured batched launch per step with
-    complex64 vectors and FP64 moments, vs a per-instance complex128 loop
-    (timed over loop_M moments)."""
+    complex64 vectors and FP64 moments, vs a per-instance complex128 loop over
+    the same phases (drawn in complex128, rounded to complex64 for the batch);
+    the FP32 path's error is max|dmu| per instance against that loop."""
     inst = W.batch_instances(n, W.generator(3, W.STREAM_SIZES))
     st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
     lats, Vs, rs = [], [], []
@@ -344,7 +355,7 @@ def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16, loop_M=64):
     sites = sum(l.n_sites for l in lats)
     for lat, V in zip(lats, Vs):
         lat.set_potential(V.float())
-    rs = [W.random_phase_device(l.n_rows, nb, 300 + i, dev, "complex64") for i, l in enumerate(lats)]
+    rs = [W.random_phase_device(l.n_rows, nb, 300 + i, dev).to(torch.complex64) for i, l in enumerate(lats)]
     batch = pv.Batch(lats)
     a = [7.0 + 0.5 * Wd for (_, Wd) in inst]
     t0 = time.perf_counter()
@@ -353,22 +364,35 @@ def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16, loop_M=64):
     first = time.perf_counter() - t0
     ms = _timed(torch, lambda: pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0), 1)
     ok = bool(torch.isfinite(mu).all().item()) and float((mu[:, :, 0] - 1).abs().max().item()) < 1e-5
+    mu64 = mu.cpu().numpy()
     lups = sum(l.n_rows for l in lats) * nb * (M // 2)
     b64 = sum(3 * l.n_rows * nb * 8 + l.n_sites * 4 for l in lats) * (M // 2)
     del rs
     torch.cuda.empty_cache()
-    # per-instance complex128 loop (each instance its own launches)
+    # per-instance complex128 loop (each instance its own launches), same phases
     for lat, V in zip(lats, Vs):
         lat.set_potential(V)
-    r128 = [W.random_phase_device(l.n_rows, nb, 300 + i, dev) for i, l in enumerate(lats)]
-    ms_loop = _timed(torch, lambda: [pv.pv_kpm_moments(l, r, loop_M, a_i, 0.0) for l, r, a_i in zip(lats, r128, a)], 1)
-    lups_loop = sum(l.n_rows for l in lats) * nb * (loop_M // 2)
+    mu128 = []
+
+    def loop():
+        mu128.clear()
+        for i, (l, a_i) in enumerate(zip(lats, a)):
+            r = W.random_phase_device(l.n_rows, nb, 300 + i, dev)
+            mu128.append(pv.pv_kpm_moments(l, r, M, a_i, 0.0))
+            del r
+    ms_loop = _timed(torch, loop, 1)
+    err = [float(np.abs(mu64[i] - m.cpu().numpy()).max()) for i, m in enumerate(mu128)]
     return {"workload": f"{n} TI realisations L~U{{24..96}} ({sites} sites), W~U[0.5,3], nb={nb}, M={M}",
             "batched_c64": {"ms_per_run": round(ms, 2), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
                             "GB/s": round(b64 / (ms * 1e-3) / 1e9, 1), "first_call_s_incl_capture": round(first, 2),
                             "mu0_check": ok, "launches_per_run": M // 2 + 1, "graph_replays": batch.stats()[1]},
-            "loop_c128": {"M": loop_M, "ms_per_run": round(ms_loop, 2),
-                          "GLUP/s": round(lups_loop / (ms_loop * 1e-3) / 1e9, 3)}}
+            "loop_c128": {"M": M, "ms_per_run": round(ms_loop, 2),
+                          "GLUP/s": round(lups / (ms_loop * 1e-3) / 1e9, 3),
+                          "note": "phase draws on the device included in the timed loop"},
+            "c64_vs_c128": {"max_abs_dmu": max(err), "median_abs_dmu": float(np.median(err)),
+                            "max_abs_dmu_per_instance": [float(f"{e:.3g}") for e in err],
+                            "note": "complex64 vectors, FP32 stencil, FP64 moments vs the complex128 run on the same "
+                                    "phases, per instance over all 16 columns and 1024 moments"}}
 
 
 def bench_adjoint(pv, torch, W, dev, ckpt=16):
@@ -377,7 +401,8 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     512 x 512 transmission gradient (50 steps, dt = 10, M = 64)."""
     st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
     lat = pv.Lattice((64, 64, 64), (1, 1, 1), st)
-    lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(4, W.STREAM_POTENTIAL))).to(dev))
+    V = torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(4, W.STREAM_POTENTIAL))).to(dev)
+    lat.set_potential(V)
     r = W.random_phase_device(lat.n_rows, 8, 400, dev)
     M = 256
     gbar = torch.from_numpy(W.generator(4, W.STREAM_COTANGENT).standard_normal((8, M))).to(dev)
@@ -400,6 +425,21 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     ms_ab = _timed(torch, lambda: pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, M // 2), 2)
     del work
     torch.cuda.empty_cache()
+    # central differences of the forward on 32 seeded sites
+    g = pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, ckpt).cpu().numpy()
+    sites = W.sample_sites(lat.n_sites, 32, W.generator(4, W.STREAM_FD_SITES))
+    fd = {}
+    for h in (1e-6, 1e-4):
+        worst = 0.0
+        for m in sites:
+            v0 = float(V[m].item())
+            vals = []
+            for sgn in (1, -1):
+                V[m] = v0 + sgn * h
+                vals.append(float((pv.pv_kpm_moments(lat, r, M, 7.0, 0.0) * gbar).sum().item()))
+            V[m] = v0
+            worst = max(worst, abs((vals[0] - vals[1]) / (2 * h) - g[m]))
+        fd[f"h={h:g}"] = float(f"{worst / np.abs(g).max():.3g}")
     lups = lat.n_rows * 8 * (M // 2)
     out = {"ti": {"workload": "TI 64^3, W=1, nb=8, M=256, checkpoint every 16, complex128",
                   "fwd_ms": round(ms_f, 3), "fwd_GLUP/s": round(lups / (ms_f * 1e-3) / 1e9, 3),
@@ -411,6 +451,9 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
                                "fwd+adj_GLUP/s": round(lups / ((ms_af + ms_ab) * 1e-3) / 1e9, 3),
                                "fwd+adj_over_fwd": round((ms_af + ms_ab) / ms_f, 2),
                                "note": "ckpt_every = M/2: the forward keeps every w_k, the adjoint recomputes none"},
+                  "fd_max_rel_err": fd,
+                  "fd_note": "gradient vs central differences of the forward on 32 seeded sites, max error relative "
+                             "to max|grad|; at h=1e-6 the loss's rounding dominates",
                   "note": "GLUP/s counted on the forward's LUPs. fwd+adj: the forward keeping its checkpoints "
                           "(fwd_ckpt_ms) then recompute + adjoint from them (adj_from_ckpt_ms), as autograd runs "
                           "them; grad_ms: the one-call gradient (its own checkpointed forward + recompute + adjoint)"}}
@@ -422,13 +465,33 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     region = torch.zeros(lg.n_rows, 1, dtype=torch.bool, device=dev)
     region.view(Lj, Li, 2)[:, 464:, :] = True
 
+    grads = []
+
     def grad_T(keep_series=False):
         V = Vg.clone().requires_grad_(True)
         psiT = pv.cheb_propagate(V, psi0, lg, 3.06, 0.05, 10.0, 64, 50, keep_series)
         T = (psiT.abs() ** 2)[region].sum()
         T.backward()
+        grads[:] = [V.grad]
         return T
     grad_T()
+    gT = grads[0].cpu().numpy()
+
+    def trans(Vv):
+        lg.set_potential(Vv)
+        p = psi0.clone()
+        pv.pv_cheb_propagate(lg, p, 3.06, 0.05, 10.0, 64, 50)
+        return float((p.abs() ** 2)[region].sum().item())
+    fd_sites = list(W.sample_sites(lg.n_sites, 24, W.generator(4, W.STREAM_FD_SITES, 1))) + \
+        list(np.argsort(-np.abs(gT))[:8])
+    worst = 0.0
+    for m in fd_sites:
+        Vp, Vm = Vg.clone(), Vg.clone()
+        Vp[m] += 1e-6
+        Vm[m] -= 1e-6
+        worst = max(worst, abs((trans(Vp) - trans(Vm)) / 2e-6 - gT[m]))
+    lg.set_potential(Vg)
+    fd_g = float(f"{worst / np.abs(gT).max():.3g}")
     ms_g = _timed(torch, grad_T, 1)
     # every step's Chebyshev vectors kept (50 * 64 vectors, 27 GB): no recompute
     grad_T(True)
@@ -439,7 +502,9 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     out["graphene"] = {"workload": "graphene 512x512x2, 50 steps dt=10 M=64, dT/dV by autograd",
                        "fwd_ms": round(ms_gf, 2), "fwd+adj_ms": round(ms_g, 2),
                        "fwd+adj_keep_series_ms": round(ms_gk, 2),
-                       "fwd_GLUP/s": round(lg.n_rows * 64 * 50 / (ms_gf * 1e-3) / 1e9, 3)}
+                       "fwd_GLUP/s": round(lg.n_rows * 64 * 50 / (ms_gf * 1e-3) / 1e9, 3),
+                       "fd_max_rel_err": {"h=1e-06": fd_g},
+                       "fd_note": "dT/dV vs central differences on 32 sites (24 seeded, the 8 largest gradients)"}
     return out
 
 

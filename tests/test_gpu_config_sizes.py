@@ -1,0 +1,141 @@
+"""Checks at the sizes the benchmark runs (GPU only, complex128 unless
+stated):
+
+* KPM gradient on TI 64^3 (W = 1, nb = 8, M = 256, checkpoints every 16
+  steps) against central differences of the GPU forward on 32 seeded sites.
+  With h = 1e-6 the difference quotient is limited by the rounding of the
+  loss, ~1e-16 |L| / (2 h) ~ 1e-9 absolute against gradients of ~1e-3
+  (measured 2e-6 relative to max|grad|): bound 1e-5.  With h = 1e-4 the
+  rounding share falls 100-fold and the O(h^2) truncation stays below it
+  (measured 2e-8): bound 1e-7.
+* Wave-packet transmission gradient on the 512 x 512 graphene ribbon
+  (50 steps, dt = 10, M = 64) against central differences with h = 1e-6 on
+  32 sites (the seeded ones and the 8 largest gradients), bound 1e-6
+  relative to max|grad| (measured 4e-9).
+* Batched KPM with complex64 vectors and FP64 moments at M = 1024 on six
+  instances of the 96-lattice workload, against each instance's complex128
+  run on the same phases (drawn in complex128, rounded to complex64): the
+  stated error of the FP32 path, max|dmu| <= 1e-6 per instance (measured
+  at most 6.5e-8).
+* Chebyshev propagation of the 1024 x 1024 ribbon (dot array, packet) for
+  200 steps of dt = 10 and back: the norm stays 1 and the packet returns,
+  both to 1e-11 (measured 3e-14 and 8e-14; each step's truncation is
+  |J_65(30.6)| ~ 1e-15)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1708_09689_amd as pv  # noqa: E402
+import workloads as W  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _ti64():
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    lat = pv.Lattice((64, 64, 64), (1, 1, 1), st)
+    V = torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(4, W.STREAM_POTENTIAL))).to(DEV)
+    lat.set_potential(V)
+    return lat, V
+
+
+def test_kpm_gradient_fd_ti64():
+    lat, V = _ti64()
+    M, nb = 256, 8
+    r = W.random_phase_device(lat.n_rows, nb, 400, DEV)
+    gbar = torch.from_numpy(W.generator(4, W.STREAM_COTANGENT).standard_normal((nb, M))).to(DEV)
+    g = pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, 16).cpu().numpy()
+    gmax = np.abs(g).max()
+    sites = W.sample_sites(lat.n_sites, 32, W.generator(4, W.STREAM_FD_SITES))
+
+    def loss():
+        return float((pv.pv_kpm_moments(lat, r, M, 7.0, 0.0) * gbar).sum().item())
+
+    for h, bound in ((1e-6, 1e-5), (1e-4, 1e-7)):
+        worst = 0.0
+        for m in sites:
+            v0 = float(V[m].item())
+            V[m] = v0 + h
+            lp = loss()
+            V[m] = v0 - h
+            lm = loss()
+            V[m] = v0
+            worst = max(worst, abs((lp - lm) / (2 * h) - g[m]) / gmax)
+        assert worst < bound, (h, worst)
+
+
+def test_transmission_gradient_fd_graphene512():
+    Li = Lj = 512
+    lat = pv.Lattice((Li, Lj), (0, 1), pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0]))
+    V0 = torch.from_numpy(W.dot_array_potential(Li, Lj, radius=10, pitch=32, first_centre=(224, 144))).to(DEV)
+    psi0 = torch.from_numpy(W.gaussian_wave_packet(Li, Lj, i0=100, width=25, energy=0.2).reshape(-1, 1)).to(DEV)
+    region = torch.zeros(lat.n_rows, 1, dtype=torch.bool, device=DEV)
+    region.view(Lj, Li, 2)[:, 464:, :] = True
+    V = V0.clone().requires_grad_(True)
+    T = (pv.cheb_propagate(V, psi0, lat, 3.06, 0.05, 10.0, 64, 50).abs() ** 2)[region].sum()
+    T.backward()
+    g = V.grad.cpu().numpy()
+    gmax = np.abs(g).max()
+    assert 0.05 < float(T.detach()) < 0.95
+    sites = list(W.sample_sites(lat.n_sites, 24, W.generator(4, W.STREAM_FD_SITES, 1))) + \
+        list(np.argsort(-np.abs(g))[:8])
+    h = 1e-6
+
+    def trans(Vv):
+        lat.set_potential(Vv)
+        p = psi0.clone()
+        pv.pv_cheb_propagate(lat, p, 3.06, 0.05, 10.0, 64, 50)
+        return float((p.abs() ** 2)[region].sum().item())
+
+    worst = 0.0
+    for m in sites:
+        Vp, Vm = V0.clone(), V0.clone()
+        Vp[m] += h
+        Vm[m] -= h
+        worst = max(worst, abs((trans(Vp) - trans(Vm)) / (2 * h) - g[m]) / gmax)
+    assert worst < 1e-6, worst
+
+
+def test_batched_c64_m1024_against_c128_per_instance():
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    inst = W.batch_instances(96, W.generator(3, W.STREAM_SIZES))
+    idx = [0, 1, 2, 3, 4, 5]
+    M, nb = 1024, 16
+    lats, V64, r128, a = [], [], [], []
+    for i in idx:
+        L, Wd = inst[i]
+        lat = pv.Lattice((L, L, L), (1, 1, 1), st)
+        lats.append(lat)
+        V64.append(torch.from_numpy(W.uniform_potential(lat.n_sites, Wd, W.generator(3, W.STREAM_POTENTIAL, i))).to(DEV))
+        r128.append(W.random_phase_device(lat.n_rows, nb, 300 + i, DEV))
+        a.append(7.0 + 0.5 * Wd)
+    mu128 = []
+    for lat, V, r, ai in zip(lats, V64, r128, a):
+        lat.set_potential(V)
+        mu128.append(pv.pv_kpm_moments(lat, r, M, ai, 0.0).cpu().numpy())
+    for lat, V in zip(lats, V64):
+        lat.set_potential(V.float())
+    batch = pv.Batch(lats)
+    mu64 = pv.pv_batch_kpm_moments(batch, [r.to(torch.complex64) for r in r128], M, a, 0.0).cpu().numpy()
+    for k in range(len(idx)):
+        assert np.abs(mu128[k][:, 0] - 1.0).max() < 1e-13
+        assert np.abs(mu64[k] - mu128[k]).max() < 1e-6, (k, np.abs(mu64[k] - mu128[k]).max())
+
+
+def test_chebtp_graphene1024_200_steps_norm_and_time_reversal():
+    Li = Lj = 1024
+    lat = pv.Lattice((Li, Lj), (0, 1), pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0]))
+    lat.set_potential(torch.from_numpy(W.dot_array_potential(Li, Lj)).to(DEV))
+    psi0 = torch.from_numpy(W.gaussian_wave_packet(Li, Lj, i0=200, width=50, energy=0.2).reshape(-1, 1)).to(DEV)
+    psi = psi0.clone()
+    pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, 200)
+    n200 = float(torch.linalg.vector_norm(psi).item())
+    moved = float(torch.linalg.vector_norm(psi - psi0).item())
+    pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, -10.0, 64, 200)
+    back = float((torch.linalg.vector_norm(psi - psi0) / torch.linalg.vector_norm(psi0)).item())
+    assert abs(n200 - 1.0) < 1e-11
+    assert moved > 0.5            # the packet did travel
+    assert back < 1e-11
