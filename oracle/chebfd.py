@@ -14,8 +14,12 @@ steps here are the standard ones that description implies:
 5. orthonormalise Y (Cholesky QR, applied twice), in float64;
 6. Rayleigh-Ritz: H_S = Q^H H Q, H_S = U diag(theta) U^H, Q <- Q U;
 7. residuals ||H q_i - theta_i q_i||;
-8. converged when the n_target Ritz values closest to the window centre lie
-   in the window with residual <= tol; otherwise X <- Q and repeat.
+8. a Ritz pair counts as converged when its value lies in the window and
+   its residual is <= tol; the iteration ends when n_target pairs have
+   converged, and returns those closest to the window centre; otherwise
+   X <- Q and repeat.  A search space larger than the window's count holds
+   Ritz values in the window that belong to no eigenvector (residuals of
+   order one); they never count, so they can not stall the iteration.
 """
 
 from __future__ import annotations
@@ -65,8 +69,9 @@ def rayleigh_ritz(H, Q):
 
 def chebfd(H, X0, a: float, b: float, lam_l: float, lam_r: float, K: int,
            n_target: int, tol: float, max_iter: int = 20):
-    """Returns (theta, Q, residuals, iterations) for the n_target Ritz pairs
-    closest to the window centre."""
+    """Returns (theta, Q, residuals, iterations) for n_target Ritz pairs:
+    the converged ones (value in the window, residual <= tol) closest to the
+    window centre first, then the others closest to the centre."""
     coef = filter_coefficients(lam_l, lam_r, a, b, K)
     centre = 0.5 * (lam_l + lam_r)
     X = np.asarray(X0, dtype=np.complex128)
@@ -75,10 +80,11 @@ def chebfd(H, X0, a: float, b: float, lam_l: float, lam_r: float, K: int,
         Q = cholesky_qr(cholesky_qr(Y))
         theta, Q, HQ = rayleigh_ritz(H, Q)
         res = np.linalg.norm(HQ - Q * theta[None, :], axis=0)
-        order = np.argsort(np.abs(theta - centre), kind="stable")[:n_target]
+        conv = (theta >= lam_l) & (theta <= lam_r) & (res <= tol)
+        dist = np.abs(theta - centre)
+        order = np.lexsort((dist, ~conv))[:n_target]     # converged first, then by distance
         sel_t, sel_r = theta[order], res[order]
-        inside = (sel_t >= lam_l) & (sel_t <= lam_r)
-        if inside.all() and (sel_r <= tol).all():
+        if conv.sum() >= n_target:
             return sel_t, Q[:, order], sel_r, it
         X = Q
     return sel_t, Q[:, order], sel_r, max_iter

@@ -43,14 +43,19 @@ def test_cholesky_qr_orthonormal():
     assert np.abs(Q @ (Q.conj().T @ X) - X).max() < 1e-12
 
 
-def test_chebfd_finds_interior_eigenvalues():
-    """TI 6x6x6, W = 2: the 16 eigenvalues closest to E = 0 (8 Kramers pairs)
-    agree with dense diagonalisation; residuals below tolerance."""
+@pytest.mark.parametrize("ns", [48, 64, 128])
+def test_chebfd_finds_interior_eigenvalues(ns):
+    """TI 6x6x6, W = 2, a window holding exactly the 16 eigenvalues closest
+    to E = 0 (8 Kramers pairs; its edges halfway to the 17th): they agree
+    with dense diagonalisation, residuals below tolerance, for search spaces
+    of 3, 4 and 8 times the count (the larger ones hold Ritz values in the
+    window that belong to no eigenvector)."""
     H, lat, _ = ti((6, 6, 6), Wd=2.0, seed=2)
     ev = np.linalg.eigvalsh(H.toarray())
     lam = np.sort(np.abs(ev))
-    w = lam[24]
-    X0 = W.random_phase_block(lat.n_rows, 48, W.generator(2, 2))
+    assert lam[16] - lam[15] > 1e-3
+    w = 0.5 * (lam[15] + lam[16])
+    X0 = W.random_phase_block(lat.n_rows, ns, W.generator(2, 2))
     th, Q, res, it = chebfd.chebfd(H, X0, 7.0, 0.0, -w, w, 300, 16, 7e-9, max_iter=15)
     near = np.sort(ev[np.argsort(np.abs(ev))][:16])
     assert it < 15
