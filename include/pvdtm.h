@@ -334,11 +334,15 @@ pv_status pv_block_rotate(int dtype, int64_t rows, int nx, int ny, const void *X
  * factorisation), and performs Rayleigh-Ritz: H_S = Q^H H Q (FP64), host
  * Jacobi eigensolver, X <- Q U with Ritz pairs ordered by |theta - centre|,
  * residuals ||H x_i - theta_i x_i|| from a shifted sweep with fused <y,y>.
- * Stops when the n_target Ritz pairs closest to the window centre lie in the
- * window with residual <= tol, or after max_iter iterations
+ * A pair has converged when theta lies in the window and its residual is
+ * <= tol (Ritz values of a search space larger than the window's count that
+ * belong to no eigenvector keep large residuals and never count).  Stops
+ * when n_target pairs have converged, or after max_iter iterations
  * (PV_ERR_NOT_CONVERGED; outputs still filled).  Synchronises the stream.
- * In/out: X (start block -> Ritz vectors); out: theta[ns], res[ns] (host),
- * *n_conv (converged among the n_target), *iters.
+ * In/out: X (start block -> Ritz vectors, converged ones first, each group
+ * ordered by |theta - centre|); out: theta[ns], res[ns] (host, same order),
+ * *n_conv (converged pairs among the first n_target), *iters.  The Gram
+ * matrices and rotations of the whole search space run as one pass each.
  */
 size_t pv_chebfd_workspace_size(const pv_lattice *lat, int dtype, int bw, int nblk);
 pv_status pv_chebfd(pv_lattice *lat, int dtype, int bw, int nblk, double a, double b,

@@ -1585,6 +1585,7 @@ struct FdLayout {
     size_t vb;      // bytes of one [rows][bw] block
     size_t Y, W, S1, S2, gp, sp, G, D;
     size_t total;
+    int groups;     // row-chunk groups of the block Gram
 };
 
 FdLayout fd_layout(const pv_lattice* l, int dtype, int bw, int nblk) {
@@ -1595,11 +1596,14 @@ FdLayout fd_layout(const pv_lattice* l, int dtype, int bw, int nblk) {
     L.W = off; off += L.vb * nblk;
     L.S1 = off; off += L.vb;
     L.S2 = off; off += L.vb;
-    L.gp = off; off += pv_gram_workspace_size(l->n_rows, bw, bw);
+    int ncu = num_cus_of_current_device();
+    if (ncu <= 0) ncu = 256;
+    L.groups = pv::block_gram_groups(l->n_rows, nblk, ncu);
+    L.gp = off; off += align_up((size_t)nblk * nblk * L.groups * bw * bw * 2 * sizeof(double));
     L.sp = off; off += pv_spmmv_workspace_size(l, dtype, bw);
     const size_t ns = (size_t)bw * nblk;
     L.G = off; off += align_up(ns * ns * 2 * sizeof(double));
-    L.D = off; off += align_up((size_t)bw * 4 * sizeof(double));
+    L.D = off; off += align_up(ns * 4 * sizeof(double));
     L.total = off;
     return L;
 }
@@ -1642,45 +1646,27 @@ extern "C" pv_status pv_chebfd(pv_lattice* l, int dtype, int bw, int nblk, doubl
     const double centre = 0.5 * (lam_l + lam_r);
     std::vector<double> Gh((size_t)ns * ns * 2);
 
-    // G = A^H B over all block pairs (A, B given as nblk blocks) -> host G[ns][ns]
+    // G = A^H B over the whole search space (A, B as nblk blocks) in one
+    // pass, then to the host: one synchronisation per Gram
+    const int64_t bstride = int64_t(Lw.vb / elem_bytes(dtype));
     auto block_gram = [&](char* A, char* B, bool hermitian) -> pv_status {
-        for (int i = 0; i < nblk; ++i)
-            for (int j = hermitian ? i : 0; j < nblk; ++j) {
-                pv_status e = pv_gram(dtype, rows, bw, bw, blk(A, i), blk(B, j), Gd, w + Lw.gp, Lw.sp - Lw.gp, stream);
-                if (e != PV_OK) return e;
-                std::vector<double> g((size_t)bw * bw * 2);
-                PV_HIP(hipMemcpyAsync(g.data(), Gd, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-                PV_HIP(hipStreamSynchronize(s));
-                for (int r = 0; r < bw; ++r)
-                    for (int c = 0; c < bw; ++c) {
-                        const size_t dst = ((size_t)(i * bw + r) * ns + (j * bw + c)) * 2;
-                        Gh[dst] = g[(r * bw + c) * 2];
-                        Gh[dst + 1] = g[(r * bw + c) * 2 + 1];
-                        if (hermitian && i != j) {
-                            const size_t t = ((size_t)(j * bw + c) * ns + (i * bw + r)) * 2;
-                            Gh[t] = g[(r * bw + c) * 2];
-                            Gh[t + 1] = -g[(r * bw + c) * 2 + 1];
-                        }
-                    }
-            }
+        PV_HIP(pv::launch_block_gram(dtype, rows, bw, nblk, A, B, bstride, hermitian ? 1 : 0,
+                                     reinterpret_cast<double*>(w + Lw.gp), Lw.groups, Gd, s));
+        PV_HIP(hipMemcpyAsync(Gh.data(), Gd, Gh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        PV_HIP(hipStreamSynchronize(s));
         return PV_OK;
     };
-    // OUT_j = sum_i IN_i M_ij for an ns x ns host matrix M
+    // OUT_j = sum_i IN_i M_ij for an ns x ns host matrix M: one upload, one
+    // launch over every output block
+    std::vector<double> Mh((size_t)ns * ns * 2);
     auto block_rotate = [&](char* IN, const std::vector<pvd::cd>& M, char* OUT) -> pv_status {
-        std::vector<double> q((size_t)bw * bw * 2);
-        for (int j = 0; j < nblk; ++j)
-            for (int i = 0; i < nblk; ++i) {
-                for (int r = 0; r < bw; ++r)
-                    for (int c = 0; c < bw; ++c) {
-                        const pvd::cd v = M[(size_t)(i * bw + r) * ns + (j * bw + c)];
-                        q[(r * bw + c) * 2] = v.real();
-                        q[(r * bw + c) * 2 + 1] = v.imag();
-                    }
-                PV_HIP(hipMemcpyAsync(Gd, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice, s));
-                pv_status e = pv_block_rotate(dtype, rows, bw, bw, blk(IN, i), Gd, i > 0, blk(OUT, j), stream);
-                if (e != PV_OK) return e;
-                PV_HIP(hipStreamSynchronize(s));  // q is reused for the next block
-            }
+        for (size_t k = 0; k < M.size(); ++k) {
+            Mh[2 * k] = M[k].real();
+            Mh[2 * k + 1] = M[k].imag();
+        }
+        PV_HIP(hipMemcpyAsync(Gd, Mh.data(), Mh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        PV_HIP(pv::launch_block_rotate(dtype, rows, bw, nblk, nblk, IN, bstride, Gd, OUT, bstride, s));
+        PV_HIP(hipStreamSynchronize(s));   // Mh is rewritten by the next rotation
         return PV_OK;
     };
     auto host_matrix = [&]() {
@@ -1741,30 +1727,57 @@ extern "C" pv_status pv_chebfd(pv_lattice* l, int dtype, int bw, int nblk, doubl
         for (int c = 0; c < ns; ++c) th[c] = ev[order[c]];
         // 4. Ritz vectors into X
         if ((st = block_rotate(cur, Uo, Xc)) != PV_OK) return st;
-        // 5. residuals ||H q - theta q|| with per-column shifts and the fused <y,y>
+        // 5. residuals ||H q - theta q|| with per-column shifts and the fused
+        // <y,y>, every block, then one copy to the host
         for (int bb = 0; bb < nblk; ++bb) {
             const std::vector<double> one(bw, 1.0), zero(bw, 0.0);
             std::vector<double> sh(th.begin() + bb * bw, th.begin() + (bb + 1) * bw);
             if ((st = pv_spmmv(l, dtype, bw, blk(Xc, bb), nullptr, blk(oth, bb), one.data(), sh.data(), zero.data(),
-                               PV_DOT_YY, Dd, w + Lw.sp, pv_spmmv_workspace_size(l, dtype, bw), stream)) != PV_OK)
+                               PV_DOT_YY, Dd + (size_t)bb * bw * 4, w + Lw.sp, pv_spmmv_workspace_size(l, dtype, bw),
+                               stream)) != PV_OK)
                 return st;
-            std::vector<double> d((size_t)bw * 4);
+        }
+        {
+            std::vector<double> d((size_t)ns * 4);
             PV_HIP(hipMemcpyAsync(d.data(), Dd, d.size() * sizeof(double), hipMemcpyDeviceToHost, s));
             PV_HIP(hipStreamSynchronize(s));
-            for (int c = 0; c < bw; ++c) rr[bb * bw + c] = std::sqrt(std::max(d[c * 4 + 3], 0.0));
+            for (int c = 0; c < ns; ++c) rr[c] = std::sqrt(std::max(d[c * 4 + 3], 0.0));
         }
-        converged = true;
-        for (int i = 0; i < n_target; ++i)
-            if (!(th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol)) converged = false;
-        if (converged) break;
+        // converged pairs: value in the window, residual <= tol (Ritz values
+        // of an oversized search space that belong to no eigenvector keep
+        // residuals of order one and never count)
+        int count = 0;
+        for (int i = 0; i < ns; ++i)
+            if (th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol) ++count;
+        converged = count >= n_target;
+        if (converged || it == max_iter) break;
     }
     if (it > max_iter) it = max_iter;
+    // converged pairs first, each group by distance from the centre (the
+    // columns already are): permute X to match
+    std::vector<int> perm(ns);
+    {
+        int k = 0;
+        for (int i = 0; i < ns; ++i)
+            if (th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol) perm[k++] = i;
+        for (int i = 0; i < ns; ++i)
+            if (!(th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol)) perm[k++] = i;
+    }
+    bool identity = true;
+    for (int i = 0; i < ns; ++i) identity = identity && perm[i] == i;
+    if (!identity) {
+        std::vector<pvd::cd> P((size_t)ns * ns, pvd::cd(0.0, 0.0));
+        for (int c = 0; c < ns; ++c) P[(size_t)perm[c] * ns + c] = 1.0;
+        char* tmp = Xc == Yb ? Wb : Yb;
+        if ((st = block_rotate(Xc, P, tmp)) != PV_OK) return st;
+        PV_HIP(pv::launch_copy(tmp, Xc, Lw.vb * nblk, s));
+        PV_HIP(hipStreamSynchronize(s));
+    }
     int nc = 0;
-    for (int i = 0; i < n_target; ++i)
-        if (th[i] >= lam_l && th[i] <= lam_r && rr[i] <= tol) ++nc;
     for (int i = 0; i < ns; ++i) {
-        theta[i] = th[i];
-        res[i] = rr[i];
+        theta[i] = th[perm[i]];
+        res[i] = rr[perm[i]];
+        if (i < n_target && theta[i] >= lam_l && theta[i] <= lam_r && res[i] <= tol) ++nc;
     }
     *n_conv = nc;
     *iters = it;

@@ -106,6 +106,153 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(const cplx<T>* __restrict_
     }
 }
 
+// Gram of a search space kept as nblk column blocks of bw columns each
+// (block i at A + i stride): workgroup (group g, block i) takes the row
+// chunks g, g + G, ... and accumulates the tiles A_i^H B_j, j in [j0, j0 +
+// nj) (j >= i only when hermitian), loading each chunk of A_i once and each
+// chunk of B_j once per i; the nblk workgroups of one group run side by side,
+// so a chunk of B_j leaves HBM once.  Tile (i, j) of group g goes to
+// partials[((i nblk + j) G + g)][bw bw][2].  KP pairs per lane per tile.
+template <typename T, int KP>
+__global__ __launch_bounds__(kBlock) void block_gram_kernel(const cplx<T>* __restrict__ A,
+                                                            const cplx<T>* __restrict__ B, int64_t stride,
+                                                            int64_t rows, int bw, int nblk, int j0, int nj,
+                                                            int hermitian, double* __restrict__ partials) {
+    constexpr int NJ = 32 / KP;
+    __shared__ cplx<double> sa[kGramRows][PV_MAX_NB_K];
+    __shared__ cplx<double> sb[kGramRows][PV_MAX_NB_K];
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x % nblk, g = blockIdx.x / nblk, G = gridDim.x / nblk;
+    const int np = bw * bw;
+    double ar[NJ][KP], ai[NJ][KP];
+#pragma unroll
+    for (int t = 0; t < NJ; ++t)
+#pragma unroll
+        for (int k = 0; k < KP; ++k) ar[t][k] = ai[t][k] = 0.0;
+    const cplx<T>* Ai = A + (int64_t)i * stride;
+    const int64_t nchunks = (rows + kGramRows - 1) / kGramRows;
+    for (int64_t ch = g; ch < nchunks; ch += G) {
+        const int64_t r0 = ch * kGramRows;
+        __syncthreads();
+        for (int e = tid; e < kGramRows * bw; e += kBlock) {
+            const int rr = e / bw, c = e % bw;
+            const int64_t r = r0 + rr;
+            cplx<double> v{0.0, 0.0};
+            if (r < rows) {
+                const cplx<T> u = Ai[r * bw + c];
+                v = cplx<double>{double(u.re), double(u.im)};
+            }
+            sa[rr][c] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < NJ; ++t) {
+            const int j = j0 + t;
+            if (t >= nj || (hermitian && j < i)) continue;
+            const cplx<T>* Bj = B + (int64_t)j * stride;
+            __syncthreads();
+            for (int e = tid; e < kGramRows * bw; e += kBlock) {
+                const int rr = e / bw, c = e % bw;
+                const int64_t r = r0 + rr;
+                cplx<double> v{0.0, 0.0};
+                if (r < rows) {
+                    const cplx<T> u = Bj[r * bw + c];
+                    v = cplx<double>{double(u.re), double(u.im)};
+                }
+                sb[rr][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                const int p = tid + kBlock * k;
+                if (p < np) {
+                    const int r = p / bw, c = p % bw;
+                    double sr = ar[t][k], si = ai[t][k];
+                    for (int rr = 0; rr < kGramRows; ++rr) {
+                        const cplx<double> u = sa[rr][r], v = sb[rr][c];
+                        sr += u.re * v.re + u.im * v.im;
+                        si += u.re * v.im - u.im * v.re;
+                    }
+                    ar[t][k] = sr;
+                    ai[t][k] = si;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NJ; ++t) {
+        const int j = j0 + t;
+        if (t >= nj || (hermitian && j < i)) continue;
+        double* out = partials + ((size_t)(i * nblk + j) * G + g) * np * 2;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int p = tid + kBlock * k;
+            if (p < np) {
+                out[2 * p] = ar[t][k];
+                out[2 * p + 1] = ai[t][k];
+            }
+        }
+    }
+}
+
+// G[(i bw + r) ns + (j bw + c)] from the tiles of block_gram_kernel, summed
+// over the G groups in a fixed order; with hermitian, tiles below the block
+// diagonal are the conjugate transposes of those above it.
+__global__ __launch_bounds__(kBlock) void block_gram_reduce_kernel(const double* __restrict__ partials, int G,
+                                                                   int bw, int nblk, int hermitian,
+                                                                   double* __restrict__ out) {
+    const int ns = bw * nblk;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= ns * ns) return;
+    const int row = e / ns, col = e % ns;
+    int i = row / bw, r = row % bw, j = col / bw, c = col % bw;
+    bool conj = false;
+    if (hermitian && j < i) {
+        const int ti = i, tr = r;
+        i = j; r = c; j = ti; c = tr;
+        conj = true;
+    }
+    const double* t = partials + (size_t)(i * nblk + j) * G * bw * bw * 2;
+    const int p = r * bw + c;
+    double sr = 0.0, si = 0.0;
+    for (int g = 0; g < G; ++g) {
+        sr += t[((size_t)g * bw * bw + p) * 2];
+        si += t[((size_t)g * bw * bw + p) * 2 + 1];
+    }
+    out[2 * (size_t)e] = sr;
+    out[2 * (size_t)e + 1] = conj ? -si : si;
+}
+
+// OUT_j = sum_i IN_i Q[i, j] over column blocks: out block j, row r, column c
+// = sum_{i, c'} IN_i[r][c'] Q[(i bw + c') (nout bw) + j bw + c], all output
+// blocks in one launch (Q complex FP64, accumulation in FP64).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void block_rotate_kernel(const cplx<T>* __restrict__ IN, int64_t in_stride,
+                                                              const double* __restrict__ Q, int64_t rows, int bw,
+                                                              int nin, int nout, cplx<T>* __restrict__ OUT,
+                                                              int64_t out_stride) {
+    const int64_t per = rows * bw;
+    const int64_t n = per * nout;
+    const int nso = nout * bw;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const int j = int(e / per);
+        const int64_t rem = e - (int64_t)j * per;
+        const int64_t r = rem / bw;
+        const int c = int(rem - r * bw);
+        double sr = 0.0, si = 0.0;
+        for (int i = 0; i < nin; ++i) {
+            const cplx<T>* x = IN + (int64_t)i * in_stride + r * bw;
+            const double* q = Q + ((size_t)(i * bw) * nso + j * bw + c) * 2;
+            for (int cc = 0; cc < bw; ++cc) {
+                const cplx<T> u = x[cc];
+                const double qr = q[(size_t)cc * nso * 2], qi = q[(size_t)cc * nso * 2 + 1];
+                sr += double(u.re) * qr - double(u.im) * qi;
+                si += double(u.re) * qi + double(u.im) * qr;
+            }
+        }
+        OUT[(int64_t)j * out_stride + rem] = cplx<T>{T(sr), T(si)};
+    }
+}
+
 // out[k] = sum_b partials[b][k], fixed order over b.
 __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double* __restrict__ partials,
                                                               int grid, int n, double* __restrict__ out) {
@@ -349,6 +496,58 @@ hipError_t launch_gram(int dtype, int64_t rows, int nx, int ny, const void* X, c
     const int n = nx * ny * 2;
     hipLaunchKernelGGL(sum_partials_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, partials,
                        grid, n, G);
+    return hipGetLastError();
+}
+
+int block_gram_groups(int64_t rows, int nblk, int num_cus) {
+    const int64_t chunks = (rows + kGramRows - 1) / kGramRows;
+    int64_t g = (2 * (int64_t)num_cus + nblk - 1) / nblk;
+    if (g > chunks) g = chunks;
+    if (g < 1) g = 1;
+    return int(g);
+}
+
+hipError_t launch_block_gram(int dtype, int64_t rows, int bw, int nblk, const void* A, const void* B,
+                             int64_t stride, int hermitian, double* partials, int groups, double* G, hipStream_t s) {
+    const int np = bw * bw;
+    const int kp = (np + kBlock - 1) / kBlock;   // 1, 4 or 16 for bw <= 64
+    const int njmax = 32 / kp;
+    for (int j0 = 0; j0 < nblk; j0 += njmax) {
+        const int nj = nblk - j0 < njmax ? nblk - j0 : njmax;
+        auto go = [&](auto tt, auto kk) {
+            using T = typename decltype(tt)::type;
+            constexpr int KP = decltype(kk)::value;
+            hipLaunchKernelGGL((block_gram_kernel<T, KP>), dim3(groups * nblk), dim3(kBlock), 0, s,
+                               static_cast<const cplx<T>*>(A), static_cast<const cplx<T>*>(B), stride, rows, bw,
+                               nblk, j0, nj, hermitian, partials);
+        };
+        auto by_kp = [&](auto tt) {
+            if (kp == 1) go(tt, std::integral_constant<int, 1>{});
+            else if (kp == 4) go(tt, std::integral_constant<int, 4>{});
+            else go(tt, std::integral_constant<int, 16>{});
+        };
+        if (dtype == 0) by_kp(Tag<double>{});
+        else by_kp(Tag<float>{});
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int n = (bw * nblk) * (bw * nblk);
+    hipLaunchKernelGGL(block_gram_reduce_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, partials, groups,
+                       bw, nblk, hermitian, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_rotate(int dtype, int64_t rows, int bw, int nin, int nout, const void* IN, int64_t in_stride,
+                               const double* Q, void* OUT, int64_t out_stride, hipStream_t s) {
+    const int g = elementwise_grid(rows * bw * nout);
+    if (dtype == 0)
+        hipLaunchKernelGGL(block_rotate_kernel<double>, dim3(g), dim3(kBlock), 0, s,
+                           static_cast<const cplx<double>*>(IN), in_stride, Q, rows, bw, nin, nout,
+                           static_cast<cplx<double>*>(OUT), out_stride);
+    else
+        hipLaunchKernelGGL(block_rotate_kernel<float>, dim3(g), dim3(kBlock), 0, s,
+                           static_cast<const cplx<float>*>(IN), in_stride, Q, rows, bw, nin, nout,
+                           static_cast<cplx<float>*>(OUT), out_stride);
     return hipGetLastError();
 }
 

@@ -112,6 +112,15 @@ hipError_t launch_scale_block(int dtype, int64_t n_elem, const void* x, double r
 hipError_t launch_gram(int dtype, int64_t rows, int nx, int ny, const void* X, const void* Y,
                        double* partials, int grid, double* G, hipStream_t s);
 int gram_grid(int64_t rows, int num_cus);
+// Gram and rotation of a search space stored as nblk blocks of bw columns
+// (block i at base + i * stride elements): G = A^H B as a dense
+// (nblk bw)^2 complex FP64 matrix in one pass; OUT_j = sum_i IN_i Q_ij.
+// Partials: nblk^2 * groups * bw^2 * 2 doubles.
+int block_gram_groups(int64_t rows, int nblk, int num_cus);
+hipError_t launch_block_gram(int dtype, int64_t rows, int bw, int nblk, const void* A, const void* B,
+                             int64_t stride, int hermitian, double* partials, int groups, double* G, hipStream_t s);
+hipError_t launch_block_rotate(int dtype, int64_t rows, int bw, int nin, int nout, const void* IN, int64_t in_stride,
+                               const double* Q, void* OUT, int64_t out_stride, hipStream_t s);
 hipError_t launch_rotate(int dtype, int64_t rows, int nx, int ny, const void* X, const double* Q,
                          int accumulate, void* Y, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

@@ -1,5 +1,6 @@
 """GPU parity of Chebyshev filter diagonalisation (filter sweeps + FP64
-Rayleigh-Ritz) against dense diagonalisation and the oracle's ChebFD.
+Rayleigh-Ritz) against dense diagonalisation and the oracle's ChebFD, on a
+window that holds exactly the 16 eigenvalues nearest E = 0.
 
 Tolerances: complex128 -- the 16 eigenvalues nearest E = 0 to 1e-10 * a,
 residuals <= tol = 1e-9 * a, returned Ritz vectors orthonormal to 1e-12.
@@ -19,27 +20,34 @@ import workloads as W  # noqa: E402
 from gpu_common import Case, dev, host  # noqa: E402
 
 
-def setup(dtype=np.complex128, vdtype=np.float64):
+def setup(dtype=np.complex128, vdtype=np.float64, bw=16, nblk=3):
     c = Case("ti", (6, 6, 6), (1, 1, 1), Wd=2.0, seed=2, vdtype=vdtype)
     ev = np.linalg.eigvalsh(c.H.toarray())
     lam = np.sort(np.abs(ev))
-    w = lam[24]
+    w = 0.5 * (lam[15] + lam[16])          # the window holds exactly the 16 nearest E = 0
     near = np.sort(ev[np.argsort(np.abs(ev))][:16])
-    X0 = W.random_phase_block(c.D, 48, W.generator(2, 2), dtype)
-    blocks = np.stack([X0[:, b * 16:(b + 1) * 16] for b in range(3)])   # [nblk][rows][bw]
+    X0 = W.random_phase_block(c.D, bw * nblk, W.generator(2, 2), dtype)
+    blocks = np.stack([X0[:, b * bw:(b + 1) * bw] for b in range(nblk)])   # [nblk][rows][bw]
     return c, w, near, X0, blocks
 
 
-def test_chebfd_c128_interior_eigenvalues():
-    c, w, near, X0, blocks = setup()
+# search spaces of nblk blocks of bw columns, 3 to 12 times the window's
+# count: the Rayleigh-Ritz Gram kernel takes 1, 4 or 16 column pairs per lane
+# (bw <= 16, 32, 64), 64-column blocks in two launches over j; the larger
+# spaces hold Ritz values in the window with residuals of order one, which
+# must not count as converged or stall the iteration
+@pytest.mark.parametrize("bw,nblk", [(16, 3), (32, 2), (8, 8), (64, 3)])
+def test_chebfd_c128_interior_eigenvalues(bw, nblk):
+    c, w, near, X0, blocks = setup(bw=bw, nblk=nblk)
+    ns = bw * nblk
     X = dev(blocks)
     a = 7.0
-    theta, res, nconv, it = pv.pv_chebfd(c.lat, X, 16, a, 0.0, -w, w, 300, 16, 1e-9 * a, max_iter=15)
+    theta, res, nconv, it = pv.pv_chebfd(c.lat, X, bw, a, 0.0, -w, w, 300, 16, 1e-9 * a, max_iter=15)
     assert nconv == 16
     assert np.abs(np.sort(theta[:16]) - near).max() < 1e-10 * a
     assert res[:16].max() <= 1e-9 * a
-    Q = host(X).transpose(1, 0, 2).reshape(c.D, 48)
-    assert np.abs(Q.conj().T @ Q - np.eye(48)).max() < 1e-12
+    Q = host(X).transpose(1, 0, 2).reshape(c.D, ns)
+    assert np.abs(Q.conj().T @ Q - np.eye(ns)).max() < 1e-12
     # residuals recomputed on the host from the returned vectors
     R = c.H @ Q[:, :16] - Q[:, :16] * theta[None, :16]
     assert np.abs(np.linalg.norm(R, axis=0) - res[:16]).max() < 1e-12 * a
