@@ -31,4 +31,6 @@ rng          counter-based (SplitMix64) on-the-fly disorder field (Sec. 3.3)
 adjoint      discrete adjoints of the KPM moments and of the Chebyshev time
              propagation with respect to the on-site potential, and central
              finite differences
+omp_sweep    the Chebyshev step and the KPM moments over the explicit matrix
+             in C++ with OpenMP (omp/cheb_omp.cpp), for the host's cores
 """
