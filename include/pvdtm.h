@@ -403,7 +403,9 @@ pv_status pv_trlanczos_fd(pv_lattice *lat, int dtype, double a, double b, double
  * checkpointed in pairs every ckpt_every steps and recomputed per segment.
  * gbar: device [nb][M]; gradV: device [n_sites] (site field) or [n_rows]
  * (orbital field), overwritten.  Needs n_orb*nb <= 64 for a site field.
- * Synchronises the stream once (gbar is read on the host).
+ * Asynchronous on the stream: gbar is read on the device (a kernel turns it
+ * into the coefficients of the G_k), so it may be produced by earlier work
+ * on the same stream.
  *
  * pv_cheb_propagate_vjp: for psi_T = U(dt)^nsteps psi0 (pv_cheb_propagate)
  * and a cotangent psibar (dL = Re <psibar, d psi_T>), returns gradV = dL/dV
@@ -428,8 +430,7 @@ pv_status pv_kpm_moments_vjp(pv_lattice *lat, int dtype, int nb, int M, double a
  * pv_kpm_moments_vjp's, and the second call may be repeated (other
  * cotangents) on the same workspace.  With ckpt_every >= M/2 the forward
  * keeps every w_k (M/2 + 6 vectors of workspace) and the adjoint recomputes
- * none.  Asynchronous on the stream (the second call synchronises once, to
- * read gbar on the host).
+ * none.  Both calls are asynchronous on the stream.
  */
 pv_status pv_kpm_moments_ckpt(pv_lattice *lat, int dtype, int nb, int M, double a, double b,
                               const void *r, double *mu, int ckpt_every, void *work,

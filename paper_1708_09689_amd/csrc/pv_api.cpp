@@ -2505,23 +2505,9 @@ pv_status kpm_vjp_impl(pv_lattice* l, int dtype, int nb, int M, double a, double
     void* F1 = S + vb * (C + 3);
     double* table = reinterpret_cast<double*>(S + vb * (C + 4));
 
-    // cotangent of the moments -> coefficients of the adjoint source terms
-    std::vector<double> g((size_t)nb * M);
-    PV_HIP(hipMemcpyAsync(g.data(), gbar, g.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    PV_HIP(hipStreamSynchronize(s));
-    std::vector<double> tab((size_t)(N + 1) * 3 * nb * 2, 0.0);
-    for (int c = 0; c < nb; ++c) {
-        const double* gc = &g[(size_t)c * M];
-        double ghat1 = gc[1];
-        for (int n = 1; n <= N - 1; ++n) ghat1 -= gc[2 * n + 1];
-        for (int k = 1; k <= N; ++k) {
-            double* row = &tab[(size_t)k * 3 * nb * 2];
-            row[(0 * nb + c) * 2] = (k == 1 ? ghat1 : 2.0 * gc[2 * k - 1]) * invD;
-            row[(1 * nb + c) * 2] = (k < N ? 4.0 * gc[2 * k] : 0.0) * invD;
-            row[(2 * nb + c) * 2] = (k < N ? 2.0 * gc[2 * k + 1] : 0.0) * invD;
-        }
-    }
-    PV_HIP(hipMemcpyAsync(table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    // cotangent of the moments -> coefficients of the adjoint source terms,
+    // on the device (no host round trip)
+    PV_HIP(pv::launch_kpm_adjoint_table(gbar, nb, M, invD, table, s));
     PV_HIP(pv::launch_zero(gradV, grad_len(l) * sizeof(double), s));
     PV_HIP(pv::launch_zero(L0, vb, s));
     PV_HIP(pv::launch_zero(L1, vb, s));

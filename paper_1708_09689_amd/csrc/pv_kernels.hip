@@ -253,6 +253,42 @@ __global__ __launch_bounds__(kBlock) void block_rotate_kernel(const cplx<T>* __r
     }
 }
 
+// Coefficients of the adjoint source terms of the KPM moments, from their
+// cotangent gbar [nb][M] (M = 2N).  With mu_{2k} = 2<w_k,w_k>/D - mu_0 and
+// mu_{2k+1} = 2 Re<w_k,w_{k+1}>/D - mu_1, the derivative of L = sum gbar mu
+// with respect to w_k is (as a sum of terms coef_j w_{k-1+j}, j = 0, 1, 2)
+//   j = 0: 2 gbar_{2k-1}, or for k = 1 ghat_1 = gbar_1 - sum_{n=1}^{N-1} gbar_{2n+1};
+//   j = 1: 4 gbar_{2k} (k < N);   j = 2: 2 gbar_{2k+1} (k < N);
+// each divided by D.  table[k][j][c] complex (imaginary parts zero), k = 0..N
+// (row 0 unused, zero).  One thread per (k, c); ghat_1 summed in order of n.
+__global__ __launch_bounds__(kBlock) void kpm_adjoint_table_kernel(const double* __restrict__ gbar, int nb, int M,
+                                                                  double invD, double* __restrict__ table) {
+    const int N = M / 2;
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= (N + 1) * nb) return;
+    const int k = e / nb, c = e % nb;
+    const double* gc = gbar + (size_t)c * M;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    if (k >= 1) {
+        if (k == 1) {
+            double ghat1 = gc[1];
+            for (int n = 1; n <= N - 1; ++n) ghat1 -= gc[2 * n + 1];
+            t0 = ghat1 * invD;
+        } else {
+            t0 = 2.0 * gc[2 * k - 1] * invD;
+        }
+        t1 = (k < N ? 4.0 * gc[2 * k] : 0.0) * invD;
+        t2 = (k < N ? 2.0 * gc[2 * k + 1] : 0.0) * invD;
+    }
+    double* row = table + (size_t)k * 3 * nb * 2;
+    row[(0 * nb + c) * 2] = t0;
+    row[(0 * nb + c) * 2 + 1] = 0.0;
+    row[(1 * nb + c) * 2] = t1;
+    row[(1 * nb + c) * 2 + 1] = 0.0;
+    row[(2 * nb + c) * 2] = t2;
+    row[(2 * nb + c) * 2 + 1] = 0.0;
+}
+
 // out[k] = sum_b partials[b][k], fixed order over b.
 __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double* __restrict__ partials,
                                                               int grid, int n, double* __restrict__ out) {
@@ -534,6 +570,13 @@ hipError_t launch_block_gram(int dtype, int64_t rows, int bw, int nblk, const vo
     const int n = (bw * nblk) * (bw * nblk);
     hipLaunchKernelGGL(block_gram_reduce_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, partials, groups,
                        bw, nblk, hermitian, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_kpm_adjoint_table(const double* gbar, int nb, int M, double invD, double* table, hipStream_t s) {
+    const int n = (M / 2 + 1) * nb;
+    hipLaunchKernelGGL(kpm_adjoint_table_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, gbar, nb, M, invD,
+                       table);
     return hipGetLastError();
 }
 

@@ -117,6 +117,9 @@ int gram_grid(int64_t rows, int num_cus);
 // (nblk bw)^2 complex FP64 matrix in one pass; OUT_j = sum_i IN_i Q_ij.
 // Partials: nblk^2 * groups * bw^2 * 2 doubles.
 int block_gram_groups(int64_t rows, int nblk, int num_cus);
+// Source-term table of the KPM adjoint from the moments' cotangent gbar
+// [nb][M] (device): table [(M/2 + 1)][3][nb] complex.
+hipError_t launch_kpm_adjoint_table(const double* gbar, int nb, int M, double invD, double* table, hipStream_t s);
 hipError_t launch_block_gram(int dtype, int64_t rows, int bw, int nblk, const void* A, const void* B,
                              int64_t stride, int hermitian, double* partials, int groups, double* G, hipStream_t s);
 hipError_t launch_block_rotate(int dtype, int64_t rows, int bw, int nin, int nout, const void* IN, int64_t in_stride,
