@@ -371,6 +371,10 @@ def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16):
     rs = [W.random_phase_device(l.n_rows, nb, 300 + i, dev).to(torch.complex64) for i, l in enumerate(lats)]
     batch = pv.Batch(lats)
     a = [7.0 + 0.5 * Wd for (_, Wd) in inst]
+    # the batch's launch shape from its own autotuner (timed on its own steps)
+    t0 = time.perf_counter()
+    shape, tune_ms = pv.pv_batch_autotune(batch, rs, a, 0.0)
+    tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     mu = pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0)       # capture + first run
     torch.cuda.synchronize()
@@ -398,7 +402,10 @@ def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16):
     return {"workload": f"{n} TI realisations L~U{{24..96}} ({sites} sites), W~U[0.5,3], nb={nb}, M={M}",
             "batched_c64": {"ms_per_run": round(ms, 2), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
                             "GB/s": round(b64 / (ms * 1e-3) / 1e9, 1), "first_call_s_incl_capture": round(first, 2),
-                            "mu0_check": ok, "launches_per_run": M // 2 + 1, "graph_replays": batch.stats()[1]},
+                            "mu0_check": ok, "launches_per_run": M // 2 + 1, "graph_replays": batch.stats()[1],
+                            "shape": {k: v for k, v in shape.items() if k in ("kernel", "elems_per_lane",
+                                                                             "workgroup_size")},
+                            "autotune_s": round(tune_s, 2), "autotune_ms_per_step": round(tune_ms, 3)},
             "loop_c128": {"M": M, "ms_per_run": round(ms_loop, 2),
                           "GLUP/s": round(lups / (ms_loop * 1e-3) / 1e9, 3),
                           "note": "phase draws on the device included in the timed loop"},

@@ -31,6 +31,16 @@
  * Errors.  Every argument is validated before the first launch; on error
  * nothing is queued, the status is returned and pv_last_error() (thread
  * local) holds a message.  No C++ exception crosses this interface.
+ * PV_ERR_OOM: the lattice's device tables (made on its first use on a
+ * device) could not be allocated; the lattice stays usable and the next
+ * call tries again.  For tests, the environment variable
+ * PV_TEST_FAIL_DEVICE_ALLOC forces the failure: "all", or k to fail only
+ * the k-th allocation of a set-up (1 coefficients, 2 generic stencil
+ * offsets, 3 the zero row).
+ * PV_ERR_NONFINITE: results read on the host hold NaN or Inf -- moments
+ * passed to pv_kpm_dos / pv_kpm_spectral_function, or the Gram and Lanczos
+ * matrices of pv_chebfd and pv_trlanczos_fd (a non-finite start block or
+ * field); the outputs are then not written.
  * Workspace.  Functions that need scratch device memory take (work,
  * work_bytes) from the caller; the matching *_workspace_size() call gives the
  * minimum size.  Too small a workspace gives PV_ERR_WORKSPACE.
@@ -573,6 +583,31 @@ pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tun
 size_t pv_autotune_workspace_size(const pv_lattice *lat, int dtype, int nb);
 pv_status pv_autotune(pv_lattice *lat, int dtype, int nb, const char *cache_path, void *work,
                       size_t work_bytes, void *stream, pv_tuning *out, double *ms);
+
+/*
+ * Launch shape of a batch (pv_batch_kpm_moments) for (dtype, nb): the
+ * kernel, elements per lane and lanes per workgroup of pv_tuning (other
+ * fields are ignored: each instance walks whole columns of its lattice with
+ * workgroups of its own).  Unset, a batch takes lattice 0's kernel and
+ * elements per lane with 256-lane workgroups.  Setting or resetting (t ==
+ * NULL) drops the captured graph.  512-lane workgroups need a compiled
+ * stencil family (PV_ERR_UNSUPPORTED otherwise).
+ *
+ * pv_batch_autotune times the candidate shapes -- the direct kernel; the
+ * staged kernel with each elements-per-lane value and 256 or 512 lanes --
+ * each on a captured run of the batch itself (8 Chebyshev steps of every
+ * instance with start blocks r and scales a, b as for pv_batch_kpm_moments,
+ * timed as the fastest of three replays), and keeps the fastest for the
+ * batch.  work: pv_batch_autotune_workspace_size() bytes, overwritten.
+ * Synchronises the stream.  out and ms (either may be NULL) receive the
+ * chosen shape and its time per batched step in milliseconds.
+ */
+pv_status pv_batch_set_tuning(pv_batch *batch, int dtype, int nb, const pv_tuning *t);
+pv_status pv_batch_get_tuning(const pv_batch *batch, int dtype, int nb, pv_tuning *t);
+size_t pv_batch_autotune_workspace_size(const pv_batch *batch, int dtype, int nb);
+pv_status pv_batch_autotune(pv_batch *batch, int dtype, int nb, const double *a, const double *b,
+                            const void *const *r, void *work, size_t work_bytes, void *stream,
+                            pv_tuning *out, double *ms);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,11 @@ SIGNATURES = {
     "pv_batch_kpm_workspace_size": (_sz, [_vp, _i, _i, _i]),
     "pv_batch_kpm_moments": (_i, [_vp, _i, _i, _i, _dp, _dp, ctypes.POINTER(_vp), _vp, _vp, _sz, _vp]),
     "pv_batch_stats": (_i, [_vp, _ip, _ip]),
+    "pv_batch_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
+    "pv_batch_get_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
+    "pv_batch_autotune_workspace_size": (_sz, [_vp, _i, _i]),
+    "pv_batch_autotune": (_i, [_vp, _i, _i, _dp, _dp, ctypes.POINTER(_vp), _vp, _sz, _vp, ctypes.POINTER(pv_tuning),
+                               _dp]),
     "pv_kpm_vjp_workspace_size": (_sz, [_vp, _i, _i, _i, _i]),
     "pv_kpm_moments_vjp": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_kpm_moments_ckpt": (_i, [_vp, _i, _i, _i, _d, _d, _vp, _vp, _i, _vp, _sz, _vp]),
@@ -630,6 +635,44 @@ def pv_batch_kpm_moments(batch: Batch, rs, M: int, a, b, mu=None, nb=None):
                                       ctypes.c_void_p(mu.data_ptr()), ctypes.c_void_p(batch._ws.data_ptr()),
                                       batch._ws.numel(), _stream()))
     return mu
+
+
+def pv_batch_set_tuning(batch: Batch, dtype: int, nb: int, tuning=None):
+    """Launch shape of the batch for (dtype, nb): dict of TUNING_FIELDS (only
+    kernel, elems_per_lane and workgroup_size count), None = the default."""
+    if tuning is None:
+        _check(lib().pv_batch_set_tuning(batch.handle, dtype, nb, None))
+        return
+    bad = set(tuning) - set(TUNING_FIELDS)
+    if bad:
+        raise ValueError(f"unknown tuning fields {sorted(bad)}")
+    t = pv_tuning(**{k: int(v) for k, v in tuning.items()})
+    _check(lib().pv_batch_set_tuning(batch.handle, dtype, nb, ctypes.byref(t)))
+
+
+def pv_batch_get_tuning(batch: Batch, dtype: int, nb: int) -> dict:
+    t = pv_tuning()
+    _check(lib().pv_batch_get_tuning(batch.handle, dtype, nb, ctypes.byref(t)))
+    return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+
+def pv_batch_autotune(batch: Batch, rs, a, b, nb=None):
+    """Time the batch's candidate launch shapes on its own captured steps and
+    keep the fastest; returns (shape dict, ms per batched step)."""
+    n = len(batch.lattices)
+    nb = nb if nb is not None else rs[0].numel() // batch.lattices[0].n_rows
+    dt = _dtype_code(rs[0])
+    for l, r in zip(batch.lattices, rs):
+        _vec(r, "r", l.n_rows, nb, dt)
+    ws = _workspace(lib().pv_batch_autotune_workspace_size(batch.handle, dt, nb), rs[0].device)
+    av = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (n,)))
+    bv = np.ascontiguousarray(np.broadcast_to(np.asarray(b, dtype=np.float64), (n,)))
+    ptrs = (_vp * n)(*[r.data_ptr() for r in rs])
+    t = pv_tuning()
+    ms = ctypes.c_double()
+    _check(lib().pv_batch_autotune(batch.handle, dt, nb, _dptr(av), _dptr(bv), ptrs, ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel(), _stream(), ctypes.byref(t), ctypes.byref(ms)))
+    return {k: getattr(t, k) for k in TUNING_FIELDS}, ms.value
 
 
 def _grad_len(lat: Lattice) -> int:

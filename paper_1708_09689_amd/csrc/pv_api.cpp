@@ -181,6 +181,18 @@ void choose_family(pv_lattice& l) {
     l.packed.insert(l.packed.end(), val.begin(), val.end());
 }
 
+// Device allocation of the lattice tables.  PV_TEST_FAIL_DEVICE_ALLOC (a test
+// hook) makes allocation number k of a set-up fail ("all": every one): 1 the
+// coefficient table, 2 the generic offsets, 3 the zero row.
+bool device_alloc(void** p, size_t bytes, int k) {
+    const char* e = std::getenv("PV_TEST_FAIL_DEVICE_ALLOC");
+    if (e && (std::strcmp(e, "all") == 0 || std::atoi(e) == k)) {
+        *p = nullptr;
+        return false;
+    }
+    return hipMalloc(p, bytes) == hipSuccess;
+}
+
 pv_status ensure_device(pv_lattice* l) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -191,16 +203,18 @@ pv_status ensure_device(pv_lattice* l) {
     if (l->d_offs) { (void)hipFree(l->d_offs); l->d_offs = nullptr; }
     if (l->d_zero) { (void)hipFree(l->d_zero); l->d_zero = nullptr; }
     const size_t cb = l->packed.size() * sizeof(double);
-    if (hipMalloc(&l->d_coef, cb) != hipSuccess) return fail(PV_ERR_OOM, "coefficient upload: out of memory");
+    if (!device_alloc(reinterpret_cast<void**>(&l->d_coef), cb, 1))
+        return fail(PV_ERR_OOM, "coefficient upload: out of memory");
     PV_HIP(hipMemcpy(l->d_coef, l->packed.data(), cb, hipMemcpyHostToDevice));
     if (!l->packed_offs.empty()) {
         const size_t ob = l->packed_offs.size() * sizeof(int);
-        if (hipMalloc(&l->d_offs, ob) != hipSuccess) return fail(PV_ERR_OOM, "offset upload: out of memory");
+        if (!device_alloc(reinterpret_cast<void**>(&l->d_offs), ob, 2))
+            return fail(PV_ERR_OOM, "offset upload: out of memory");
         PV_HIP(hipMemcpy(l->d_offs, l->packed_offs.data(), ob, hipMemcpyHostToDevice));
     }
     {
         const size_t zb = (size_t)l->L[0] * l->n_orb * PV_MAX_NB * 16;
-        if (hipMalloc(&l->d_zero, zb) != hipSuccess) return fail(PV_ERR_OOM, "zero row: out of memory");
+        if (!device_alloc(&l->d_zero, zb, 3)) return fail(PV_ERR_OOM, "zero row: out of memory");
         PV_HIP(hipMemset(l->d_zero, 0, zb));
     }
     l->dev = dev;
@@ -938,6 +952,8 @@ extern "C" pv_status pv_kpm_moments(pv_lattice* l, int dtype, int nb, int M, dou
 
 extern "C" pv_status pv_kpm_dos(int M, const double* mu, double a, double b, int nE, const double* E, double* rho) {
     if (M < 1 || !mu || nE < 0 || (nE && (!E || !rho)) || !(a > 0.0)) return fail(PV_ERR_INVALID_ARG, "pv_kpm_dos: bad arguments");
+    for (int n = 0; n < M; ++n)
+        if (!std::isfinite(mu[n])) return fail(PV_ERR_NONFINITE, "pv_kpm_dos: moment %d is not finite", n);
     // Jackson damping g_n (Weisse et al. 2006)
     const double q = M_PI / (M + 1);
     std::vector<double> g(M);
@@ -1654,6 +1670,9 @@ extern "C" pv_status pv_chebfd(pv_lattice* l, int dtype, int bw, int nblk, doubl
                                      reinterpret_cast<double*>(w + Lw.gp), Lw.groups, Gd, s));
         PV_HIP(hipMemcpyAsync(Gh.data(), Gd, Gh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         PV_HIP(hipStreamSynchronize(s));
+        for (double v : Gh)
+            if (!std::isfinite(v))
+                return fail(PV_ERR_NONFINITE, "search space holds non-finite values (start block or field)");
         return PV_OK;
     };
     // OUT_j = sum_i IN_i M_ij for an ns x ns host matrix M: one upload, one
@@ -1903,7 +1922,11 @@ extern "C" pv_status pv_trlanczos_fd(pv_lattice* l, int dtype, double a, double 
         PV_HIP(hipMemcpyAsync(v.data(), hd, v.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         PV_HIP(hipStreamSynchronize(s));
         out.resize((size_t)r * c);
-        for (size_t i = 0; i < out.size(); ++i) out[i] = pvd::cd(v[2 * i], v[2 * i + 1]);
+        for (size_t i = 0; i < out.size(); ++i) {
+            if (!std::isfinite(v[2 * i]) || !std::isfinite(v[2 * i + 1]))
+                return fail(PV_ERR_NONFINITE, "Lanczos block holds non-finite values (start block or field)");
+            out[i] = pvd::cd(v[2 * i], v[2 * i + 1]);
+        }
         return PV_OK;
     };
     auto upload = [&](const std::vector<pvd::cd>& M) -> pv_status {
@@ -2119,6 +2142,11 @@ extern "C" pv_status pv_trlanczos_fd(pv_lattice* l, int dtype, double a, double 
 struct pv_batch {
     std::vector<pv_lattice*> lats;
     int family = 0, n_orb = 0;
+    // launch shape per (dtype, log2 nb) from pv_batch_autotune (kernel,
+    // elems_per_lane, workgroup_size); unset: lattice 0's kernel and elements
+    // per lane with 256-lane workgroups
+    pv_tuning tune[2][7] = {};
+    bool tuned[2][7] = {};
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -2128,6 +2156,9 @@ struct pv_batch {
 
 namespace {
 
+// Chebyshev steps of each timed run of pv_batch_autotune
+constexpr int kBatchTuneSteps = 8;
+
 struct BatchLayout {
     size_t tables, block_inst, inst_block0, invD, partials, partial_stride, moments, vecs, total;
     std::vector<size_t> vec_off;  // per instance: A at vec_off[i], B at vec_off[i] + vb_i
@@ -2136,25 +2167,37 @@ struct BatchLayout {
     int staged;
 };
 
-// Launch description of instance i of a batch (the batch takes the kernel
-// choice and elements per lane of lattice 0's tuning for every instance).
+// Launch shape of a batch: its own (pv_batch_autotune) or, unset, lattice
+// 0's kernel choice and elements per lane with 256-lane workgroups.
+pv_tuning batch_shape(const pv_batch* B, int dtype, int nb) {
+    const int di = dtype == PV_C128 ? 0 : 1, ni = log2_nb(nb);
+    if (B->tuned[di][ni]) return B->tune[di][ni];
+    pv_tuning t{};
+    t.kernel = B->lats[0]->tune[di][ni].kernel;
+    t.elems_per_lane = B->lats[0]->tune[di][ni].elems_per_lane;
+    return t;
+}
+
+// Launch description of instance i of a batch (every instance takes the
+// batch's shape).
 pv::SweepParams batch_params(const pv_batch* B, int i, int dtype, int nb) {
     pv::SweepParams p = base_params(B->lats[i], dtype, nb);
     p.vtype = (dtype == PV_C128) ? 0 : B->lats[i]->vtype;
-    const pv_tuning& t = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    const pv_tuning t = batch_shape(B, dtype, nb);
     p.kernel = t.kernel;
     p.st_E = t.elems_per_lane;
+    p.st_nt = t.workgroup_size;
     return p;
 }
 
-// The staged kernel serves a batch unless lattice 0's tuning asks for the
-// direct one; by default only batches of instances averaging at least 2^20
-// elements per block (smaller ones are launch-latency bound).
+// The staged kernel serves a batch unless its shape asks for the direct one;
+// by default only batches of instances averaging at least 2^20 elements per
+// block (smaller ones are launch-latency bound).
 bool batch_may_stage(const pv_batch* B, int dtype, int nb) {
     static const char* env = std::getenv("PV_SWEEP");
     if (B->family == pv::FAM_GENERIC || (env && std::atoi(env) == 1)) return false;
     if (B->n_orb * nb > pv::STAGED_MAX_SITE) return false;
-    const int kind = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)].kernel;
+    const int kind = batch_shape(B, dtype, nb).kernel;
     if (kind != 0 || (env && std::atoi(env) == 2)) return kind != 1;
     int64_t elems = 0;
     for (const pv_lattice* l : B->lats) elems += l->n_rows * nb;
@@ -2285,10 +2328,10 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
 
     // fingerprint of everything the captured graph bakes in; the graph writes
     // the moments into the workspace, so the caller's mu may move between calls
-    const pv_tuning& t0 = B->lats[0]->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    const pv_tuning t0 = batch_shape(B, dtype, nb);
     std::vector<uint64_t> key = {(uint64_t)dtype, (uint64_t)nb, (uint64_t)M, (uint64_t)(uintptr_t)work,
                                  (uint64_t)work_bytes, (uint64_t)L.staged, (uint64_t)t0.kernel,
-                                 (uint64_t)t0.elems_per_lane};
+                                 (uint64_t)t0.elems_per_lane, (uint64_t)t0.workgroup_size};
     char* const mu_ws = static_cast<char*>(work) + L.moments;
     const size_t mu_bytes = (size_t)n * nb * M * sizeof(double);
     for (int i = 0; i < n; ++i) {
@@ -2404,6 +2447,128 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     ++B->captures;
     PV_HIP(hipGraphLaunch(B->exec, s));
     PV_HIP(hipMemcpyAsync(mu, mu_ws, mu_bytes, hipMemcpyDeviceToDevice, s));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_batch_set_tuning(pv_batch* B, int dtype, int nb, const pv_tuning* t) {
+    if (!B) return fail(PV_ERR_INVALID_ARG, "batch is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if (t && (st = check_tuning(dtype, *t)) != PV_OK) return st;
+    if (t && t->workgroup_size == 512 && B->family == pv::FAM_GENERIC)
+        return fail(PV_ERR_UNSUPPORTED, "512-lane batched sweeps need a compiled stencil family");
+    const int di = dtype == PV_C128 ? 0 : 1, ni = log2_nb(nb);
+    pv_tuning z{};
+    if (t) {
+        // a batch takes the kernel, elements per lane and lanes per
+        // workgroup; every instance walks whole columns
+        z.kernel = t->kernel;
+        z.elems_per_lane = t->elems_per_lane;
+        z.workgroup_size = t->workgroup_size;
+    }
+    B->tune[di][ni] = z;
+    B->tuned[di][ni] = t != nullptr;
+    release_graph(B);
+    return PV_OK;
+}
+
+extern "C" pv_status pv_batch_get_tuning(const pv_batch* B, int dtype, int nb, pv_tuning* t) {
+    if (!B || !t) return fail(PV_ERR_INVALID_ARG, "batch or output is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    *t = batch_shape(B, dtype, nb);
+    return PV_OK;
+}
+
+extern "C" size_t pv_batch_autotune_workspace_size(const pv_batch* B, int dtype, int nb) {
+    const size_t kpm = pv_batch_kpm_workspace_size(B, dtype, nb, 2 * kBatchTuneSteps);
+    if (!kpm) return 0;
+    return kpm + align_up(B->lats.size() * (size_t)nb * 2 * kBatchTuneSteps * sizeof(double));
+}
+
+extern "C" pv_status pv_batch_autotune(pv_batch* B, int dtype, int nb, const double* a, const double* b,
+                                       const void* const* r, void* work, size_t work_bytes, void* stream,
+                                       pv_tuning* out, double* ms_out) {
+    if (!B) return fail(PV_ERR_INVALID_ARG, "batch is NULL");
+    pv_status st;
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    const int M = 2 * kBatchTuneSteps;
+    const size_t need_kpm = pv_batch_kpm_workspace_size(B, dtype, nb, M);
+    const size_t need = pv_batch_autotune_workspace_size(B, dtype, nb);
+    if (!need) return fail(PV_ERR_INVALID_ARG, "batch does not take dtype %d with nb = %d", dtype, nb);
+    if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int di = dtype == PV_C128 ? 0 : 1, ni = log2_nb(nb);
+    const pv_tuning saved = B->tune[di][ni];
+    const bool saved_set = B->tuned[di][ni];
+    // moments of the timed runs, after the runs' own workspace
+    double* mu = reinterpret_cast<double*>(static_cast<char*>(work) + need_kpm);
+    hipEvent_t e0, e1;
+    PV_HIP(hipEventCreate(&e0));
+    PV_HIP(hipEventCreate(&e1));
+    // time of one step of the captured batch under shape t: the first call
+    // captures, then the fastest of three replays of kBatchTuneSteps steps
+    auto measure = [&](const pv_tuning& t, double& ms) -> pv_status {
+        B->tune[di][ni] = t;
+        B->tuned[di][ni] = true;
+        pv_status e = pv_batch_kpm_moments(B, dtype, nb, M, a, b, r, mu, work, need_kpm, stream);
+        if (e != PV_OK) return e;
+        ms = 1e300;
+        for (int k = 0; k < 3; ++k) {
+            PV_HIP(hipEventRecord(e0, s));
+            if ((e = pv_batch_kpm_moments(B, dtype, nb, M, a, b, r, mu, work, need_kpm, stream)) != PV_OK) return e;
+            PV_HIP(hipEventRecord(e1, s));
+            PV_HIP(hipEventSynchronize(e1));
+            float tt = 0.f;
+            PV_HIP(hipEventElapsedTime(&tt, e0, e1));
+            ms = std::min(ms, double(tt) / kBatchTuneSteps);
+        }
+        return PV_OK;
+    };
+    // candidates: the direct kernel; the staged one with each elements per
+    // lane and 256 or 512 lanes (512 for compiled families)
+    std::vector<pv_tuning> cand;
+    {
+        pv_tuning t{};
+        t.kernel = 1;
+        cand.push_back(t);
+        if (B->family != pv::FAM_GENERIC && B->n_orb * nb <= pv::STAGED_MAX_SITE)
+            for (int wg : {0, 512})
+                for (int e : {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4}) {
+                    t = pv_tuning{};
+                    t.kernel = 2;
+                    t.elems_per_lane = e;
+                    t.workgroup_size = wg;
+                    cand.push_back(t);
+                }
+    }
+    pv_tuning best{};
+    double best_ms = 1e300;
+    pv_status err = PV_OK;
+    for (const pv_tuning& t : cand) {
+        double ms = 0.0;
+        if ((err = measure(t, ms)) != PV_OK) break;
+        if (ms < 0.99 * best_ms) {
+            best_ms = ms;
+            best = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != PV_OK) {
+        B->tune[di][ni] = saved;
+        B->tuned[di][ni] = saved_set;
+        release_graph(B);
+        return err;
+    }
+    B->tune[di][ni] = best;
+    B->tuned[di][ni] = true;
+    release_graph(B);
+    if (out) *out = best;
+    if (ms_out) *ms_out = best_ms;
     return PV_OK;
 }
 

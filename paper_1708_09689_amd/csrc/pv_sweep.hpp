@@ -1167,8 +1167,8 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
 // Staged sweep over a batch of lattices in one launch: instance i owns the
 // workgroups [inst_block0[i], inst_block0[i+1]), a multiple of 8 starting at
 // a multiple of 8, split into its 8 XCD parts like a single-lattice launch.
-template <class P, typename T, typename VT, int E, unsigned EPM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PV_STAGED_WAVES_PER_EU)))
+template <class P, typename T, typename VT, int E, unsigned EPM, int NT = kBlock>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PV_STAGED_WAVES_PER_EU)))
 void batch_staged_kernel(const KArgs<T, VT>* __restrict__ table, const int* __restrict__ block_inst,
                          const int* __restrict__ inst_block0, int red_step) {
     const int b = blockIdx.x;
@@ -1178,7 +1178,7 @@ void batch_staged_kernel(const KArgs<T, VT>* __restrict__ table, const int* __re
     KArgs<T, VT> a = table[i];
     a.red_step = red_step;
     const int lb = b - b0;
-    staged_block<P, T, VT, E, EPM, kBlock>(a, b, lb & 7, lb >> 3, (b1 - b0) >> 3);
+    staged_block<P, T, VT, E, EPM, NT>(a, b, lb & 7, lb >> 3, (b1 - b0) >> 3);
 }
 
 // NT lanes per workgroup (256, or 512 for twice the tile length: half the
@@ -1518,13 +1518,18 @@ hipError_t batch_fill_record_fam(const SweepParams& p, int staged, void* dst, in
                     return hipErrorInvalidValue;
                 make_kargs<P, T, VT>(p, false, a);
                 const int e = staged_elems(p);
+                const bool w512 = p.st_nt == 512;
                 int G8;
                 if constexpr (sizeof(T) == 8)
-                    G8 = e == 2 ? staged_setup<P, T, VT, 2>(p, 1 << 30, true, a)
-                                : staged_setup<P, T, VT, 1>(p, 1 << 30, true, a);
+                    G8 = e == 2 ? (w512 ? staged_setup<P, T, VT, 2, 512>(p, 1 << 30, true, a)
+                                        : staged_setup<P, T, VT, 2>(p, 1 << 30, true, a))
+                                : (w512 ? staged_setup<P, T, VT, 1, 512>(p, 1 << 30, true, a)
+                                        : staged_setup<P, T, VT, 1>(p, 1 << 30, true, a));
                 else
-                    G8 = e == 4 ? staged_setup<P, T, VT, 4>(p, 1 << 30, true, a)
-                                : staged_setup<P, T, VT, 2>(p, 1 << 30, true, a);
+                    G8 = e == 4 ? (w512 ? staged_setup<P, T, VT, 4, 512>(p, 1 << 30, true, a)
+                                        : staged_setup<P, T, VT, 4>(p, 1 << 30, true, a))
+                                : (w512 ? staged_setup<P, T, VT, 2, 512>(p, 1 << 30, true, a)
+                                        : staged_setup<P, T, VT, 2>(p, 1 << 30, true, a));
                 std::memcpy(dst, &a, sizeof(a));
                 *nblocks = 8 * G8;
                 return hipSuccess;
@@ -1547,25 +1552,34 @@ hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* 
         if constexpr (P::FAMILY != FAM_GENERIC) {
             if (staged) {
                 constexpr unsigned KPM = EP_STORE_Y | EP_DOTS;
-                auto go = [&](auto ke) -> hipError_t {
+                auto go = [&](auto ke, auto kn) -> hipError_t {
                     constexpr int E = decltype(ke)::value;
-                    const size_t lds = staged_lds_bytes<P, T, E, KPM>();
+                    constexpr int NT = decltype(kn)::value;
+                    const size_t lds = staged_lds_bytes<P, T, E, KPM, NT>();
                     if (lds > 65536) {
                         hipError_t e = hipFuncSetAttribute(
-                            reinterpret_cast<const void*>(&batch_staged_kernel<P, T, VT, E, KPM>),
+                            reinterpret_cast<const void*>(&batch_staged_kernel<P, T, VT, E, KPM, NT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
                         if (e != hipSuccess) return e;
                     }
-                    hipLaunchKernelGGL((batch_staged_kernel<P, T, VT, E, KPM>), dim3(grid), dim3(kBlock), lds, s,
+                    hipLaunchKernelGGL((batch_staged_kernel<P, T, VT, E, KPM, NT>), dim3(grid), dim3(NT), lds, s,
                                        static_cast<const KArgs<T, VT>*>(table), block_inst, inst_block0, red_step);
                     return hipGetLastError();
                 };
                 if (p.ep != KPM) return hipErrorInvalidValue;
                 const int e = staged_elems(p);
-                if constexpr (sizeof(T) == 8)
-                    return e == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 1>{});
-                else
-                    return e == 4 ? go(std::integral_constant<int, 4>{}) : go(std::integral_constant<int, 2>{});
+                using I = std::integral_constant<int, 1>;
+                using I2 = std::integral_constant<int, 2>;
+                using I4 = std::integral_constant<int, 4>;
+                using N256 = std::integral_constant<int, kBlock>;
+                using N512 = std::integral_constant<int, 512>;
+                if constexpr (sizeof(T) == 8) {
+                    if (p.st_nt == 512) return e == 2 ? go(I2{}, N512{}) : go(I{}, N512{});
+                    return e == 2 ? go(I2{}, N256{}) : go(I{}, N256{});
+                } else {
+                    if (p.st_nt == 512) return e == 4 ? go(I4{}, N512{}) : go(I2{}, N512{});
+                    return e == 4 ? go(I4{}, N256{}) : go(I2{}, N256{});
+                }
             }
         }
         hipLaunchKernelGGL((batch_sweep_kernel<P, T, VT>), dim3(grid), dim3(kBlock), 0, s,

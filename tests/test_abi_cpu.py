@@ -312,3 +312,16 @@ def test_library_built_from_these_sources(lib):
     could differ from the ones it declares)."""
     from paper_1708_09689_amd import build
     assert lib.pv_source_hash().decode() == build.source_hash()
+
+
+def test_dos_of_non_finite_moments_is_an_error(lib):
+    """A NaN or Inf moment gives PV_ERR_NONFINITE (status 7), not a NaN
+    density."""
+    mu = np.zeros(16)
+    mu[0] = 1.0
+    for bad in (np.nan, np.inf):
+        mu[5] = bad
+        with pytest.raises(pv.PvError) as e:
+            pv.pv_kpm_dos(mu, np.linspace(-1, 1, 5), 7.0, 0.0)
+        assert e.value.status == 7
+        assert b"not finite" in lib.pv_last_error()

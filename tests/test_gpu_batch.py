@@ -127,3 +127,50 @@ def test_batched_staged_elements_per_lane(dtype, elems):
         ref = kpm.moments_doubling(H, rs[i].astype(np.complex128), 40, a[i], b[i])
         tol = 1e-12 if dtype == np.complex128 else 1e-4
         assert np.abs(mu[i] - ref).max() < tol, (elems, i)
+
+
+@pytest.mark.parametrize("dtype,elems,wg", [(np.complex128, 1, 512), (np.complex128, 2, 512), (np.complex128, 2, 0),
+                                            (np.complex64, 2, 512), (np.complex64, 4, 512), (np.complex64, 4, 0)])
+def test_batch_shape_set_on_the_batch(dtype, elems, wg):
+    """A shape set on the batch (pv_batch_set_tuning), 256- or 512-lane
+    workgroups, serves every instance: each equals its oracle run (complex64
+    to the stated 1e-4 on the FP32-rounded field), and lattice 0's own
+    tuning no longer matters."""
+    vd = np.float64 if dtype == np.complex128 else np.float32
+    cases, rs, a, b = instances(dtype, vd, nb=16)
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    batch = pv.Batch([c.lat for c in cases])
+    shape = {"kernel": 2, "elems_per_lane": elems, "workgroup_size": wg}
+    pv.pv_batch_set_tuning(batch, code, 16, shape)
+    assert {k: v for k, v in pv.pv_batch_get_tuning(batch, code, 16).items() if v} == \
+        {k: v for k, v in shape.items() if v}
+    pv.pv_lattice_set_tuning(cases[0].lat, code, 16, {"kernel": 1})    # ignored by the batch
+    try:
+        mu = host(pv.pv_batch_kpm_moments(batch, [dev(r) for r in rs], 40, a, b))
+    finally:
+        pv.pv_lattice_set_tuning(cases[0].lat, code, 16, None)
+    import oracle.hamiltonian as oh
+    for i, c in enumerate(cases):
+        H = c.H if dtype == np.complex128 else oh.assemble(c.model, c.olat, c.V.astype(np.float32).astype(np.float64))
+        ref = kpm.moments_doubling(H, rs[i].astype(np.complex128), 40, a[i], b[i])
+        tol = 1e-12 if dtype == np.complex128 else 1e-4
+        assert np.abs(mu[i] - ref).max() < tol, (elems, wg, i)
+
+
+def test_batch_autotune_picks_a_candidate_and_keeps_results():
+    """pv_batch_autotune times the batch's candidate shapes on its own steps,
+    keeps the fastest, and the batch then gives the same moments as with the
+    direct kernel (to the dots' summation order)."""
+    cases, rs, a, b = instances(nb=8)
+    batch = pv.Batch([c.lat for c in cases])
+    rd = [dev(r) for r in rs]
+    pv.pv_batch_set_tuning(batch, pv.PV_C128, 8, {"kernel": 1})
+    mu_d = host(pv.pv_batch_kpm_moments(batch, rd, 32, a, b)).copy()
+    shape, ms = pv.pv_batch_autotune(batch, rd, a, b)
+    assert ms > 0.0
+    assert shape["kernel"] in (1, 2) and shape["workgroup_size"] in (0, 512)
+    assert pv.pv_batch_get_tuning(batch, pv.PV_C128, 8) == shape
+    mu_t = host(pv.pv_batch_kpm_moments(batch, rd, 32, a, b))
+    assert np.abs(mu_t - mu_d).max() < 1e-13
+    pv.pv_batch_set_tuning(batch, pv.PV_C128, 8, None)
+    assert pv.pv_batch_get_tuning(batch, pv.PV_C128, 8)["workgroup_size"] == 0
