@@ -876,8 +876,14 @@ struct StagedCtx {
             for (int k = 0; k < S::TCH; ++k) dz[tid + k * S::NTH] = st.z[k];
         }
         if (a.field == 2) {
+            // only the entries the tile reads (TW >> vshift: one per site or
+            // orbital row) are generated, not one per lane and element
+            const int nent = S::TW >> vshift;
 #pragma unroll
-            for (int k = 0; k < E; ++k) vl[tid + k * S::NTH] = field_at(a, st.vrow + voff[k]);
+            for (int k = 0; k < E; ++k) {
+                const int q = tid + k * S::NTH;
+                if (q < nent) vl[q] = field_at(a, st.vrow + voff[k]);
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < E; ++k) vl[tid + k * S::NTH] = T(st.v[k]);
