@@ -566,6 +566,41 @@ pv_status pv_lattice_set_tuning(pv_lattice *lat, int dtype, int nb, const pv_tun
 pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tuning *t);
 
 /*
+ * Generated stencil kernels (Sec. 3.2: the DSL front end generates the code
+ * of a model's stencil).  A stencil that none of the built-in families
+ * matches (PV_FAM_GENERIC: any DSL program or descriptor) is described at
+ * lattice creation as a pattern struct -- its offsets in descriptor order
+ * and, for every block entry, whether it is zero, real, imaginary or complex
+ * -- and its sweeps take the built-in families' staged and direct kernels
+ * instantiated for that pattern, compiled with hipRTC for the current
+ * device on the first launch that needs an instance (about a second each;
+ * the code objects stay loaded until the process ends, and PV_CODEGEN_CACHE
+ * may name a directory that keeps them across processes).  Compile on a
+ * launch outside stream capture first: compilation is not a stream operation.
+ * Results equal the interpreted generic kernels' up to the summation order
+ * of the stencil terms.  3D stencils with an offset that has both a y and a
+ * z step take the direct kernel, others the staged one as the built-in
+ * families do (with 512-lane workgroups available to the autotuner).
+ * A failed compilation returns PV_ERR_HIP with the compiler's log in
+ * pv_last_error().  The batched sweeps (pv_batch_*) keep the interpreted
+ * kernels.
+ *
+ * set_codegen: enable (1, the default) or disable (0: the interpreted
+ * generic kernels, which read every entry's column and value at run time)
+ * for this lattice; PV_CODEGEN=0 in the environment disables it for every
+ * lattice.  get_codegen: *active = 1 when sweeps of the lattice take
+ * generated kernels (a generic stencil with a pattern, enabled).
+ * codegen_source: the pattern struct's C++ text, NUL-terminated into buf
+ * (truncated to len - 1 bytes; buf may be NULL), *needed (may be NULL) =
+ * its length + 1; PV_ERR_UNSUPPORTED for built-in families and for stencils
+ * whose block rows need more than 96 per-lane entry slots (those always take
+ * the interpreted kernels).
+ */
+pv_status pv_lattice_set_codegen(pv_lattice *lat, int enable);
+pv_status pv_lattice_get_codegen(const pv_lattice *lat, int *active);
+pv_status pv_lattice_codegen_source(const pv_lattice *lat, char *buf, size_t len, size_t *needed);
+
+/*
  * Autotuner: times candidate shapes of one Chebyshev step (sweep with fused
  * dots and its reduction) on the stream's device and applies the fastest to
  * the lattice for (dtype, nb); then, separately, those of one series step

@@ -113,6 +113,9 @@ SIGNATURES = {
                              _sz, _vp]),
     "pv_lattice_set_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
     "pv_lattice_get_tuning": (_i, [_vp, _i, _i, ctypes.POINTER(pv_tuning)]),
+    "pv_lattice_set_codegen": (_i, [_vp, _i]),
+    "pv_lattice_get_codegen": (_i, [_vp, _ip]),
+    "pv_lattice_codegen_source": (_i, [_vp, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
     "pv_autotune_workspace_size": (_sz, [_vp, _i, _i]),
     "pv_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p, _vp, _sz, _vp, ctypes.POINTER(pv_tuning), _dp]),
 }
@@ -543,6 +546,28 @@ def pv_lattice_get_tuning(lat, dtype: int, nb: int) -> dict:
     t = pv_tuning()
     _check(lib().pv_lattice_get_tuning(lat.handle, dtype, nb, ctypes.byref(t)))
     return {k: getattr(t, k) for k in TUNING_FIELDS}
+
+
+def pv_lattice_set_codegen(lat, enable: bool):
+    """Generated kernels (True, the default) or the interpreted generic ones
+    (False) for the sweeps of a generic-stencil lattice."""
+    _check(lib().pv_lattice_set_codegen(lat.handle, 1 if enable else 0))
+
+
+def pv_lattice_get_codegen(lat) -> bool:
+    """True when sweeps of the lattice take kernels generated from its stencil."""
+    v = ctypes.c_int()
+    _check(lib().pv_lattice_get_codegen(lat.handle, ctypes.byref(v)))
+    return bool(v.value)
+
+
+def pv_lattice_codegen_source(lat) -> str:
+    """C++ text of the pattern struct the generated kernels are compiled for."""
+    n = ctypes.c_size_t()
+    _check(lib().pv_lattice_codegen_source(lat.handle, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().pv_lattice_codegen_source(lat.handle, buf, n.value, ctypes.byref(n)))
+    return buf.value.decode()
 
 
 def pv_autotune(lat, nb: int, dtype: int = PV_C128, cache_path=None, device="cuda"):

@@ -57,11 +57,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def embed_kernel_sources(objdir: str) -> str:
+    """C++ file holding the text of the sweep kernel headers, which the
+    library compiles at run time (hipRTC) for stencils outside the built-in
+    families."""
+    parts = ["// Written by build.py: kernel headers compiled at run time for generated stencils.",
+             "namespace pv {", "extern const char* const kRtcKernelsHpp;", "extern const char* const kRtcSweepHpp;"]
+    for sym, name in (("kRtcKernelsHpp", "pv_kernels.hpp"), ("kRtcSweepHpp", "pv_sweep.hpp")):
+        with open(os.path.join(CSRC, name)) as fh:
+            text = fh.read()
+        if ")PVRTC" in text:
+            raise RuntimeError(f"{name} holds the raw-string delimiter")
+        parts.append(f'const char* const {sym} = R"PVRTC({text})PVRTC";')
+    parts.append("}  // namespace pv")
+    out = os.path.join(objdir, "pv_rtc_source.cpp")
+    body = "\n".join(parts) + "\n"
+    if not os.path.exists(out) or open(out).read() != body:
+        with open(out, "w") as fh:
+            fh.write(body)
+    return out
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    srcs.append(embed_kernel_sources(objdir))
     objs = [os.path.join(objdir, os.path.basename(src) + ".o") for src in srcs]
     stamp = f'-DPV_SOURCE_HASH="{source_hash()}"'
     cmds = [[hipcc(), *HIP_FLAGS, stamp, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj] for src, obj in zip(srcs, objs)]
@@ -77,7 +99,7 @@ def build(verbose: bool = False) -> str:
                 sys.stderr.write(done.stdout + done.stderr)
                 raise subprocess.CalledProcessError(done.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lhiprtc", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -35,6 +35,10 @@ pv_status fail(pv_status s, const char* fmt, ...) {
 }
 
 pv_status hip_fail(hipError_t e, const char* where) {
+    // a generated kernel that did not compile or load says why
+    const std::string cg = pv::codegen_error();
+    pv::codegen_clear_error();
+    if (!cg.empty()) return fail(PV_ERR_HIP, "%s: %s: %s", where, hipGetErrorString(e), cg.c_str());
     return fail(PV_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
@@ -98,6 +102,11 @@ struct pv_lattice {
     // launch shapes per (dtype, log2 nb)
     pv_tuning tune[2][7] = {};
     pv_tuning tune_acc[2][7] = {};   // series steps (autotuned); kernel 0 = follow tune
+    // generic stencils: the pattern struct of their generated kernels (empty
+    // when a lane's row needs more slots than a kernel holds), and whether
+    // sweeps take them (pv_lattice_set_codegen)
+    std::string cg_src;
+    int codegen = 1;
 };
 
 namespace {
@@ -146,6 +155,59 @@ bool try_family(pv_lattice& l) {
     return true;
 }
 
+int generic_side_halo(const pv_lattice* l);
+
+// Pattern struct of a generic stencil for its generated kernels (Sec. 3.2:
+// the DSL's code generation), in the form of the built-in families: the
+// offsets in descriptor order and, for every block entry, whether it is
+// zero, real, imaginary or complex (the values stay in the coefficient
+// table).  Empty when a lane's row would need more slots than a kernel holds.
+std::string codegen_pattern(const pv_lattice& l) {
+    const int NO = l.n_orb, NT = l.n_terms;
+    auto code = [&](int t, int o, int q) {
+        const double* e = &l.packed[(((size_t)t * NO + o) * NO + q) * 2];
+        if (e[0] == 0.0 && e[1] == 0.0) return 0;
+        if (e[1] == 0.0) return 1;
+        return e[0] == 0.0 ? 2 : 3;
+    };
+    int slots = 0;
+    for (int t = 0; t <= NT; ++t)
+        for (int kd = 1; kd <= 3; ++kd) {
+            int K = 0;
+            for (int o = 0; o < NO; ++o) {
+                int c = 0;
+                for (int q = 0; q < NO; ++q)
+                    if (!(t == NT && q == o) && code(t, o, q) == kd) ++c;
+                K = std::max(K, c);
+            }
+            slots += K;
+        }
+    if (slots > pv::MAX_SLOTS_K) return std::string();
+    static const char* const kCode[4] = {"CZ", "CR", "CI", "CC"};
+    std::string s = "struct PatCG {\n";
+    s += "    static constexpr int FAMILY = FAM_CODEGEN, NO = " + std::to_string(NO) + ", NT = " + std::to_string(NT) +
+         ", DIM = " + std::to_string(l.dim) + ";\n";
+    s += std::string("    static constexpr bool SIDE_HALO = ") + (generic_side_halo(&l) ? "true" : "false") + ";\n";
+    s += "    static constexpr int off[" + std::to_string(std::max(NT, 1)) + "][3] = {";
+    for (int t = 0; t < std::max(NT, 1); ++t) {
+        const int* d = NT ? &l.offsets[3 * t] : nullptr;
+        s += (t ? ", {" : "{") + std::to_string(d ? d[0] : 0) + ", " + std::to_string(d ? d[1] : 0) + ", " +
+             std::to_string(d ? d[2] : 0) + "}";
+    }
+    s += "};\n    static constexpr unsigned char code[NT + 1][NO][NO] = {\n";
+    for (int t = 0; t <= NT; ++t) {
+        s += "        {";
+        for (int o = 0; o < NO; ++o) {
+            s += o ? ", {" : "{";
+            for (int q = 0; q < NO; ++q) s += std::string(q ? ", " : "") + kCode[code(t, o, q)];
+            s += "}";
+        }
+        s += "},\n";
+    }
+    s += "    };\n};\n";
+    return s;
+}
+
 void choose_family(pv_lattice& l) {
     if (try_family<pv::PatTI>(l)) return;
     if (try_family<pv::PatGraphene2>(l)) return;
@@ -179,6 +241,7 @@ void choose_family(pv_lattice& l) {
     l.packed_offs.insert(l.packed_offs.end(), ptr.begin(), ptr.end());
     l.packed_offs.insert(l.packed_offs.end(), col.begin(), col.end());
     l.packed.insert(l.packed.end(), val.begin(), val.end());
+    l.cg_src = codegen_pattern(l);
 }
 
 // Device allocation of the lattice tables.  PV_TEST_FAIL_DEVICE_ALLOC (a test
@@ -282,6 +345,16 @@ int generic_side_halo(const pv_lattice* l) {
     return 0;
 }
 
+// Sweeps of a generic stencil take its generated kernels unless the lattice
+// or PV_CODEGEN=0 turns them off, or the pattern has too many slots.
+bool uses_codegen(const pv_lattice* l) {
+    static const bool env_on = [] {
+        const char* e = std::getenv("PV_CODEGEN");
+        return !(e && std::strcmp(e, "0") == 0);
+    }();
+    return l->family == pv::FAM_GENERIC && l->codegen && !l->cg_src.empty() && env_on;
+}
+
 pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     pv::SweepParams p{};
     p.family = l->family;
@@ -304,6 +377,11 @@ pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     p.offs = l->d_offs;
     p.generic_stageable = generic_stageable(l);
     p.generic_side_halo = generic_side_halo(l);
+    if (uses_codegen(l)) {
+        p.cg_src = l->cg_src.c_str();
+        p.cg_dim = l->dim;
+        p.cg_halo = p.generic_side_halo;
+    }
     return p;
 }
 
@@ -1303,10 +1381,26 @@ std::string tune_key(const pv_lattice* l, int dtype, int nb) {
         arch = prop.gcnArchName;
         cus = prop.multiProcessorCount;
     }
+    // generic stencils: their offsets, and the generated kernels' pattern when
+    // sweeps use them (FNV-1a)
+    unsigned long long gh = 0;
+    if (l->family == pv::FAM_GENERIC) {
+        gh = 14695981039346656037ull;
+        auto mix = [&](const void* data, size_t n) {
+            for (size_t i = 0; i < n; ++i) {
+                gh ^= static_cast<const unsigned char*>(data)[i];
+                gh *= 1099511628211ull;
+            }
+        };
+        mix(l->offsets.data(), l->offsets.size() * sizeof(int));
+        if (uses_codegen(l)) mix(l->cg_src.data(), l->cg_src.size());
+    }
     char buf[512];
-    std::snprintf(buf, sizeof buf, "family=%d orb=%d L=%lldx%lldx%lld bc=%d%d%d nb=%d dtype=%d vtype=%d dev=%s cus=%d",
+    std::snprintf(buf, sizeof buf,
+                  "family=%d orb=%d L=%lldx%lldx%lld bc=%d%d%d nb=%d dtype=%d vtype=%d dev=%s cus=%d stencil=%016llx",
                   l->family, l->n_orb, (long long)l->L[0], (long long)l->L[1], (long long)l->L[2], l->periodic[0],
-                  l->periodic[1], l->periodic[2], nb, dtype, l->rng_on ? 2 : (l->V ? l->vtype : -1), arch.c_str(), cus);
+                  l->periodic[1], l->periodic[2], nb, dtype, l->rng_on ? 2 : (l->V ? l->vtype : -1), arch.c_str(), cus,
+                  gh);
     return buf;
 }
 
@@ -1382,6 +1476,35 @@ extern "C" pv_status pv_lattice_get_tuning(const pv_lattice* l, int dtype, int n
     if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
     if ((st = check_nb(nb)) != PV_OK) return st;
     *t = l->tune[dtype == PV_C128 ? 0 : 1][log2_nb(nb)];
+    return PV_OK;
+}
+
+extern "C" pv_status pv_lattice_set_codegen(pv_lattice* l, int enable) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if (enable != 0 && enable != 1) return fail(PV_ERR_INVALID_ARG, "enable must be 0 or 1");
+    l->codegen = enable;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_lattice_get_codegen(const pv_lattice* l, int* active) {
+    if (!l || !active) return fail(PV_ERR_INVALID_ARG, "lattice or output is NULL");
+    *active = uses_codegen(l) ? 1 : 0;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_lattice_codegen_source(const pv_lattice* l, char* buf, size_t len, size_t* needed) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    if (l->family != pv::FAM_GENERIC)
+        return fail(PV_ERR_UNSUPPORTED, "the stencil is a built-in family (family %d): no generated pattern", l->family);
+    if (l->cg_src.empty())
+        return fail(PV_ERR_UNSUPPORTED, "the stencil's rows need more than %d slots: no generated pattern",
+                    pv::MAX_SLOTS_K);
+    if (needed) *needed = l->cg_src.size() + 1;
+    if (buf && len) {
+        const size_t n = std::min(len - 1, l->cg_src.size());
+        std::memcpy(buf, l->cg_src.data(), n);
+        buf[n] = '\0';
+    }
     return PV_OK;
 }
 
@@ -1483,7 +1606,8 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
         return hipSuccess;
     };
     hipError_t herr = hipSuccess;
-    const bool compiled = l->family != pv::FAM_GENERIC || generic_stageable(l);
+    const bool cg = uses_codegen(l);
+    const bool compiled = l->family != pv::FAM_GENERIC || generic_stageable(l) || (cg && l->dim == 2);
     const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
     // coordinate search: 1. kernel, elements per lane and lanes per workgroup
     // at default shapes;
@@ -1512,7 +1636,7 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
             const int es[2] = {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4};
             for (int wg : {256, 512})
                 for (int e : es) {
-                    if (wg == 512 && l->family == pv::FAM_GENERIC) continue;
+                    if (wg == 512 && l->family == pv::FAM_GENERIC && !cg) continue;
                     t = pv_tuning{};
                     t.kernel = 2;
                     t.elems_per_lane = e;

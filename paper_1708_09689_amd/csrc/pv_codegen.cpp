@@ -1,0 +1,312 @@
+// Stencil kernels generated at run time from a stencil's own block structure
+// (Sec. 3.2: the DSL front end generates the stencil code of a model).
+//
+// The built-in families (TI, graphene, Weyl) fix their offsets and the zero /
+// real / imaginary / complex structure of every block at compile time, so a
+// lane's row of every block sits in registers as "slots".  A stencil that
+// none of them matches (any DSL program) is described the same way by the
+// host -- a pattern struct pv::PatCG with its offsets and entry codes -- and
+// the very sweep templates of the built-in families (staged and direct) are
+// instantiated for it with hipRTC the first time a launch needs them.  The
+// code objects stay loaded for the life of the process, one per device,
+// pattern and kernel instance; PV_CODEGEN_CACHE names a directory that keeps
+// them across processes.
+#include "pv_sweep.hpp"
+
+#include <hip/hiprtc.h>
+
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace pv {
+
+// Text of pv_kernels.hpp and pv_sweep.hpp, embedded by the build.
+extern const char* const kRtcKernelsHpp;
+extern const char* const kRtcSweepHpp;
+
+namespace {
+
+thread_local std::string g_err;
+
+// Host stand-in of a generated pattern: the launch set-up (kernel arguments,
+// walk and strip layout, LDS size) depends only on the orbitals, the lattice
+// dimension and the side rows' x halo.
+template <int NO_, int DIM_, bool SH>
+struct PatShape {
+    static constexpr int FAMILY = FAM_CODEGEN, NO = NO_, NT = 0, DIM = DIM_;
+    static constexpr bool SIDE_HALO = SH;
+    static constexpr int off[1][3] = {{0, 0, 0}};
+    static constexpr unsigned char code[1][NO_][NO_] = {};
+};
+
+struct Compiled {
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int occ = 1;   // workgroups resident per CU at the instance's LDS size
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, std::string, std::string>, Compiled> g_fns;   // (device, pattern, instance)
+
+const char* const kOpts[] = {"-O3", "-std=c++17", "-DPV_RTC=1",
+                             // keep the compiler from forming packed FP32 instructions
+                             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+
+uint64_t fnv1a(uint64_t h, const char* s, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= static_cast<unsigned char>(s[i]);
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+uint64_t fnv1a(uint64_t h, const std::string& s) { return fnv1a(h, s.data(), s.size() + 1); }
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "gfx950";
+    const std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Cache file: the kernel's symbol name on the first line, then the code object.
+bool read_cached(const std::string& path, std::string& lowered, std::vector<char>& code) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f || !std::getline(f, lowered) || lowered.empty()) return false;
+    code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+    return !code.empty();
+}
+
+void write_cached(const std::string& path, const std::string& lowered, const std::vector<char>& code) {
+    const std::string tmp = path + ".tmp" + std::to_string(reinterpret_cast<uintptr_t>(&code));
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        if (!f) return;
+        f << lowered << '\n';
+        f.write(code.data(), std::streamsize(code.size()));
+        if (!f) return;
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+// Code object and symbol of the instance `expr` for the pattern.
+bool build(const std::string& pat, const std::string& expr, const std::string& arch, std::string& lowered,
+           std::vector<char>& code) {
+    const std::string src = "#include \"pv_sweep.hpp\"\n\nnamespace pv {\n\n" + pat + "\n}  // namespace pv\n";
+    std::string path;
+    if (const char* dir = std::getenv("PV_CODEGEN_CACHE"); dir && *dir) {
+        uint64_t h = 14695981039346656037ull;
+        h = fnv1a(h, arch);
+        h = fnv1a(h, src);
+        h = fnv1a(h, expr);
+        h = fnv1a(h, std::string(kRtcKernelsHpp));
+        h = fnv1a(h, std::string(kRtcSweepHpp));
+        for (const char* o : kOpts) h = fnv1a(h, std::string(o));
+        char name[64];
+        std::snprintf(name, sizeof name, "/pvcg_%016llx.co", static_cast<unsigned long long>(h));
+        path = std::string(dir) + name;
+        if (read_cached(path, lowered, code)) return true;
+    }
+    hiprtcProgram prog;
+    const char* hdrs[2] = {kRtcKernelsHpp, kRtcSweepHpp};
+    const char* names[2] = {"pv_kernels.hpp", "pv_sweep.hpp"};
+    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "pv_codegen.hip", 2, hdrs, names);
+    if (r != HIPRTC_SUCCESS) {
+        g_err = std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r);
+        return false;
+    }
+    std::vector<const char*> opts;
+    const std::string archopt = "--offload-arch=" + arch;
+    opts.push_back(archopt.c_str());
+    for (const char* o : kOpts) opts.push_back(o);
+    if ((r = hiprtcAddNameExpression(prog, expr.c_str())) == HIPRTC_SUCCESS)
+        r = hiprtcCompileProgram(prog, int(opts.size()), opts.data());
+    if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        std::string log;
+        if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 1) {
+            log.resize(n);
+            if (hiprtcGetProgramLog(prog, &log[0]) != HIPRTC_SUCCESS) log.clear();
+        }
+        g_err = std::string("hipRTC compile of ") + expr + ": " + hiprtcGetErrorString(r) + "\n" + log.substr(0, 4000);
+        (void)hiprtcDestroyProgram(&prog);
+        return false;
+    }
+    const char* lo = nullptr;
+    size_t n = 0;
+    if (hiprtcGetLoweredName(prog, expr.c_str(), &lo) != HIPRTC_SUCCESS || !lo ||
+        hiprtcGetCodeSize(prog, &n) != HIPRTC_SUCCESS || n == 0) {
+        g_err = "hipRTC: no code object for " + expr;
+        (void)hiprtcDestroyProgram(&prog);
+        return false;
+    }
+    lowered = lo;
+    code.resize(n);
+    r = hiprtcGetCode(prog, code.data());
+    (void)hiprtcDestroyProgram(&prog);
+    if (r != HIPRTC_SUCCESS) {
+        g_err = std::string("hiprtcGetCode: ") + hiprtcGetErrorString(r);
+        return false;
+    }
+    if (!path.empty()) write_cached(path, lowered, code);
+    return true;
+}
+
+// The loaded kernel for (current device, pattern, instance), compiled on
+// first use.  nt and lds: the launch's workgroup and LDS size (for the
+// occupancy that sizes staged grids).
+hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t lds, Compiled& out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const auto key = std::make_tuple(dev, std::string(pat), expr);
+    const auto it = g_fns.find(key);
+    if (it != g_fns.end()) {
+        out = it->second;
+        return hipSuccess;
+    }
+    g_err.clear();
+    std::string lowered;
+    std::vector<char> code;
+    if (!build(pat, expr, device_arch(), lowered, code)) return hipErrorInvalidImage;
+    Compiled c;
+    if ((e = hipModuleLoadData(&c.mod, code.data())) != hipSuccess) {
+        g_err = "hipModuleLoadData of " + expr + ": " + hipGetErrorString(e);
+        return e;
+    }
+    if ((e = hipModuleGetFunction(&c.fn, c.mod, lowered.c_str())) != hipSuccess) {
+        g_err = "hipModuleGetFunction " + lowered + ": " + hipGetErrorString(e);
+        (void)hipModuleUnload(c.mod);
+        return e;
+    }
+    int n = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, c.fn, nt, lds) != hipSuccess || n < 1) n = 1;
+    c.occ = n;
+    g_fns.emplace(key, c);
+    out = c;
+    return hipSuccess;
+}
+
+template <typename T>
+const char* tname() {
+    return sizeof(T) == 8 ? "double" : "float";
+}
+
+// Staged sweep of E elements per lane, NT lanes, epilogue flags epm (0: read
+// at run time): the set-up of launch_staged with the generated kernel.
+template <class P, typename T, typename VT, int E, int NT>
+hipError_t staged_go(SweepParams& p, int num_cus, hipStream_t s, unsigned epm) {
+    KArgs<T, VT> a;
+    make_kargs<P, T, VT>(p, false, a);
+    const size_t lds = staged_lds_bytes_for<P, T, E, NT>(epm == 0u || (epm & EP_ACC_ADD) != 0u);
+    char expr[160];
+    std::snprintf(expr, sizeof expr, "&pv::staged_kernel<pv::PatCG, %s, %s, %d, %uu, %d>", tname<T>(), tname<VT>(),
+                  E, epm, NT);
+    Compiled c;
+    if (const hipError_t e = function_for(p.cg_src, expr, NT, lds, c); e != hipSuccess) return e;
+    int G8 = p.st_G8 > 0 ? p.st_G8 : (num_cus >= 8 ? num_cus / 8 : 1) * c.occ;
+    if (G8 > 256) G8 = 256;
+    G8 = staged_setup<P, T, VT, E, NT>(p, G8, false, a);
+    p.grid = 8 * G8;
+    void* args[] = {&a};
+    return hipModuleLaunchKernel(c.fn, unsigned(p.grid), 1, 1, NT, 1, 1, unsigned(lds), s, args, nullptr);
+}
+
+// Epilogue specialisations as for the built-in families: the Chebyshev step
+// with dots, the series step and the plain sweep (without z when gamma = 0)
+// with uniform alpha, beta, gamma; everything else reads its flags at run
+// time (complex128: one element per lane).
+template <class P, typename T, typename VT, int E>
+hipError_t staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
+    constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD, PLAIN = EP_STORE_Y;
+    if (p.colp == nullptr) {
+        unsigned epm = 0u;
+        if (p.ep == KPM) epm = KPM;
+        else if (p.ep == SERIES) epm = SERIES;
+        else if (p.ep == PLAIN) epm = p.gamma == 0.0 ? (PLAIN | EP_NO_Z) : PLAIN;
+        if (epm != 0u)
+            return p.st_nt == 512 ? staged_go<P, T, VT, E, 512>(p, num_cus, s, epm)
+                                  : staged_go<P, T, VT, E, kBlock>(p, num_cus, s, epm);
+    }
+    if constexpr (sizeof(T) == 8 && E == 2) {
+        SweepParams q = p;
+        q.st_C = q.st_Bm = q.st_G8 = 0;
+        const hipError_t e = staged_go<P, T, VT, 1, kBlock>(q, num_cus, s, 0u);
+        p.grid = q.grid;
+        return e;
+    } else {
+        return staged_go<P, T, VT, E, kBlock>(p, num_cus, s, 0u);
+    }
+}
+
+// Kernel choice of a built-in family: staged when the pattern allows it (2D,
+// or 3D with no offset that has both a y and a z step), the block is 16-byte
+// aligned in whole chunks per site and the launch asks for it or is large;
+// else the direct kernel.
+template <class P, typename T, typename VT>
+hipError_t typed(SweepParams& p, int num_cus, hipStream_t s) {
+    static const int env_kernel = env_int("PV_SWEEP", 0);
+    const int kind = p.kernel > 0 ? p.kernel : env_kernel;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(p.x) | reinterpret_cast<uintptr_t>(p.zero_row)) & 15) == 0;
+    const bool can = P::DIM == 2 || p.generic_stageable;
+    const bool whole = (P::NO * p.nb * int(sizeof(cplx<T>))) % 16 == 0;
+    if (can && aligned && whole && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && staged_default(p)))) {
+        const int e = staged_elems(p);
+        if constexpr (sizeof(T) == 8)
+            return e == 2 ? staged_ep<P, T, VT, 2>(p, num_cus, s) : staged_ep<P, T, VT, 1>(p, num_cus, s);
+        else
+            return e == 4 ? staged_ep<P, T, VT, 4>(p, num_cus, s) : staged_ep<P, T, VT, 2>(p, num_cus, s);
+    }
+    KArgs<T, VT> a;
+    make_kargs<P, T, VT>(p, false, a);
+    p.grid = int(8 * ((a.ntiles + a.tpb - 1) / a.tpb));
+    char expr[128];
+    std::snprintf(expr, sizeof expr, "&pv::sweep_kernel<pv::PatCG, %s, %s>", tname<T>(), tname<VT>());
+    Compiled c;
+    if (const hipError_t e = function_for(p.cg_src, expr, kBlock, 0, c); e != hipSuccess) return e;
+    void* args[] = {&a};
+    return hipModuleLaunchKernel(c.fn, unsigned(p.grid), 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
+}
+
+template <int NO, int DIM, bool SH>
+hipError_t by_types(SweepParams& p, int num_cus, hipStream_t s) {
+    using P = PatShape<NO, DIM, SH>;
+    if (p.dtype == 0) {
+        if (p.vtype != 0) return hipErrorInvalidValue;
+        return typed<P, double, double>(p, num_cus, s);
+    }
+    if (p.vtype == 0) return typed<P, float, double>(p, num_cus, s);
+    return typed<P, float, float>(p, num_cus, s);
+}
+
+template <int NO>
+hipError_t by_shape(SweepParams& p, int num_cus, hipStream_t s) {
+    if (p.cg_dim == 2) return by_types<NO, 2, false>(p, num_cus, s);
+    return p.cg_halo ? by_types<NO, 3, true>(p, num_cus, s) : by_types<NO, 3, false>(p, num_cus, s);
+}
+
+}  // namespace
+
+hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s) {
+    g_err.clear();
+    if (!p.cg_src) return hipErrorInvalidValue;
+    switch (p.n_orb) {
+        case 1: return by_shape<1>(p, num_cus, s);
+        case 2: return by_shape<2>(p, num_cus, s);
+        case 4: return by_shape<4>(p, num_cus, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+const char* codegen_error() { return g_err.c_str(); }
+void codegen_clear_error() { g_err.clear(); }
+
+}  // namespace pv

@@ -2,10 +2,17 @@
 // (pv_kernels.hip).  Not installed; not part of the public ABI.
 #pragma once
 
+#ifndef PV_RTC
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
+#else
+// run-time compiled kernels: the fixed-width integers of the RTC runtime header
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#endif
 
 namespace pv {
 
@@ -14,6 +21,8 @@ constexpr int PV_MAX_TERMS_K = 26;   // neighbour offsets per stencil (the C ABI
 // Largest site (n_orb * nb elements) the staged sweep kernel takes; wider
 // blocks use the direct kernel.
 constexpr int STAGED_MAX_SITE = 128;
+// Most slots (per-lane block entries kept in registers) a compiled pattern has.
+constexpr int MAX_SLOTS_K = 96;
 
 // Kernel families: a family fixes the stencil's offsets and the zero / real /
 // imaginary structure of every block at compile time; values stay runtime.
@@ -23,6 +32,7 @@ enum Family : int {
     FAM_GRAPHENE2 = 2,   // two-site honeycomb, n_orb = 2, offsets +-x, +-y (2D)
     FAM_GRAPHENE4 = 3,   // four-site graphene cell (Sec. 2.1), n_orb = 4 (2D)
     FAM_WEYL = 4,        // Weyl semimetal (Sec. 2.3), n_orb = 2, 3D
+    FAM_CODEGEN = 5,     // a stencil's own pattern, generated and compiled at run time
 };
 
 // Block-entry codes.
@@ -39,6 +49,7 @@ enum : unsigned {
     EP_NO_Z = 64u,       // launch-internal: gamma = 0, z is neither loaded nor staged
 };
 
+#ifndef PV_RTC
 struct SweepParams {
     int family;
     int dtype;            // 0 = complex128, 1 = complex64
@@ -91,6 +102,11 @@ struct SweepParams {
     double* red_out;
     int red_grid, red_mode, red_M, red_step;
     double red_invD;
+    // generated kernels (generic stencils): source of the stencil's pattern
+    // struct pv::PatCG, NULL for the interpreted generic kernels; its
+    // lattice dimension and whether side rows need the x halo
+    const char* cg_src;
+    int cg_dim, cg_halo;
 };
 
 // Number of workgroups a sweep of an nb-wide block over the lattice uses
@@ -98,6 +114,13 @@ struct SweepParams {
 // number in p.grid.
 int64_t sweep_grid_max(const int64_t L[3], int n_orb, int nb);
 hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s);
+// Sweep of a generic stencil with kernels generated from its pattern
+// (p.cg_src) and compiled at run time on first use (pv_codegen.cpp).  A
+// failed compilation returns hipErrorInvalidImage and leaves the compiler's
+// message in codegen_error() (this thread).
+hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s);
+const char* codegen_error();
+void codegen_clear_error();
 
 // Fixed-order reduction of [grid][nb][4] partials.
 //   mode 0: dots[c][0..3] = sums
@@ -166,6 +189,7 @@ hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* tabl
 hipError_t launch_batch_reduce(const double* partials, const int* inst_block0, int n_inst, int nb, int mode,
                                double* mu, int M, int step, const double* invD, hipStream_t s);
 
+#endif  // PV_RTC
 }  // namespace pv
 
 namespace pv {
@@ -181,6 +205,7 @@ namespace pv {
 // B_{-e_j} = -(t/2)(G1 - i G_{j+1}), B_{+e_j} = B_{-e_j}^H, E0 = m G1.
 struct PatTI {
     static constexpr int FAMILY = FAM_TI, NO = 4, NT = 6, DIM = 3;
+    static constexpr bool SIDE_HALO = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CR, CZ, CZ, CI}, {CZ, CR, CI, CZ}, {CZ, CI, CR, CZ}, {CI, CZ, CZ, CR}},
@@ -196,6 +221,7 @@ struct PatTI {
 // Two-site honeycomb on an (i, j) grid: A(s) <- B(s), B(s - e_i), B(s - e_j).
 struct PatGraphene2 {
     static constexpr int FAMILY = FAM_GRAPHENE2, NO = 2, NT = 4, DIM = 2;
+    static constexpr bool SIDE_HALO = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CZ, CR}, {CZ, CZ}}, {{CZ, CZ}, {CR, CZ}},
@@ -208,6 +234,7 @@ struct PatGraphene2 {
 // B_{-y} = T_y, B_{+y} = T_y^T, E0 = T_n (chain 0-1-2-3).
 struct PatGraphene4 {
     static constexpr int FAMILY = FAM_GRAPHENE4, NO = 4, NT = 4, DIM = 2;
+    static constexpr bool SIDE_HALO = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CZ, CZ, CZ, CZ}, {CR, CZ, CZ, CZ}, {CZ, CZ, CZ, CR}, {CZ, CZ, CZ, CZ}},
@@ -222,6 +249,7 @@ struct PatGraphene4 {
 // B_{-z} = (sigma_x + i sigma_z)/2 (and their adjoints), E0 = -sigma_x(2 + cos k0).
 struct PatWeyl {
     static constexpr int FAMILY = FAM_WEYL, NO = 2, NT = 6, DIM = 3;
+    static constexpr bool SIDE_HALO = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CZ, CR}, {CR, CZ}}, {{CZ, CR}, {CR, CZ}},

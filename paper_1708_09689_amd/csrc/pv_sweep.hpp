@@ -31,11 +31,13 @@
 // the same XCD shortly before (same L2).
 #include "pv_kernels.hpp"
 
+#ifndef PV_RTC
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
 #include <utility>
+#endif
 
 namespace pv {
 namespace {
@@ -45,10 +47,15 @@ struct alignas(2 * sizeof(T)) cplx {
     T re, im;
 };
 
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+
 template <int N, int I = 0, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
     if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
+        f(IntC<I>{});
         sfor<N, I + 1>(f);
     }
 }
@@ -165,7 +172,7 @@ __device__ __forceinline__ T field_at(const KArgs<T, VT>& a, int64_t i) {
 // in each row o (q[o] = its column, -1 if the row has fewer).
 template <class P>
 struct Slots {
-    static constexpr int MAX = 96;
+    static constexpr int MAX = MAX_SLOTS_K;
     int n = 0;
     int t[MAX] = {};
     unsigned char kind[MAX] = {};
@@ -204,8 +211,8 @@ struct Slots {
 };
 
 // Generic family descriptor: NO orbitals, runtime offsets, dense blocks.
-// SH: the staged kernel loads the side rows with the x halo (stencils with
-// hops that have a y and an x step).
+// SH (every pattern's SIDE_HALO): the staged kernel loads the side rows with
+// the x halo (stencils with hops that have a y and an x step).
 template <int NO_, bool SH = false>
 struct PatGeneric {
     static constexpr int FAMILY = FAM_GENERIC, NO = NO_, NT = 0, DIM = 3;
@@ -216,10 +223,7 @@ struct PatGeneric {
 
 template <class P>
 constexpr bool side_halo() {
-    if constexpr (P::FAMILY == FAM_GENERIC)
-        return P::SIDE_HALO;
-    else
-        return false;
+    return P::SIDE_HALO;
 }
 
 template <typename T>
@@ -720,8 +724,8 @@ struct StagedSet {
     int64_t vrow;     // first field entry of the set's row
 };
 
-// Side rows hold the tile, or for generic stencils with hops that have a y
-// and an x step the tile with the one-site x halo of ring rows.
+// Side rows hold the tile, or for stencils with hops that have a y and an x
+// step (P::SIDE_HALO) the tile with the one-site x halo of ring rows.
 template <class P, typename T, int E, int NT>
 struct StagedSide {
     static constexpr int NTR = P::DIM == 3 ? 2 : 0;
@@ -1108,8 +1112,14 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                                 if constexpr (dx < 0) v = zero_unless(xlo, v);
                                 if constexpr (dx > 0) v = zero_unless(xhi, v);
                             } else {
-                                static_assert(dx == 0 && dw == 0, "side rows carry no x or w offset");
-                                v = cx.tra[(dm < 0 ? 0 : S::TW) + l + dqj];
+                                // side rows start at the tile, or one site
+                                // before it in the instance with the halo
+                                constexpr bool HALO = Ctx::Side::HALO;
+                                static_assert(dw == 0, "side rows carry no w offset");
+                                static_assert(dx == 0 || HALO, "x steps on side rows need their halo");
+                                v = cx.tra[(dm < 0 ? 0 : Ctx::Side::SLEN) + (HALO ? site : 0) + l + dx * site + dqj];
+                                if constexpr (dx < 0) v = zero_unless(xlo, v);
+                                if constexpr (dx > 0) v = zero_unless(xhi, v);
                             }
                         }
                         mac<T>(hr, hi, SL.kind[jx], cre[jx], cim[jx], v);
@@ -1197,6 +1207,7 @@ void staged_kernel(KArgs<T, VT> a) {
     staged_block<P, T, VT, E, EPM, NT>(a, b, p8 ? (b & 7) : 0, p8 ? (b >> 3) : b, p8 ? (g >> 3) : g);
 }
 
+#ifndef PV_RTC
 // Tiles per workgroup: enough workgroups to keep every CU busy for several
 // rounds (>= 32 per CU), at most 64 tiles each (fewer workgroups also means
 // fewer partial dot products to reduce).  PV_TILES_PER_BLOCK overrides it
@@ -1594,8 +1605,10 @@ hipError_t launch_batch_sweep_fam(const SweepParams& p, int staged, const void* 
     });
 }
 
+#endif  // PV_RTC
 }  // namespace
 
+#ifndef PV_RTC
 // One translation unit per family (pv_fam_*.hip) defines these.
 #define PV_FAMILY_ENTRY_POINTS(name)                                                                          \
     hipError_t launch_sweep_##name(SweepParams& p, int num_cus, hipStream_t s);                              \
@@ -1609,5 +1622,6 @@ PV_FAMILY_ENTRY_POINTS(graphene4)
 PV_FAMILY_ENTRY_POINTS(weyl)
 PV_FAMILY_ENTRY_POINTS(generic)
 #undef PV_FAMILY_ENTRY_POINTS
+#endif
 
 }  // namespace pv

@@ -325,3 +325,85 @@ def test_dos_of_non_finite_moments_is_an_error(lib):
             pv.pv_kpm_dos(mu, np.linspace(-1, 1, 5), 7.0, 0.0)
         assert e.value.status == 7
         assert b"not finite" in lib.pv_last_error()
+
+
+def _pattern_fields(text):
+    """Offsets, entry codes and flags of a generated pattern struct's text."""
+    head = re.search(r"NO = (\d+), NT = (\d+), DIM = (\d+);", text)
+    no, nt, dim = (int(v) for v in head.groups())
+    halo = re.search(r"SIDE_HALO = (true|false);", text).group(1) == "true"
+    offs = re.search(r"off\[\d+\]\[3\] = \{(.*)\};", text).group(1)
+    offsets = [tuple(int(v) for v in m) for m in re.findall(r"\{(-?\d+), (-?\d+), (-?\d+)\}", offs)]
+    codes = re.findall(r"\b(C[ZRIC])\b", text.split("code[")[1])
+    kinds = np.array([{"CZ": 0, "CR": 1, "CI": 2, "CC": 3}[c] for c in codes]).reshape(nt + 1, no, no)
+    return no, nt, dim, halo, offsets[:nt], kinds
+
+
+def _entry_kind(z):
+    return 0 if z == 0 else (1 if z.imag == 0 else (2 if z.real == 0 else 3))
+
+
+@pytest.mark.parametrize("dim,per_hops,halo", [
+    (3, [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0)], True),    # y steps with x steps: halo side rows
+    (3, [(1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1)], False),
+    (3, [(0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], False),   # direct kernel only
+    (2, [(1, 1, 0), (-1, -1, 0)], False),
+])
+def test_generated_pattern_states_the_stencil_structure(lib, dim, per_hops, halo):
+    """The pattern struct generated for a generic stencil lists its offsets in
+    descriptor order and, per block entry, the zero / real / imaginary /
+    complex kind of the value the lattice holds (on-site block last); the
+    side-row halo flag is set exactly when an offset has both a y and an x
+    step on a 3D lattice."""
+    g = np.random.default_rng(5)
+    no = 2
+    base = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0)] + ([(0, 0, 1), (0, 0, -1)] if dim == 3 else [])
+    offsets, blocks = [], []
+    for o in base + per_hops:
+        if tuple(-v for v in o) in offsets:
+            continue
+        B = np.array([[1.0, 0.5j], [0.0, -0.3 + 0.2j]]) * g.choice([1.0, -0.5])
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.2, 0.1 - 0.4j], [0.1 + 0.4j, -0.1]])
+    st = {"dim": dim, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    L = (6, 5, 4) if dim == 3 else (6, 5)
+    lat = pv.Lattice(L, (1, 1, 1), st)
+    assert lat.family == 0
+    assert pv.pv_lattice_get_codegen(lat)
+    NO, NT, DIM, HALO, offs, kinds = _pattern_fields(pv.pv_lattice_codegen_source(lat))
+    assert (NO, NT, DIM, HALO) == (no, len(offsets), dim, halo)
+    assert offs == [tuple(o) for o in offsets]
+    for t, B in enumerate(blocks + [E0]):
+        for o in range(no):
+            for q in range(no):
+                assert kinds[t, o, q] == _entry_kind(B[o, q]), (t, o, q)
+    pv.pv_lattice_set_codegen(lat, False)
+    assert not pv.pv_lattice_get_codegen(lat)
+    pv.pv_lattice_set_codegen(lat, True)
+    assert pv.pv_lattice_get_codegen(lat)
+
+
+def test_generated_pattern_availability(lib):
+    """Built-in families have no generated pattern; a stencil whose block rows
+    need more per-lane slots than a kernel holds (26 dense complex 4x4
+    blocks: 104 slots) keeps the interpreted kernels; bad arguments fail."""
+    ti = pv.Lattice((4, 4, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0]))
+    assert ti.family == 1 and not pv.pv_lattice_get_codegen(ti)
+    with pytest.raises(pv.PvError, match="built-in family"):
+        pv.pv_lattice_codegen_source(ti)
+    g = np.random.default_rng(9)
+    offsets, blocks = [], []
+    for o in [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1) if (dx, dy, dz) > (0, 0, 0)]:
+        B = g.standard_normal((4, 4)) + 1j * g.standard_normal((4, 4))
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    st = {"dim": 3, "n_orb": 4, "offsets": np.array(offsets), "blocks": np.array(blocks),
+          "onsite": np.eye(4, dtype=np.complex128), "pot_mode": pv.PV_POT_SITE}
+    dense = pv.Lattice((3, 3, 3), (1, 1, 1), st)
+    assert dense.family == 0 and not pv.pv_lattice_get_codegen(dense)
+    with pytest.raises(pv.PvError, match="slots"):
+        pv.pv_lattice_codegen_source(dense)
+    assert lib.pv_lattice_set_codegen(ti.handle, 2) == 1
+    assert lib.pv_lattice_get_codegen(None, None) == 1

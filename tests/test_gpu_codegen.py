@@ -1,0 +1,166 @@
+"""GPU parity of the generated stencil kernels (Sec. 3.2: kernels generated
+from a stencil's own block structure, compiled at run time) against the
+oracle on the explicit matrix of the same stencil, and against the
+interpreted generic kernels.
+
+Stencils: the TI plus next-nearest-neighbour hops -(t'/2) G1 (t' = 0.1)
+along (+-1, 0, +-1) (staged), along (+-1, +-1, 0) (staged with halo side
+rows) and along (0, +-1, +-1) (a y step with a z step: direct kernel), and a
+2D two-orbital stencil with complex blocks and diagonal hops (staged along y,
+which the interpreted generic path never takes).
+
+Tolerances: complex128 1e-13 relative to max|y| (the generated kernels sum a
+row's terms in slot order, the oracle in matrix order); complex64 vectors
+2e-6 relative (FP32 stencil arithmetic, as for the built-in families)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1708_09689_amd as pv  # noqa: E402
+from oracle import chebtp, kpm, spmmv  # noqa: E402
+import workloads as W  # noqa: E402
+
+from gpu_common import dev, host, rel_err  # noqa: E402
+from test_gpu_sweep import _explicit_matrix  # noqa: E402
+
+G1 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
+NNN = {
+    "xz": [(1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1)],
+    "xy": [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0)],
+    "yz": [(0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)],
+}
+
+
+def stencil(name):
+    """(stencil dict, offsets, blocks, on-site block) of a test stencil."""
+    if name == "2d":
+        g = np.random.default_rng(17)
+        offsets, blocks = [], []
+        for o in [(1, 0, 0), (0, 1, 0), (1, 1, 0), (1, -1, 0)]:
+            B = (g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))) * np.array([[1, 0], [1, 1]])
+            offsets += [o, tuple(-v for v in o)]
+            blocks += [B, B.conj().T]
+        E0 = np.array([[0.3, 0.2 - 0.5j], [0.2 + 0.5j, -0.1]])
+        dim, no = 2, 2
+    else:
+        ti = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+        offsets = [tuple(int(v) for v in o) for o in np.asarray(ti["offsets"]).reshape(-1, 3)] + NNN[name]
+        blocks = list(np.asarray(ti["blocks"]).reshape(-1, 4, 4)) + [-0.05 * G1] * 4
+        E0 = np.asarray(ti["onsite"]).reshape(4, 4)
+        dim, no = 3, 4
+    st = {"dim": dim, "n_orb": no, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    return st, offsets, blocks, E0
+
+
+class GenCase:
+    def __init__(self, name, L, per, vdtype=np.float64, seed=3):
+        self.st, offsets, blocks, E0 = stencil(name)
+        self.lat = pv.Lattice(L, per, self.st)
+        assert self.lat.family == 0 and pv.pv_lattice_get_codegen(self.lat)
+        n_sites = int(np.prod(L))
+        V = W.uniform_potential(n_sites, 1.0, W.generator(seed, W.STREAM_POTENTIAL)).astype(vdtype)
+        self.lat.set_potential(dev(V))
+        self.ol, self.H = _explicit_matrix(L, per, self.st["n_orb"], offsets, blocks, E0, V.astype(np.float64), False)
+        self.D = self.ol.n_rows
+
+
+CASES = [("xz", (13, 6, 5), (1, 1, 1)), ("xy", (11, 7, 4), (0, 1, 1)), ("yz", (9, 6, 5), (1, 0, 1)),
+         ("2d", (37, 9), (0, 1))]
+
+
+@pytest.mark.parametrize("name,L,per", CASES)
+@pytest.mark.parametrize("dtype,nb", [(np.complex128, 1), (np.complex128, 4), (np.complex128, 16),
+                                      (np.complex64, 16)])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_generated_step_matches_oracle_and_interpreted(name, L, per, dtype, nb, kernel):
+    """Chebyshev step with dots, y = alpha (H - beta) x + gamma z, on the
+    generated kernels (direct, or staged where the offsets allow it) against
+    the oracle; then the same launch on the interpreted generic kernels."""
+    c = GenCase(name, L, per, np.float64 if dtype == np.complex128 else np.float32)
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    pv.pv_lattice_set_tuning(c.lat, code, nb, {"kernel": kernel})
+    x = W.gaussian_block(c.D, nb, W.generator(4, 2, nb), dtype)
+    z = W.gaussian_block(c.D, nb, W.generator(4, 3, nb), dtype)
+    x64, z64 = x.astype(np.complex128), z.astype(np.complex128)
+    ref = spmmv.spmmv(c.H, x64, 0.4, 0.2, -1.0, z64)
+    tol = 1e-13 if dtype == np.complex128 else 2e-6
+    outs = []
+    for gen in (True, False):
+        pv.pv_lattice_set_codegen(c.lat, gen)
+        assert pv.pv_lattice_get_codegen(c.lat) == gen
+        y = dev(z.copy())
+        d = host(pv.pv_spmmv(c.lat, dev(x), y, 0.4, 0.2, -1.0, z=y, dot_flags=7))
+        out = host(y).astype(np.complex128)
+        assert rel_err(out, ref) < tol, gen
+        xx = np.sum(np.abs(x64) ** 2, axis=0)
+        assert np.abs(d[:, 0] - xx).max() < (1e-12 if dtype == np.complex128 else 1e-5) * xx.max()
+        outs.append(out)
+    assert rel_err(outs[0], outs[1]) < tol
+
+
+@pytest.mark.parametrize("name,L,per", CASES)
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+def test_generated_512_lane_shapes(name, L, per, dtype):
+    """The longer tiles of the built-in families (512-lane workgroups, two
+    complex128 or four complex64 elements per lane) on generated kernels:
+    Chebyshev step with dots, the series step and the plain sweep without z
+    (for the yz stencil, which only the direct kernel takes, the shape falls
+    back to it)."""
+    c = GenCase(name, L, per, np.float64 if dtype == np.complex128 else np.float32, seed=8)
+    nb = 8
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    pv.pv_lattice_set_tuning(c.lat, code, nb, {"kernel": 2, "elems_per_lane": 2 if dtype == np.complex128 else 4,
+                                               "workgroup_size": 512})
+    tol = 1e-13 if dtype == np.complex128 else 2e-6
+    x = W.gaussian_block(c.D, nb, W.generator(9, 2), dtype)
+    z = W.gaussian_block(c.D, nb, W.generator(9, 3), dtype)
+    x64, z64 = x.astype(np.complex128), z.astype(np.complex128)
+    y = dev(z.copy())
+    pv.pv_spmmv(c.lat, dev(x), y, 0.7, -0.1, -1.0, z=y, dot_flags=7)
+    assert rel_err(host(y).astype(np.complex128), spmmv.spmmv(c.H, x64, 0.7, -0.1, -1.0, z64)) < tol
+    y = dev(np.full(x.shape, np.nan, dtype=dtype))
+    pv.pv_spmmv(c.lat, dev(x), y, 0.5, 0.3, 0.0)
+    out = host(y).astype(np.complex128)
+    assert np.isfinite(out).all()
+    assert rel_err(out, spmmv.spmmv(c.H, x64, 0.5, 0.3, 0.0)) < tol
+    a = float(np.abs(c.H).sum(axis=1).max()) * 1.05
+    coef = W.generator(9, 4).standard_normal(9) + 1j * W.generator(9, 5).standard_normal(9)
+    Y = torch.empty(x.shape, dtype=torch.complex128 if dtype == np.complex128 else torch.complex64, device="cuda")
+    pv.pv_cheb_series(c.lat, dev(x), Y, a, 0.1, coef)
+    ref = chebtp.cheb_series(c.H, x64, a, 0.1, coef)
+    assert rel_err(host(Y).astype(np.complex128), ref) < (1e-12 if dtype == np.complex128 else 2e-5)
+
+
+@pytest.mark.parametrize("name,L,per", CASES[:3])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_generated_per_column_coefficients(name, L, per, kernel):
+    """Per-column alpha, beta, gamma take the kernels that read their
+    epilogue at run time (one complex128 element per lane)."""
+    c = GenCase(name, L, per, seed=11)
+    nb = 4
+    pv.pv_lattice_set_tuning(c.lat, pv.PV_C128, nb, {"kernel": kernel, "elems_per_lane": 2})
+    g = W.generator(11, 7)
+    alpha, beta, gamma = 0.5 + g.random(nb), g.standard_normal(nb), g.standard_normal(nb)
+    x = W.gaussian_block(c.D, nb, W.generator(11, 2))
+    z = W.gaussian_block(c.D, nb, W.generator(11, 3))
+    y = dev(z.copy())
+    pv.pv_spmmv(c.lat, dev(x), y, alpha, beta, gamma, z=y, dot_flags=7)
+    assert rel_err(host(y), spmmv.spmmv(c.H, x, alpha, beta, gamma, z)) < 1e-13
+
+
+@pytest.mark.parametrize("name,L,per", [CASES[1], CASES[2], CASES[3]])
+def test_generated_kpm_moments(name, L, per):
+    """KPM moments (Chebyshev steps with fused dots, the reduction folded into
+    the next sweep) on the generated kernels against the oracle's moments by
+    the product doubling on the explicit matrix."""
+    c = GenCase(name, L, per, seed=13)
+    nb, M = 4, 48
+    a = float(np.abs(c.H).sum(axis=1).max()) * 1.05
+    r = W.random_phase_block(c.D, nb, W.generator(13, 2))
+    mu = pv.pv_kpm_moments(c.lat, dev(r), M, a, 0.05)
+    ref = kpm.moments_doubling(c.H, r, M, a, 0.05)
+    assert np.abs(host(mu) - ref).max() < 1e-12
