@@ -589,9 +589,10 @@ def bench_dsl(pv, torch, W, dev, nb=16):
     family) and the TI plus next-nearest-neighbour hops -(t'/2) G1, t' = 0.1,
     along (+-1, 0, +-1), along (+-1, +-1, 0) and along (0, +-1, +-1) (no
     compiled family).  Those run on kernels generated from the stencil's
-    pattern (staged for the first two, direct for the third, which has y
-    steps with z steps), each in the launch shape the autotuner picks, and
-    on the interpreted generic kernels in their default shape."""
+    pattern (staged: the third stages its side rows at z -+ 1 as well), each
+    in the launch shape the autotuner picks, and on the interpreted generic
+    kernels in their default shape (staged for the first two, direct for the
+    third)."""
     ti = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
     G1 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
     h = -0.05 * G1

@@ -155,7 +155,17 @@ bool try_family(pv_lattice& l) {
     return true;
 }
 
-int generic_side_halo(const pv_lattice* l);
+// Side rows a generated 3D pattern stages: with the x halo when some offset
+// has a y and an x step, at w -+ 1 too when some offset has a y and a z step.
+void codegen_side_flags(const pv_lattice& l, bool& halo, bool& sidew) {
+    halo = sidew = false;
+    if (l.dim != 3) return;
+    for (int t = 0; t < l.n_terms; ++t) {
+        const int* d = &l.offsets[3 * t];
+        halo = halo || (d[1] != 0 && d[0] != 0);
+        sidew = sidew || (d[1] != 0 && d[2] != 0);
+    }
+}
 
 // Pattern struct of a generic stencil for its generated kernels (Sec. 3.2:
 // the DSL's code generation), in the form of the built-in families: the
@@ -187,7 +197,10 @@ std::string codegen_pattern(const pv_lattice& l) {
     std::string s = "struct PatCG {\n";
     s += "    static constexpr int FAMILY = FAM_CODEGEN, NO = " + std::to_string(NO) + ", NT = " + std::to_string(NT) +
          ", DIM = " + std::to_string(l.dim) + ";\n";
-    s += std::string("    static constexpr bool SIDE_HALO = ") + (generic_side_halo(&l) ? "true" : "false") + ";\n";
+    bool halo, sidew;
+    codegen_side_flags(l, halo, sidew);
+    s += std::string("    static constexpr bool SIDE_HALO = ") + (halo ? "true" : "false") +
+         ", SIDE_W = " + (sidew ? "true" : "false") + ";\n";
     s += "    static constexpr int off[" + std::to_string(std::max(NT, 1)) + "][3] = {";
     for (int t = 0; t < std::max(NT, 1); ++t) {
         const int* d = NT ? &l.offsets[3 * t] : nullptr;
@@ -378,9 +391,12 @@ pv::SweepParams base_params(const pv_lattice* l, int dtype, int nb) {
     p.generic_stageable = generic_stageable(l);
     p.generic_side_halo = generic_side_halo(l);
     if (uses_codegen(l)) {
+        bool halo, sidew;
+        codegen_side_flags(*l, halo, sidew);
         p.cg_src = l->cg_src.c_str();
         p.cg_dim = l->dim;
-        p.cg_halo = p.generic_side_halo;
+        p.cg_halo = halo;
+        p.cg_sidew = sidew;
     }
     return p;
 }
@@ -1607,7 +1623,7 @@ extern "C" pv_status pv_autotune(pv_lattice* l, int dtype, int nb, const char* c
     };
     hipError_t herr = hipSuccess;
     const bool cg = uses_codegen(l);
-    const bool compiled = l->family != pv::FAM_GENERIC || generic_stageable(l) || (cg && l->dim == 2);
+    const bool compiled = l->family != pv::FAM_GENERIC || generic_stageable(l) || cg;
     const int lw = int(l->dim == 3 ? l->L[2] : l->L[1]);
     // coordinate search: 1. kernel, elements per lane and lanes per workgroup
     // at default shapes;

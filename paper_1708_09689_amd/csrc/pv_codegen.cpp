@@ -36,11 +36,11 @@ thread_local std::string g_err;
 
 // Host stand-in of a generated pattern: the launch set-up (kernel arguments,
 // walk and strip layout, LDS size) depends only on the orbitals, the lattice
-// dimension and the side rows' x halo.
-template <int NO_, int DIM_, bool SH>
+// dimension and the side rows (x halo, rows at w -+ 1).
+template <int NO_, int DIM_, bool SH, bool SW>
 struct PatShape {
     static constexpr int FAMILY = FAM_CODEGEN, NO = NO_, NT = 0, DIM = DIM_;
-    static constexpr bool SIDE_HALO = SH;
+    static constexpr bool SIDE_HALO = SH, SIDE_W = SW;
     static constexpr int off[1][3] = {{0, 0, 0}};
     static constexpr unsigned char code[1][NO_][NO_] = {};
 };
@@ -195,6 +195,15 @@ hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t
     return hipSuccess;
 }
 
+// LDS bytes a workgroup may use on the current device.
+size_t max_lds() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return size_t(v);
+}
+
 template <typename T>
 const char* tname() {
     return sizeof(T) == 8 ? "double" : "float";
@@ -227,14 +236,24 @@ hipError_t staged_go(SweepParams& p, int num_cus, hipStream_t s, unsigned epm) {
 template <class P, typename T, typename VT, int E>
 hipError_t staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
     constexpr unsigned KPM = EP_STORE_Y | EP_DOTS, SERIES = EP_STORE_Y | EP_ACC_ADD, PLAIN = EP_STORE_Y;
+    constexpr int E0 = sizeof(T) == 8 ? 1 : 2;
+    if constexpr (E != E0) {
+        // a tile whose rows (six side rows with SIDE_W) overflow the CU's LDS
+        // takes the shortest tile instead
+        if (staged_lds_bytes_for<P, T, E, kBlock>(true) > max_lds() ||
+            (p.st_nt == 512 && staged_lds_bytes_for<P, T, E, 512>(true) > max_lds()))
+            return staged_ep<P, T, VT, E0>(p, num_cus, s);
+    }
     if (p.colp == nullptr) {
         unsigned epm = 0u;
         if (p.ep == KPM) epm = KPM;
         else if (p.ep == SERIES) epm = SERIES;
         else if (p.ep == PLAIN) epm = p.gamma == 0.0 ? (PLAIN | EP_NO_Z) : PLAIN;
-        if (epm != 0u)
-            return p.st_nt == 512 ? staged_go<P, T, VT, E, 512>(p, num_cus, s, epm)
-                                  : staged_go<P, T, VT, E, kBlock>(p, num_cus, s, epm);
+        if (epm != 0u) {
+            if (p.st_nt == 512 && staged_lds_bytes_for<P, T, E, 512>(true) <= max_lds())
+                return staged_go<P, T, VT, E, 512>(p, num_cus, s, epm);
+            return staged_go<P, T, VT, E, kBlock>(p, num_cus, s, epm);
+        }
     }
     if constexpr (sizeof(T) == 8 && E == 2) {
         SweepParams q = p;
@@ -247,18 +266,18 @@ hipError_t staged_ep(SweepParams& p, int num_cus, hipStream_t s) {
     }
 }
 
-// Kernel choice of a built-in family: staged when the pattern allows it (2D,
-// or 3D with no offset that has both a y and a z step), the block is 16-byte
-// aligned in whole chunks per site and the launch asks for it or is large;
-// else the direct kernel.
+// Kernel choice of a built-in family: staged when the block is 16-byte
+// aligned in whole chunks per site and the launch asks for it or is large
+// (every generated pattern stages: 3D stencils with hops that have a y and a
+// z step take six side rows, (m -+ 1, w) and (m -+ 1, w -+ 1)); else the
+// direct kernel.
 template <class P, typename T, typename VT>
 hipError_t typed(SweepParams& p, int num_cus, hipStream_t s) {
     static const int env_kernel = env_int("PV_SWEEP", 0);
     const int kind = p.kernel > 0 ? p.kernel : env_kernel;
     const bool aligned = ((reinterpret_cast<uintptr_t>(p.x) | reinterpret_cast<uintptr_t>(p.zero_row)) & 15) == 0;
-    const bool can = P::DIM == 2 || p.generic_stageable;
     const bool whole = (P::NO * p.nb * int(sizeof(cplx<T>))) % 16 == 0;
-    if (can && aligned && whole && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && staged_default(p)))) {
+    if (aligned && whole && P::NO * p.nb <= STAGED_MAX_SITE && (kind == 2 || (kind == 0 && staged_default(p)))) {
         const int e = staged_elems(p);
         if constexpr (sizeof(T) == 8)
             return e == 2 ? staged_ep<P, T, VT, 2>(p, num_cus, s) : staged_ep<P, T, VT, 1>(p, num_cus, s);
@@ -276,9 +295,9 @@ hipError_t typed(SweepParams& p, int num_cus, hipStream_t s) {
     return hipModuleLaunchKernel(c.fn, unsigned(p.grid), 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
 }
 
-template <int NO, int DIM, bool SH>
+template <int NO, int DIM, bool SH, bool SW>
 hipError_t by_types(SweepParams& p, int num_cus, hipStream_t s) {
-    using P = PatShape<NO, DIM, SH>;
+    using P = PatShape<NO, DIM, SH, SW>;
     if (p.dtype == 0) {
         if (p.vtype != 0) return hipErrorInvalidValue;
         return typed<P, double, double>(p, num_cus, s);
@@ -289,8 +308,10 @@ hipError_t by_types(SweepParams& p, int num_cus, hipStream_t s) {
 
 template <int NO>
 hipError_t by_shape(SweepParams& p, int num_cus, hipStream_t s) {
-    if (p.cg_dim == 2) return by_types<NO, 2, false>(p, num_cus, s);
-    return p.cg_halo ? by_types<NO, 3, true>(p, num_cus, s) : by_types<NO, 3, false>(p, num_cus, s);
+    if (p.cg_dim == 2) return by_types<NO, 2, false, false>(p, num_cus, s);
+    if (p.cg_sidew)
+        return p.cg_halo ? by_types<NO, 3, true, true>(p, num_cus, s) : by_types<NO, 3, false, true>(p, num_cus, s);
+    return p.cg_halo ? by_types<NO, 3, true, false>(p, num_cus, s) : by_types<NO, 3, false, false>(p, num_cus, s);
 }
 
 }  // namespace

@@ -104,9 +104,9 @@ struct SweepParams {
     double red_invD;
     // generated kernels (generic stencils): source of the stencil's pattern
     // struct pv::PatCG, NULL for the interpreted generic kernels; its
-    // lattice dimension and whether side rows need the x halo
+    // lattice dimension and side-row flags (x halo, rows at w -+ 1)
     const char* cg_src;
-    int cg_dim, cg_halo;
+    int cg_dim, cg_halo, cg_sidew;   // cg_sidew: some offset has a y and a z step
 };
 
 // Number of workgroups a sweep of an nb-wide block over the lattice uses
@@ -205,7 +205,7 @@ namespace pv {
 // B_{-e_j} = -(t/2)(G1 - i G_{j+1}), B_{+e_j} = B_{-e_j}^H, E0 = m G1.
 struct PatTI {
     static constexpr int FAMILY = FAM_TI, NO = 4, NT = 6, DIM = 3;
-    static constexpr bool SIDE_HALO = false;
+    static constexpr bool SIDE_HALO = false, SIDE_W = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CR, CZ, CZ, CI}, {CZ, CR, CI, CZ}, {CZ, CI, CR, CZ}, {CI, CZ, CZ, CR}},
@@ -221,7 +221,7 @@ struct PatTI {
 // Two-site honeycomb on an (i, j) grid: A(s) <- B(s), B(s - e_i), B(s - e_j).
 struct PatGraphene2 {
     static constexpr int FAMILY = FAM_GRAPHENE2, NO = 2, NT = 4, DIM = 2;
-    static constexpr bool SIDE_HALO = false;
+    static constexpr bool SIDE_HALO = false, SIDE_W = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CZ, CR}, {CZ, CZ}}, {{CZ, CZ}, {CR, CZ}},
@@ -234,7 +234,7 @@ struct PatGraphene2 {
 // B_{-y} = T_y, B_{+y} = T_y^T, E0 = T_n (chain 0-1-2-3).
 struct PatGraphene4 {
     static constexpr int FAMILY = FAM_GRAPHENE4, NO = 4, NT = 4, DIM = 2;
-    static constexpr bool SIDE_HALO = false;
+    static constexpr bool SIDE_HALO = false, SIDE_W = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CZ, CZ, CZ, CZ}, {CR, CZ, CZ, CZ}, {CZ, CZ, CZ, CR}, {CZ, CZ, CZ, CZ}},
@@ -249,7 +249,7 @@ struct PatGraphene4 {
 // B_{-z} = (sigma_x + i sigma_z)/2 (and their adjoints), E0 = -sigma_x(2 + cos k0).
 struct PatWeyl {
     static constexpr int FAMILY = FAM_WEYL, NO = 2, NT = 6, DIM = 3;
-    static constexpr bool SIDE_HALO = false;
+    static constexpr bool SIDE_HALO = false, SIDE_W = false;
     static constexpr int off[NT][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
     static constexpr unsigned char code[NT + 1][NO][NO] = {
         {{CZ, CR}, {CR, CZ}}, {{CZ, CR}, {CR, CZ}},

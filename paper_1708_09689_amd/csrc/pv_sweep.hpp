@@ -216,7 +216,7 @@ struct Slots {
 template <int NO_, bool SH = false>
 struct PatGeneric {
     static constexpr int FAMILY = FAM_GENERIC, NO = NO_, NT = 0, DIM = 3;
-    static constexpr bool SIDE_HALO = SH;
+    static constexpr bool SIDE_HALO = SH, SIDE_W = false;
     static constexpr int off[1][3] = {{0, 0, 0}};
     static constexpr unsigned char code[1][NO_][NO_] = {};   // no compiled slots
 };
@@ -717,7 +717,6 @@ __device__ __forceinline__ u32x4 ld_chunk_nt(const void* base, uint32_t boff) {
 template <class P, typename T, typename VT, int E, int NT>
 struct StagedSet {
     using S = Staged<T, E, NT>;
-    static constexpr int NTR = P::DIM == 3 ? 2 : 0;
     u32x4 ring[S::RCH];
     u32x4 z[S::TCH];
     VT v[E];          // stored field entries (converted when handed to LDS)
@@ -725,10 +724,15 @@ struct StagedSet {
 };
 
 // Side rows hold the tile, or for stencils with hops that have a y and an x
-// step (P::SIDE_HALO) the tile with the one-site x halo of ring rows.
+// step (P::SIDE_HALO) the tile with the one-site x halo of ring rows.  They
+// are the rows (m -+ 1, w), and for stencils with hops that have a y and a z
+// step (P::SIDE_W) also (m -+ 1, w -+ 1): side row idx(dm, dw).
 template <class P, typename T, int E, int NT>
 struct StagedSide {
-    static constexpr int NTR = P::DIM == 3 ? 2 : 0;
+    static constexpr int NTR = P::DIM == 3 ? (P::SIDE_W ? 6 : 2) : 0;
+    __host__ __device__ static constexpr int idx(int dm, int dw) {
+        return (dm < 0 ? 0 : 1) + (P::SIDE_W ? 2 * (dw + 1) : 0);
+    }
     static constexpr bool HALO = side_halo<P>();
     static constexpr int SCH = HALO ? Staged<T, E, NT>::RCH : Staged<T, E, NT>::TCH;   // chunks per lane
     static constexpr int SLEN = HALO ? Staged<T, E, NT>::RCH * NT * Staged<T, E, NT>::CE
@@ -743,7 +747,7 @@ struct StagedCtx {
     using S = Staged<T, E, NT>;
     using Set = StagedSet<P, T, VT, E, NT>;
     using Side = StagedSide<P, T, E, NT>;
-    static constexpr int NTR = Set::NTR;
+    static constexpr int NTR = Side::NTR;
     const KArgs<T, VT>& a;
     cplx<T>* ring;   // [3][seg]
     cplx<T>* tra;    // [NTR][Side::SLEN]
@@ -831,7 +835,8 @@ struct StagedCtx {
 #pragma unroll
         for (int k = 0; k < E; ++k) st.v[k] = vp[voff[k]];
     }
-    // Side rows (m -+ 1, w_row), w_row clamped to the walk (3D lattices).
+    // Side rows (m -+ 1, w_row) (and (m -+ 1, w_row -+ 1) for SIDE_W),
+    // w_row clamped to the walk (3D lattices).
     __device__ __forceinline__ void issue_side(Side& sd, int w_row) const {
         if constexpr (ACC) {
             const int wr = w_row < wb ? w_row : wb - 1;
@@ -843,7 +848,7 @@ struct StagedCtx {
             const int wr = w_row < wb ? w_row : wb - 1;
 #pragma unroll
             for (int h = 0; h < NTR; ++h) {
-                const cplx<T>* sp = row_ptr(m + (h == 0 ? -1 : 1), wr);
+                const cplx<T>* sp = row_ptr(m + ((h & 1) ? 1 : -1), wr + (P::SIDE_W ? (h >> 1) - 1 : 0));
                 if constexpr (Side::HALO) {
 #pragma unroll
                     for (int k = 0; k < Side::SCH; ++k) sd.side[h][k] = ld_chunk<T>(sp, roff[k]);
@@ -913,7 +918,7 @@ __host__ __device__ constexpr int staged_seg() {
 }
 template <class P, typename T, int E, int NT>
 __host__ __device__ constexpr size_t staged_table_offset(bool acc) {
-    return (size_t(3 * staged_seg<T, E, NT>() + (P::DIM == 3 ? 2 : 0) * StagedSide<P, T, E, NT>::SLEN +
+    return (size_t(3 * staged_seg<T, E, NT>() + StagedSide<P, T, E, NT>::NTR * StagedSide<P, T, E, NT>::SLEN +
                    (1 + (acc ? 1 : 0)) * Staged<T, E, NT>::TW) *
                 Staged<T, E, NT>::ES +
             size_t(E * NT) * sizeof(T) + 15) / 16 * 16;
@@ -1115,9 +1120,10 @@ __device__ __forceinline__ void staged_block(const KArgs<T, VT>& a, int b_out, i
                                 // side rows start at the tile, or one site
                                 // before it in the instance with the halo
                                 constexpr bool HALO = Ctx::Side::HALO;
-                                static_assert(dw == 0, "side rows carry no w offset");
+                                static_assert(dw == 0 || P::SIDE_W, "side rows at w -+ 1 need SIDE_W");
                                 static_assert(dx == 0 || HALO, "x steps on side rows need their halo");
-                                v = cx.tra[(dm < 0 ? 0 : Ctx::Side::SLEN) + (HALO ? site : 0) + l + dx * site + dqj];
+                                constexpr int h = Ctx::Side::idx(dm, dw);
+                                v = cx.tra[h * Ctx::Side::SLEN + (HALO ? site : 0) + l + dx * site + dqj];
                                 if constexpr (dx < 0) v = zero_unless(xlo, v);
                                 if constexpr (dx > 0) v = zero_unless(xhi, v);
                             }

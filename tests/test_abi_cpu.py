@@ -331,7 +331,8 @@ def _pattern_fields(text):
     """Offsets, entry codes and flags of a generated pattern struct's text."""
     head = re.search(r"NO = (\d+), NT = (\d+), DIM = (\d+);", text)
     no, nt, dim = (int(v) for v in head.groups())
-    halo = re.search(r"SIDE_HALO = (true|false);", text).group(1) == "true"
+    flags = re.search(r"SIDE_HALO = (true|false), SIDE_W = (true|false);", text)
+    halo = (flags.group(1) == "true", flags.group(2) == "true")
     offs = re.search(r"off\[\d+\]\[3\] = \{(.*)\};", text).group(1)
     offsets = [tuple(int(v) for v in m) for m in re.findall(r"\{(-?\d+), (-?\d+), (-?\d+)\}", offs)]
     codes = re.findall(r"\b(C[ZRIC])\b", text.split("code[")[1])
@@ -344,17 +345,19 @@ def _entry_kind(z):
 
 
 @pytest.mark.parametrize("dim,per_hops,halo", [
-    (3, [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0)], True),    # y steps with x steps: halo side rows
-    (3, [(1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1)], False),
-    (3, [(0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], False),   # direct kernel only
-    (2, [(1, 1, 0), (-1, -1, 0)], False),
+    (3, [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0)], (True, False)),   # y with x steps: halo side rows
+    (3, [(1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1)], (False, False)),
+    (3, [(0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], (False, True)),   # y with z steps: rows at w -+ 1
+    (3, [(1, 1, 1), (-1, -1, -1)], (True, True)),
+    (2, [(1, 1, 0), (-1, -1, 0)], (False, False)),
 ])
 def test_generated_pattern_states_the_stencil_structure(lib, dim, per_hops, halo):
     """The pattern struct generated for a generic stencil lists its offsets in
     descriptor order and, per block entry, the zero / real / imaginary /
-    complex kind of the value the lattice holds (on-site block last); the
-    side-row halo flag is set exactly when an offset has both a y and an x
-    step on a 3D lattice."""
+    complex kind of the value the lattice holds (on-site block last); on a 3D
+    lattice the side-row halo flag is set exactly when an offset has both a y
+    and an x step, the flag for side rows at w -+ 1 exactly when one has both
+    a y and a z step."""
     g = np.random.default_rng(5)
     no = 2
     base = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0)] + ([(0, 0, 1), (0, 0, -1)] if dim == 3 else [])

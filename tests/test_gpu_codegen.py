@@ -4,10 +4,11 @@ oracle on the explicit matrix of the same stencil, and against the
 interpreted generic kernels.
 
 Stencils: the TI plus next-nearest-neighbour hops -(t'/2) G1 (t' = 0.1)
-along (+-1, 0, +-1) (staged), along (+-1, +-1, 0) (staged with halo side
-rows) and along (0, +-1, +-1) (a y step with a z step: direct kernel), and a
-2D two-orbital stencil with complex blocks and diagonal hops (staged along y,
-which the interpreted generic path never takes).
+along (+-1, 0, +-1), along (+-1, +-1, 0) (halo side rows), along
+(0, +-1, +-1) (y steps with z steps: side rows at w -+ 1 as well) and along
++-(1, 1, 1) with +-(1, -1, 0) (both), and a 2D two-orbital stencil with
+complex blocks and diagonal hops.  The staged kernel takes all of them on
+the generated path; the interpreted generic path stages only the first two.
 
 Tolerances: complex128 1e-13 relative to max|y| (the generated kernels sum a
 row's terms in slot order, the oracle in matrix order); complex64 vectors
@@ -31,6 +32,7 @@ NNN = {
     "xz": [(1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1)],
     "xy": [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0)],
     "yz": [(0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)],
+    "xyz": [(1, 1, 1), (-1, -1, -1), (1, -1, 0), (-1, 1, 0)],
 }
 
 
@@ -69,7 +71,7 @@ class GenCase:
 
 
 CASES = [("xz", (13, 6, 5), (1, 1, 1)), ("xy", (11, 7, 4), (0, 1, 1)), ("yz", (9, 6, 5), (1, 0, 1)),
-         ("2d", (37, 9), (0, 1))]
+         ("xyz", (10, 5, 6), (0, 1, 0)), ("2d", (37, 9), (0, 1))]
 
 
 @pytest.mark.parametrize("name,L,per", CASES)
@@ -108,8 +110,8 @@ def test_generated_512_lane_shapes(name, L, per, dtype):
     """The longer tiles of the built-in families (512-lane workgroups, two
     complex128 or four complex64 elements per lane) on generated kernels:
     Chebyshev step with dots, the series step and the plain sweep without z
-    (for the yz stencil, which only the direct kernel takes, the shape falls
-    back to it)."""
+    (where six side rows would overflow the LDS, the launch takes the
+    shortest tile instead)."""
     c = GenCase(name, L, per, np.float64 if dtype == np.complex128 else np.float32, seed=8)
     nb = 8
     code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
@@ -135,7 +137,7 @@ def test_generated_512_lane_shapes(name, L, per, dtype):
     assert rel_err(host(Y).astype(np.complex128), ref) < (1e-12 if dtype == np.complex128 else 2e-5)
 
 
-@pytest.mark.parametrize("name,L,per", CASES[:3])
+@pytest.mark.parametrize("name,L,per", CASES[:4])
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_generated_per_column_coefficients(name, L, per, kernel):
     """Per-column alpha, beta, gamma take the kernels that read their
@@ -152,7 +154,7 @@ def test_generated_per_column_coefficients(name, L, per, kernel):
     assert rel_err(host(y), spmmv.spmmv(c.H, x, alpha, beta, gamma, z)) < 1e-13
 
 
-@pytest.mark.parametrize("name,L,per", [CASES[1], CASES[2], CASES[3]])
+@pytest.mark.parametrize("name,L,per", CASES[1:])
 def test_generated_kpm_moments(name, L, per):
     """KPM moments (Chebyshev steps with fused dots, the reduction folded into
     the next sweep) on the generated kernels against the oracle's moments by
