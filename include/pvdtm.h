@@ -248,6 +248,10 @@ pv_status pv_spmmv(pv_lattice *lat, int dtype, int nb, const void *x, const void
  *     behind; calls that overlap on one GPU (several streams or host threads)
  *     race, so the caller serialises them.  Per-column (non-uniform) alpha,
  *     beta, gamma synchronise the stream, as in pv_spmmv.
+ *   - Generic stencils (generated kernels, see pv_lattice_set_codegen) take
+ *     a generated kernel only when an earlier call on this GPU loaded that
+ *     instance, else the interpreted generic kernel: compiling and loading
+ *     one allocates.
  */
 #define PV_NOALLOC_SCRATCH_BYTES (64 << 20)
 pv_status pv_spmmv_noalloc(pv_lattice *lat, int dtype, int nb, const void *x, const void *z, void *y,

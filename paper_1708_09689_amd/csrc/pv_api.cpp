@@ -824,10 +824,11 @@ pv_status spmmv_check(pv_lattice* l, int dtype, int nb, const void* x, const voi
 
 pv_status spmmv_launch(pv_lattice* l, int dtype, int nb, const void* x, const void* z, void* y, const double* alpha,
                        const double* beta, const double* gamma, unsigned dot_flags, double* dots, bool uniform,
-                       bool need_z, double* partials, double* colp, hipStream_t s) {
+                       bool need_z, double* partials, double* colp, hipStream_t s, bool no_compile = false) {
     pv_status st;
     pv::SweepParams p = base_params(l, dtype, nb);
     if ((st = fill_traversal(l, dtype, nb, p)) != PV_OK) return st;
+    p.cg_nocompile = no_compile ? 1 : 0;
     p.x = x;
     p.z = need_z ? z : nullptr;
     p.y = y;
@@ -867,9 +868,11 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
     if (work_bytes < need || (!work && need)) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
     if ((st = ensure_device(l)) != PV_OK) return st;
     char* w = static_cast<char*>(work);
+    // a generated kernel is taken only when an earlier call loaded it (loading
+    // a code object allocates), else the interpreted generic one
     return spmmv_launch(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z,
                         reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb)),
-                        static_cast<hipStream_t>(stream));
+                        static_cast<hipStream_t>(stream), true);
 }
 
 // ---------------------------------------------------------------------------
@@ -927,9 +930,11 @@ extern "C" pv_status pv_spmmv_noalloc(pv_lattice* l, int dtype, int nb, const vo
     void* ptr = nullptr;
     if ((st = scratch_of_device(dev, &ptr)) != PV_OK) return st;
     char* w = static_cast<char*>(ptr);
+    // a generated kernel is taken only when an earlier call loaded it (loading
+    // a code object allocates), else the interpreted generic one
     return spmmv_launch(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z,
                         reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb)),
-                        static_cast<hipStream_t>(stream));
+                        static_cast<hipStream_t>(stream), true);
 }
 
 // ---------------------------------------------------------------------------

@@ -160,9 +160,10 @@ bool build(const std::string& pat, const std::string& expr, const std::string& a
 }
 
 // The loaded kernel for (current device, pattern, instance), compiled on
-// first use.  nt and lds: the launch's workgroup and LDS size (for the
-// occupancy that sizes staged grids).
-hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t lds, Compiled& out) {
+// first use (nocompile: hipErrorNotReady instead).  nt and lds: the launch's
+// workgroup and LDS size (for the occupancy that sizes staged grids).
+hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t lds, bool nocompile,
+                        Compiled& out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -173,6 +174,7 @@ hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t
         out = it->second;
         return hipSuccess;
     }
+    if (nocompile) return hipErrorNotReady;
     g_err.clear();
     std::string lowered;
     std::vector<char> code;
@@ -195,12 +197,18 @@ hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t
     return hipSuccess;
 }
 
-// LDS bytes a workgroup may use on the current device.
+// LDS bytes a workgroup may use on the current device (asked once per device).
 size_t max_lds() {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-        return 65536;
+    static std::mutex mu;
+    static std::map<int, size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    cache[dev] = size_t(v);
     return size_t(v);
 }
 
@@ -220,7 +228,7 @@ hipError_t staged_go(SweepParams& p, int num_cus, hipStream_t s, unsigned epm) {
     std::snprintf(expr, sizeof expr, "&pv::staged_kernel<pv::PatCG, %s, %s, %d, %uu, %d>", tname<T>(), tname<VT>(),
                   E, epm, NT);
     Compiled c;
-    if (const hipError_t e = function_for(p.cg_src, expr, NT, lds, c); e != hipSuccess) return e;
+    if (const hipError_t e = function_for(p.cg_src, expr, NT, lds, p.cg_nocompile != 0, c); e != hipSuccess) return e;
     int G8 = p.st_G8 > 0 ? p.st_G8 : (num_cus >= 8 ? num_cus / 8 : 1) * c.occ;
     if (G8 > 256) G8 = 256;
     G8 = staged_setup<P, T, VT, E, NT>(p, G8, false, a);
@@ -290,7 +298,7 @@ hipError_t typed(SweepParams& p, int num_cus, hipStream_t s) {
     char expr[128];
     std::snprintf(expr, sizeof expr, "&pv::sweep_kernel<pv::PatCG, %s, %s>", tname<T>(), tname<VT>());
     Compiled c;
-    if (const hipError_t e = function_for(p.cg_src, expr, kBlock, 0, c); e != hipSuccess) return e;
+    if (const hipError_t e = function_for(p.cg_src, expr, kBlock, 0, p.cg_nocompile != 0, c); e != hipSuccess) return e;
     void* args[] = {&a};
     return hipModuleLaunchKernel(c.fn, unsigned(p.grid), 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
 }

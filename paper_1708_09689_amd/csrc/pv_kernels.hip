@@ -480,7 +480,12 @@ hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s) {
         case FAM_GRAPHENE2: return launch_sweep_graphene2(p, num_cus, s);
         case FAM_GRAPHENE4: return launch_sweep_graphene4(p, num_cus, s);
         case FAM_WEYL: return launch_sweep_weyl(p, num_cus, s);
-        default: return p.cg_src ? launch_codegen(p, num_cus, s) : launch_sweep_generic(p, num_cus, s);
+        default:
+            if (p.cg_src) {
+                const hipError_t e = launch_codegen(p, num_cus, s);
+                if (e != hipErrorNotReady || !p.cg_nocompile) return e;
+            }
+            return launch_sweep_generic(p, num_cus, s);
     }
 }
 

@@ -107,6 +107,7 @@ struct SweepParams {
     // lattice dimension and side-row flags (x halo, rows at w -+ 1)
     const char* cg_src;
     int cg_dim, cg_halo, cg_sidew;   // cg_sidew: some offset has a y and a z step
+    int cg_nocompile;   // take a generated kernel only if loaded (else the interpreted one)
 };
 
 // Number of workgroups a sweep of an nb-wide block over the lattice uses
@@ -117,7 +118,8 @@ hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s);
 // Sweep of a generic stencil with kernels generated from its pattern
 // (p.cg_src) and compiled at run time on first use (pv_codegen.cpp).  A
 // failed compilation returns hipErrorInvalidImage and leaves the compiler's
-// message in codegen_error() (this thread).
+// message in codegen_error() (this thread); with p.cg_nocompile an instance
+// not loaded yet returns hipErrorNotReady without compiling.
 hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s);
 const char* codegen_error();
 void codegen_clear_error();

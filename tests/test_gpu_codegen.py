@@ -166,3 +166,34 @@ def test_generated_kpm_moments(name, L, per):
     mu = pv.pv_kpm_moments(c.lat, dev(r), M, a, 0.05)
     ref = kpm.moments_doubling(c.H, r, M, a, 0.05)
     assert np.abs(host(mu) - ref).max() < 1e-12
+
+
+def test_generated_kernels_replay_in_a_captured_graph():
+    """A sweep on generated kernels captured into a graph (after an eager call
+    compiled and loaded the instance) replays correctly, several times, with
+    eager work on the same buffers between the replays."""
+    c = GenCase("xy", (11, 7, 4), (0, 1, 1), seed=21)
+    nb = 4
+    xh = W.gaussian_block(c.D, nb, W.generator(21, 2))
+    x = dev(xh)
+    y = torch.empty_like(x)
+    dots = torch.empty((nb, 4), dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pv.pv_spmmv(c.lat, x, y, 0.5, 0.1, 0.0, dot_flags=7, dots=dots)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager_y, eager_d = host(y).copy(), host(dots).copy()
+    assert rel_err(eager_y, spmmv.spmmv(c.H, xh, 0.5, 0.1, 0.0)) < 1e-13
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pv.pv_spmmv(c.lat, x, y, 0.5, 0.1, 0.0, dot_flags=7, dots=dots)
+    for k in range(3):
+        y.fill_(float("nan"))
+        dots.fill_(float("nan"))
+        pv.pv_spmmv(c.lat, x, torch.empty_like(x), 1.0, 0.0, 0.0)   # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(y), eager_y), k
+        assert np.array_equal(host(dots), eager_d), k

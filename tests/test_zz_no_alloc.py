@@ -73,3 +73,56 @@ def test_noalloc_sweep_needs_device_tables_and_bounds_scratch():
     pv.pv_spmmv(c.lat, x, torch.empty_like(x), 1.0, 0.0, 0.0)
     pv.pv_spmmv_noalloc(c.lat, x, y, 1.0, 0.0, 0.0)
     assert rel_err(host(y), spmmv.spmmv(c.H, host(x), 1.0, 0.0, 0.0)) < 1e-13
+
+
+def _generic_case(seed, L, per):
+    """A two-orbital generic stencil (no built-in family) with diagonal hops,
+    its lattice with a site field, and the oracle's explicit matrix."""
+    from test_gpu_sweep import _explicit_matrix
+    g = np.random.default_rng(seed)
+    offsets, blocks = [], []
+    for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, -1)]:
+        B = (g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))) * (g.random((2, 2)) < 0.7)
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.2, 0.1 - 0.3j], [0.1 + 0.3j, -0.4]])
+    st = {"dim": 3, "n_orb": 2, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    lat = pv.Lattice(L, per, st)
+    assert lat.family == 0 and pv.pv_lattice_get_codegen(lat)
+    V = W.uniform_potential(int(np.prod(L)), 1.0, W.generator(seed, 1))
+    lat.set_potential(dev(V))
+    _, H = _explicit_matrix(L, per, 2, offsets, blocks, E0, V, False)
+    return lat, H
+
+
+def test_noalloc_generic_stencil_takes_loaded_generated_kernels_only():
+    """Generic stencils: the allocation-free sweep takes a generated kernel
+    only when an earlier call on the GPU loaded that instance (bitwise equal
+    to pv_spmmv then), else the interpreted kernel (same result up to the
+    summation order), and never compiles."""
+    nb = 4
+    lat, H = _generic_case(41, (12, 6, 5), (1, 1, 0))
+    D = H.shape[0]
+    x = W.gaussian_block(D, nb, W.generator(41, 2))
+    z = W.gaussian_block(D, nb, W.generator(41, 3))
+    ref = spmmv.spmmv(H, x, 0.3, 0.2, -1.0, z)
+    # loaded: pv_spmmv with the same arguments first
+    y_ref = dev(z.copy())
+    d_ref = pv.pv_spmmv(lat, dev(x), y_ref, 0.3, 0.2, -1.0, z=y_ref, dot_flags=7)
+    y = dev(z.copy())
+    dots = torch.full((nb, 4), float("nan"), dtype=torch.float64, device="cuda")
+    pv.pv_spmmv_noalloc(lat, dev(x), y, 0.3, 0.2, -1.0, z=y, dot_flags=7, dots=dots)
+    assert np.array_equal(host(y), host(y_ref))
+    assert np.array_equal(host(dots), host(d_ref))
+    assert rel_err(host(y), ref) < 1e-13
+    # not loaded: another pattern whose only earlier sweep had another epilogue
+    lat2, H2 = _generic_case(43, (9, 7, 6), (0, 1, 1))
+    D2 = H2.shape[0]
+    x2 = W.gaussian_block(D2, nb, W.generator(43, 2))
+    z2 = W.gaussian_block(D2, nb, W.generator(43, 3))
+    pv.pv_spmmv(lat2, dev(x2), torch.empty((D2, nb), dtype=torch.complex128, device="cuda"), 1.0, 0.0, 0.0)
+    y2 = dev(z2.copy())
+    pv.pv_spmmv_noalloc(lat2, dev(x2), y2, 0.3, 0.2, -1.0, z=y2, dot_flags=7, dots=dots)
+    assert rel_err(host(y2), spmmv.spmmv(H2, x2, 0.3, 0.2, -1.0, z2)) < 1e-13
+    assert np.isfinite(host(dots)).all()
