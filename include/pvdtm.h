@@ -603,6 +603,10 @@ pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tun
 pv_status pv_lattice_set_codegen(pv_lattice *lat, int enable);
 pv_status pv_lattice_get_codegen(const pv_lattice *lat, int *active);
 pv_status pv_lattice_codegen_source(const pv_lattice *lat, char *buf, size_t len, size_t *needed);
+/* Number of generated kernel instances compiled (or read from the cache) and
+ * loaded in this process, over all devices: an instance is one kernel for
+ * one pattern, launch shape and epilogue. */
+int pv_codegen_instances(void);
 
 /*
  * Autotuner: times candidate shapes of one Chebyshev step (sweep with fused

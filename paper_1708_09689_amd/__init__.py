@@ -116,6 +116,7 @@ SIGNATURES = {
     "pv_lattice_set_codegen": (_i, [_vp, _i]),
     "pv_lattice_get_codegen": (_i, [_vp, _ip]),
     "pv_lattice_codegen_source": (_i, [_vp, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
+    "pv_codegen_instances": (_i, []),
     "pv_autotune_workspace_size": (_sz, [_vp, _i, _i]),
     "pv_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p, _vp, _sz, _vp, ctypes.POINTER(pv_tuning), _dp]),
 }
@@ -559,6 +560,11 @@ def pv_lattice_get_codegen(lat) -> bool:
     v = ctypes.c_int()
     _check(lib().pv_lattice_get_codegen(lat.handle, ctypes.byref(v)))
     return bool(v.value)
+
+
+def pv_codegen_instances() -> int:
+    """Generated kernel instances loaded in this process."""
+    return int(lib().pv_codegen_instances())
 
 
 def pv_lattice_codegen_source(lat) -> str:

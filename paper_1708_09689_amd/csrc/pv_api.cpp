@@ -868,11 +868,9 @@ extern "C" pv_status pv_spmmv(pv_lattice* l, int dtype, int nb, const void* x, c
     if (work_bytes < need || (!work && need)) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
     if ((st = ensure_device(l)) != PV_OK) return st;
     char* w = static_cast<char*>(work);
-    // a generated kernel is taken only when an earlier call loaded it (loading
-    // a code object allocates), else the interpreted generic one
     return spmmv_launch(l, dtype, nb, x, z, y, alpha, beta, gamma, dot_flags, dots, uniform, need_z,
                         reinterpret_cast<double*>(w), reinterpret_cast<double*>(w + partial_bytes(l, nb)),
-                        static_cast<hipStream_t>(stream), true);
+                        static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -1512,6 +1510,8 @@ extern "C" pv_status pv_lattice_get_codegen(const pv_lattice* l, int* active) {
     *active = uses_codegen(l) ? 1 : 0;
     return PV_OK;
 }
+
+extern "C" int pv_codegen_instances(void) { return pv::codegen_instances(); }
 
 extern "C" pv_status pv_lattice_codegen_source(const pv_lattice* l, char* buf, size_t len, size_t* needed) {
     if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");

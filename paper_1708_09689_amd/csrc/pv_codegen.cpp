@@ -76,12 +76,13 @@ std::string device_arch() {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
-// Cache file: the kernel's symbol name on the first line, then the code object.
+// Cache file: the kernel's symbol name on the first line, then the code object
+// (an ELF file; anything else is a miss).
 bool read_cached(const std::string& path, std::string& lowered, std::vector<char>& code) {
     std::ifstream f(path, std::ios::binary);
     if (!f || !std::getline(f, lowered) || lowered.empty()) return false;
     code.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
-    return !code.empty();
+    return code.size() > 64 && std::memcmp(code.data(), "\x7f" "ELF", 4) == 0;
 }
 
 void write_cached(const std::string& path, const std::string& lowered, const std::vector<char>& code) {
@@ -96,11 +97,13 @@ void write_cached(const std::string& path, const std::string& lowered, const std
     std::rename(tmp.c_str(), path.c_str());
 }
 
-// Code object and symbol of the instance `expr` for the pattern.
-bool build(const std::string& pat, const std::string& expr, const std::string& arch, std::string& lowered,
-           std::vector<char>& code) {
+// Code object and symbol of the instance `expr` for the pattern; *cached
+// says whether they came from the on-disk cache (use_cache: look there).
+bool build(const std::string& pat, const std::string& expr, const std::string& arch, bool use_cache,
+           std::string& lowered, std::vector<char>& code, bool* cached) {
     const std::string src = "#include \"pv_sweep.hpp\"\n\nnamespace pv {\n\n" + pat + "\n}  // namespace pv\n";
     std::string path;
+    *cached = false;
     if (const char* dir = std::getenv("PV_CODEGEN_CACHE"); dir && *dir) {
         uint64_t h = 14695981039346656037ull;
         h = fnv1a(h, arch);
@@ -112,7 +115,10 @@ bool build(const std::string& pat, const std::string& expr, const std::string& a
         char name[64];
         std::snprintf(name, sizeof name, "/pvcg_%016llx.co", static_cast<unsigned long long>(h));
         path = std::string(dir) + name;
-        if (read_cached(path, lowered, code)) return true;
+        if (use_cache && read_cached(path, lowered, code)) {
+            *cached = true;
+            return true;
+        }
     }
     hiprtcProgram prog;
     const char* hdrs[2] = {kRtcKernelsHpp, kRtcSweepHpp};
@@ -176,19 +182,29 @@ hipError_t function_for(const char* pat, const std::string& expr, int nt, size_t
     }
     if (nocompile) return hipErrorNotReady;
     g_err.clear();
-    std::string lowered;
-    std::vector<char> code;
-    if (!build(pat, expr, device_arch(), lowered, code)) return hipErrorInvalidImage;
+    const std::string arch = device_arch();
     Compiled c;
-    if ((e = hipModuleLoadData(&c.mod, code.data())) != hipSuccess) {
-        g_err = "hipModuleLoadData of " + expr + ": " + hipGetErrorString(e);
-        return e;
+    // a cached code object that does not load (a damaged file) is compiled again
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        std::string lowered;
+        std::vector<char> code;
+        bool cached = false;
+        if (!build(pat, expr, arch, attempt == 0, lowered, code, &cached)) return hipErrorInvalidImage;
+        e = hipModuleLoadData(&c.mod, code.data());
+        if (e == hipSuccess) {
+            e = hipModuleGetFunction(&c.fn, c.mod, lowered.c_str());
+            if (e == hipSuccess) break;
+            (void)hipModuleUnload(c.mod);
+            c.mod = nullptr;
+            g_err = "hipModuleGetFunction " + lowered + ": " + hipGetErrorString(e);
+        } else {
+            g_err = "hipModuleLoadData of " + expr + ": " + hipGetErrorString(e);
+        }
+        if (!cached) return e;
+        (void)hipGetLastError();
     }
-    if ((e = hipModuleGetFunction(&c.fn, c.mod, lowered.c_str())) != hipSuccess) {
-        g_err = "hipModuleGetFunction " + lowered + ": " + hipGetErrorString(e);
-        (void)hipModuleUnload(c.mod);
-        return e;
-    }
+    if (e != hipSuccess) return e;
+    g_err.clear();
     int n = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&n, c.fn, nt, lds) != hipSuccess || n < 1) n = 1;
     c.occ = n;
@@ -336,6 +352,11 @@ hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s) {
 }
 
 const char* codegen_error() { return g_err.c_str(); }
+
+int codegen_instances() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return int(g_fns.size());
+}
 void codegen_clear_error() { g_err.clear(); }
 
 }  // namespace pv

@@ -123,6 +123,8 @@ hipError_t launch_sweep(SweepParams& p, int num_cus, hipStream_t s);
 hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s);
 const char* codegen_error();
 void codegen_clear_error();
+// Generated kernel instances loaded in this process (all devices).
+int codegen_instances();
 
 // Fixed-order reduction of [grid][nb][4] partials.
 //   mode 0: dots[c][0..3] = sums

@@ -94,6 +94,7 @@ def test_generated_step_matches_oracle_and_interpreted(name, L, per, dtype, nb, 
     for gen in (True, False):
         pv.pv_lattice_set_codegen(c.lat, gen)
         assert pv.pv_lattice_get_codegen(c.lat) == gen
+        n0 = pv.pv_codegen_instances()
         y = dev(z.copy())
         d = host(pv.pv_spmmv(c.lat, dev(x), y, 0.4, 0.2, -1.0, z=y, dot_flags=7))
         out = host(y).astype(np.complex128)
@@ -101,6 +102,7 @@ def test_generated_step_matches_oracle_and_interpreted(name, L, per, dtype, nb, 
         xx = np.sum(np.abs(x64) ** 2, axis=0)
         assert np.abs(d[:, 0] - xx).max() < (1e-12 if dtype == np.complex128 else 1e-5) * xx.max()
         outs.append(out)
+        assert pv.pv_codegen_instances() >= n0 and (pv.pv_codegen_instances() > 0 or not gen)
     assert rel_err(outs[0], outs[1]) < tol
 
 
@@ -197,3 +199,86 @@ def test_generated_kernels_replay_in_a_captured_graph():
         torch.cuda.synchronize()
         assert np.array_equal(host(y), eager_y), k
         assert np.array_equal(host(dots), eager_d), k
+
+
+_CACHE_RUN = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, {root!r}); sys.path.insert(0, {tests!r})
+import paper_1708_09689_amd as pv, workloads as W
+from test_gpu_codegen import stencil
+st, _, _, _ = stencil("xz")
+st["blocks"] = np.array(st["blocks"]) * 1.0
+st["onsite"] = np.asarray(st["onsite"]) + np.diag([0.01, 0.02, 0.03, 0.04])   # a pattern no other test compiles
+lat = pv.Lattice((9, 6, 5), (1, 1, 1), st)
+x = torch.from_numpy(W.gaussian_block(lat.n_rows, 4, W.generator(77, 2))).cuda()
+y = torch.empty_like(x)
+pv.pv_lattice_set_tuning(lat, pv.PV_C128, 4, {{"kernel": 2}})
+assert pv.pv_lattice_get_codegen(lat)
+pv.pv_spmmv(lat, x, y, 0.5, 0.1, 0.0)
+assert pv.pv_codegen_instances() == 1
+np.save({out!r}, y.cpu().numpy())
+"""
+
+
+def test_codegen_disk_cache_across_processes(tmp_path):
+    """PV_CODEGEN_CACHE keeps generated code objects across processes: the
+    first process writes one, a file that is not a code object is compiled
+    again and replaced, and every process computes the same result."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "cache"
+    cache.mkdir()
+    env = dict(os.environ, PV_CODEGEN_CACHE=str(cache))
+    outs = []
+    for k in range(3):
+        out = str(tmp_path / f"y{k}.npy")
+        code = _CACHE_RUN.format(root=root, tests=os.path.join(root, "tests"), out=out)
+        r = subprocess.run([sys.executable, "-c", code], env=env, timeout=150, capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr
+        outs.append(np.load(out))
+        files = sorted(cache.glob("pvcg_*.co"))
+        assert len(files) == 1, (k, sorted(p.name for p in cache.iterdir()), r.stderr[-2000:])
+        body = files[0].read_bytes()
+        assert b"\x7fELF" in body[:512]
+        if k == 0:
+            files[0].write_bytes(b"not a code object\n" + b"x" * 100)   # damaged entry: compiled again
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_sweeps_compile_each_generated_instance_once():
+    """The first sweep of a pattern, launch shape and epilogue compiles and
+    loads one generated instance; repeating it, or running the interpreted
+    kernels, loads none; another epilogue loads one more."""
+    g = np.random.default_rng(99)
+    offsets, blocks = [], []
+    for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)]:
+        B = (g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))) * np.array([[1, 1], [0, 1]])
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.5, 0.25j], [-0.25j, 0.0]])
+    st = {"dim": 3, "n_orb": 2, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    L, per = (10, 6, 5), (1, 0, 1)
+    lat = pv.Lattice(L, per, st)
+    V = W.uniform_potential(int(np.prod(L)), 1.0, W.generator(99, 1))
+    lat.set_potential(dev(V))
+    _, H = _explicit_matrix(L, per, 2, offsets, blocks, E0, V, False)
+    nb = 2
+    pv.pv_lattice_set_tuning(lat, pv.PV_C128, nb, {"kernel": 2})
+    xh = W.gaussian_block(H.shape[0], nb, W.generator(99, 2))
+    x, y = dev(xh), torch.empty((H.shape[0], nb), dtype=torch.complex128, device="cuda")
+    n0 = pv.pv_codegen_instances()
+    pv.pv_spmmv(lat, x, y, 0.5, 0.1, 0.0)
+    assert pv.pv_codegen_instances() == n0 + 1
+    assert rel_err(host(y), spmmv.spmmv(H, xh, 0.5, 0.1, 0.0)) < 1e-13
+    pv.pv_spmmv(lat, x, y, 0.5, 0.1, 0.0)
+    assert pv.pv_codegen_instances() == n0 + 1
+    pv.pv_lattice_set_codegen(lat, False)
+    pv.pv_spmmv(lat, x, y, 0.5, 0.1, 0.0)
+    assert pv.pv_codegen_instances() == n0 + 1
+    pv.pv_lattice_set_codegen(lat, True)
+    dots = torch.empty((nb, 4), dtype=torch.float64, device="cuda")
+    pv.pv_spmmv(lat, x, y, 0.5, 0.1, 0.0, dot_flags=7, dots=dots)   # the Chebyshev-step epilogue
+    assert pv.pv_codegen_instances() == n0 + 2

@@ -107,12 +107,15 @@ def test_noalloc_generic_stencil_takes_loaded_generated_kernels_only():
     x = W.gaussian_block(D, nb, W.generator(41, 2))
     z = W.gaussian_block(D, nb, W.generator(41, 3))
     ref = spmmv.spmmv(H, x, 0.3, 0.2, -1.0, z)
-    # loaded: pv_spmmv with the same arguments first
+    # loaded: pv_spmmv with the same arguments first (compiles the instance)
+    n0 = pv.pv_codegen_instances()
     y_ref = dev(z.copy())
     d_ref = pv.pv_spmmv(lat, dev(x), y_ref, 0.3, 0.2, -1.0, z=y_ref, dot_flags=7)
+    assert pv.pv_codegen_instances() == n0 + 1
     y = dev(z.copy())
     dots = torch.full((nb, 4), float("nan"), dtype=torch.float64, device="cuda")
     pv.pv_spmmv_noalloc(lat, dev(x), y, 0.3, 0.2, -1.0, z=y, dot_flags=7, dots=dots)
+    assert pv.pv_codegen_instances() == n0 + 1
     assert np.array_equal(host(y), host(y_ref))
     assert np.array_equal(host(dots), host(d_ref))
     assert rel_err(host(y), ref) < 1e-13
@@ -123,6 +126,8 @@ def test_noalloc_generic_stencil_takes_loaded_generated_kernels_only():
     z2 = W.gaussian_block(D2, nb, W.generator(43, 3))
     pv.pv_spmmv(lat2, dev(x2), torch.empty((D2, nb), dtype=torch.complex128, device="cuda"), 1.0, 0.0, 0.0)
     y2 = dev(z2.copy())
+    n1 = pv.pv_codegen_instances()
     pv.pv_spmmv_noalloc(lat2, dev(x2), y2, 0.3, 0.2, -1.0, z=y2, dot_flags=7, dots=dots)
+    assert pv.pv_codegen_instances() == n1   # nothing compiled
     assert rel_err(host(y2), spmmv.spmmv(H2, x2, 0.3, 0.2, -1.0, z2)) < 1e-13
     assert np.isfinite(host(dots)).all()
