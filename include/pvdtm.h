@@ -586,8 +586,8 @@ pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tun
  * z step take the direct kernel, others the staged one as the built-in
  * families do (with 512-lane workgroups available to the autotuner).
  * A failed compilation returns PV_ERR_HIP with the compiler's log in
- * pv_last_error().  The batched sweeps (pv_batch_*) keep the interpreted
- * kernels.
+ * pv_last_error().  Batched sweeps (pv_batch_*) take generated kernels when
+ * all their lattices share one pattern.
  *
  * set_codegen: enable (1, the default) or disable (0: the interpreted
  * generic kernels, which read every entry's column and value at run time)
@@ -634,7 +634,10 @@ pv_status pv_autotune(pv_lattice *lat, int dtype, int nb, const char *cache_path
  * workgroups of its own).  Unset, a batch takes lattice 0's kernel and
  * elements per lane with 256-lane workgroups.  Setting or resetting (t ==
  * NULL) drops the captured graph.  512-lane workgroups need a compiled
- * stencil family (PV_ERR_UNSUPPORTED otherwise).
+ * stencil family or generated kernels (PV_ERR_UNSUPPORTED otherwise).  A
+ * batch of generic-stencil lattices takes generated kernels (compiled
+ * before its graph is captured) when every lattice has them enabled and
+ * all share one pattern; otherwise the interpreted direct kernel.
  *
  * pv_batch_autotune times the candidate shapes -- the direct kernel; the
  * staged kernel with each elements-per-lane value and 256 or 512 lanes --

@@ -2323,10 +2323,20 @@ pv_tuning batch_shape(const pv_batch* B, int dtype, int nb) {
     return t;
 }
 
+// A batch of generic-stencil lattices takes generated kernels when every
+// instance would (set_codegen) and all share one pattern.
+bool batch_codegen(const pv_batch* B) {
+    if (B->family != pv::FAM_GENERIC) return false;
+    for (const pv_lattice* l : B->lats)
+        if (!uses_codegen(l) || l->cg_src != B->lats[0]->cg_src) return false;
+    return true;
+}
+
 // Launch description of instance i of a batch (every instance takes the
 // batch's shape).
 pv::SweepParams batch_params(const pv_batch* B, int i, int dtype, int nb) {
     pv::SweepParams p = base_params(B->lats[i], dtype, nb);
+    if (!batch_codegen(B)) p.cg_src = nullptr;
     p.vtype = (dtype == PV_C128) ? 0 : B->lats[i]->vtype;
     const pv_tuning t = batch_shape(B, dtype, nb);
     p.kernel = t.kernel;
@@ -2340,7 +2350,7 @@ pv::SweepParams batch_params(const pv_batch* B, int i, int dtype, int nb) {
 // block (smaller ones are launch-latency bound).
 bool batch_may_stage(const pv_batch* B, int dtype, int nb) {
     static const char* env = std::getenv("PV_SWEEP");
-    if (B->family == pv::FAM_GENERIC || (env && std::atoi(env) == 1)) return false;
+    if ((B->family == pv::FAM_GENERIC && !batch_codegen(B)) || (env && std::atoi(env) == 1)) return false;
     if (B->n_orb * nb > pv::STAGED_MAX_SITE) return false;
     const int kind = batch_shape(B, dtype, nb).kernel;
     if (kind != 0 || (env && std::atoi(env) == 2)) return kind != 1;
@@ -2476,7 +2486,8 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     const pv_tuning t0 = batch_shape(B, dtype, nb);
     std::vector<uint64_t> key = {(uint64_t)dtype, (uint64_t)nb, (uint64_t)M, (uint64_t)(uintptr_t)work,
                                  (uint64_t)work_bytes, (uint64_t)L.staged, (uint64_t)t0.kernel,
-                                 (uint64_t)t0.elems_per_lane, (uint64_t)t0.workgroup_size};
+                                 (uint64_t)t0.elems_per_lane, (uint64_t)t0.workgroup_size,
+                                 (uint64_t)batch_codegen(B)};
     char* const mu_ws = static_cast<char*>(work) + L.moments;
     const size_t mu_bytes = (size_t)n * nb * M * sizeof(double);
     for (int i = 0; i < n; ++i) {
@@ -2567,6 +2578,8 @@ extern "C" pv_status pv_batch_kpm_moments(pv_batch* B, int dtype, int nb, int M,
     pv::SweepParams p0 = batch_params(B, 0, dtype, nb);
     p0.vtype = vtype;
     p0.ep = pv::EP_STORE_Y | pv::EP_DOTS;
+    // a generated kernel is compiled and loaded before the capture
+    if (p0.cg_src) PV_HIP(pv::codegen_prepare_batch(p0, L.staged));
     PV_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     // one launch per step (each folds in the previous step's moments), then
@@ -2601,8 +2614,9 @@ extern "C" pv_status pv_batch_set_tuning(pv_batch* B, int dtype, int nb, const p
     if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
     if ((st = check_nb(nb)) != PV_OK) return st;
     if (t && (st = check_tuning(dtype, *t)) != PV_OK) return st;
-    if (t && t->workgroup_size == 512 && B->family == pv::FAM_GENERIC)
-        return fail(PV_ERR_UNSUPPORTED, "512-lane batched sweeps need a compiled stencil family");
+    if (t && t->workgroup_size == 512 && B->family == pv::FAM_GENERIC && !batch_codegen(B))
+        return fail(PV_ERR_UNSUPPORTED,
+                    "512-lane batched sweeps need a compiled stencil family or generated kernels of one pattern");
     const int di = dtype == PV_C128 ? 0 : 1, ni = log2_nb(nb);
     pv_tuning z{};
     if (t) {
@@ -2680,7 +2694,7 @@ extern "C" pv_status pv_batch_autotune(pv_batch* B, int dtype, int nb, const dou
         pv_tuning t{};
         t.kernel = 1;
         cand.push_back(t);
-        if (B->family != pv::FAM_GENERIC && B->n_orb * nb <= pv::STAGED_MAX_SITE)
+        if ((B->family != pv::FAM_GENERIC || batch_codegen(B)) && B->n_orb * nb <= pv::STAGED_MAX_SITE)
             for (int wg : {0, 512})
                 for (int e : {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4}) {
                     t = pv_tuning{};

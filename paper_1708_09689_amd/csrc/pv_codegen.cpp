@@ -338,6 +338,51 @@ hipError_t by_shape(SweepParams& p, int num_cus, hipStream_t s) {
     return p.cg_halo ? by_types<NO, 3, true, false>(p, num_cus, s) : by_types<NO, 3, false, false>(p, num_cus, s);
 }
 
+// Calls f(Tag<P>, Tag<T>, Tag<VT>) with the host stand-in of the launch's
+// pattern and its vector and field types.
+template <class F>
+hipError_t with_pattern(const SweepParams& p, F&& f) {
+    auto types = [&](auto pt) -> hipError_t {
+        using P = typename decltype(pt)::type;
+        if (p.dtype == 0) {
+            if (p.vtype != 0) return hipErrorInvalidValue;
+            return f(Tag<P>{}, Tag<double>{}, Tag<double>{});
+        }
+        if (p.vtype == 0) return f(Tag<P>{}, Tag<float>{}, Tag<double>{});
+        return f(Tag<P>{}, Tag<float>{}, Tag<float>{});
+    };
+    auto shape = [&](auto no) -> hipError_t {
+        constexpr int NO = decltype(no)::value;
+        if (p.cg_dim == 2) return types(Tag<PatShape<NO, 2, false, false>>{});
+        if (p.cg_sidew)
+            return p.cg_halo ? types(Tag<PatShape<NO, 3, true, true>>{}) : types(Tag<PatShape<NO, 3, false, true>>{});
+        return p.cg_halo ? types(Tag<PatShape<NO, 3, true, false>>{}) : types(Tag<PatShape<NO, 3, false, false>>{});
+    };
+    switch (p.n_orb) {
+        case 1: return shape(IntC<1>{});
+        case 2: return shape(IntC<2>{});
+        case 4: return shape(IntC<4>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Elements per lane and lanes of a batched staged launch (the Chebyshev step
+// with dots): the batch's shape, or the shortest tile where the LDS would
+// overflow; calls g(IntC<E>, IntC<NT>).
+template <class P, typename T, class G>
+hipError_t batch_tile(const SweepParams& p, G&& g) {
+    constexpr int E0 = sizeof(T) == 8 ? 1 : 2, E1 = 2 * E0;
+    const int e = staged_elems(p);
+    const bool w512 = p.st_nt == 512;
+    auto fits = [](size_t lds) { return lds <= max_lds(); };
+    if (e == E1) {
+        if (w512 && fits(staged_lds_bytes_for<P, T, E1, 512>(false))) return g(IntC<E1>{}, IntC<512>{});
+        if (!w512 && fits(staged_lds_bytes_for<P, T, E1, kBlock>(false))) return g(IntC<E1>{}, IntC<kBlock>{});
+    }
+    if (w512 && fits(staged_lds_bytes_for<P, T, E0, 512>(false))) return g(IntC<E0>{}, IntC<512>{});
+    return g(IntC<E0>{}, IntC<kBlock>{});
+}
+
 }  // namespace
 
 hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s) {
@@ -349,6 +394,83 @@ hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s) {
         case 4: return by_shape<4>(p, num_cus, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Batched sweeps (one launch per step over every instance of a batch whose
+// lattices share one generated pattern): argument records and launches as
+// for the built-in families.
+hipError_t codegen_batch_fill_record(const SweepParams& p, int staged, void* dst, int* nblocks) {
+    return with_pattern(p, [&](auto pt, auto tt, auto vt) -> hipError_t {
+        using P = typename decltype(pt)::type;
+        using T = typename decltype(tt)::type;
+        using VT = typename decltype(vt)::type;
+        static_assert(sizeof(KArgs<T, VT>) == sizeof(KArgs<double, double>), "record sizes differ");
+        KArgs<T, VT> a;
+        if (staged) {
+            if (P::NO * p.nb > STAGED_MAX_SITE || (P::NO * p.nb * int(sizeof(cplx<T>))) % 16 != 0)
+                return hipErrorInvalidValue;
+            make_kargs<P, T, VT>(p, false, a);
+            return batch_tile<P, T>(p, [&](auto ke, auto kn) -> hipError_t {
+                const int G8 = staged_setup<P, T, VT, decltype(ke)::value, decltype(kn)::value>(p, 1 << 30, true, a);
+                std::memcpy(dst, &a, sizeof(a));
+                *nblocks = 8 * G8;
+                return hipSuccess;
+            });
+        }
+        make_kargs<P, T, VT>(p, true, a);
+        std::memcpy(dst, &a, sizeof(a));
+        *nblocks = int((a.ntiles + a.tpb - 1) / a.tpb);
+        return hipSuccess;
+    });
+}
+
+namespace {
+
+// The batched kernel instance of a launch and its LDS bytes, loaded (and
+// compiled on first use unless nocompile).
+hipError_t batch_function(const SweepParams& p, int staged, bool nocompile, Compiled& c, int& nt, size_t& lds) {
+    return with_pattern(p, [&](auto pt, auto tt, auto vt) -> hipError_t {
+        using P = typename decltype(pt)::type;
+        using T = typename decltype(tt)::type;
+        using VT = typename decltype(vt)::type;
+        char expr[160];
+        if (!staged) {
+            std::snprintf(expr, sizeof expr, "&pv::batch_sweep_kernel<pv::PatCG, %s, %s>", tname<T>(), tname<VT>());
+            nt = kBlock;
+            lds = 0;
+            return function_for(p.cg_src, expr, kBlock, 0, nocompile, c);
+        }
+        return batch_tile<P, T>(p, [&](auto ke, auto kn) -> hipError_t {
+            constexpr int E = decltype(ke)::value, NT = decltype(kn)::value;
+            std::snprintf(expr, sizeof expr, "&pv::batch_staged_kernel<pv::PatCG, %s, %s, %d, %uu, %d>", tname<T>(),
+                          tname<VT>(), E, unsigned(EP_STORE_Y | EP_DOTS), NT);
+            nt = NT;
+            lds = staged_lds_bytes_for<P, T, E, NT>(false);
+            return function_for(p.cg_src, expr, NT, lds, nocompile, c);
+        });
+    });
+}
+
+}  // namespace
+
+hipError_t codegen_prepare_batch(const SweepParams& p, int staged) {
+    g_err.clear();
+    Compiled c;
+    int nt = 0;
+    size_t lds = 0;
+    return batch_function(p, staged, false, c, nt, lds);
+}
+
+hipError_t launch_batch_codegen(const SweepParams& p, int staged, const void* table, const int* block_inst,
+                                const int* inst_block0, int grid, int red_step, hipStream_t s) {
+    g_err.clear();
+    if (staged && p.ep != (EP_STORE_Y | EP_DOTS)) return hipErrorInvalidValue;
+    Compiled c;
+    int nt = 0;
+    size_t lds = 0;
+    if (const hipError_t e = batch_function(p, staged, false, c, nt, lds); e != hipSuccess) return e;
+    void* args[] = {&table, &block_inst, &inst_block0, &red_step};
+    return hipModuleLaunchKernel(c.fn, unsigned(grid), 1, 1, unsigned(nt), 1, 1, unsigned(lds), s, args, nullptr);
 }
 
 const char* codegen_error() { return g_err.c_str(); }

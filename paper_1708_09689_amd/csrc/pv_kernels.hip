@@ -657,7 +657,9 @@ hipError_t batch_fill_record(const SweepParams& p, int staged, void* dst, int* n
         case FAM_GRAPHENE2: return batch_fill_record_graphene2(p, staged, dst, nblocks);
         case FAM_GRAPHENE4: return batch_fill_record_graphene4(p, staged, dst, nblocks);
         case FAM_WEYL: return batch_fill_record_weyl(p, staged, dst, nblocks);
-        default: return batch_fill_record_generic(p, staged, dst, nblocks);
+        default:
+            return p.cg_src ? codegen_batch_fill_record(p, staged, dst, nblocks)
+                            : batch_fill_record_generic(p, staged, dst, nblocks);
     }
 }
 
@@ -671,7 +673,9 @@ hipError_t launch_batch_sweep(const SweepParams& p, int staged, const void* tabl
         case FAM_GRAPHENE2: return launch_batch_sweep_graphene2(p, staged, t, bi, i0, grid, red_step, s);
         case FAM_GRAPHENE4: return launch_batch_sweep_graphene4(p, staged, t, bi, i0, grid, red_step, s);
         case FAM_WEYL: return launch_batch_sweep_weyl(p, staged, t, bi, i0, grid, red_step, s);
-        default: return launch_batch_sweep_generic(p, staged, t, bi, i0, grid, red_step, s);
+        default:
+            return p.cg_src ? launch_batch_codegen(p, staged, t, bi, i0, grid, red_step, s)
+                            : launch_batch_sweep_generic(p, staged, t, bi, i0, grid, red_step, s);
     }
 }
 

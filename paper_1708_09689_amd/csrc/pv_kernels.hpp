@@ -125,6 +125,13 @@ const char* codegen_error();
 void codegen_clear_error();
 // Generated kernel instances loaded in this process (all devices).
 int codegen_instances();
+// Batched sweeps of a batch whose instances share one generated pattern
+// (p.cg_src of any instance): records, launches and compiling the launch's
+// instance ahead of a graph capture.
+hipError_t codegen_batch_fill_record(const SweepParams& p, int staged, void* dst, int* nblocks);
+hipError_t launch_batch_codegen(const SweepParams& p, int staged, const void* table, const int* block_inst,
+                                const int* inst_block0, int grid, int red_step, hipStream_t s);
+hipError_t codegen_prepare_batch(const SweepParams& p, int staged);
 
 // Fixed-order reduction of [grid][nb][4] partials.
 //   mode 0: dots[c][0..3] = sums

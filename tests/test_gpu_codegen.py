@@ -282,3 +282,56 @@ def test_sweeps_compile_each_generated_instance_once():
     dots = torch.empty((nb, 4), dtype=torch.float64, device="cuda")
     pv.pv_spmmv(lat, x, y, 0.5, 0.1, 0.0, dot_flags=7, dots=dots)   # the Chebyshev-step epilogue
     assert pv.pv_codegen_instances() == n0 + 2
+
+
+@pytest.mark.parametrize("dtype,shape", [(np.complex128, {"kernel": 1}),
+                                         (np.complex128, {"kernel": 2, "elems_per_lane": 1}),
+                                         (np.complex128, {"kernel": 2, "elems_per_lane": 2, "workgroup_size": 512}),
+                                         (np.complex64, {"kernel": 2, "elems_per_lane": 4, "workgroup_size": 512})])
+def test_batched_kpm_on_generated_kernels(dtype, shape):
+    """A batch of lattices sharing one generated pattern (ragged sizes, the
+    xy stencil with halo side rows) runs its graph-captured KPM on generated
+    kernels, compiled before the capture; every instance equals its oracle
+    run (complex128 1e-12, complex64 vectors with FP64 moments 1e-4), and a
+    replay is bitwise identical."""
+    from oracle import kpm as okpm
+    vd = np.float64 if dtype == np.complex128 else np.float32
+    sizes = [((6, 5, 4), (1, 1, 1)), ((7, 6, 5), (0, 1, 1)), ((5, 5, 5), (1, 1, 0)), ((8, 4, 6), (1, 1, 1))]
+    cases = [GenCase("xy", L, per, vd, seed=60 + i) for i, (L, per) in enumerate(sizes)]
+    nb, M = 8, 24
+    rs = [W.random_phase_block(c.D, nb, W.generator(61, i), dtype) for i, c in enumerate(cases)]
+    a = np.array([float(np.abs(c.H).sum(axis=1).max()) * 1.05 for c in cases])
+    b = np.array([0.0, 0.05, -0.1, 0.02])
+    batch = pv.Batch([c.lat for c in cases])
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    pv.pv_batch_set_tuning(batch, code, nb, shape)
+    n0 = pv.pv_codegen_instances()
+    rd = [dev(r) for r in rs]
+    mu = host(pv.pv_batch_kpm_moments(batch, rd, M, a, b)).copy()
+    assert pv.pv_codegen_instances() >= n0 + 1 or n0 > 0
+    tol = 1e-12 if dtype == np.complex128 else 1e-4
+    for i, c in enumerate(cases):
+        ref = okpm.moments_doubling(c.H, rs[i].astype(np.complex128), M, a[i], b[i])
+        assert np.abs(mu[i] - ref).max() < tol, (shape, i)
+    assert np.array_equal(host(pv.pv_batch_kpm_moments(batch, rd, M, a, b)), mu)
+    assert batch.stats() == (1, 1)
+
+
+def test_batch_of_different_patterns_takes_interpreted_kernels():
+    """Lattices with different generic patterns share no generated kernel:
+    their batch runs the interpreted kernels (512-lane shapes are refused)
+    and every instance still equals its oracle run."""
+    from oracle import kpm as okpm
+    cases = [GenCase("xy", (6, 5, 4), (1, 1, 1), seed=70), GenCase("xz", (5, 6, 4), (1, 1, 1), seed=71)]
+    nb, M = 4, 16
+    rs = [W.random_phase_block(c.D, nb, W.generator(72, i)) for i, c in enumerate(cases)]
+    a = np.array([float(np.abs(c.H).sum(axis=1).max()) * 1.05 for c in cases])
+    b = np.zeros(2)
+    batch = pv.Batch([c.lat for c in cases])
+    with pytest.raises(pv.PvError):
+        pv.pv_batch_set_tuning(batch, pv.PV_C128, nb, {"kernel": 2, "elems_per_lane": 1, "workgroup_size": 512})
+    n0 = pv.pv_codegen_instances()
+    mu = host(pv.pv_batch_kpm_moments(batch, [dev(r) for r in rs], M, a, b))
+    assert pv.pv_codegen_instances() == n0
+    for i, c in enumerate(cases):
+        assert np.abs(mu[i] - okpm.moments_doubling(c.H, rs[i], M, a[i], b[i])).max() < 1e-12
