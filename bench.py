@@ -650,7 +650,9 @@ def bench_fd(pv, torch, W, dev, half=0.05):
     and ChebFD on the same window, complex128.  ChebFD takes a search space of
     about 2.5 times the pairs trLanczosFD finds (whole 32-column blocks) and a
     filter degree of 2.4 pi a / h for the window's half-width h: the Jackson
-    damping then smears the window's edges over about 0.4 h."""
+    damping then smears the window's edges over about 0.4 h.  ChebFD runs
+    again with complex64 vectors (FP64 Gram and Rayleigh-Ritz) to a residual
+    tolerance of 1e-4 a, its eigenvalues compared with the complex128 run's."""
     st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
     lat = pv.Lattice((240, 240, 6), (1, 1, 0), st)
     lat.set_potential(torch.from_numpy(W.uniform_potential(lat.n_sites, 1.0, W.generator(6, W.STREAM_POTENTIAL))).to(dev))
@@ -682,6 +684,19 @@ def bench_fd(pv, torch, W, dev, half=0.05):
                          "max_residual": float(resf[:nt].max()),
                          "max_abs_theta_diff_vs_trlanczos": float(np.abs(np.sort(thf[:nt]) - th).max())}
         out["chebfd_over_trlanczos_time"] = round(t_fd / t_tr, 2)
+        # the same run with complex64 vectors (FP32 filter sweeps; Gram,
+        # Rayleigh-Ritz and residuals in FP64), to a tolerance FP32 reaches
+        X32 = torch.from_numpy(W.gaussian_block(lat.n_rows, ns, W.generator(6, W.STREAM_VECTORS, 1))
+                               .astype(np.complex64)).to(dev)
+        t0 = time.perf_counter()
+        th32, res32, nconv32, it32 = pv.pv_chebfd(lat, X32, 32, a, 0.0, -half, half, degree, nt, 1e-4 * a,
+                                                  max_iter=30, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        out["chebfd_c64"] = {"converged": int(nconv32), "targets": nt, "iterations": it32, "seconds": round(t32, 2),
+                             "tol": 1e-4 * a, "max_residual": float(res32[:nt].max()),
+                             "max_abs_theta_diff_vs_c128": float(np.abs(np.sort(th32[:nt]) - np.sort(thf[:nt])).max()),
+                             "note": "complex64 vectors, FP64 Gram / Rayleigh-Ritz / residuals"}
     out["note"] = ("the 256x256x64 periodic TI at W=2 (64 eigenvalues near E=0, degree 500) has an open bulk gap: a "
                    "KPM count finds 2.8 states with |E| < 0.5 and 11,882 with |E| < 0.7, so its 64 states nearest 0 "
                    "sit on a band edge inside the filter's resolution; the filter step at that size is the "

@@ -319,25 +319,6 @@ hipError_t typed(SweepParams& p, int num_cus, hipStream_t s) {
     return hipModuleLaunchKernel(c.fn, unsigned(p.grid), 1, 1, kBlock, 1, 1, 0, s, args, nullptr);
 }
 
-template <int NO, int DIM, bool SH, bool SW>
-hipError_t by_types(SweepParams& p, int num_cus, hipStream_t s) {
-    using P = PatShape<NO, DIM, SH, SW>;
-    if (p.dtype == 0) {
-        if (p.vtype != 0) return hipErrorInvalidValue;
-        return typed<P, double, double>(p, num_cus, s);
-    }
-    if (p.vtype == 0) return typed<P, float, double>(p, num_cus, s);
-    return typed<P, float, float>(p, num_cus, s);
-}
-
-template <int NO>
-hipError_t by_shape(SweepParams& p, int num_cus, hipStream_t s) {
-    if (p.cg_dim == 2) return by_types<NO, 2, false, false>(p, num_cus, s);
-    if (p.cg_sidew)
-        return p.cg_halo ? by_types<NO, 3, true, true>(p, num_cus, s) : by_types<NO, 3, false, true>(p, num_cus, s);
-    return p.cg_halo ? by_types<NO, 3, true, false>(p, num_cus, s) : by_types<NO, 3, false, false>(p, num_cus, s);
-}
-
 // Calls f(Tag<P>, Tag<T>, Tag<VT>) with the host stand-in of the launch's
 // pattern and its vector and field types.
 template <class F>
@@ -388,12 +369,10 @@ hipError_t batch_tile(const SweepParams& p, G&& g) {
 hipError_t launch_codegen(SweepParams& p, int num_cus, hipStream_t s) {
     g_err.clear();
     if (!p.cg_src) return hipErrorInvalidValue;
-    switch (p.n_orb) {
-        case 1: return by_shape<1>(p, num_cus, s);
-        case 2: return by_shape<2>(p, num_cus, s);
-        case 4: return by_shape<4>(p, num_cus, s);
-        default: return hipErrorInvalidValue;
-    }
+    return with_pattern(p, [&](auto pt, auto tt, auto vt) -> hipError_t {
+        return typed<typename decltype(pt)::type, typename decltype(tt)::type, typename decltype(vt)::type>(
+            p, num_cus, s);
+    });
 }
 
 // Batched sweeps (one launch per step over every instance of a batch whose
