@@ -335,3 +335,25 @@ def test_batch_of_different_patterns_takes_interpreted_kernels():
     assert pv.pv_codegen_instances() == n0
     for i, c in enumerate(cases):
         assert np.abs(mu[i] - okpm.moments_doubling(c.H, rs[i], M, a[i], b[i])).max() < 1e-12
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_generated_kernels_with_the_on_the_fly_field(kernel):
+    """Generated kernels evaluate the counter-based disorder field inside the
+    sweep like the built-in families: KPM moments of the xy stencil with the
+    field W (u_i - 1/2) generated on the fly equal the oracle's on the
+    explicit matrix with the same field."""
+    from oracle import rng
+    st, offsets, blocks, E0 = stencil("xy")
+    L, per = (11, 6, 5), (1, 1, 0)
+    lat = pv.Lattice(L, per, st)
+    lat.set_random_potential(4321, 1.5)
+    V = rng.field(4321, 1.5, int(np.prod(L)))
+    _, H = _explicit_matrix(L, per, 4, offsets, blocks, E0, V, False)
+    nb, M = 4, 32
+    pv.pv_lattice_set_tuning(lat, pv.PV_C128, nb, {"kernel": kernel})
+    a = float(np.abs(H).sum(axis=1).max()) * 1.05
+    r = W.random_phase_block(H.shape[0], nb, W.generator(43, 2))
+    mu = host(pv.pv_kpm_moments(lat, dev(r), M, a, 0.0))
+    assert pv.pv_codegen_instances() > 0
+    assert np.abs(mu - kpm.moments_doubling(H, r, M, a, 0.0)).max() < 1e-12
