@@ -366,7 +366,7 @@ def test_generated_kernels_kpm_gradient(name):
     oracle's discrete adjoint on the explicit matrix, with checkpoints."""
     from oracle import adjoint
     c = GenCase(name, (7, 5, 4), (1, 0, 1), seed=80)
-    nb, M = 3, 24
+    nb, M = 4, 24
     a = float(np.abs(c.H).sum(axis=1).max()) * 1.05
     r = W.random_phase_block(c.D, nb, W.generator(81, 2))
     gbar = W.generator(81, 3).standard_normal((nb, M))
