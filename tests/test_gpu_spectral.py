@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 import paper_1708_09689_amd as pv  # noqa: E402
 from oracle import kpm, spectral  # noqa: E402
 
-from gpu_common import Case, dev, host, SHAPE_KINDS, shape  # noqa: E402
+from gpu_common import Case, host, SHAPE_KINDS, shape  # noqa: E402
 
 K0 = math.pi / 2
 

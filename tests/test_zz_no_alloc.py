@@ -4,8 +4,6 @@ smaller block, each compared with pv_spmmv on the same inputs (bitwise: the
 same kernels in the same launch shapes) and with the oracle (complex128,
 1e-13 relative to max|y|; dots 1e-12 relative)."""
 
-import ctypes
-
 import numpy as np
 import pytest
 
