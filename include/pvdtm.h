@@ -586,7 +586,8 @@ pv_status pv_lattice_get_tuning(const pv_lattice *lat, int dtype, int nb, pv_tun
  * z step take the direct kernel, others the staged one as the built-in
  * families do (with 512-lane workgroups available to the autotuner).
  * A failed compilation returns PV_ERR_HIP with the compiler's log in
- * pv_last_error().  Batched sweeps (pv_batch_*) take generated kernels when
+ * pv_last_error() (for tests, PV_TEST_FAIL_CODEGEN=1 in the environment
+ * makes every compilation fail); the lattice stays usable.  Batched sweeps (pv_batch_*) take generated kernels when
  * all their lattices share one pattern.
  *
  * set_codegen: enable (1, the default) or disable (0: the interpreted

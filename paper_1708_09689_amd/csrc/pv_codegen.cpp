@@ -120,6 +120,11 @@ bool build(const std::string& pat, const std::string& expr, const std::string& a
             return true;
         }
     }
+    // test hook: PV_TEST_FAIL_CODEGEN=1 makes every compilation fail
+    if (const char* f = std::getenv("PV_TEST_FAIL_CODEGEN"); f && std::strcmp(f, "1") == 0) {
+        g_err = "hipRTC compile of " + expr + ": failed on request (PV_TEST_FAIL_CODEGEN)";
+        return false;
+    }
     hiprtcProgram prog;
     const char* hdrs[2] = {kRtcKernelsHpp, kRtcSweepHpp};
     const char* names[2] = {"pv_kernels.hpp", "pv_sweep.hpp"};

@@ -373,3 +373,41 @@ def test_generated_kernels_kpm_gradient(name):
     g = host(pv.pv_kpm_moments_vjp(c.lat, dev(r), M, a, 0.05, dev(gbar), ckpt_every=5))
     ref = adjoint.kpm_vjp(c.H, 4, "site", r, M, a, 0.05, gbar)
     assert np.abs(g - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_failed_compilation_is_an_error_and_the_lattice_stays_usable(monkeypatch):
+    """A generated kernel that does not compile (forced with the test hook)
+    fails the sweep with PV_ERR_HIP and the compiler's message; the same
+    lattice then runs on the interpreted kernels, and on generated ones once
+    compilation works again."""
+    g = np.random.default_rng(123)
+    offsets, blocks = [], []
+    for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1)]:
+        B = (g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))) * np.array([[0, 1], [1, 1]])
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    E0 = np.array([[0.1, 0.0], [0.0, -0.3]])
+    st = {"dim": 3, "n_orb": 2, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+          "pot_mode": pv.PV_POT_SITE}
+    L, per = (6, 5, 4), (1, 1, 1)
+    lat = pv.Lattice(L, per, st)
+    V = W.uniform_potential(int(np.prod(L)), 1.0, W.generator(123, 1))
+    lat.set_potential(dev(V))
+    _, H = _explicit_matrix(L, per, 2, offsets, blocks, E0, V, False)
+    xh = W.gaussian_block(H.shape[0], 2, W.generator(123, 2))
+    x, y = dev(xh), torch.empty((H.shape[0], 2), dtype=torch.complex128, device="cuda")
+    n0 = pv.pv_codegen_instances()
+    monkeypatch.setenv("PV_TEST_FAIL_CODEGEN", "1")
+    with pytest.raises(pv.PvError) as e:
+        pv.pv_spmmv(lat, x, y, 0.5, 0.0, 0.0)
+    assert e.value.status == 6 and "PV_TEST_FAIL_CODEGEN" in str(e.value)
+    assert pv.pv_codegen_instances() == n0
+    pv.pv_lattice_set_codegen(lat, False)
+    pv.pv_spmmv(lat, x, y, 0.5, 0.0, 0.0)
+    assert rel_err(host(y), spmmv.spmmv(H, xh, 0.5, 0.0, 0.0)) < 1e-13
+    monkeypatch.delenv("PV_TEST_FAIL_CODEGEN")
+    pv.pv_lattice_set_codegen(lat, True)
+    y.zero_()
+    pv.pv_spmmv(lat, x, y, 0.5, 0.0, 0.0)
+    assert pv.pv_codegen_instances() == n0 + 1
+    assert rel_err(host(y), spmmv.spmmv(H, xh, 0.5, 0.0, 0.0)) < 1e-13
