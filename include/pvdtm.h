@@ -645,7 +645,8 @@ pv_status pv_autotune(pv_lattice *lat, int dtype, int nb, const char *cache_path
  * each on a captured run of the batch itself (8 Chebyshev steps of every
  * instance with start blocks r and scales a, b as for pv_batch_kpm_moments,
  * timed as the fastest of three replays), and keeps the fastest for the
- * batch.  work: pv_batch_autotune_workspace_size() bytes, overwritten.
+ * batch.  work: pv_batch_autotune_workspace_size() bytes (the largest
+ * over the candidate shapes, whatever shape the batch holds), overwritten.
  * Synchronises the stream.  out and ms (either may be NULL) receive the
  * chosen shape and its time per batched step in milliseconds.
  */

@@ -2641,8 +2641,51 @@ extern "C" pv_status pv_batch_get_tuning(const pv_batch* B, int dtype, int nb, p
     return PV_OK;
 }
 
+namespace {
+
+// Launch shapes pv_batch_autotune times: the direct kernel; the staged one
+// with each elements per lane and 256 or 512 lanes
+std::vector<pv_tuning> batch_tune_candidates(const pv_batch* B, int dtype, int nb) {
+    std::vector<pv_tuning> cand;
+    pv_tuning t{};
+    t.kernel = 1;
+    cand.push_back(t);
+    if ((B->family != pv::FAM_GENERIC || batch_codegen(B)) && B->n_orb * nb <= pv::STAGED_MAX_SITE)
+        for (int wg : {0, 512})
+            for (int e : {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4}) {
+                t = pv_tuning{};
+                t.kernel = 2;
+                t.elems_per_lane = e;
+                t.workgroup_size = wg;
+                cand.push_back(t);
+            }
+    return cand;
+}
+
+// Workspace of the timed runs: the block counts, hence the layout, depend on
+// the launch shape, so the largest over the candidates (0: unsupported)
+size_t batch_tune_kpm_bytes(const pv_batch* B, int dtype, int nb) {
+    pv_batch probe;   // the batch's lattices under one candidate shape (no graph)
+    probe.lats = B->lats;
+    probe.family = B->family;
+    probe.n_orb = B->n_orb;
+    const int di = dtype == PV_C128 ? 0 : 1, ni = log2_nb(nb);
+    size_t most = 0;
+    for (const pv_tuning& t : batch_tune_candidates(B, dtype, nb)) {
+        probe.tune[di][ni] = t;
+        probe.tuned[di][ni] = true;
+        const size_t k = pv_batch_kpm_workspace_size(&probe, dtype, nb, 2 * kBatchTuneSteps);
+        if (!k) return 0;
+        most = std::max(most, k);
+    }
+    return most;
+}
+
+}  // namespace
+
 extern "C" size_t pv_batch_autotune_workspace_size(const pv_batch* B, int dtype, int nb) {
-    const size_t kpm = pv_batch_kpm_workspace_size(B, dtype, nb, 2 * kBatchTuneSteps);
+    if (!B || !is_pow2(nb) || nb > PV_MAX_NB || (dtype != PV_C128 && dtype != PV_C64)) return 0;
+    const size_t kpm = batch_tune_kpm_bytes(B, dtype, nb);
     if (!kpm) return 0;
     return kpm + align_up(B->lats.size() * (size_t)nb * 2 * kBatchTuneSteps * sizeof(double));
 }
@@ -2655,7 +2698,7 @@ extern "C" pv_status pv_batch_autotune(pv_batch* B, int dtype, int nb, const dou
     if ((st = check_nb(nb)) != PV_OK) return st;
     if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "unknown dtype %d", dtype);
     const int M = 2 * kBatchTuneSteps;
-    const size_t need_kpm = pv_batch_kpm_workspace_size(B, dtype, nb, M);
+    const size_t need_kpm = batch_tune_kpm_bytes(B, dtype, nb);
     const size_t need = pv_batch_autotune_workspace_size(B, dtype, nb);
     if (!need) return fail(PV_ERR_INVALID_ARG, "batch does not take dtype %d with nb = %d", dtype, nb);
     if (!work || work_bytes < need) return fail(PV_ERR_WORKSPACE, "workspace %zu < %zu bytes", work_bytes, need);
@@ -2687,23 +2730,7 @@ extern "C" pv_status pv_batch_autotune(pv_batch* B, int dtype, int nb, const dou
         }
         return PV_OK;
     };
-    // candidates: the direct kernel; the staged one with each elements per
-    // lane and 256 or 512 lanes (512 for compiled families)
-    std::vector<pv_tuning> cand;
-    {
-        pv_tuning t{};
-        t.kernel = 1;
-        cand.push_back(t);
-        if ((B->family != pv::FAM_GENERIC || batch_codegen(B)) && B->n_orb * nb <= pv::STAGED_MAX_SITE)
-            for (int wg : {0, 512})
-                for (int e : {dtype == PV_C128 ? 1 : 2, dtype == PV_C128 ? 2 : 4}) {
-                    t = pv_tuning{};
-                    t.kernel = 2;
-                    t.elems_per_lane = e;
-                    t.workgroup_size = wg;
-                    cand.push_back(t);
-                }
-    }
+    const std::vector<pv_tuning> cand = batch_tune_candidates(B, dtype, nb);
     pv_tuning best{};
     double best_ms = 1e300;
     pv_status err = PV_OK;

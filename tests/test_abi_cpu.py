@@ -410,3 +410,32 @@ def test_generated_pattern_availability(lib):
         pv.pv_lattice_codegen_source(dense)
     assert lib.pv_lattice_set_codegen(ti.handle, 2) == 1
     assert lib.pv_lattice_get_codegen(None, None) == 1
+
+
+def test_batch_autotune_workspace_covers_every_candidate_shape(lib):
+    """The autotune workspace holds the timed runs under every shape it tries
+    (block counts differ between shapes) whatever shape the batch holds."""
+    g = np.random.default_rng(5)
+    offsets, blocks = [], []
+    for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1)]:
+        B = g.standard_normal((2, 2)) + 1j * g.standard_normal((2, 2))
+        offsets += [o, tuple(-v for v in o)]
+        blocks += [B, B.conj().T]
+    st = {"dim": 3, "n_orb": 2, "offsets": np.array(offsets), "blocks": np.array(blocks),
+          "onsite": np.eye(2, dtype=np.complex128), "pot_mode": pv.PV_POT_NONE}
+    sizes = [(6, 5, 4), (7, 6, 5), (8, 4, 6)]
+    ti = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    for stencil in (st, ti):
+        lats = [pv.Lattice(L, (1, 1, 1), stencil) for L in sizes]
+        batch = pv.Batch(lats)
+        for dt, elems in ((pv.PV_C128, (1, 2)), (pv.PV_C64, (2, 4))):
+            for nb in (1, 8):
+                need = lib.pv_batch_autotune_workspace_size(batch.handle, dt, nb)
+                mu_bytes = len(lats) * nb * 16 * 8
+                shapes = [{"kernel": 1}] + [{"kernel": 2, "elems_per_lane": e, "workgroup_size": wg}
+                                            for wg in (0, 512) for e in elems]
+                for t in shapes:
+                    pv.pv_batch_set_tuning(batch, dt, nb, t)
+                    assert lib.pv_batch_autotune_workspace_size(batch.handle, dt, nb) == need
+                    assert lib.pv_batch_kpm_workspace_size(batch.handle, dt, nb, 16) + mu_bytes <= need
+                pv.pv_batch_set_tuning(batch, dt, nb, None)

@@ -411,3 +411,21 @@ def test_failed_compilation_is_an_error_and_the_lattice_stays_usable(monkeypatch
     pv.pv_spmmv(lat, x, y, 0.5, 0.0, 0.0)
     assert pv.pv_codegen_instances() == n0 + 1
     assert rel_err(host(y), spmmv.spmmv(H, xh, 0.5, 0.0, 0.0)) < 1e-13
+
+
+def test_batch_autotune_on_generated_kernels():
+    """pv_batch_autotune on a batch sharing one generated pattern times the
+    staged candidates too (512 lanes included) and keeps results equal to
+    the direct generated kernel's up to the dots' summation order."""
+    cases = [GenCase("xz", L, (1, 1, 1), seed=90 + i) for i, L in enumerate([(6, 5, 4), (7, 6, 5), (8, 4, 6)])]
+    nb, M = 8, 16
+    rs = [dev(W.random_phase_block(c.D, nb, W.generator(91, i))) for i, c in enumerate(cases)]
+    a = np.array([float(np.abs(c.H).sum(axis=1).max()) * 1.05 for c in cases])
+    b = np.zeros(3)
+    batch = pv.Batch([c.lat for c in cases])
+    pv.pv_batch_set_tuning(batch, pv.PV_C128, nb, {"kernel": 1})
+    mu_d = host(pv.pv_batch_kpm_moments(batch, rs, M, a, b)).copy()
+    shape, ms = pv.pv_batch_autotune(batch, rs, a, b)
+    assert ms > 0.0 and shape["kernel"] in (1, 2) and shape["workgroup_size"] in (0, 512)
+    mu_t = host(pv.pv_batch_kpm_moments(batch, rs, M, a, b))
+    assert np.abs(mu_t - mu_d).max() < 1e-13
