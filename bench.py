@@ -279,6 +279,20 @@ def bench_kpm16(pv, torch, W, dev):
             "note": "cache-resident (0.6 MB): launch-latency bound, no HBM roofline claim"}
 
 
+def bench_random_block(pv, torch, lat, dev, nb=32):
+    """Random start blocks generated on the device for the benchmark lattice
+    (counter-based generator, n_rows x nb): write-only, 16 B per complex128
+    element, against the copy probe's bound of one read and one write."""
+    out = torch.empty((lat.n_rows, nb), dtype=torch.complex128, device=dev)
+    res = {"workload": f"TI 256x256x64 start block, nb={nb}, complex128 ({out.numel() * 16 / 1e9:.1f} GB)"}
+    for name, kind in (("phase", pv.PV_RANDOM_PHASE), ("z4", pv.PV_RANDOM_Z4)):
+        pv.pv_random_block(lat, nb, 5, kind, out=out)
+        ms = _timed(torch, lambda: pv.pv_random_block(lat, nb, 5, kind, out=out), 5)
+        res[f"{name}_ms"] = round(ms, 3)
+        res[f"{name}_GBs_written"] = round(out.numel() * 16 / (ms * 1e-3) / 1e9, 1)
+    return res
+
+
 def bench_chebtp_graphene(pv, torch, W, dev, steps=5):
     """Graphene two-site cells 1024 x 1024 (open x, periodic y), 8x8 dot array
     (radius 20, V0 = 0.1), Gaussian packet (width 50, E = 0.2), a = 3.06,
@@ -801,7 +815,8 @@ def main():
                          ("batched_kpm_96", lambda: bench_batch(pv, torch, W, dev)),
                          ("adjoint", lambda: bench_adjoint(pv, torch, W, dev)),
                          ("weyl_spectral", lambda: bench_weyl_spectral(pv, torch, W, dev)),
-                         ("dsl_stencils", lambda: bench_dsl(pv, torch, W, dev))):
+                         ("dsl_stencils", lambda: bench_dsl(pv, torch, W, dev)),
+                         ("random_start_block", lambda: bench_random_block(pv, torch, lat, dev))):
             t0 = time.perf_counter()
             configs[name] = fn()
             torch.cuda.empty_cache()

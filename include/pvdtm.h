@@ -259,6 +259,27 @@ pv_status pv_spmmv_noalloc(pv_lattice *lat, int dtype, int nb, const void *x, co
                            double *dots, void *stream);
 
 /*
+ * Random start blocks for the stochastic trace of KPM (Sec. 4.2), generated
+ * on the device.  Sec. 3.4 fills vectors from a function of the site, the
+ * orbital, the column and a random seed; here every entry is a pure function
+ * of (seed, global element index), from the counter-based generator of the
+ * on-the-fly field (SplitMix64, Sec. 3.3): element (r, c) of out takes index
+ * i = (row0 + r) * nb + c and z_i = output number i + 1 of the stream seeded
+ * with seed, and
+ *     kind PV_RANDOM_PHASE:  exp(i phi), phi = 2 pi u, u = (z_i >> 11) 2^-53
+ *                            (cos and sin in FP64)
+ *     kind PV_RANDOM_Z4:     i^k, k = z_i >> 62: 1, i, -1 or -i
+ * PV_C64 blocks hold the FP64 values rounded to FP32.  out: device block of
+ * dtype, n_rows x nb (rows row0 .. row0 + n_rows - 1 of a block over a larger
+ * row range; row0 = 0 for the lattice's own block), written.  row0 >= 0 and
+ * (row0 + n_rows) * nb < 2^63, else PV_ERR_INVALID_ARG before any launch.
+ */
+#define PV_RANDOM_PHASE 0
+#define PV_RANDOM_Z4 1
+pv_status pv_random_block(pv_lattice *lat, int dtype, int nb, uint64_t seed, int kind, int64_t row0, void *out,
+                          void *stream);
+
+/*
  * KPM moments (Sec. 2.2 DOS, Sec. 4): for every column c of the start block r
  *     mu[c][n] = Re <r_c, T_n(H~) r_c> / D,  H~ = (H - b)/a,  n = 0..M-1,
  * with D = n_rows, formed from M/2 fused sweeps through

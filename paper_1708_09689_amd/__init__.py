@@ -28,6 +28,7 @@ PV_CHECK_HERMITIAN = 1
 PV_DOT_XX, PV_DOT_XY, PV_DOT_YY = 1, 2, 4
 PV_MAX_TERMS, PV_MAX_ORB, PV_MAX_NB = 26, 4, 64
 PV_MODEL_TI, PV_MODEL_GRAPHENE2, PV_MODEL_GRAPHENE4, PV_MODEL_WEYL = 0, 1, 2, 3
+PV_RANDOM_PHASE, PV_RANDOM_Z4 = 0, 1
 FAMILY_NAMES = {0: "generic", 1: "ti", 2: "graphene2", 3: "graphene4", 4: "weyl"}
 
 STATUS_NAMES = {0: "PV_OK", 1: "PV_ERR_INVALID_ARG", 2: "PV_ERR_UNSUPPORTED", 3: "PV_ERR_NOT_HERMITIAN",
@@ -105,6 +106,7 @@ SIGNATURES = {
     "pv_cheb_propagate_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_cheb_propagate_vjp_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
+    "pv_random_block": (_i, [_vp, _i, _i, ctypes.c_uint64, _i, _i64, _vp, _vp]),
     "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
     "pv_dsl_stencil": (_i, [ctypes.c_char_p, _dp, _i, _ip, _ip, _ip, _ip, _dp, _dp, _ip, _ip]),
     "pv_trlanczos_filter": (_i, [_d, _d, _d, _d, _i, _dp, _dp]),
@@ -516,6 +518,19 @@ def pv_bloch_block(lat, k, orbital, layer=None, dtype=PV_C128, out=None, device=
     axis, index = (-1, 0) if layer is None else layer
     _check(lib().pv_bloch_block(lat.handle, dtype, nb, _dptr(k), orb.ctypes.data_as(_ip), axis, index,
                                 _vec(out, "out", lat.n_rows, nb, dtype), _stream()))
+    return out
+
+
+def pv_random_block(lat, nb: int, seed: int, kind=PV_RANDOM_PHASE, dtype=PV_C128, row0: int = 0, out=None,
+                    device="cuda"):
+    """Random start block [n_rows, nb] from the counter-based generator:
+    entry (r, c) is a function of (seed, (row0 + r) * nb + c) only."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((lat.n_rows, nb), dtype=torch.complex128 if dtype == PV_C128 else torch.complex64,
+                          device=device)
+    _check(lib().pv_random_block(lat.handle, dtype, nb, seed & 0xFFFFFFFFFFFFFFFF, kind, row0,
+                                 _vec(out, "out", lat.n_rows, nb, dtype), _stream()))
     return out
 
 

@@ -1114,6 +1114,25 @@ extern "C" pv_status pv_bloch_block(pv_lattice* l, int dtype, int nb, const doub
     return PV_OK;
 }
 
+extern "C" pv_status pv_random_block(pv_lattice* l, int dtype, int nb, uint64_t seed, int kind, int64_t row0,
+                                     void* out, void* stream) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "dtype must be PV_C128 or PV_C64");
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if (kind != PV_RANDOM_PHASE && kind != PV_RANDOM_Z4)
+        return fail(PV_ERR_INVALID_ARG, "kind %d: need PV_RANDOM_PHASE or PV_RANDOM_Z4", kind);
+    if (row0 < 0 || row0 > INT64_MAX / nb - l->n_rows)
+        return fail(PV_ERR_INVALID_ARG, "row0 = %lld: need 0 <= row0 and (row0 + n_rows) * nb < 2^63",
+                    (long long)row0);
+    if ((st = check_vec(out, dtype, "out")) != PV_OK) return st;
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    PV_HIP(pv::launch_random_block(dtype, kind, l->n_rows * nb, seed, uint64_t(row0) * uint64_t(nb), out,
+                                   static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Chebyshev series / propagation
 // ---------------------------------------------------------------------------

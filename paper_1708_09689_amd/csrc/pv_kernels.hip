@@ -1,6 +1,6 @@
 // HIP kernels of the library outside the sweep: fixed-order reductions of
 // the fused dot products, tall-skinny Gram / rotation, scaling, copies, Bloch
-// start blocks; and the dispatch of a sweep to its stencil family's
+// and random start blocks; and the dispatch of a sweep to its stencil family's
 // translation unit (the sweep kernels themselves are in pv_sweep.hpp).
 #include "pv_sweep.hpp"
 
@@ -420,6 +420,28 @@ __global__ __launch_bounds__(kBlock) void bloch_kernel(cplx<T>* __restrict__ out
     }
 }
 
+// Random start blocks (one element per lane): element e takes the
+// generator's output for index i0 + e; a random phase exp(2 pi i u) from its
+// top 53 bits, or the Z4 phase i^k from its top two.
+template <typename T, int KIND>
+__global__ __launch_bounds__(kBlock) void random_block_kernel(cplx<T>* __restrict__ out, int64_t n, uint64_t seed,
+                                                            uint64_t i0) {
+    constexpr double kTwoPi = 6.283185307179586;   // the double nearest 2 pi
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kBlock) {
+        const uint64_t z = splitmix64_at(seed, i0 + uint64_t(e));
+        double re, im;
+        if constexpr (KIND == 0) {
+            const double u = double(z >> 11) * 0x1.0p-53;
+            sincos(kTwoPi * u, &im, &re);
+        } else {
+            const int k = int(z >> 62);
+            re = k == 0 ? 1.0 : (k == 2 ? -1.0 : 0.0);
+            im = k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0);
+        }
+        out[e] = cplx<T>{T(re), T(im)};
+    }
+}
+
 }  // namespace
 
 static int elementwise_grid(int64_t n);
@@ -449,6 +471,24 @@ hipError_t launch_bloch(int dtype, int64_t n_sites, int n_orb, int nb, int Lx, i
     else
         hipLaunchKernelGGL(bloch_kernel<float>, dim3(g), dim3(kBlock), 0, s, static_cast<cplx<float>*>(out), n,
                            n_orb, nb, Lx, Ly, cols, axis, index);
+    return hipGetLastError();
+}
+
+hipError_t launch_random_block(int dtype, int kind, int64_t n, uint64_t seed, uint64_t i0, void* out, hipStream_t s) {
+    const int g = elementwise_grid(n);
+    if (dtype == 0) {
+        auto* o = static_cast<cplx<double>*>(out);
+        if (kind == 0)
+            hipLaunchKernelGGL((random_block_kernel<double, 0>), dim3(g), dim3(kBlock), 0, s, o, n, seed, i0);
+        else
+            hipLaunchKernelGGL((random_block_kernel<double, 1>), dim3(g), dim3(kBlock), 0, s, o, n, seed, i0);
+    } else {
+        auto* o = static_cast<cplx<float>*>(out);
+        if (kind == 0)
+            hipLaunchKernelGGL((random_block_kernel<float, 0>), dim3(g), dim3(kBlock), 0, s, o, n, seed, i0);
+        else
+            hipLaunchKernelGGL((random_block_kernel<float, 1>), dim3(g), dim3(kBlock), 0, s, o, n, seed, i0);
+    }
     return hipGetLastError();
 }
 

@@ -181,6 +181,11 @@ struct BlochCols {
 hipError_t launch_bloch(int dtype, int64_t n_sites, int n_orb, int nb, int Lx, int Ly, const BlochCols& cols,
                         int axis, int64_t index, void* out, hipStream_t s);
 
+// Random start blocks: out[e] for e < n takes the counter-based generator's
+// output number i0 + e + 1 of the stream seeded with seed, mapped to a
+// random phase (kind 0) or a Z4 phase (kind 1).
+hipError_t launch_random_block(int dtype, int kind, int64_t n, uint64_t seed, uint64_t i0, void* out, hipStream_t s);
+
 // Batched sweeps: one argument record per instance (built on the host with
 // batch_fill_record from that instance's launch description), a table of
 // records in device memory, and per-workgroup instance maps.  staged: every

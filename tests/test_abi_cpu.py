@@ -439,3 +439,21 @@ def test_batch_autotune_workspace_covers_every_candidate_shape(lib):
                     assert lib.pv_batch_autotune_workspace_size(batch.handle, dt, nb) == need
                     assert lib.pv_batch_kpm_workspace_size(batch.handle, dt, nb, 16) + mu_bytes <= need
                 pv.pv_batch_set_tuning(batch, dt, nb, None)
+
+
+def test_random_block_argument_errors_before_any_launch(lib):
+    lat = pv.Lattice((4, 4, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: validation fails first
+    cases = [
+        ((lat.handle, 0, 3, 1, 0, 0, fake, None), 2, b"power of two"),        # nb
+        ((lat.handle, 0, 4, 1, 2, 0, fake, None), 1, b"kind"),                # unknown kind
+        ((lat.handle, 0, 4, 1, 0, -1, fake, None), 1, b"row0"),               # negative row0
+        ((lat.handle, 0, 64, 1, 0, (1 << 63) // 64, fake, None), 1, b"row0"),  # index overflow
+        ((lat.handle, 0, 4, 1, 0, 0, ctypes.c_void_p((1 << 20) + 8), None), 1, b"out"),   # misaligned
+        ((lat.handle, 0, 4, 1, 0, 0, None, None), 1, b"out"),                 # NULL
+        ((lat.handle, 2, 4, 1, 0, 0, fake, None), 1, b"dtype"),
+        ((None, 0, 4, 1, 0, 0, fake, None), 1, b"NULL"),
+    ]
+    for args, status, text in cases:
+        assert lib.pv_random_block(*args) == status
+        assert text in lib.pv_last_error()

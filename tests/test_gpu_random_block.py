@@ -1,0 +1,82 @@
+"""Random start blocks generated on the device (pv_random_block) against the
+oracle's implementation of the same counter-based generator (oracle.rng).
+
+Tolerances:
+* Z4 phases: bit-exact (the value is chosen by two integer bits).
+* Random phases, complex128: both sides take cos and sin of the same double
+  2 pi u in FP64; each library result lies within one unit in the last place
+  of the exact value, so the two differ by at most two units of 2^-53 near
+  magnitude 1: 1e-15 absolute.
+* Random phases, complex64: the FP64 value rounded to FP32 on both sides; a
+  difference of the FP64 values can move the rounding across a midpoint, so
+  at most one FP32 unit (2^-24 for magnitudes in [0.5, 1)): 6e-8 absolute.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1708_09689_amd as pv  # noqa: E402
+from oracle import kpm, rng  # noqa: E402
+
+from gpu_common import Case, host  # noqa: E402
+
+TI = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+KINDS = [(pv.PV_RANDOM_PHASE, rng.PHASE), (pv.PV_RANDOM_Z4, rng.Z4)]
+
+
+def _check(got, ref, kind, dtype):
+    if kind == rng.Z4:
+        assert np.array_equal(got, ref.astype(got.dtype))
+    elif dtype == pv.PV_C128:
+        assert np.abs(got - ref).max() <= 1e-15
+    else:
+        assert np.abs(got.astype(np.complex128) - ref.astype(np.complex64).astype(np.complex128)).max() <= 6e-8
+
+
+@pytest.mark.parametrize("L,nb", [((37, 9, 6), 1), ((37, 9, 6), 4), ((13, 11, 7), 32), ((64, 64, 32), 32),
+                                  ((1, 1, 1), 2)])
+@pytest.mark.parametrize("dtype", [pv.PV_C128, pv.PV_C64])
+@pytest.mark.parametrize("kind,okind", KINDS)
+def test_random_block_matches_oracle(L, nb, dtype, kind, okind):
+    # (64, 64, 32) x 4 orbitals x 32 columns: 16.8M elements, eight grid-stride
+    # passes; the others end in a partial workgroup
+    lat = pv.Lattice(L, (1, 1, 1), TI)
+    for seed, row0 in [(0x1708_09689, 0), (7, 12345)]:
+        out = pv.pv_random_block(lat, nb, seed, kind, dtype, row0=row0)
+        ref = rng.random_block(seed, lat.n_rows, nb, okind, row0=row0)
+        _check(host(out), ref, okind, dtype)
+
+
+@pytest.mark.parametrize("kind,okind", KINDS)
+def test_random_block_row_windows_and_unit_modulus_at_full_size(kind, okind):
+    """The 256 x 256 x 64 TI block of 32 complex128 columns (8.6 GB): sampled
+    entries against the oracle, unit modulus everywhere, and a block of the
+    upper half of the rows (row0) equal to the whole block's rows there."""
+    lat = pv.Lattice((256, 256, 64), (1, 1, 1), TI)
+    nb, seed = 32, 2024
+    out = pv.pv_random_block(lat, nb, seed, kind)
+    g = np.random.default_rng(5)
+    rows = np.concatenate([g.integers(0, lat.n_rows, 4096), [0, lat.n_rows - 1]])
+    cols = np.concatenate([g.integers(0, nb, 4096), [0, nb - 1]])
+    got = out[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+    _check(got, rng.random_block_at(seed, nb, okind, rows, cols), okind, pv.PV_C128)
+    assert float((out.abs() - 1.0).abs().max()) <= 1e-15
+    half = pv.Lattice((256, 256, 32), (1, 1, 1), TI)
+    top = pv.pv_random_block(half, nb, seed, kind, row0=half.n_rows)
+    assert torch.equal(top, out[half.n_rows:])
+
+
+def test_kpm_on_device_start_blocks_matches_oracle():
+    """KPM moments (stochastic trace, Sec. 4.2) from a device-generated
+    random-phase block equal the oracle's from its own block (1e-12, as the
+    other KPM parity tests); mu_0 = 1 for unit-modulus columns."""
+    c = Case("ti", (12, 10, 8), (1, 1, 0), Wd=2.0, seed=3)
+    nb, M, seed = 4, 64, 99
+    r = pv.pv_random_block(c.lat, nb, seed, pv.PV_RANDOM_PHASE)
+    mu = host(pv.pv_kpm_moments(c.lat, r, M, 7.0, 0.0))
+    ref = kpm.moments_direct(c.H, rng.random_block(seed, c.D, nb, rng.PHASE), M, 7.0, 0.0)
+    assert np.abs(mu - ref).max() < 1e-12
+    assert np.abs(mu[:, 0] - 1.0).max() < 1e-14
