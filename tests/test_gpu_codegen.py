@@ -429,3 +429,59 @@ def test_batch_autotune_on_generated_kernels():
     assert ms > 0.0 and shape["kernel"] in (1, 2) and shape["workgroup_size"] in (0, 512)
     mu_t = host(pv.pv_batch_kpm_moments(batch, rs, M, a, b))
     assert np.abs(mu_t - mu_d).max() < 1e-13
+
+
+def _extra_case(name, L, per, vdtype):
+    """A generated-kernel lattice with a per-orbital field ("2d_orbital": the
+    2D two-orbital stencil) or a single-orbital 3D stencil with complex
+    diagonal hops ("cubic1"), and the oracle's explicit matrix."""
+    if name == "2d_orbital":
+        st, offsets, blocks, E0 = stencil("2d")
+        st = dict(st, pot_mode=pv.PV_POT_ORBITAL)
+    else:
+        g = np.random.default_rng(23)
+        offsets, blocks = [], []
+        for o in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (0, 1, -1), (1, 0, 1)]:
+            B = np.array([[g.standard_normal() + 1j * g.standard_normal()]])
+            offsets += [o, tuple(-v for v in o)]
+            blocks += [B, B.conj().T]
+        E0 = np.array([[0.25 + 0j]])
+        st = {"dim": 3, "n_orb": 1, "offsets": np.array(offsets), "blocks": np.array(blocks), "onsite": E0,
+              "pot_mode": pv.PV_POT_SITE}
+    lat = pv.Lattice(L, per, st)
+    assert lat.family == 0 and pv.pv_lattice_get_codegen(lat)
+    orbital = st["pot_mode"] == pv.PV_POT_ORBITAL
+    n = int(np.prod(L)) * (st["n_orb"] if orbital else 1)
+    V = W.uniform_potential(n, 1.0, W.generator(29, W.STREAM_POTENTIAL)).astype(vdtype)
+    lat.set_potential(dev(V))
+    ol, H = _explicit_matrix(L, per, st["n_orb"], offsets, blocks, E0, V.astype(np.float64), orbital)
+    return lat, H, ol.n_rows
+
+
+@pytest.mark.parametrize("name,L,per", [("2d_orbital", (41, 7), (1, 0)), ("cubic1", (23, 6, 5), (1, 1, 0))])
+@pytest.mark.parametrize("dtype,nb", [(np.complex128, 1), (np.complex128, 4), (np.complex64, 1), (np.complex64, 4)])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_generated_per_orbital_field_and_single_orbital_stencils(name, L, per, dtype, nb, kernel):
+    """Generated kernels with a field per orbital row, and on a one-orbital
+    stencil, where a complex64 site of one column is half a 16-byte chunk (the
+    staged request then takes the direct kernel); against the oracle and the
+    interpreted kernels."""
+    lat, H, D = _extra_case(name, L, per, np.float64 if dtype == np.complex128 else np.float32)
+    code = pv.PV_C128 if dtype == np.complex128 else pv.PV_C64
+    pv.pv_lattice_set_tuning(lat, code, nb, {"kernel": kernel})
+    x = W.gaussian_block(D, nb, W.generator(5, 2, nb), dtype)
+    z = W.gaussian_block(D, nb, W.generator(5, 3, nb), dtype)
+    ref = spmmv.spmmv(H, x.astype(np.complex128), 0.4, 0.2, -1.0, z.astype(np.complex128))
+    tol = 1e-13 if dtype == np.complex128 else 2e-6
+    outs = []
+    for gen in (True, False):
+        pv.pv_lattice_set_codegen(lat, gen)
+        n0 = pv.pv_codegen_instances()
+        y = dev(z.copy())
+        pv.pv_spmmv(lat, dev(x), y, 0.4, 0.2, -1.0, z=y, dot_flags=7)
+        out = host(y).astype(np.complex128)
+        assert rel_err(out, ref) < tol, gen
+        if gen:
+            assert pv.pv_codegen_instances() >= n0 and pv.pv_codegen_instances() > 0
+        outs.append(out)
+    assert rel_err(outs[0], outs[1]) < tol
