@@ -196,6 +196,27 @@ def memcpy_probe(torch, dev, nbytes=4 << 30, reps=10) -> float:
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def torch_triad_probe(torch, dev, nbytes=4 << 30, reps=10) -> float:
+    """y = x + z by PyTorch's own elementwise kernel (GB/s, two reads + one
+    write): a triad that is not this library's, as a cross-check of the
+    triad probe's ceiling."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    z = torch.empty_like(x).fill_(2.0)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        torch.add(x, z, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(x, z, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, z, y
+    return 3.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(nb: int, budget_s: float = 8.0) -> dict:
     """The oracle on a bounded sample of the same workload (the same x-y
     planes, 4 of the 64 z-layers): its C++/OpenMP Chebyshev step with fused
@@ -760,6 +781,7 @@ def main():
     triad_gbs = None if args.no_copy else triad_probe(pv, torch, dev)
     read_gbs = None if args.no_copy else read_probe(pv, torch, dev)
     memcpy_gbs = None if args.no_copy else memcpy_probe(torch, dev)
+    torch_triad_gbs = None if args.no_copy else torch_triad_probe(torch, dev)
 
     # headline
     set_field(args.dtype)
@@ -876,6 +898,7 @@ def main():
         "frac_of_triad_probe": None if triad_gbs is None else round(achieved / triad_gbs, 4),
         "read_probe_GBs": None if read_gbs is None else round(read_gbs, 1),
         "memcpy_d2d_GBs": None if memcpy_gbs is None else round(memcpy_gbs, 1),
+        "torch_triad_GBs": None if torch_triad_gbs is None else round(torch_triad_gbs, 1),
         "metric_parts": parts,
         "variants": variants,
         "workloads": configs,
