@@ -259,6 +259,25 @@ pv_status pv_spmmv_noalloc(pv_lattice *lat, int dtype, int nb, const void *x, co
                            double *dots, void *stream);
 
 /*
+ * Vector block from a host callback (Sec. 3.4: the initial-vector interface
+ * of the paper's library).  For every site (x, y, z), orbital o and column k,
+ * with r = {x, y, z, o}:
+ *     Re out[(s*n_orb + o)*nb + k] = fnc(r, k, parm, seed)
+ *     Im out[...]                  = fnc_im(r, k, parm, seed)  (0 if NULL)
+ * called on the host by one thread in memory order (column fastest, then
+ * orbital, x, y, z).  parm is handed through; seed points to a 128-bit state (two uint64_t) that the
+ * library sets from `seed_value` (SplitMix64 outputs 1 and 2 of the stream
+ * seeded with it) before the first call, for the callback's own random
+ * draws.  out: device block of dtype (complex64 takes the values rounded to
+ * FP32), n_rows x nb, written by a copy queued on `stream` after its earlier
+ * work; the call returns when out holds the block.  Host memory for one block is allocated for the copy
+ * (PV_ERR_OOM if it cannot be).
+ */
+typedef double (*pv_vector_func)(const int64_t *r, int k, void *parm, void *seed);
+pv_status pv_vector_from_func(pv_lattice *lat, int dtype, int nb, pv_vector_func fnc, pv_vector_func fnc_im,
+                              void *parm, uint64_t seed_value, void *out, void *stream);
+
+/*
  * Random start blocks for the stochastic trace of KPM (Sec. 4.2), generated
  * on the device.  Sec. 3.4 fills vectors from a function of the site, the
  * orbital, the column and a random seed; here every entry is a pure function

@@ -107,6 +107,7 @@ SIGNATURES = {
     "pv_cheb_propagate_vjp_keep": (_i, [_vp, _i, _i, _d, _d, _d, _i, _i, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]),
     "pv_bloch_block": (_i, [_vp, _i, _i, _dp, _ip, _i, _i64, _vp, _vp]),
     "pv_random_block": (_i, [_vp, _i, _i, ctypes.c_uint64, _i, _i64, _vp, _vp]),
+    "pv_vector_from_func": (_i, [_vp, _i, _i, _vp, _vp, _vp, ctypes.c_uint64, _vp, _vp]),
     "pv_kpm_spectral_function": (_i, [_i, _i, _dp, _d, _d, _d, _i, _dp, _dp]),
     "pv_dsl_stencil": (_i, [ctypes.c_char_p, _dp, _i, _ip, _ip, _ip, _ip, _dp, _dp, _ip, _ip]),
     "pv_trlanczos_filter": (_i, [_d, _d, _d, _d, _i, _dp, _dp]),
@@ -531,6 +532,26 @@ def pv_random_block(lat, nb: int, seed: int, kind=PV_RANDOM_PHASE, dtype=PV_C128
                           device=device)
     _check(lib().pv_random_block(lat.handle, dtype, nb, seed & 0xFFFFFFFFFFFFFFFF, kind, row0,
                                  _vec(out, "out", lat.n_rows, nb, dtype), _stream()))
+    return out
+
+
+PV_VECTOR_FUNC = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p)
+
+
+def pv_vector_from_func(lat, nb: int, fnc, fnc_im=None, seed: int = 0, dtype=PV_C128, out=None, device="cuda"):
+    """Block [n_rows, nb] from host callbacks fnc(r, k, parm, seed) -> real
+    part (and fnc_im for the imaginary part), r = (x, y, z, orbital), as
+    the C interface calls them (ctypes arguments; parm is NULL here)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((lat.n_rows, nb), dtype=torch.complex128 if dtype == PV_C128 else torch.complex64,
+                          device=device)
+    cf = PV_VECTOR_FUNC(fnc)
+    ci = PV_VECTOR_FUNC(fnc_im) if fnc_im is not None else None
+    _check(lib().pv_vector_from_func(lat.handle, dtype, nb, ctypes.cast(cf, _vp),
+                                     None if ci is None else ctypes.cast(ci, _vp), None,
+                                     seed & 0xFFFFFFFFFFFFFFFF, _vec(out, "out", lat.n_rows, nb, dtype), _stream()))
     return out
 
 

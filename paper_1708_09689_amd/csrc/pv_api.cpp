@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -1111,6 +1112,62 @@ extern "C" pv_status pv_bloch_block(pv_lattice* l, int dtype, int nb, const doub
     if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
     PV_HIP(pv::launch_bloch(dtype, l->n_sites, l->n_orb, nb, int(l->L[0]), int(l->L[1]), cols, layer_axis,
                             layer_index, out, static_cast<hipStream_t>(stream)));
+    return PV_OK;
+}
+
+extern "C" pv_status pv_vector_from_func(pv_lattice* l, int dtype, int nb, pv_vector_func fnc,
+                                         pv_vector_func fnc_im, void* parm, uint64_t seed_value, void* out,
+                                         void* stream) {
+    if (!l) return fail(PV_ERR_INVALID_ARG, "lattice is NULL");
+    pv_status st;
+    if (dtype != PV_C128 && dtype != PV_C64) return fail(PV_ERR_INVALID_ARG, "dtype must be PV_C128 or PV_C64");
+    if ((st = check_nb(nb)) != PV_OK) return st;
+    if (!fnc) return fail(PV_ERR_INVALID_ARG, "fnc is NULL");
+    if ((st = check_vec(out, dtype, "out")) != PV_OK) return st;
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PV_ERR_NO_DEVICE, "no HIP device");
+    const size_t n = size_t(l->n_rows) * size_t(nb);
+    std::vector<double> h64;
+    std::vector<float> h32;
+    try {
+        if (dtype == PV_C128) h64.resize(2 * n);
+        else h32.resize(2 * n);
+    } catch (const std::bad_alloc&) {
+        return fail(PV_ERR_OOM, "host buffer of %zu elements", n);
+    }
+    // the callback's 128-bit state: SplitMix64 outputs 1 and 2 of seed_value
+    uint64_t state[2];
+    for (int j = 0; j < 2; ++j) {
+        uint64_t z = seed_value + uint64_t(j + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        state[j] = z ^ (z >> 31);
+    }
+    size_t e = 0;
+    int64_t r[4];
+    for (int64_t z = 0; z < l->L[2]; ++z)
+        for (int64_t y = 0; y < l->L[1]; ++y)
+            for (int64_t x = 0; x < l->L[0]; ++x)
+                for (int o = 0; o < l->n_orb; ++o)
+                    for (int k = 0; k < nb; ++k, ++e) {
+                        r[0] = x;
+                        r[1] = y;
+                        r[2] = z;
+                        r[3] = o;
+                        const double re = fnc(r, k, parm, state);
+                        const double im = fnc_im ? fnc_im(r, k, parm, state) : 0.0;
+                        if (dtype == PV_C128) {
+                            h64[2 * e] = re;
+                            h64[2 * e + 1] = im;
+                        } else {
+                            h32[2 * e] = float(re);
+                            h32[2 * e + 1] = float(im);
+                        }
+                    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const void* src = dtype == PV_C128 ? static_cast<const void*>(h64.data()) : static_cast<const void*>(h32.data());
+    PV_HIP(hipMemcpyAsync(out, src, n * elem_bytes(dtype), hipMemcpyHostToDevice, s));
+    PV_HIP(hipStreamSynchronize(s));
     return PV_OK;
 }
 

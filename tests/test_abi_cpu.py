@@ -457,3 +457,24 @@ def test_random_block_argument_errors_before_any_launch(lib):
     for args, status, text in cases:
         assert lib.pv_random_block(*args) == status
         assert text in lib.pv_last_error()
+
+
+def test_vector_from_func_argument_errors_before_any_callback(lib):
+    lat = pv.Lattice((4, 4, 4), (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0, 0]))
+    calls = []
+    f = pv.PV_VECTOR_FUNC(lambda r, k, parm, seed: calls.append(k) or 0.0)
+    fp = ctypes.cast(f, ctypes.c_void_p)
+    fake = ctypes.c_void_p(1 << 20)
+    cases = [
+        ((lat.handle, 0, 3, fp, None, None, 1, fake, None), 2, b"power of two"),
+        ((lat.handle, 0, 4, None, None, None, 1, fake, None), 1, b"fnc"),
+        ((lat.handle, 0, 4, fp, None, None, 1, ctypes.c_void_p((1 << 20) + 8), None), 1, b"out"),
+        ((lat.handle, 5, 4, fp, None, None, 1, fake, None), 1, b"dtype"),
+        ((None, 0, 4, fp, None, None, 1, fake, None), 1, b"NULL"),
+    ]
+    for args, status, text in cases:
+        assert lib.pv_vector_from_func(*args) == status
+        assert text in lib.pv_last_error()
+    # no device: refused before the callback is called
+    assert lib.pv_vector_from_func(lat.handle, 0, 4, fp, None, None, 1, fake, None) == 8
+    assert calls == []

@@ -1,5 +1,6 @@
 """Random start blocks generated on the device (pv_random_block) against the
-oracle's implementation of the same counter-based generator (oracle.rng).
+oracle's implementation of the same counter-based generator (oracle.rng);
+blocks filled from host callbacks (pv_vector_from_func).
 
 Tolerances:
 * Z4 phases: bit-exact (the value is chosen by two integer bits).
@@ -11,6 +12,8 @@ Tolerances:
   difference of the FP64 values can move the rounding across a midpoint, so
   at most one FP32 unit (2^-24 for magnitudes in [0.5, 1)): 6e-8 absolute.
 """
+
+import ctypes
 
 import numpy as np
 import pytest
@@ -80,3 +83,35 @@ def test_kpm_on_device_start_blocks_matches_oracle():
     ref = kpm.moments_direct(c.H, rng.random_block(seed, c.D, nb, rng.PHASE), M, 7.0, 0.0)
     assert np.abs(mu - ref).max() < 1e-12
     assert np.abs(mu[:, 0] - 1.0).max() < 1e-14
+
+
+@pytest.mark.parametrize("dtype", [pv.PV_C128, pv.PV_C64])
+def test_vector_from_func_fills_memory_order_with_the_callbacks(dtype):
+    """pv_vector_from_func (the paper's initial-vector callback, Sec. 3.4):
+    entry (s, o, k) is fnc(r, k) + i fnc_im(r, k) with r = (x, y, z, o),
+    exactly (the values are exact in FP32); the seed state handed to the
+    callback is SplitMix64 outputs 1 and 2 of the seed (oracle generator), and
+    the calls run in memory order (a callback counting its calls)."""
+    L, nb = (5, 4, 3), 2
+    lat = pv.Lattice(L, (1, 1, 0), TI)
+    re = lambda r, k, parm, seed: r[0] + 8.0 * r[1] + 64.0 * r[2] + 512.0 * r[3] + 0.25 * k
+    im = lambda r, k, parm, seed: -(r[0] + 8.0 * r[1]) - 0.5 * k
+    out = host(pv.pv_vector_from_func(lat, nb, re, im, seed=11, dtype=dtype))
+    z, y, x, o, k = np.meshgrid(np.arange(L[2]), np.arange(L[1]), np.arange(L[0]), np.arange(4), np.arange(nb),
+                                indexing="ij")
+    ref = (x + 8.0 * y + 64.0 * z + 512.0 * o + 0.25 * k) - 1j * (x + 8.0 * y + 0.5 * k)
+    assert np.array_equal(out.astype(np.complex128), ref.reshape(lat.n_rows, nb))
+    # the 128-bit state: read once, then advanced by the callback per call
+    seen = []
+
+    def counter(r, k, parm, seed):
+        s = ctypes.cast(seed, ctypes.POINTER(ctypes.c_uint64))
+        if not seen:
+            seen.extend([s[0], s[1]])
+        s[0] = (s[0] + 1) & 0xFFFFFFFFFFFFFFFF
+        return float((s[0] - seen[0]) & 0xFFFF)
+
+    cnt = host(pv.pv_vector_from_func(lat, nb, counter, seed=12345, dtype=dtype))
+    assert [int(v) for v in rng.splitmix64(12345, 0, 2)] == seen
+    assert np.array_equal(cnt.real.reshape(-1), np.arange(1, lat.n_rows * nb + 1, dtype=np.float64))
+    assert np.all(cnt.imag == 0)
