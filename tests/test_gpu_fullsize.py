@@ -1,7 +1,10 @@
 """Parity at the full benchmark size: TI 256 x 256 x 64 periodic (D =
-16,777,216 rows), W = 2, the Chebyshev step with fused dots in the launch
-configurations the benchmark times: the autotuner's shape (as bench.py
-obtains it) and every shape whose traffic bench.py reports.
+16,777,216 rows), W = 2, in the launch configurations the benchmark times:
+the Chebyshev step with fused dots at every block width and vector type of
+its variants in the autotuner's shape (as bench.py obtains it) and in every
+shape whose traffic bench.py reports; the step with the field generated in
+the kernel; the plain sweep with gamma = 0; and the degree-8 series of the
+filter workload.
 
 The oracle cannot assemble H at this size, so the output is checked on
 sampled sites: the oracle builds the explicit rows of H for those sites, the
@@ -9,7 +12,12 @@ test gathers the x entries those rows touch from the device, and compares
 alpha (H x - beta x) + gamma z there.  Sites include every face, edge and
 corner of the periodic box.  The dot products are checked against the closed
 form <x, x> = D of random-phase columns.  Tolerances as in the small parity
-tests (complex128 1e-13, complex64 2e-6 relative to the sampled maximum)."""
+tests (complex128 1e-13, complex64 2e-6 relative to the sampled maximum).
+
+The series is checked by its light cone: T_k(H~) X at a site depends only on
+X within k hops, so the oracle applies the series to the rows of H on the
+ball of K hops around each sampled site (X gathered from the device there)
+and compares the centre's rows, exact up to rounding (1e-12 relative)."""
 
 import numpy as np
 import pytest
@@ -19,7 +27,7 @@ pytestmark = pytest.mark.gpu
 
 import bench  # noqa: E402
 import paper_1708_09689_amd as pv  # noqa: E402
-from oracle import hamiltonian, lattice, models  # noqa: E402
+from oracle import hamiltonian, lattice, models, rng  # noqa: E402
 import workloads as W  # noqa: E402
 
 L = (256, 256, 64)
@@ -43,8 +51,10 @@ def launch_shapes(dtype, nb):
     return [None] + [sh for sh, _ in bench.COUNTED_TRAFFIC.get((dtype, nb), [])]
 
 
-@pytest.mark.parametrize("dtype,nb,k", [("c128", 32, k) for k in range(len(launch_shapes("c128", 32)))] +
-                                       [("c64", 16, k) for k in range(len(launch_shapes("c64", 16)))])
+CASES = [(dt, nb, k) for dt in ("c128", "c64") for nb in (1, 4, 16, 32) for k in range(len(launch_shapes(dt, nb)))]
+
+
+@pytest.mark.parametrize("dtype,nb,k", CASES)
 def test_fullsize_chebyshev_step_sampled(dtype, nb, k):
     dev = torch.device("cuda:0")
     c128 = dtype == "c128"
@@ -82,3 +92,111 @@ def test_fullsize_chebyshev_step_sampled(dtype, nb, k):
     assert np.abs(out - ref).max() < tol * np.abs(ref).max()
     d = dots.cpu().numpy()
     assert np.abs(d[:, 0] - lat.n_rows).max() < (1e-12 if c128 else 1e-6) * lat.n_rows
+
+
+def _fullsize_lattice(dev, c128=True, field="stored"):
+    lat = pv.Lattice(L, (1, 1, 1), pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0]))
+    olat = lattice.Lattice(L, (1, 1, 1), 4)
+    if field == "stored":
+        V = W.uniform_potential(olat.n_sites, 2.0, W.generator(2, W.STREAM_POTENTIAL))
+        lat.set_potential(torch.from_numpy(V if c128 else V.astype(np.float32)).to(dev))
+        Vq = V if c128 else V.astype(np.float32).astype(np.float64)
+    else:
+        lat.set_random_potential(0x1708, 2.0)
+        Vq = rng.field(0x1708, 2.0, olat.n_sites)
+        if not c128:
+            Vq = Vq.astype(np.float32).astype(np.float64)
+    return lat, olat, Vq
+
+
+def _rows(sites):
+    return (np.asarray(sites)[:, None] * 4 + np.arange(4)[None, :]).ravel()
+
+
+def _gather(t, rows):
+    return t[torch.from_numpy(np.asarray(rows)).to(t.device)].cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("dtype,nb", [("c128", 1), ("c128", 4), ("c64", 1), ("c64", 4)])
+def test_fullsize_generated_field_step_sampled(dtype, nb):
+    """The Chebyshev step with the field generated in the kernel (the
+    benchmark's 'generated in the kernel' variants) at full size, against the
+    oracle's generator at the sampled sites."""
+    dev = torch.device("cuda:0")
+    c128 = dtype == "c128"
+    lat, olat, Vq = _fullsize_lattice(dev, c128, field="generated")
+    code = pv.PV_C128 if c128 else pv.PV_C64
+    pv.pv_autotune(lat, nb, code)
+    tname = "complex128" if c128 else "complex64"
+    x = W.random_phase_device(lat.n_rows, nb, 910 + nb, dev, tname)
+    y = W.random_phase_device(lat.n_rows, nb, 911 + nb, dev, tname)
+    sites = sampled_sites(olat)
+    rows = _rows(sites)
+    z_before = _gather(y, rows)
+    pv.pv_spmmv(lat, x, y, 2.0 / A_SCALE, 0.0, -1.0, z=y, dot_flags=pv.PV_DOT_XX | pv.PV_DOT_XY)
+    Hs = hamiltonian.rows_of_sites(models.topological_insulator(1.0, 2.0), olat, Vq, sites).tocsr()
+    cols = np.unique(Hs.indices)
+    ref = 2.0 / A_SCALE * (Hs[:, cols] @ _gather(x, cols)) - z_before
+    out = _gather(y, rows)
+    assert np.abs(out - ref).max() < (1e-13 if c128 else 2e-6) * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("nb", [4, 32])
+def test_fullsize_plain_sweep_sampled(nb):
+    """y = alpha (H - beta) x with gamma = 0 (the kernel that neither loads
+    nor stages z) in the autotuned shape, as the plain-SpMMV workload runs it;
+    y starts as NaN, which must not reach the output."""
+    dev = torch.device("cuda:0")
+    lat, olat, Vq = _fullsize_lattice(dev)
+    pv.pv_autotune(lat, nb, pv.PV_C128)
+    x = W.random_phase_device(lat.n_rows, nb, 920 + nb, dev)
+    y = torch.full_like(x, float("nan"))
+    pv.pv_spmmv(lat, x, y, 1.0 / A_SCALE, 0.3, 0.0)
+    sites = sampled_sites(olat)
+    rows = _rows(sites)
+    Hs = hamiltonian.rows_of_sites(models.topological_insulator(1.0, 2.0), olat, Vq, sites).tocsr()
+    cols = np.unique(Hs.indices)
+    ref = (Hs[:, cols] @ _gather(x, cols) - 0.3 * _gather(x, rows)) / A_SCALE
+    out = _gather(y, rows)
+    assert np.abs(out - ref).max() < 1e-13 * np.abs(ref).max()
+    assert bool(torch.isfinite(y).all())
+
+
+def _ball(model, olat, Vq, centre, K):
+    """Sites within K hops of centre (breadth first over H's couplings)."""
+    seen = {int(centre)}
+    frontier = [int(centre)]
+    for _ in range(K):
+        Hf = hamiltonian.rows_of_sites(model, olat, Vq, np.array(frontier)).tocsr()
+        nxt = set(int(c) // 4 for c in np.unique(Hf.indices)) - seen
+        seen |= nxt
+        frontier = sorted(nxt)
+    return np.array(sorted(seen), dtype=np.int64)
+
+
+def test_fullsize_filter_series_sampled():
+    """The filter workload: Y = sum_k c_k T_k(H~) X, degree 8, nb = 32,
+    complex128, in the lattice's series shape from the autotuner; each
+    sampled site against the oracle's series on its 8-hop ball."""
+    from oracle import chebtp
+    dev = torch.device("cuda:0")
+    nb, K = 32, 8
+    lat, olat, Vq = _fullsize_lattice(dev)
+    pv.pv_autotune(lat, nb, pv.PV_C128)
+    X = W.random_phase_device(lat.n_rows, nb, 77, dev)
+    Y = torch.empty_like(X)
+    coef = np.linspace(1.0, 0.1, K + 1)
+    pv.pv_cheb_series(lat, X, Y, A_SCALE, 0.0, coef)
+    model = models.topological_insulator(1.0, 2.0)
+    Lx, Ly, Lz = L
+    centres = [0, Lx - 1 + Lx * (Ly - 1 + Ly * (Lz - 1)), 63 + Lx * (31 + Ly * 20), 128 + Lx * (160 + Ly * 1),
+               77 + Lx * (5 + Ly * 40)]
+    for s0 in centres:
+        ball = _ball(model, olat, Vq, s0, K)
+        brow = _rows(ball)
+        Hb = hamiltonian.rows_of_sites(model, olat, Vq, ball).tocsc()[:, brow].tocsr()
+        Yb = chebtp.cheb_series(Hb, _gather(X, brow), A_SCALE, 0.0, coef)
+        k = int(np.searchsorted(ball, s0))
+        ref = Yb[4 * k:4 * k + 4]
+        out = _gather(Y, _rows([s0]))
+        assert np.abs(out - ref).max() < 1e-12 * np.abs(ref).max(), s0
