@@ -17,10 +17,20 @@ stated):
   run on the same phases (drawn in complex128, rounded to complex64): the
   stated error of the FP32 path, max|dmu| <= 1e-6 per instance (measured
   at most 6.5e-8).
+* The whole 96-lattice batch as the benchmark runs it (its own autotuned
+  shape, complex64 start blocks from pv_random_block, FP32 field), with the
+  moments of its smallest lattice (L = 24) against the oracle's FP64
+  moments of the same rounded inputs: 1e-6 (the FP32 path's stated error);
+  and that lattice's complex128 run against the oracle: 1e-12.
 * Chebyshev propagation of the 1024 x 1024 ribbon (dot array, packet) for
   200 steps of dt = 10 and back: the norm stays 1 and the packet returns,
   both to 1e-11 (measured 3e-14 and 8e-14; each step's truncation is
-  |J_65(30.6)| ~ 1e-15)."""
+  |J_65(30.6)| ~ 1e-15).
+* One propagation step of that ribbon against the oracle on sampled cells:
+  a step of M = 64 products reaches 64 hops, so the oracle propagates the
+  rows of H on each sampled cell's 64-hop ball (psi gathered from the
+  device) and the centre is exact up to rounding: 1e-12 relative to the
+  largest sampled amplitude."""
 
 import numpy as np
 import pytest
@@ -139,3 +149,85 @@ def test_chebtp_graphene1024_200_steps_norm_and_time_reversal():
     assert abs(n200 - 1.0) < 1e-11
     assert moved > 0.5            # the packet did travel
     assert back < 1e-11
+
+
+def test_batched_96_lattices_smallest_instance_against_oracle():
+    from oracle import hamiltonian, kpm, lattice, models, rng
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    inst = W.batch_instances(96, W.generator(3, W.STREAM_SIZES))
+    M, nb = 1024, 16
+    lats, V64, rs, a = [], [], [], []
+    for i, (L, Wd) in enumerate(inst):
+        lat = pv.Lattice((L, L, L), (1, 1, 1), st)
+        V = W.uniform_potential(lat.n_sites, Wd, W.generator(3, W.STREAM_POTENTIAL, i))
+        lat.set_potential(torch.from_numpy(V).float().to(DEV))
+        lats.append(lat)
+        V64.append(V)
+        rs.append(pv.pv_random_block(lat, nb, 300 + i, pv.PV_RANDOM_PHASE, pv.PV_C64, device=DEV))
+        a.append(7.0 + 0.5 * Wd)
+    batch = pv.Batch(lats)
+    pv.pv_batch_autotune(batch, rs, a, 0.0)
+    mu = pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0).cpu().numpy()
+    k = int(np.argmin([L for L, _ in inst]))
+    L = inst[k][0]
+    print(f"batched: 96 lattices, oracle on instance {k} (L = {L})", flush=True)
+    ol = lattice.Lattice((L, L, L), (1, 1, 1), 4)
+    model = models.topological_insulator(1.0, 2.0)
+    H32 = hamiltonian.assemble(model, ol, V64[k].astype(np.float32).astype(np.float64))
+    r32 = rng.random_block(300 + k, ol.n_rows, nb, rng.PHASE).astype(np.complex64).astype(np.complex128)
+    ref32 = kpm.moments_doubling(H32, r32, M, a[k], 0.0)
+    assert np.abs(mu[k] - ref32).max() < 1e-6
+    # the same lattice's complex128 run (FP64 field, unrounded phases)
+    lat = lats[k]
+    lat.set_potential(torch.from_numpy(V64[k]).to(DEV))
+    r = pv.pv_random_block(lat, nb, 300 + k, pv.PV_RANDOM_PHASE, pv.PV_C128, device=DEV)
+    mu128 = pv.pv_kpm_moments(lat, r, M, a[k], 0.0).cpu().numpy()
+    ref = kpm.moments_doubling(hamiltonian.assemble(model, ol, V64[k]), rng.random_block(300 + k, ol.n_rows, nb,
+                                                                                        rng.PHASE), M, a[k], 0.0)
+    assert np.abs(mu128 - ref).max() < 1e-12
+
+
+def _ball(model, olat, V, centre, K, no):
+    seen = {int(centre)}
+    frontier = [int(centre)]
+    for _ in range(K):
+        Hf = hamiltonian_rows(model, olat, V, np.array(frontier))
+        nxt = set(int(c) // no for c in np.unique(Hf.indices)) - seen
+        seen |= nxt
+        frontier = sorted(nxt)
+    return np.array(sorted(seen), dtype=np.int64)
+
+
+def hamiltonian_rows(model, olat, V, sites):
+    from oracle import hamiltonian
+    return hamiltonian.rows_of_sites(model, olat, V, sites).tocsr()
+
+
+def test_chebtp_graphene1024_step_against_oracle_light_cone():
+    from oracle import chebtp, lattice, models
+    Li = Lj = 1024
+    lat = pv.Lattice((Li, Lj), (0, 1), pv.pv_model_stencil(pv.PV_MODEL_GRAPHENE2, [1.0]))
+    V = W.dot_array_potential(Li, Lj)
+    lat.set_potential(torch.from_numpy(V).to(DEV))
+    psi0 = W.gaussian_wave_packet(Li, Lj, i0=200, width=50, energy=0.2).reshape(-1, 1)
+    psi = torch.from_numpy(psi0.copy()).to(DEV)
+    pv.pv_cheb_propagate(lat, psi, 3.06, 0.05, 10.0, 64, 1)
+    out_all = psi.cpu().numpy()
+    model = models.graphene_two_site(1.0)
+    ol = lattice.Lattice((Li, Lj), (0, 1), 2)
+    # cells in the packet, at the open edge i = 0 and in the dot array
+    cells = [200 + Li * 0, 170 + Li * 511, 260 + Li * 1023, 0 + Li * 300, 448 + Li * 288]
+    peak = 0.0
+    errs = []
+    for c0 in cells:
+        ball = _ball(model, ol, V, c0, 64, 2)
+        brow = (ball[:, None] * 2 + np.arange(2)[None, :]).ravel()
+        Hb = hamiltonian_rows(model, ol, V, ball).tocsc()[:, brow].tocsr()
+        yb = chebtp.propagate(Hb, psi0[brow], 3.06, 0.05, 10.0, 64, 1)
+        j = int(np.searchsorted(ball, c0))
+        ref = yb[2 * j:2 * j + 2, 0]
+        out = out_all[2 * c0:2 * c0 + 2, 0]
+        peak = max(peak, np.abs(ref).max())
+        errs.append(np.abs(out - ref).max())
+    assert peak > 1e-4
+    assert max(errs) < 1e-12 * peak
