@@ -22,6 +22,12 @@ stated):
   moments of its smallest lattice (L = 24) against the oracle's FP64
   moments of the same rounded inputs: 1e-6 (the FP32 path's stated error);
   and that lattice's complex128 run against the oracle: 1e-12.
+* Interior eigenpairs of the benchmark's TI slab (240 x 240 x 6, |E| <
+  0.05) by trLanczosFD: the oracle's H gives each returned pair a residual
+  at most the tolerance 1e-9 a (plus 1e-12 for the two residual
+  computations' rounding), so by the Bauer-Fike bound each value lies within
+  it of an eigenvalue; the vectors are orthonormal to 1e-12, the values lie
+  in the window and come in Kramers pairs (real field) to 1e-9.
 * Chebyshev propagation of the 1024 x 1024 ribbon (dot array, packet) for
   200 steps of dt = 10 and back: the norm stays 1 and the packet returns,
   both to 1e-11 (measured 3e-14 and 8e-14; each step's truncation is
@@ -231,3 +237,30 @@ def test_chebtp_graphene1024_step_against_oracle_light_cone():
         errs.append(np.abs(out - ref).max())
     assert peak > 1e-4
     assert max(errs) < 1e-12 * peak
+
+
+def test_interior_eigenpairs_slab_residuals_against_oracle_H():
+    from oracle import hamiltonian, lattice, models
+    st = pv.pv_model_stencil(pv.PV_MODEL_TI, [1.0, 2.0, 0.0, 0.0])
+    L = (240, 240, 6)
+    lat = pv.Lattice(L, (1, 1, 0), st)
+    V = W.uniform_potential(lat.n_sites, 1.0, W.generator(6, W.STREAM_POTENTIAL))
+    lat.set_potential(torch.from_numpy(V).to(DEV))
+    a, half = 6.0, 0.05
+    V0 = torch.from_numpy(W.gaussian_block(lat.n_rows, 4, W.generator(6, W.STREAM_VECTORS))).to(DEV)
+    th, res, X, _ = pv.pv_trlanczos_fd(lat, V0, a, 0.0, -half, half, 400, 160, 1e-9 * a, max_restarts=40,
+                                       n_out=64)
+    n = th.size
+    print(f"trLanczosFD on the slab: {n} pairs", flush=True)
+    assert n >= 40 and n % 2 == 0
+    Q = X[:, :n].cpu().numpy()
+    H = hamiltonian.assemble(models.topological_insulator(1.0, 2.0), lattice.Lattice(L, (1, 1, 0), 4), V)
+    R = H @ Q - Q * th[None, :]
+    r = np.linalg.norm(R, axis=0)
+    assert r.max() <= 1e-9 * a + 1e-12
+    assert np.abs(r - res).max() < 1e-12
+    G = Q.conj().T @ Q
+    assert np.abs(G - np.eye(n)).max() < 1e-12
+    assert np.all(np.abs(th) < half)
+    ths = np.sort(th)
+    assert np.abs(ths[0::2] - ths[1::2]).max() < 1e-9
