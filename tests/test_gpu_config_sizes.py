@@ -28,6 +28,10 @@ stated):
   computations' rounding), so by the Bauer-Fike bound each value lies within
   it of an eigenvalue; the vectors are orthonormal to 1e-12, the values lie
   in the window and come in Kramers pairs (real field) to 1e-9.
+* The Weyl A(k, E) workload (256 x 32 x 32, periodic x, y, open z, W = 2,
+  surface Bloch columns in blocks of 32, M = 256): the first block's
+  moments, two columns against the oracle (1e-12), and A(E) from them
+  against the oracle's reconstruction (1e-10 relative).
 * Chebyshev propagation of the 1024 x 1024 ribbon (dot array, packet) for
   200 steps of dt = 10 and back: the norm stays 1 and the packet returns,
   both to 1e-11 (measured 3e-14 and 8e-14; each step's truncation is
@@ -264,3 +268,28 @@ def test_interior_eigenpairs_slab_residuals_against_oracle_H():
     assert np.all(np.abs(th) < half)
     ths = np.sort(th)
     assert np.abs(ths[0::2] - ths[1::2]).max() < 1e-9
+
+
+def test_weyl_spectral_block_at_benchmark_size():
+    import math
+    from oracle import hamiltonian, kpm, lattice, models, spectral
+    L = (256, 32, 32)
+    lat = pv.Lattice(L, (1, 1, 0), pv.pv_model_stencil(pv.PV_MODEL_WEYL, [math.pi / 2]))
+    V = W.uniform_potential(lat.n_sites, 2.0, W.generator(5, W.STREAM_POTENTIAL))
+    lat.set_potential(torch.from_numpy(V).to(DEV))
+    kx = 2 * math.pi * np.arange(16) / 256
+    ks = np.array([[k, 0.0, 0.0] for k in kx for _ in (0, 1)])
+    nu = [n for _ in kx for n in (0, 1)]
+    a, M = 7.5, 256
+    R = pv.pv_bloch_block(lat, ks, nu, layer=(2, 0))
+    mu = pv.pv_kpm_moments(lat, R, M, a, 0.0).cpu().numpy()
+    ol = lattice.Lattice(L, (1, 1, 0), 2)
+    H = hamiltonian.assemble(models.weyl_semimetal(math.pi / 2), ol, V)
+    cols = [0, 31]
+    r = spectral.bloch_block(ol, 2, ks[cols], [nu[c] for c in cols], layer=(2, 0))
+    ref = kpm.moments_doubling(H, r, M, a, 0.0)
+    assert np.abs(mu[cols] - ref).max() < 1e-12
+    E = np.linspace(-3.0, 3.0, 13)
+    A = pv.pv_kpm_spectral_function(mu[cols], E, a, 0.0, 32.0)
+    Aref = spectral.spectral_function(ref, E, a, 0.0, 32.0)
+    assert np.abs(A - Aref).max() < 1e-10 * np.abs(Aref).max()
