@@ -24,6 +24,8 @@
 #include <tuple>
 #include <vector>
 
+#include <unistd.h>
+
 namespace pv {
 
 // Text of pv_kernels.hpp and pv_sweep.hpp, embedded by the build.
@@ -86,7 +88,10 @@ bool read_cached(const std::string& path, std::string& lowered, std::vector<char
 }
 
 void write_cached(const std::string& path, const std::string& lowered, const std::vector<char>& code) {
-    const std::string tmp = path + ".tmp" + std::to_string(reinterpret_cast<uintptr_t>(&code));
+    // a name of this process and call: processes sharing the directory never
+    // write one temporary file, and the rename publishes whole files only
+    const std::string tmp = path + ".tmp" + std::to_string(static_cast<long>(getpid())) + "_" +
+                            std::to_string(reinterpret_cast<uintptr_t>(&code));
     {
         std::ofstream f(tmp, std::ios::binary);
         if (!f) return;
