@@ -9,6 +9,9 @@
  *   - model stencils: Sec. 2.1 (graphene), 2.2 (3D TI), 2.3 (Weyl);
  *   - fused sweep y = alpha (H - beta) x + gamma y with partial dot products:
  *     Sec. 3.2, generated-code listing (scale_h, shift_h, scale_z, dot_xx/xy/yy);
+ *   - start vectors: Sec. 3.4 (initial-vector callback), Sec. 3.3 and 4.2
+ *     (random blocks from the counter-based generator, for the stochastic
+ *     trace);
  *   - KPM moments: Sec. 2.2 (DOS) and Sec. 4;
  *   - Chebyshev time propagation: Sec. 4.1, Eq. (U_1);
  *   - Chebyshev filter diagonalisation with Rayleigh-Ritz: Sec. 4.2.
