@@ -277,6 +277,21 @@ def _timed(torch, fn, reps=1):
     return e0.elapsed_time(e1) / reps
 
 
+def with_hbm_fracs(obj):
+    """Every result holding "GB/s" (or "approx_GB/s") also gets its fraction
+    of the 8 TB/s HBM peak, "frac_hbm_peak"."""
+    if isinstance(obj, dict):
+        for key in ("GB/s", "approx_GB/s"):
+            if isinstance(obj.get(key), (int, float)) and "frac_hbm_peak" not in obj:
+                obj["frac_hbm_peak"] = round(obj[key] / HBM_PEAK_GBS, 4)
+        for v in obj.values():
+            with_hbm_fracs(v)
+    elif isinstance(obj, list):
+        for v in obj:
+            with_hbm_fracs(v)
+    return obj
+
+
 def bench_kpm16(pv, torch, W, dev):
     """TI 16^3 periodic, W = 1, one random-phase column, M = 128 (a = 7):
     eager launches vs the same run replayed as a captured HIP graph."""
@@ -498,8 +513,17 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
             worst = max(worst, abs((vals[0] - vals[1]) / (2 * h) - g[m]))
         fd[f"h={h:g}"] = float(f"{worst / np.abs(g).max():.3g}")
     lups = lat.n_rows * 8 * (M // 2)
+    # algorithmic bytes: a forward step 48 B per LUP (+ the field), the
+    # checkpointed backward recomputes the forward once and runs adjoint
+    # steps of 96 B per LUP
+    fwd_bytes = bytes_per_step(lat.n_rows, lat.n_sites, 8, "c128") * (M // 2)
+    fa_gbs = 4 * fwd_bytes / ((ms_cf + ms_cb) * 1e-3) / 1e9
     out = {"ti": {"workload": "TI 64^3, W=1, nb=8, M=256, checkpoint every 16, complex128",
                   "fwd_ms": round(ms_f, 3), "fwd_GLUP/s": round(lups / (ms_f * 1e-3) / 1e9, 3),
+                  "fwd_GB/s": round(fwd_bytes / (ms_f * 1e-3) / 1e9, 1),
+                  "fwd_frac_hbm_peak": round(fwd_bytes / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "fwd+adj_GB/s": round(fa_gbs, 1), "fwd+adj_frac_hbm_peak": round(fa_gbs / HBM_PEAK_GBS, 4),
+                  "bytes_note": "fwd+adj bytes: forward 48 B/LUP, recompute 48, adjoint 96 (4x the forward's)",
                   "grad_ms": round(ms_b, 3), "grad_over_fwd": round(ms_b / ms_f, 2),
                   "fwd_ckpt_ms": round(ms_cf, 3), "adj_from_ckpt_ms": round(ms_cb, 3),
                   "fwd+adj_GLUP/s": round(lups / ((ms_cf + ms_cb) * 1e-3) / 1e9, 3),
@@ -588,9 +612,11 @@ def bench_weyl_spectral(pv, torch, W, dev, nk=64, M=256):
     E = np.array([0.0])
     A0 = [float(pv.pv_kpm_spectral_function(mu[2 * i:2 * i + 2], E, a, 0.0, 32.0)[0]) for i in range(nk)]
     lups = lat.n_rows * 32 * (M // 2) * len(R)
+    wbytes = bytes_per_step(lat.n_rows, lat.n_sites, 32, "c128") * (M // 2) * len(R)
     return {"workload": f"Weyl 256x32x32 (periodic x,y, open z), W=2, surface Bloch states, {nk} k_x x 2 orbitals, "
                         f"M={M}, complex128, blocks of 32",
             "ms_total": round(ms, 2), "GLUP/s": round(lups / (ms * 1e-3) / 1e9, 3),
+            "GB/s": round(wbytes / (ms * 1e-3) / 1e9, 1),
             "A_E0_along_kx_first8": [round(v, 4) for v in A0[:8]]}
 
 
@@ -901,7 +927,7 @@ def main():
         "torch_triad_GBs": None if torch_triad_gbs is None else round(torch_triad_gbs, 1),
         "metric_parts": parts,
         "variants": variants,
-        "workloads": configs,
+        "workloads": with_hbm_fracs(configs),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

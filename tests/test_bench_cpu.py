@@ -45,3 +45,12 @@ def test_bench_refuses_several_gpus():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert out.returncode != 0 and "one GPU" in out.stderr
+
+
+def test_every_workload_rate_gets_its_hbm_fraction():
+    import bench
+    d = {"a": {"GB/s": 4000.0, "runs": [{"approx_GB/s": 2000}]}, "b": {"GB/s": None}, "c": {"ms": 1.0}}
+    out = bench.with_hbm_fracs(d)
+    assert out["a"]["frac_hbm_peak"] == 0.5
+    assert out["a"]["runs"][0]["frac_hbm_peak"] == 0.25
+    assert "frac_hbm_peak" not in out["b"] and "frac_hbm_peak" not in out["c"]
