@@ -277,6 +277,29 @@ def _timed(torch, fn, reps=1):
     return e0.elapsed_time(e1) / reps
 
 
+def fp32_step_error(pv, torch, lat, dev, nb, set_field):
+    """The FP32 path's error at the benchmark size: one Chebyshev step with
+    dots from the same complex64-representable x and z, complex64 vectors
+    with the FP32 field against complex128 vectors with the FP64 field (the
+    complex128 path equals the oracle to 1e-13 in the parity tests)."""
+    import workloads as W
+    x32 = W.random_phase_device(lat.n_rows, nb, 930 + nb, dev, "complex64")
+    z32 = W.random_phase_device(lat.n_rows, nb, 931 + nb, dev, "complex64")
+    flags = pv.PV_DOT_XX | pv.PV_DOT_XY
+    set_field("c128")
+    y64 = z32.to(torch.complex128)
+    d64 = pv.pv_spmmv(lat, x32.to(torch.complex128), y64, 2.0 / A_SCALE, B_SHIFT, -1.0, z=y64, dot_flags=flags)
+    set_field("c64")
+    y32 = z32.clone()
+    d32 = pv.pv_spmmv(lat, x32, y32, 2.0 / A_SCALE, B_SHIFT, -1.0, z=y32, dot_flags=flags)
+    torch.cuda.synchronize()
+    step = float(((y32.to(torch.complex128) - y64).abs().max() / y64.abs().max()).item())
+    dots = float(((d32[:, :2] - d64[:, :2]).abs().max() / d64[:, 0].abs().max()).item())
+    return {"step_max_rel": float(f"{step:.3g}"), "dots_max_rel": float(f"{dots:.3g}"),
+            "note": f"one Chebyshev step at nb={nb} from the same complex64-representable input: complex64 vectors "
+                    "and FP32 field vs complex128 and FP64 field; max |dy| / max |y|, and max |d(xx, xy)| / max xx"}
+
+
 def with_hbm_fracs(obj):
     """Every result holding "GB/s" (or "approx_GB/s") also gets its fraction
     of the 8 TB/s HBM peak, "frac_hbm_peak"."""
@@ -884,7 +907,10 @@ def main():
     parts = {"fp64": {"GLUP/s": round(glups, 3), "frac_hbm_peak": round(achieved / HBM_PEAK_GBS, 4)}}
     v32 = [v for v in variants if v["dtype"] == "c64" and v["nb"] == args.nb and "field" not in v]
     if v32:
-        parts["fp32_vectors_fp64_dots"] = {"GLUP/s": v32[0]["GLUP/s"], "frac_hbm_peak": v32[0]["frac_hbm_peak"]}
+        parts["fp32_vectors_fp64_dots"] = {"GLUP/s": v32[0]["GLUP/s"], "frac_hbm_peak": v32[0]["frac_hbm_peak"],
+                                           "error_vs_fp64": fp32_step_error(pv, torch, lat, dev, args.nb, set_field)}
+        set_field(args.dtype)
+        torch.cuda.empty_cache()
     if "adjoint" in configs:
         ti = configs["adjoint"]["ti"]
         parts["forward_vs_forward_plus_adjoint"] = {"workload": ti["workload"], "fwd_GLUP/s": ti["fwd_GLUP/s"],
