@@ -315,6 +315,12 @@ def with_hbm_fracs(obj):
     return obj
 
 
+def _median_timed(torch, fn, reps=1, runs=3):
+    """Median over `runs` of _timed: a one-off stall of a few tens of
+    milliseconds in one run does not decide the figure."""
+    return sorted(_timed(torch, fn, reps) for _ in range(runs))[runs // 2]
+
+
 def bench_kpm16(pv, torch, W, dev):
     """TI 16^3 periodic, W = 1, one random-phase column, M = 128 (a = 7):
     eager launches vs the same run replayed as a captured HIP graph."""
@@ -325,11 +331,11 @@ def bench_kpm16(pv, torch, W, dev):
     mu = torch.empty((1, 128), dtype=torch.float64, device=dev)
     for _ in range(3):
         pv.pv_kpm_moments(lat, r, 128, 7.0, 0.0, mu=mu)
-    ms_eager = _timed(torch, lambda: pv.pv_kpm_moments(lat, r, 128, 7.0, 0.0, mu=mu), 20)
+    ms_eager = _median_timed(torch, lambda: pv.pv_kpm_moments(lat, r, 128, 7.0, 0.0, mu=mu), 20)
     batch = pv.Batch([lat])
     for _ in range(3):
         pv.pv_batch_kpm_moments(batch, [r], 128, [7.0], [0.0])
-    ms_graph = _timed(torch, lambda: pv.pv_batch_kpm_moments(batch, [r], 128, [7.0], [0.0]), 20)
+    ms_graph = _median_timed(torch, lambda: pv.pv_batch_kpm_moments(batch, [r], 128, [7.0], [0.0]), 20)
     lups = lat.n_rows * 64
     return {"workload": "TI 16x16x16 periodic, W=1, nb=1, M=128 (64 sweeps), complex128",
             "us_per_kpm_eager": round(ms_eager * 1e3, 1), "us_per_kpm_graph": round(ms_graph * 1e3, 1),
@@ -346,7 +352,7 @@ def bench_random_block(pv, torch, lat, dev, nb=32):
     res = {"workload": f"TI 256x256x64 start block, nb={nb}, complex128 ({out.numel() * 16 / 1e9:.1f} GB)"}
     for name, kind in (("phase", pv.PV_RANDOM_PHASE), ("z4", pv.PV_RANDOM_Z4)):
         pv.pv_random_block(lat, nb, 5, kind, out=out)
-        ms = _timed(torch, lambda: pv.pv_random_block(lat, nb, 5, kind, out=out), 5)
+        ms = _median_timed(torch, lambda: pv.pv_random_block(lat, nb, 5, kind, out=out), 5)
         res[f"{name}_ms"] = round(ms, 3)
         res[f"{name}_GBs_written"] = round(out.numel() * 16 / (ms * 1e-3) / 1e9, 1)
     return res
@@ -394,7 +400,7 @@ def bench_filter(pv, torch, lat, dev, nb=32, K=8):
     Y = torch.empty_like(X)
     coef = np.linspace(1.0, 0.1, K + 1)
     pv.pv_cheb_series(lat, X, Y, A_SCALE, B_SHIFT, coef)
-    ms = _timed(torch, lambda: pv.pv_cheb_series(lat, X, Y, A_SCALE, B_SHIFT, coef), 2) / K
+    ms = _median_timed(torch, lambda: pv.pv_cheb_series(lat, X, Y, A_SCALE, B_SHIFT, coef), 2) / K
     by = lat.n_rows * nb * 16 * 5 + lat.n_sites * 8
     return {"workload": f"TI 256x256x64, nb={nb}, complex128, series of degree {K} (filter step)",
             "ms_per_sweep": round(ms, 4), "GLUP/s": round(lat.n_rows * nb / (ms * 1e-3) / 1e9, 3),
@@ -412,7 +418,7 @@ def bench_plain(pv, torch, lat, dev):
         x = W.random_phase_device(lat.n_rows, nb, 78, dev)
         y = torch.empty_like(x)
         pv.pv_spmmv(lat, x, y, 1.0 / A_SCALE, B_SHIFT, 0.0, nb=nb)
-        ms = _timed(torch, lambda: pv.pv_spmmv(lat, x, y, 1.0 / A_SCALE, B_SHIFT, 0.0, nb=nb), 20)
+        ms = _median_timed(torch, lambda: pv.pv_spmmv(lat, x, y, 1.0 / A_SCALE, B_SHIFT, 0.0, nb=nb), 20)
         by = lat.n_rows * nb * 16 * 2 + lat.n_sites * 8
         out[f"nb{nb}"] = {"ms_per_sweep": round(ms, 4), "GLUP/s": round(lat.n_rows * nb / (ms * 1e-3) / 1e9, 3),
                           "GB/s": round(by / (ms * 1e-3) / 1e9, 1),
@@ -454,7 +460,7 @@ def bench_batch(pv, torch, W, dev, n=96, M=1024, nb=16):
     mu = pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0)       # capture + first run
     torch.cuda.synchronize()
     first = time.perf_counter() - t0
-    ms = _timed(torch, lambda: pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0), 1)
+    ms = _median_timed(torch, lambda: pv.pv_batch_kpm_moments(batch, rs, M, a, 0.0), 1)
     ok = bool(torch.isfinite(mu).all().item()) and float((mu[:, :, 0] - 1).abs().max().item()) < 1e-5
     mu64 = mu.cpu().numpy()
     lups = sum(l.n_rows for l in lats) * nb * (M // 2)
@@ -502,15 +508,15 @@ def bench_adjoint(pv, torch, W, dev, ckpt=16):
     M = 256
     gbar = torch.from_numpy(W.generator(4, W.STREAM_COTANGENT).standard_normal((8, M))).to(dev)
     pv.pv_kpm_moments(lat, r, M, 7.0, 0.0)
-    ms_f = _timed(torch, lambda: pv.pv_kpm_moments(lat, r, M, 7.0, 0.0), 2)
+    ms_f = _median_timed(torch, lambda: pv.pv_kpm_moments(lat, r, M, 7.0, 0.0), 2)
     pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, ckpt)
-    ms_b = _timed(torch, lambda: pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, ckpt), 2)
+    ms_b = _median_timed(torch, lambda: pv.pv_kpm_moments_vjp(lat, r, M, 7.0, 0.0, gbar, ckpt), 2)
     # the pair autograd runs: a forward that keeps its checkpoints, then the
     # recompute + adjoint from them
     _, work = pv.pv_kpm_moments_ckpt(lat, r, M, 7.0, 0.0, ckpt)
-    ms_cf = _timed(torch, lambda: pv.pv_kpm_moments_ckpt(lat, r, M, 7.0, 0.0, ckpt), 2)
+    ms_cf = _median_timed(torch, lambda: pv.pv_kpm_moments_ckpt(lat, r, M, 7.0, 0.0, ckpt), 2)
     pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, ckpt)
-    ms_cb = _timed(torch, lambda: pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, ckpt), 2)
+    ms_cb = _median_timed(torch, lambda: pv.pv_kpm_moments_vjp_ckpt(lat, r, M, 7.0, 0.0, gbar, work, ckpt), 2)
     del work
     # memory-rich variant: one segment (ckpt_every = M/2), every w_k kept by
     # the forward (M/2 + 6 vectors, 18 GB here), no recompute
@@ -630,7 +636,7 @@ def bench_weyl_spectral(pv, torch, W, dev, nk=64, M=256):
     R = [pv.pv_bloch_block(lat, k, n, layer=(2, 0)) for k, n in blocks]
     pv.pv_kpm_moments(lat, R[0], M, a, 0.0)
     mus = []
-    ms = _timed(torch, lambda: mus.extend(pv.pv_kpm_moments(lat, r, M, a, 0.0) for r in R), 1)
+    ms = _median_timed(torch, lambda: mus.extend(pv.pv_kpm_moments(lat, r, M, a, 0.0) for r in R), 1)
     mu = torch.cat(mus[-len(R):]).cpu().numpy()
     E = np.array([0.0])
     A0 = [float(pv.pv_kpm_spectral_function(mu[2 * i:2 * i + 2], E, a, 0.0, 32.0)[0]) for i in range(nk)]
